@@ -1,0 +1,224 @@
+/*
+ * cs.h - contingency screening on one MI355X (gfx950).
+ *
+ * The per-contingency evaluation loop of "High-performance computing enabled
+ * contingency analysis for modern power networks" (arXiv 2512.08465):
+ *
+ *   Section II.A   every N-1 and N-2 outage of lines, transformers and
+ *                  generators (the list is the caller's; loads may be
+ *                  outaged too);
+ *   Section II.B.3 islanding check: connected subgraphs after the outage,
+ *                  more than one is severe; the island with the largest
+ *                  generation is solved;
+ *   Section II.B.1 AC optimal power flow on that island: non-convergence or a
+ *                  limit violation is severe.  Solved by a primal-dual
+ *                  interior-point method, one dense LU-factorised KKT system
+ *                  per Newton step;
+ *   Section II.B.2 linearised state matrix at the OPF point and its full
+ *                  eigenspectrum: an eigenvalue with non-negative real part is
+ *                  severe; the minimum damping ratio is reported;
+ *   Section II.C   eq. (1)-(3): F_i = lambda_i, F_ij = lambda_i lambda_j,
+ *                  R_i = F_i S_i + sum_j F_ij S_ij over the list.
+ *
+ * Conventions
+ *   - Every call returns an int status: CS_OK (0) or a negative CS_E* code.
+ *     The message of the last failure on the calling thread is returned by
+ *     cs_last_error().  Validation failures reject the whole call and write no
+ *     output.  Islanding, OPF failure and instability are results, not errors.
+ *   - Per-unit quantities on base_mva; angles in radians; times in seconds.
+ *   - Component ids: [0, n_branch) branches, then [n_branch, n_branch+n_gen)
+ *     generators, then loads.  An outage row (i, j) outages i and j; j = -1
+ *     marks an N-1 outage.
+ *   - Buffers passed in are owned by the caller and only read during the call
+ *     (cs_net_create copies the network to the device).
+ *   - All device work runs on one HIP device chosen at cs_ctx_create.
+ */
+#ifndef CS_H
+#define CS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CS_ABI_VERSION 1
+
+enum {
+  CS_OK = 0,
+  CS_EINVAL = -1,   /* invalid argument (message names it)                   */
+  CS_ENOMEM = -2,   /* host or device allocation failed                        */
+  CS_EHBM = -3,     /* one scenario's workspace exceeds the HBM budget         */
+  CS_EDEVICE = -4,  /* HIP runtime error                                       */
+  CS_EUNSUPPORTED = -5 /* a model or size this build does not support        */
+};
+
+enum { CS_PREC_FP64 = 0 };
+
+/* cause bits of cs_result.cause (severity criteria of Section II.B) */
+enum {
+  CS_CAUSE_ISLAND = 1,      /* more than one island after the outage          */
+  CS_CAUSE_OPF = 2,         /* OPF not converged (or not solvable)            */
+  CS_CAUSE_LIMIT = 4,       /* converged OPF violates a limit by > 1e-6 p.u.  */
+  CS_CAUSE_SSS = 8,         /* an eigenvalue with Re >= 0                     */
+  CS_CAUSE_NUMERICAL = 16   /* singular/non-finite KKT, divergence, QR failure */
+};
+
+/* cs_result.opf_status */
+enum { CS_OPF_CONVERGED = 0, CS_OPF_MAXIT = 1, CS_OPF_NUMERICAL = 2, CS_OPF_NOT_RUN = 3 };
+
+/* cs_result.near: the decision lies close to a threshold */
+enum { CS_NEAR_SSS = 1 /* |max Re| <= near_eps */, CS_NEAR_OPF = 2 /* iters >= max_it-2 */,
+       CS_NEAR_LIMIT = 4 /* max violation above 1e-7 (a decade below the test) */ };
+
+#define CS_N_DYN 14  /* dyn row: H D Xd Xq Xd' Xq' Td0' Tq0' Rs KA TA R Tg Tt */
+
+/* Network description, host structure-of-arrays (copied at cs_net_create). */
+typedef struct {
+  int32_t n_bus, n_branch, n_gen, n_load;
+  int32_t ref_bus;            /* angle reference bus                          */
+  double base_mva;            /* MVA base of the per-unit system (cost scale) */
+  double f_hz;                /* nominal frequency                            */
+  const double *vmin, *vmax;  /* [n_bus] voltage limits                        */
+  const double *gs, *bs;      /* [n_bus] shunt conductance/susceptance         */
+  const int32_t *br_from, *br_to;              /* [n_branch] bus ids          */
+  const double *br_r, *br_x, *br_b;            /* series r, x; total charging */
+  const double *br_rate;      /* rating |S| (p.u.); 0 = unconstrained          */
+  const double *br_tap;       /* off-nominal tap on the from side; 0 means 1   */
+  const double *br_shift;     /* phase shift (rad)                             */
+  const int32_t *gen_bus;     /* [n_gen]                                       */
+  const int32_t *gen_kind;    /* 0 = synchronous generator (only kind here)    */
+  const double *pmin, *pmax, *qmin, *qmax;     /* [n_gen] limits (p.u.)       */
+  const double *c2, *c1, *c0; /* cost c2 (Sb P)^2 + c1 (Sb P) + c0, $/h        */
+  const double *dyn;          /* [n_gen][CS_N_DYN], system base                */
+  const int32_t *load_bus;    /* [n_load]                                      */
+  const double *pd, *qd;      /* [n_load] constant power at the OPF stage      */
+} cs_net_desc;
+
+typedef struct {
+  int32_t prec;        /* CS_PREC_FP64                                        */
+  int32_t max_it;      /* IPM iteration cap (default 150)                     */
+  double tol;          /* IPM termination tolerance (default 1e-8)            */
+  double near_eps;     /* |max Re lambda| flagged as near (default 1e-6)      */
+  size_t hbm_budget;   /* bytes of scenario workspace; 0 = context default    */
+  int32_t batch;       /* scenarios resident at once; 0 = from the budget     */
+  int32_t timing;      /* 1: time every kernel launch with HIP events on the
+                          launch stream and accumulate cs_stats (adds one
+                          synchronisation per OPF iteration)                 */
+} cs_opts;
+
+/* Per-kernel accumulated device time of the calls made with opts.timing = 1
+ * since the last cs_stats_reset.  units = matrices or scenarios processed. */
+enum { CS_K_TOPOLOGY = 0, CS_K_KKT_ASSEMBLE, CS_K_KKT_LU, CS_K_IPM_UPDATE,
+       CS_K_DYN_ASSEMBLE, CS_K_DYN_LU, CS_K_STATE_MATRIX, CS_K_EIG, CS_K_CLASSIFY,
+       CS_K_RISK, CS_K_COUNT };
+typedef struct {
+  double ms[CS_K_COUNT];          /* summed launch durations                 */
+  int64_t launches[CS_K_COUNT];
+  int64_t units[CS_K_COUNT];      /* e.g. KKT factorisations performed       */
+  int64_t kkt_order;              /* order of the last KKT system factorised */
+  int64_t dyn_order;              /* order of the last algebraic system      */
+} cs_stats;
+
+/* One record per scenario (48 bytes), the paper's per-scenario record. */
+typedef struct {
+  uint8_t severe;       /* S_c in {0, 1}                                     */
+  uint8_t cause;        /* CS_CAUSE_* bits                                   */
+  uint8_t opf_status;   /* CS_OPF_*                                          */
+  uint8_t near;         /* CS_NEAR_* bits                                    */
+  int16_t n_islands;    /* connected subgraphs after the outage              */
+  int16_t opf_iters;    /* Newton steps taken                                */
+  int32_t n_states;     /* order of the state matrix (0 if not built)        */
+  int32_t reserved;
+  double opf_cost;      /* $/h; NaN if the OPF did not run                   */
+  double max_real_eig;  /* max Re lambda; NaN if not computed                */
+  double min_damping;   /* min damping ratio of oscillatory modes (1 if none) */
+  double max_violation; /* largest limit excess (p.u., <= 0 when feasible)   */
+} cs_result;
+
+typedef struct cs_ctx cs_ctx;
+typedef struct cs_net cs_net;
+
+void cs_opts_default(cs_opts* opts);
+
+/* Create a context on HIP device `device`.  hbm_budget bounds the scenario
+ * workspace of each call (0 = 48 GiB).  Errors: CS_EINVAL, CS_EDEVICE. */
+int cs_ctx_create(int device, size_t hbm_budget, cs_ctx** out);
+void cs_ctx_destroy(cs_ctx* ctx);
+
+/* Validate the network and copy it to the device (Section II.B.3 step 1: the
+ * numerical model the outages are applied to).  Errors: CS_EINVAL (sizes,
+ * bus ids, self-loops, non-finite values, a non-synchronous generator),
+ * CS_ENOMEM, CS_EDEVICE. */
+int cs_net_create(cs_ctx* ctx, const cs_net_desc* desc, cs_net** out);
+void cs_net_destroy(cs_net* net);
+
+/* Screen n outages (host buffers).  outages: int32 [n][2]; lambda: failure
+ * rates [n_comp] in 1/yr (>= 0, finite); opts may be NULL for defaults.
+ * out: [n] records; risk: [n_comp] R_i (may be NULL).  R_i sums eq. (3) over
+ * the list as given, in list order.  Errors: CS_EINVAL (component id out of
+ * range, i == j, bad lambda), CS_EHBM, CS_ENOMEM, CS_EDEVICE. */
+int cs_screen(cs_ctx* ctx, cs_net* net, const int32_t* outages, int64_t n,
+              const double* lambda, const cs_opts* opts, cs_result* out,
+              double* risk);
+
+/* Same, with device-resident buffers (e.g. from torch) and a HIP stream
+ * (NULL = the default stream).  The outage list is validated on the device
+ * and an invalid entry fails the call with CS_EINVAL before any result is
+ * written.  Returns after the work on `stream` completes. */
+int cs_screen_device(cs_ctx* ctx, cs_net* net, const int32_t* d_outages,
+                     int64_t n, const double* d_lambda, const cs_opts* opts,
+                     cs_result* d_out, double* d_risk, void* stream);
+
+/* One scenario in full detail, for parity checks.  Host buffers:
+ * vm, va [n_bus] (NaN outside the solved island), pg, qg [n_gen] (NaN when
+ * out of service), eig_re, eig_im [7 n_gen] with *n_eig set to the number
+ * written, label [n_bus] (island label = smallest bus id of the island).
+ * Any pointer except rec may be NULL. */
+int cs_detail(cs_ctx* ctx, cs_net* net, const int32_t outage[2],
+              const cs_opts* opts, cs_result* rec, double* vm, double* va,
+              double* pg, double* qg, double* eig_re, double* eig_im,
+              int32_t* n_eig, int32_t* label);
+
+/* Kernel-level entry points (device buffers, for testing the dense kernels
+ * alone).  Batched LU with partial pivoting of `batch` column-major n x n
+ * matrices followed by the solve of nrhs right-hand sides stored as extra
+ * columns: A is [batch][ncols = n + nrhs][lda], overwritten by the factors
+ * and the solutions.  info[b] = 1 if matrix b hit an exactly zero pivot. */
+int cs_dense_solve_batched(const cs_ctx* ctx, double* d_A, int32_t n,
+                           int32_t nrhs, int32_t lda, int32_t batch,
+                           int32_t* d_info, void* stream);
+
+/* Eigenvalues of `batch` column-major n x n matrices (lda), overwritten by
+ * their Hessenberg/Schur work; wr, wi: [batch][n].  info[b] = 1 if QR did
+ * not converge. */
+int cs_eigvals_batched(const cs_ctx* ctx, double* d_A, int32_t n, int32_t lda,
+                       int32_t batch, double* d_wr, double* d_wi,
+                       int32_t* d_info, void* stream);
+
+/* Parity/debug: run the OPF of one scenario for `iters` Newton steps, then
+ * evaluate and assemble the KKT system at the point reached (Section II.B.1).
+ * Host outputs, each may be NULL: K [nk + 1][nk] column-major (the last
+ * column is the right-hand side; layout of the fixed-position KKT: theta,
+ * V, Pg, Qg, then P and Q balance multipliers, with identity rows for
+ * removed variables), x [2 n_bus + 2 n_gen], lam [2 n_bus],
+ * z, mu [2 n_branch + 2 n_bus + 4 n_gen], metrics [8] (feasibility,
+ * gradient, complementarity, cost change, barrier, last-pivot-zero flag, cost,
+ * Newton steps taken), status (CS_OPF_*; CS_OPF_MAXIT
+ * means still iterating), order (= nk). */
+int cs_kkt_at(cs_ctx* ctx, cs_net* net, const int32_t outage[2], int32_t iters,
+              double* K, double* x, double* lam, double* z, double* mu,
+              double* metrics, int32_t* status, int32_t* order);
+
+/* Copy / clear the context's kernel timing counters. */
+int cs_stats_get(const cs_ctx* ctx, cs_stats* out);
+int cs_stats_reset(cs_ctx* ctx);
+
+const char* cs_last_error(void);
+int cs_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CS_H */

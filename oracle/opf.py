@@ -245,6 +245,29 @@ class OPFProblem:
         return self.pack(va, vm, pg, qg)
 
 
+def kkt_system(P, x, lam, mu, z, gamma, g, h, Jg, Jh, Lx, aux):
+    """The reduced Newton system [M Jg'; Jg 0] [dx; dlam] = [-N; -g]."""
+    neq = len(g)
+    Hl = P.lagrangian_hessian(x, lam, mu, aux)
+    zinv = 1.0 / z
+    M = Hl + Jh.T @ ((mu * zinv)[:, None] * Jh)
+    N = Lx + Jh.T @ (zinv * (gamma + mu * h))
+    K = np.block([[M, Jg.T], [Jg, np.zeros((neq, neq))]])
+    rhs = -np.concatenate([N, g])
+    return K, rhs
+
+
+def initial_state(P):
+    """Start of the iteration: x0, z0 = max(-h, 1), gamma = 1, mu = 1/z, lam = 0."""
+    x = P.initial_point()
+    g, h, Jg, Jh, aux = P.evaluate(x)
+    z = np.maximum(-h, 1.0)
+    gamma = 1.0
+    mu = gamma / z
+    lam = np.zeros(2 * P.nb)
+    return x, lam, z, mu, gamma
+
+
 def solve_opf(net, sub, opts: OPFOptions = OPFOptions(), keep_history=False) -> OPFResult:
     """Primal-dual interior point, one dense LU-solved KKT system per step."""
     P = OPFProblem(net, sub)
@@ -277,12 +300,8 @@ def solve_opf(net, sub, opts: OPFOptions = OPFOptions(), keep_history=False) -> 
             status = MAXIT
             break
         it += 1
-        Hl = P.lagrangian_hessian(x, lam, mu, aux)
+        K, rhs = kkt_system(P, x, lam, mu, z, gamma, g, h, Jg, Jh, Lx, aux)
         zinv = 1.0 / z
-        M = Hl + Jh.T @ ((mu * zinv)[:, None] * Jh)
-        N = Lx + Jh.T @ (zinv * (gamma + mu * h))
-        K = np.block([[M, Jg.T], [Jg, np.zeros((neq, neq))]])
-        rhs = -np.concatenate([N, g])
         if not np.all(np.isfinite(K)) or not np.all(np.isfinite(rhs)):
             status = NUMERICAL
             break

@@ -106,8 +106,8 @@ def evaluate(net, outage, opts: ScreenOptions = ScreenOptions(),
     else:
         if o.max_violation > LIMIT_TOL:
             cause |= CAUSE_LIMIT
-        if abs(o.max_violation - LIMIT_TOL) <= LIMIT_TOL:
-            near |= NEAR_LIMIT
+        if o.max_violation > 0.1 * LIMIT_TOL:
+            near |= NEAR_LIMIT          # within a decade of the limit test
         dm = dynamics.DynModel(net, sub, o.vm, o.va, o.pg, o.qg)
         A = dm.state_matrix()
         res.n_states = A.shape[0]

@@ -1,0 +1,274 @@
+"""MI355X contingency screening: Python binding of the C-ABI in include/cs.h.
+
+Argument marshalling only; every step of the screening runs in the HIP
+library ``libcs.so`` built in this directory.  Importing works without a GPU;
+creating a context requires one and fails loudly if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcs.so")
+
+CS_OK, CS_EINVAL, CS_ENOMEM, CS_EHBM, CS_EDEVICE, CS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+CAUSE_ISLAND, CAUSE_OPF, CAUSE_LIMIT, CAUSE_SSS, CAUSE_NUMERICAL = 1, 2, 4, 8, 16
+OPF_CONVERGED, OPF_MAXIT, OPF_NUMERICAL, OPF_NOT_RUN = 0, 1, 2, 3
+NEAR_SSS, NEAR_OPF, NEAR_LIMIT = 1, 2, 4
+N_DYN = 14
+
+RESULT_DTYPE = np.dtype([
+    ("severe", np.uint8), ("cause", np.uint8), ("opf_status", np.uint8), ("near", np.uint8),
+    ("n_islands", np.int16), ("opf_iters", np.int16), ("n_states", np.int32),
+    ("reserved", np.int32), ("opf_cost", np.float64), ("max_real_eig", np.float64),
+    ("min_damping", np.float64), ("max_violation", np.float64)])
+assert RESULT_DTYPE.itemsize == 48
+
+
+class CSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"cs error {code}: {msg}")
+        self.code = code
+
+
+class _NetDesc(ctypes.Structure):
+    _fields_ = [("n_bus", ctypes.c_int32), ("n_branch", ctypes.c_int32),
+                ("n_gen", ctypes.c_int32), ("n_load", ctypes.c_int32),
+                ("ref_bus", ctypes.c_int32), ("base_mva", ctypes.c_double),
+                ("f_hz", ctypes.c_double)] + \
+               [(k, ctypes.c_void_p) for k in (
+                   "vmin", "vmax", "gs", "bs", "br_from", "br_to", "br_r", "br_x",
+                   "br_b", "br_rate", "br_tap", "br_shift", "gen_bus", "gen_kind",
+                   "pmin", "pmax", "qmin", "qmax", "c2", "c1", "c0", "dyn",
+                   "load_bus", "pd", "qd")]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("max_it", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("near_eps", ctypes.c_double),
+                ("hbm_budget", ctypes.c_size_t), ("batch", ctypes.c_int32),
+                ("timing", ctypes.c_int32)]
+
+
+KERNELS = ("topology", "kkt_assemble", "kkt_lu", "ipm_update", "dyn_assemble", "dyn_lu",
+           "state_matrix", "eig", "classify", "risk")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * len(KERNELS)),
+                ("launches", ctypes.c_int64 * len(KERNELS)),
+                ("units", ctypes.c_int64 * len(KERNELS)),
+                ("kkt_order", ctypes.c_int64), ("dyn_order", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def library():
+    """Load libcs.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2512_08465_amd.build`")
+    # PyTorch provides device memory and streams, so the process must use its
+    # HIP runtime: load it first, and libcs.so binds to the same
+    # libamdhip64.so.7 instead of loading a second runtime.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    sig = {
+        "cs_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(vp)]),
+        "cs_ctx_destroy": (None, [vp]),
+        "cs_net_create": (ctypes.c_int, [vp, ctypes.POINTER(_NetDesc), ctypes.POINTER(vp)]),
+        "cs_net_destroy": (None, [vp]),
+        "cs_opts_default": (None, [ctypes.POINTER(Options)]),
+        "cs_screen": (ctypes.c_int, [vp, vp, vp, i64, dp, ctypes.POINTER(Options), vp, dp]),
+        "cs_screen_device": (ctypes.c_int, [vp, vp, vp, i64, dp, ctypes.POINTER(Options),
+                                            vp, dp, vp]),
+        "cs_detail": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(Options), vp, dp, dp, dp,
+                                     dp, dp, dp, vp, vp]),
+        "cs_dense_solve_batched": (ctypes.c_int, [vp, dp, i32, i32, i32, i32, vp, vp]),
+        "cs_eigvals_batched": (ctypes.c_int, [vp, dp, i32, i32, i32, dp, dp, vp, vp]),
+        "cs_kkt_at": (ctypes.c_int, [vp, vp, vp, i32, dp, dp, dp, dp, dp, dp, vp, vp]),
+        "cs_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(Stats)]),
+        "cs_stats_reset": (ctypes.c_int, [vp]),
+        "cs_last_error": (ctypes.c_char_p, []),
+        "cs_abi_version": (ctypes.c_int, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+EXPORTED = ("cs_ctx_create", "cs_ctx_destroy", "cs_net_create", "cs_net_destroy",
+            "cs_opts_default", "cs_screen", "cs_screen_device", "cs_detail",
+            "cs_dense_solve_batched", "cs_eigvals_batched", "cs_kkt_at", "cs_stats_get",
+            "cs_stats_reset", "cs_last_error", "cs_abi_version")
+
+
+def _check(rc):
+    if rc != CS_OK:
+        raise CSError(rc, library().cs_last_error().decode())
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    library().cs_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """A device context (cs_ctx)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        self._h = ctypes.c_void_p()
+        _check(library().cs_ctx_create(device, hbm_budget, ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            library().cs_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(library().cs_stats_get(self._h, ctypes.byref(st)))
+        out = {k: dict(ms=st.ms[i], launches=st.launches[i], units=st.units[i])
+               for i, k in enumerate(KERNELS)}
+        out["kkt_order"] = st.kkt_order
+        out["dyn_order"] = st.dyn_order
+        return out
+
+    def reset_stats(self):
+        _check(library().cs_stats_reset(self._h))
+
+    # kernel-level entry points (device pointers, e.g. torch tensors' data_ptr)
+    def dense_solve_batched(self, a_ptr, n, nrhs, lda, batch, info_ptr=None, stream=None):
+        _check(library().cs_dense_solve_batched(self._h, a_ptr, n, nrhs, lda, batch,
+                                                info_ptr, stream))
+
+    def eigvals_batched(self, a_ptr, n, lda, batch, wr_ptr, wi_ptr, info_ptr=None, stream=None):
+        _check(library().cs_eigvals_batched(self._h, a_ptr, n, lda, batch, wr_ptr, wi_ptr,
+                                            info_ptr, stream))
+
+
+_F64 = ("vmin", "vmax", "gs", "bs", "br_r", "br_x", "br_b", "br_rate", "br_tap", "br_shift",
+        "pmin", "pmax", "qmin", "qmax", "c2", "c1", "c0", "dyn", "pd", "qd")
+_I32 = ("br_from", "br_to", "gen_bus", "gen_kind", "load_bus")
+
+
+class Network:
+    """A device-resident network (cs_net) built from a case dict."""
+
+    def __init__(self, ctx: Context, case: dict):
+        self.ctx = ctx
+        self._keep = {}
+        d = _NetDesc()
+        for k in ("n_bus", "n_branch", "n_gen", "n_load", "ref_bus"):
+            setattr(d, k, int(case[k]))
+        d.base_mva = float(case["base_mva"])
+        d.f_hz = float(case.get("f_hz", 60.0))
+        for k in _F64:
+            a = np.ascontiguousarray(case[k], dtype=np.float64)
+            self._keep[k] = a
+            setattr(d, k, a.ctypes.data)
+        for k in _I32:
+            a = np.ascontiguousarray(case[k], dtype=np.int32)
+            self._keep[k] = a
+            setattr(d, k, a.ctypes.data)
+        self.n_bus, self.n_branch = int(case["n_bus"]), int(case["n_branch"])
+        self.n_gen, self.n_load = int(case["n_gen"]), int(case["n_load"])
+        self.n_comp = self.n_branch + self.n_gen + self.n_load
+        self._h = ctypes.c_void_p()
+        _check(library().cs_net_create(ctx.handle, ctypes.byref(d), ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            library().cs_net_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def screen(self, outages, lam=None, options: Options | None = None):
+        """Host buffers in, (records, risk) out."""
+        out_list = np.ascontiguousarray(outages, dtype=np.int32).reshape(-1, 2)
+        n = len(out_list)
+        res = np.zeros(n, dtype=RESULT_DTYPE)
+        lam_a = None if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
+        risk = None if lam is None else np.zeros(self.n_comp)
+        o = options or default_options()
+        _check(library().cs_screen(self.ctx.handle, self._h, _ptr(out_list), n, _ptr(lam_a),
+                                   ctypes.byref(o), _ptr(res), _ptr(risk)))
+        return res, risk
+
+    def screen_device(self, d_outages, n, d_lambda, d_results, d_risk,
+                      options: Options | None = None, stream=None):
+        """Device pointers in and out (e.g. torch tensors' data_ptr())."""
+        o = options or default_options()
+        _check(library().cs_screen_device(self.ctx.handle, self._h, d_outages, n, d_lambda,
+                                          ctypes.byref(o), d_results, d_risk, stream))
+
+    def kkt_at(self, outage, iters: int):
+        """KKT system and iterate after ``iters`` Newton steps (parity/debug)."""
+        nb, nl, ng = self.n_bus, self.n_branch, self.n_gen
+        nk = 4 * nb + 2 * ng
+        K = np.zeros((nk + 1, nk))
+        x = np.zeros(2 * nb + 2 * ng)
+        lam = np.zeros(2 * nb)
+        z = np.zeros(2 * nl + 2 * nb + 4 * ng)
+        mu = np.zeros_like(z)
+        met = np.zeros(8)
+        status = np.zeros(1, np.int32)
+        order = np.zeros(1, np.int32)
+        o2 = np.ascontiguousarray(outage, dtype=np.int32).reshape(2)
+        _check(library().cs_kkt_at(self.ctx.handle, self._h, _ptr(o2), int(iters), _ptr(K),
+                                   _ptr(x), _ptr(lam), _ptr(z), _ptr(mu), _ptr(met),
+                                   _ptr(status), _ptr(order)))
+        return dict(K=K[:nk].T.copy(), rhs=K[nk].copy(), x=x, lam=lam, z=z, mu=mu,
+                    metrics=met, status=int(status[0]))
+
+    def detail(self, outage, options: Options | None = None):
+        o = options or default_options()
+        rec = np.zeros(1, dtype=RESULT_DTYPE)
+        vm = np.zeros(self.n_bus)
+        va = np.zeros(self.n_bus)
+        pg = np.zeros(self.n_gen)
+        qg = np.zeros(self.n_gen)
+        er = np.zeros(7 * self.n_gen)
+        ei = np.zeros(7 * self.n_gen)
+        ne = np.zeros(1, dtype=np.int32)
+        lab = np.zeros(self.n_bus, dtype=np.int32)
+        o2 = np.ascontiguousarray(outage, dtype=np.int32).reshape(2)
+        _check(library().cs_detail(self.ctx.handle, self._h, _ptr(o2), ctypes.byref(o),
+                                   _ptr(rec), _ptr(vm), _ptr(va), _ptr(pg), _ptr(qg),
+                                   _ptr(er), _ptr(ei), _ptr(ne), _ptr(lab)))
+        k = int(ne[0])
+        return dict(record=rec[0], vm=vm, va=va, pg=pg, qg=qg,
+                    eig=er[:k] + 1j * ei[:k], label=lab)

@@ -1,0 +1,763 @@
+// Host runtime and C-ABI of the screening library.
+//
+// A call screens its outage list in batches of B resident scenario slots
+// (B from the HBM budget).  Per batch, on one HIP stream:
+//   islands -> setup -> { OPF evaluate/assemble -> LU+solve -> step } until no
+//   slot is still iterating -> dynamic Jacobians -> LU+solve (g_y^{-1} g_x)
+//   -> state matrix -> Hessenberg + QR -> classify;
+// then one risk reduction over the whole list.  The network is resident on the
+// device from cs_net_create; per-call workspace is cached in the context and
+// grown when a larger network or batch needs it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cs.h"
+#include "cs_internal.h"
+
+namespace cs {
+size_t lu_lds_bytes(int n);
+size_t opf_eval_lds(int nb, int nl, int ng);
+size_t form_state_lds(int ng);
+void launch_setup_k(const DevNet& net, const Slots& s, int count, const int* outages,
+                    long long scen0, hipStream_t st);
+void lu_set_attrs(size_t bytes);
+void opf_set_attrs(size_t bytes);
+void dyn_set_attrs(size_t bytes);
+constexpr size_t kLdsMax = 160 * 1024;
+}  // namespace cs
+
+using namespace cs;
+
+static thread_local std::string g_err;
+static size_t set_kernel_attrs(int device);
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return fail(CS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct cs_ctx {
+  int device = 0;
+  size_t hbm_budget = 0;
+  hipStream_t stream = nullptr;
+  int* d_counter = nullptr;
+  int* h_counter = nullptr;
+  // cached workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  // kernel timing
+  cs_stats stats{};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  size_t lds_max = 64 * 1024;   // dynamic LDS per workgroup this device allows
+};
+
+// Brackets one launch with events when timing is on and adds its duration.
+struct Timer {
+  cs_ctx* c;
+  bool on;
+  hipStream_t st;
+  int k;
+  Timer(cs_ctx* c_, bool on_, hipStream_t st_, int k_) : c(c_), on(on_), st(st_), k(k_) {
+    if (on) hipEventRecord(c->ev0, st);
+  }
+  int done(int64_t units) {
+    if (!on) return CS_OK;
+    if (hipEventRecord(c->ev1, st) != hipSuccess || hipEventSynchronize(c->ev1) != hipSuccess)
+      return fail(CS_EDEVICE, "timing event failed");
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    c->stats.ms[k] += ms;
+    c->stats.launches[k] += 1;
+    c->stats.units[k] += units;
+    return CS_OK;
+  }
+};
+
+struct cs_net {
+  cs_ctx* ctx = nullptr;
+  DevNet d{};
+  std::vector<void*> allocs;
+  int nb = 0, nl = 0, ng = 0, nd = 0;
+};
+
+// Raise the dynamic LDS limit of the kernels that need more than the
+// default to what the device allows; returns that limit.  Errors are cleared
+// so they do not surface in a later, unrelated runtime call.
+static size_t set_kernel_attrs(int device) {
+  int per_block = 0, optin = 0;
+  hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+  hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, device);
+  size_t lim = (size_t)std::max(per_block, optin);
+  lim = std::min(lim, kLdsMax);
+  if (lim > 64 * 1024) {
+    lu_set_attrs(lim);
+    opf_set_attrs(lim);
+    dyn_set_attrs(lim);
+  }
+  (void)hipGetLastError();
+  return lim;
+}
+
+extern "C" {
+
+const char* cs_last_error(void) { return g_err.c_str(); }
+int cs_abi_version(void) { return CS_ABI_VERSION; }
+
+void cs_opts_default(cs_opts* o) {
+  if (!o) return;
+  o->prec = CS_PREC_FP64;
+  o->max_it = 150;
+  o->tol = 1e-8;
+  o->near_eps = 1e-6;
+  o->hbm_budget = 0;
+  o->batch = 0;
+  o->timing = 0;
+}
+
+int cs_ctx_create(int device, size_t hbm_budget, cs_ctx** out) {
+  if (!out) return fail(CS_EINVAL, "cs_ctx_create: out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev)
+    return fail(CS_EINVAL, "cs_ctx_create: device " + std::to_string(device) +
+                               " out of range (" + std::to_string(ndev) + " devices)");
+  HIPCHK(hipSetDevice(device));
+  cs_ctx* c = new cs_ctx();
+  c->device = device;
+  c->hbm_budget = hbm_budget ? hbm_budget : ((size_t)48 << 30);
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+      hipMalloc(&c->d_counter, sizeof(int)) != hipSuccess ||
+      hipHostMalloc(&c->h_counter, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return fail(CS_EDEVICE, "cs_ctx_create: stream or counter allocation failed");
+  }
+  // kernels whose LDS may exceed the default dynamic limit
+  c->lds_max = set_kernel_attrs(device);
+  *out = c;
+  return CS_OK;
+}
+
+void cs_ctx_destroy(cs_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  if (c->ws) hipFree(c->ws);
+  if (c->d_counter) hipFree(c->d_counter);
+  if (c->h_counter) hipHostFree(c->h_counter);
+  if (c->stream) hipStreamDestroy(c->stream);
+  if (c->ev0) hipEventDestroy(c->ev0);
+  if (c->ev1) hipEventDestroy(c->ev1);
+  delete c;
+}
+
+int cs_stats_get(const cs_ctx* c, cs_stats* out) {
+  if (!c || !out) return fail(CS_EINVAL, "cs_stats_get: NULL argument");
+  *out = c->stats;
+  return CS_OK;
+}
+
+int cs_stats_reset(cs_ctx* c) {
+  if (!c) return fail(CS_EINVAL, "cs_stats_reset: NULL argument");
+  c->stats = cs_stats{};
+  return CS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ network
+template <class T>
+static int upload(cs_net* n, const T* host, size_t count, const T** dst) {
+  void* p = nullptr;
+  const size_t bytes = std::max<size_t>(1, count) * sizeof(T);
+  if (hipMalloc(&p, bytes) != hipSuccess) return fail(CS_ENOMEM, "device allocation failed");
+  n->allocs.push_back(p);
+  if (count && hipMemcpy(p, host, count * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(CS_EDEVICE, "host to device copy failed");
+  *dst = static_cast<const T*>(p);
+  return CS_OK;
+}
+
+static bool all_finite(const double* a, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+extern "C" void cs_net_destroy(cs_net* n) {
+  if (!n) return;
+  if (n->ctx) hipSetDevice(n->ctx->device);
+  for (void* p : n->allocs) hipFree(p);
+  delete n;
+}
+
+extern "C" int cs_net_create(cs_ctx* ctx, const cs_net_desc* d, cs_net** out) {
+  if (!ctx || !d || !out) return fail(CS_EINVAL, "cs_net_create: NULL argument");
+  *out = nullptr;
+  const int nb = d->n_bus, nl = d->n_branch, ng = d->n_gen, nd = d->n_load;
+  if (nb <= 0 || nl < 0 || ng <= 0 || nd < 0)
+    return fail(CS_EINVAL, "cs_net_create: sizes must be n_bus > 0, n_gen > 0, others >= 0");
+  if (nb > 4096 || ng > 1024 || 7 * ng - 1 > 1024)
+    return fail(CS_EUNSUPPORTED, "cs_net_create: at most 4096 buses and 146 generators' worth of states (1024)");
+  if (d->ref_bus < 0 || d->ref_bus >= nb) return fail(CS_EINVAL, "cs_net_create: ref_bus out of range");
+  if (!(d->base_mva > 0) || !(d->f_hz > 0)) return fail(CS_EINVAL, "cs_net_create: base_mva and f_hz must be > 0");
+  const double* need[] = {d->vmin, d->vmax, d->gs, d->bs, d->br_r, d->br_x, d->br_b, d->br_rate,
+                          d->pmin, d->pmax, d->qmin, d->qmax, d->c2, d->c1, d->c0, d->dyn, d->pd, d->qd};
+  for (const double* p : need)
+    if (!p) return fail(CS_EINVAL, "cs_net_create: a required array is NULL");
+  if (!d->br_from || !d->br_to || !d->gen_bus || (nd && !d->load_bus))
+    return fail(CS_EINVAL, "cs_net_create: an index array is NULL");
+  if (!all_finite(d->vmin, nb) || !all_finite(d->vmax, nb) || !all_finite(d->gs, nb) ||
+      !all_finite(d->bs, nb) || !all_finite(d->br_r, nl) || !all_finite(d->br_x, nl) ||
+      !all_finite(d->br_b, nl) || !all_finite(d->br_rate, nl) || !all_finite(d->pmin, ng) ||
+      !all_finite(d->pmax, ng) || !all_finite(d->qmin, ng) || !all_finite(d->qmax, ng) ||
+      !all_finite(d->c2, ng) || !all_finite(d->c1, ng) || !all_finite(d->c0, ng) ||
+      !all_finite(d->dyn, ng * CS_N_DYN) || !all_finite(d->pd, nd) || !all_finite(d->qd, nd))
+    return fail(CS_EINVAL, "cs_net_create: non-finite value in the network");
+  for (int l = 0; l < nl; ++l) {
+    if (d->br_from[l] < 0 || d->br_from[l] >= nb || d->br_to[l] < 0 || d->br_to[l] >= nb)
+      return fail(CS_EINVAL, "cs_net_create: branch " + std::to_string(l) + " bus out of range");
+    if (d->br_from[l] == d->br_to[l])
+      return fail(CS_EINVAL, "cs_net_create: branch " + std::to_string(l) + " is a self-loop");
+    if (d->br_r[l] == 0.0 && d->br_x[l] == 0.0)
+      return fail(CS_EINVAL, "cs_net_create: branch " + std::to_string(l) + " has zero impedance");
+  }
+  for (int b = 0; b < nb; ++b)
+    if (!(d->vmin[b] > 0) || d->vmin[b] > d->vmax[b])
+      return fail(CS_EINVAL, "cs_net_create: bus " + std::to_string(b) + " needs 0 < vmin <= vmax");
+  for (int g = 0; g < ng; ++g) {
+    if (d->gen_bus[g] < 0 || d->gen_bus[g] >= nb)
+      return fail(CS_EINVAL, "cs_net_create: generator " + std::to_string(g) + " bus out of range");
+    if (d->gen_kind && d->gen_kind[g] != 0)
+      return fail(CS_EUNSUPPORTED, "cs_net_create: only synchronous generators (kind 0)");
+    if (d->pmin[g] > d->pmax[g] || d->qmin[g] > d->qmax[g])
+      return fail(CS_EINVAL, "cs_net_create: generator " + std::to_string(g) + " has min > max");
+    const double* p = d->dyn + (size_t)g * CS_N_DYN;
+    // H, Td0', Tq0', TA, R, Tg, Tt appear as divisors
+    if (!(p[0] > 0) || !(p[6] > 0) || !(p[7] > 0) || !(p[10] > 0) || !(p[11] > 0) ||
+        !(p[12] > 0) || !(p[13] > 0))
+      return fail(CS_EINVAL, "cs_net_create: generator " + std::to_string(g) +
+                                 " needs positive H, Td0', Tq0', TA, R, Tg, Tt");
+  }
+  for (int k = 0; k < nd; ++k)
+    if (d->load_bus[k] < 0 || d->load_bus[k] >= nb)
+      return fail(CS_EINVAL, "cs_net_create: load " + std::to_string(k) + " bus out of range");
+
+  {
+    const size_t nk = 4 * (size_t)nb + 2 * (size_t)ng;
+    const size_t lim = ctx->lds_max;
+    if (lu_lds_bytes((int)nk) > lim || opf_eval_lds(nb, nl, ng) > lim ||
+        form_state_lds(ng) > lim || 8 * (size_t)(2 * nl + 2 * nb + 4 * ng) > lim)
+      return fail(CS_EUNSUPPORTED, "cs_net_create: network too large for the on-chip working set (KKT order " +
+                                       std::to_string(nk) + ", " + std::to_string(lim) +
+                                       " bytes of LDS per workgroup)");
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  cs_net* n = new cs_net();
+  n->ctx = ctx;
+  n->nb = nb; n->nl = nl; n->ng = ng; n->nd = nd;
+  // branch admittances (pi model, tap and shift on the from side)
+  std::vector<double> yffr(nl), yffi(nl), yftr(nl), yfti(nl), ytfr(nl), ytfi(nl), yttr(nl), ytti(nl);
+  for (int l = 0; l < nl; ++l) {
+    const double r = d->br_r[l], x = d->br_x[l], b = d->br_b[l];
+    const double den = r * r + x * x;
+    const double ys_r = r / den, ys_i = -x / den;
+    double tap = d->br_tap ? d->br_tap[l] : 1.0;
+    if (tap == 0.0) tap = 1.0;
+    const double sh = d->br_shift ? d->br_shift[l] : 0.0;
+    const double cr = tap * std::cos(sh), ci = tap * std::sin(sh);  // t e^{j phi}
+    yttr[l] = ys_r;
+    ytti[l] = ys_i + 0.5 * b;
+    yffr[l] = yttr[l] / (tap * tap);
+    yffi[l] = ytti[l] / (tap * tap);
+    // Yft = -ys / conj(t e^{j phi}),  Ytf = -ys / (t e^{j phi})
+    const double t2 = cr * cr + ci * ci;
+    // -ys / (cr - j ci) = -ys (cr + j ci) / t2
+    yftr[l] = -(ys_r * cr - ys_i * ci) / t2;
+    yfti[l] = -(ys_r * ci + ys_i * cr) / t2;
+    // -ys / (cr + j ci) = -ys (cr - j ci) / t2
+    ytfr[l] = -(ys_r * cr + ys_i * ci) / t2;
+    ytfi[l] = -(ys_i * cr - ys_r * ci) / t2;
+  }
+  // CSR incidence, ascending ids within each bus
+  auto csr = [&](int nitems, auto bus_of, std::vector<int>& ptr, std::vector<int>& idx) {
+    ptr.assign(nb + 1, 0);
+    for (int i = 0; i < nitems; ++i) bus_of(i, [&](int b) { ptr[b + 1]++; });
+    for (int b = 0; b < nb; ++b) ptr[b + 1] += ptr[b];
+    idx.assign(ptr[nb], 0);
+    std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+    for (int i = 0; i < nitems; ++i) bus_of(i, [&](int b) { idx[fill[b]++] = i; });
+  };
+  std::vector<int> bbp, bbi, bgp, bgi, blp, bli;
+  csr(nl, [&](int l, auto add) { add(d->br_from[l]); add(d->br_to[l]); }, bbp, bbi);
+  csr(ng, [&](int g, auto add) { add(d->gen_bus[g]); }, bgp, bgi);
+  csr(nd, [&](int k, auto add) { add(d->load_bus[k]); }, blp, bli);
+  std::vector<double> rate(d->br_rate, d->br_rate + nl);
+  int rc = CS_OK;
+  DevNet& D = n->d;
+  D.nb = nb; D.nl = nl; D.ng = ng; D.nd = nd; D.ref_bus = d->ref_bus;
+  D.base_mva = d->base_mva;
+  D.ws = 2.0 * M_PI * d->f_hz;
+#define UP(ptr, cnt, dst) if (rc == CS_OK) rc = upload(n, ptr, cnt, &dst)
+  UP(d->br_from, nl, D.br_f); UP(d->br_to, nl, D.br_t);
+  UP(yffr.data(), nl, D.yff_re); UP(yffi.data(), nl, D.yff_im);
+  UP(yftr.data(), nl, D.yft_re); UP(yfti.data(), nl, D.yft_im);
+  UP(ytfr.data(), nl, D.ytf_re); UP(ytfi.data(), nl, D.ytf_im);
+  UP(yttr.data(), nl, D.ytt_re); UP(ytti.data(), nl, D.ytt_im);
+  UP(rate.data(), nl, D.rate);
+  UP(d->vmin, nb, D.vmin); UP(d->vmax, nb, D.vmax); UP(d->gs, nb, D.gs); UP(d->bs, nb, D.bs);
+  UP(bbp.data(), nb + 1, D.bus_br_ptr); UP(bbi.data(), bbi.size(), D.bus_br);
+  UP(bgp.data(), nb + 1, D.bus_gen_ptr); UP(bgi.data(), bgi.size(), D.bus_gen);
+  UP(blp.data(), nb + 1, D.bus_load_ptr); UP(bli.data(), bli.size(), D.bus_load);
+  UP(d->gen_bus, ng, D.gen_bus);
+  UP(d->pmin, ng, D.pmin); UP(d->pmax, ng, D.pmax); UP(d->qmin, ng, D.qmin); UP(d->qmax, ng, D.qmax);
+  UP(d->c2, ng, D.c2); UP(d->c1, ng, D.c1); UP(d->c0, ng, D.c0);
+  UP(d->dyn, (size_t)ng * CS_N_DYN, D.dyn);
+  UP(d->load_bus, nd, D.load_bus); UP(d->pd, nd, D.pd); UP(d->qd, nd, D.qd);
+#undef UP
+  if (rc != CS_OK) {
+    cs_net_destroy(n);
+    return rc;
+  }
+  *out = n;
+  return CS_OK;
+}
+
+// ---------------------------------------------------------------- workspace
+static size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Plan {
+  Slots s{};
+  size_t per_slot = 0;
+};
+
+static Plan plan_sizes(const cs_net* n) {
+  Plan p;
+  Slots& s = p.s;
+  const int nb = n->nb, nl = n->nl, ng = n->ng;
+  s.nx = 2 * nb + 2 * ng;
+  s.neq = 2 * nb;
+  s.nk = s.nx + s.neq;
+  s.ldk = (int)round_up(s.nk, 2);
+  s.ni = 2 * nl + 2 * nb + 4 * ng;
+  s.ny = 2 * ng + 2 * nb;
+  s.ldy = (int)round_up(s.ny, 2);
+  s.nyc = s.ny + 3 * ng;
+  s.na = 7 * ng - 1;
+  s.lda_a = (int)round_up(std::max(s.na, 1), 2);
+  s.k_stride = round_up(std::max((size_t)(s.nk + 1) * s.ldk, (size_t)s.nyc * s.ldy), 64);
+  s.a_stride = round_up((size_t)s.lda_a * s.na, 64);
+  const size_t piv = std::max(s.nk, s.ny);
+  p.per_slot = 8 * (s.k_stride + s.a_stride + s.nx + s.neq + 3 * (size_t)s.ni + 8 * (size_t)nl +
+                    2 * (size_t)nb +
+                    2 * (size_t)s.na) +
+               4 * ((size_t)nb + piv) + nb + nl + ng + sizeof(SlotState) + 16 * 64;
+  return p;
+}
+
+// carve the slot arrays out of one allocation
+static int bind_workspace(cs_ctx* c, const cs_net* n, Plan& p, int B) {
+  Slots& s = p.s;
+  const size_t nb = n->nb, nl = n->nl, ng = n->ng;
+  const size_t piv = std::max(s.nk, s.ny);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = round_up(off, 256);
+    off = o + bytes;
+    return o;
+  };
+  const size_t oK = take(8 * s.k_stride * B);
+  const size_t oA = take(8 * s.a_stride * B);
+  const size_t ox = take(8 * (size_t)s.nx * B);
+  const size_t ol = take(8 * (size_t)s.neq * B);
+  const size_t oz = take(8 * (size_t)s.ni * B);
+  const size_t om = take(8 * (size_t)s.ni * B);
+  const size_t oh = take(8 * (size_t)s.ni * B);
+  const size_t ojh = take(8 * 8 * nl * B + 64);
+  const size_t opd = take(8 * nb * B);
+  const size_t oqd = take(8 * nb * B);
+  const size_t owr = take(8 * (size_t)s.na * B);
+  const size_t owi = take(8 * (size_t)s.na * B);
+  const size_t olab = take(4 * nb * B);
+  const size_t opiv = take(4 * piv * B);
+  const size_t obus = take(nb * B);
+  const size_t obr = take(nl * B + 64);
+  const size_t ogen = take(ng * B + 64);
+  const size_t ost = take(sizeof(SlotState) * (size_t)B);
+  const size_t need = off;
+  if (need > c->ws_bytes) {
+    if (c->ws) hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    if (hipMalloc(&c->ws, need) != hipSuccess) return fail(CS_ENOMEM, "workspace allocation failed");
+    c->ws_bytes = need;
+  }
+  char* base = static_cast<char*>(c->ws);
+  s.B = B;
+  s.K = reinterpret_cast<double*>(base + oK);
+  s.A = reinterpret_cast<double*>(base + oA);
+  s.x = reinterpret_cast<double*>(base + ox);
+  s.lam = reinterpret_cast<double*>(base + ol);
+  s.z = reinterpret_cast<double*>(base + oz);
+  s.mu = reinterpret_cast<double*>(base + om);
+  s.hv = reinterpret_cast<double*>(base + oh);
+  s.jh = reinterpret_cast<double*>(base + ojh);
+  s.pd = reinterpret_cast<double*>(base + opd);
+  s.qd = reinterpret_cast<double*>(base + oqd);
+  s.wr = reinterpret_cast<double*>(base + owr);
+  s.wi = reinterpret_cast<double*>(base + owi);
+  s.label = reinterpret_cast<int*>(base + olab);
+  s.piv = reinterpret_cast<int*>(base + opiv);
+  s.bus_on = reinterpret_cast<uint8_t*>(base + obus);
+  s.br_on = reinterpret_cast<uint8_t*>(base + obr);
+  s.gen_on = reinterpret_cast<uint8_t*>(base + ogen);
+  s.st = reinterpret_cast<SlotState*>(base + ost);
+  return CS_OK;
+}
+
+
+// ------------------------------------------------------------------ screen
+static int run_screen(cs_ctx* c, cs_net* n, const int* d_out_list, long long N,
+                      const double* d_lambda, const cs_opts* o, cs_result* d_res,
+                      double* d_risk, hipStream_t st, Plan* keep) {
+  cs_opts opts;
+  cs_opts_default(&opts);
+  if (o) opts = *o;
+  if (opts.prec != CS_PREC_FP64) return fail(CS_EUNSUPPORTED, "cs_screen: only CS_PREC_FP64");
+  if (opts.max_it < 1 || opts.max_it > 10000) return fail(CS_EINVAL, "cs_screen: max_it out of range");
+  if (!(opts.tol > 0)) return fail(CS_EINVAL, "cs_screen: tol must be > 0");
+  HIPCHK(hipSetDevice(c->device));
+  Plan p = plan_sizes(n);
+  const size_t budget = opts.hbm_budget ? opts.hbm_budget : c->hbm_budget;
+  if (p.per_slot > budget)
+    return fail(CS_EHBM, "cs_screen: one scenario needs " + std::to_string(p.per_slot) +
+                             " bytes, over the budget of " + std::to_string(budget));
+  long long B = (long long)(budget / p.per_slot);
+  if (opts.batch > 0) B = std::min<long long>(B, opts.batch);
+  B = std::max<long long>(1, std::min<long long>(B, std::max<long long>(N, 1)));
+  B = std::min<long long>(B, 1 << 20);
+  int rc = bind_workspace(c, n, p, (int)B);
+  if (rc != CS_OK) return rc;
+  const Slots& s = p.s;
+  const DevNet& D = n->d;
+  const bool tm = opts.timing != 0;
+  const int pstride = std::max(s.nk, s.ny);
+#define TIMED(kind, units, launch)                     \
+  do {                                                 \
+    Timer t_(c, tm, st, kind);                         \
+    launch;                                            \
+    int r_ = t_.done(units);                           \
+    if (r_ != CS_OK) return r_;                        \
+  } while (0)
+  for (long long b0 = 0; b0 < N; b0 += B) {
+    const int cnt = (int)std::min<long long>(B, N - b0);
+    TIMED(CS_K_TOPOLOGY, cnt, (launch_islands(D, s, d_out_list, b0, cnt, st),
+                               launch_setup_k(D, s, cnt, d_out_list, b0, st)));
+    for (int it = 0; it <= opts.max_it; ++it) {
+      TIMED(CS_K_KKT_ASSEMBLE, cnt, launch_opf_eval(D, s, cnt, opts.tol, opts.max_it, st));
+      int nfac = 0;
+      if (tm) {
+        nfac = count_jobs(s, cnt, c->d_counter, c->h_counter, st);
+        if (nfac < 0) return fail(CS_EDEVICE, "cs_screen: device error in the OPF loop");
+        c->stats.kkt_order = s.nk;
+      }
+      TIMED(CS_K_KKT_LU, nfac, launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv,
+                                              pstride, s.st, cnt, nullptr, st));
+      TIMED(CS_K_IPM_UPDATE, nfac, launch_opf_update(D, s, cnt, 1e10, st));
+      const int act = count_active(s, cnt, PH_IPM, c->d_counter, c->h_counter, st);
+      if (act < 0) return fail(CS_EDEVICE, "cs_screen: device error in the OPF loop");
+      if (act == 0) break;
+    }
+    int ndyn = 0;
+    if (tm) {
+      ndyn = count_active(s, cnt, PH_DYN, c->d_counter, c->h_counter, st);
+      c->stats.dyn_order = s.ny;
+    }
+    TIMED(CS_K_DYN_ASSEMBLE, ndyn, launch_dyn_assemble(D, s, cnt, st));
+    TIMED(CS_K_DYN_LU, ndyn, launch_lu_solve(s.K, s.k_stride, s.ny, s.nyc, s.ldy, s.piv, pstride,
+                                            s.st, cnt, nullptr, st));
+    TIMED(CS_K_STATE_MATRIX, ndyn, launch_form_state(D, s, cnt, st));
+    TIMED(CS_K_EIG, ndyn, launch_eig(s.A, s.a_stride, s.lda_a, nullptr, 0, s.wr, s.wi, s.na,
+                                     s.st, cnt, nullptr, st));
+    TIMED(CS_K_CLASSIFY, cnt, launch_classify(s, cnt, opts.near_eps, opts.max_it, d_res, st));
+    HIPCHK(hipGetLastError());
+  }
+  if (d_risk) {
+    const int n_comp = n->nl + n->ng + n->nd;
+    TIMED(CS_K_RISK, n_comp,
+          launch_risk(d_out_list, N, reinterpret_cast<const uint8_t*>(d_res),
+                      (int)sizeof(cs_result), d_lambda, n_comp, d_risk, st));
+  }
+#undef TIMED
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  if (keep) *keep = p;
+  return CS_OK;
+}
+
+static int validate_host(const cs_net* n, const int32_t* outages, int64_t N, const double* lam) {
+  const int n_comp = n->nl + n->ng + n->nd;
+  for (int64_t i = 0; i < N; ++i) {
+    const int a = outages[2 * i], b = outages[2 * i + 1];
+    if (a < 0 || a >= n_comp)
+      return fail(CS_EINVAL, "outage row " + std::to_string(i) + ": component id out of range");
+    if (b != -1 && (b < 0 || b >= n_comp || b == a))
+      return fail(CS_EINVAL, "outage row " + std::to_string(i) +
+                                 ": second id must be -1 or a distinct valid id");
+  }
+  if (lam)
+    for (int i = 0; i < n_comp; ++i)
+      if (!(lam[i] >= 0) || !std::isfinite(lam[i]))
+        return fail(CS_EINVAL, "failure rate " + std::to_string(i) + " must be finite and >= 0");
+  return CS_OK;
+}
+
+extern "C" int cs_screen(cs_ctx* c, cs_net* n, const int32_t* outages, int64_t N,
+                         const double* lambda, const cs_opts* opts, cs_result* out,
+                         double* risk) {
+  if (!c || !n || (N > 0 && (!outages || !out)) || N < 0)
+    return fail(CS_EINVAL, "cs_screen: NULL argument or negative n");
+  if (risk && !lambda) return fail(CS_EINVAL, "cs_screen: risk requested without lambda");
+  int rc = validate_host(n, outages, N, lambda);
+  if (rc != CS_OK) return rc;
+  const int n_comp = n->nl + n->ng + n->nd;
+  if (N == 0) {
+    if (risk)
+      for (int i = 0; i < n_comp; ++i) risk[i] = 0.0;
+    return CS_OK;
+  }
+  HIPCHK(hipSetDevice(c->device));
+  int* d_list = nullptr;
+  double* d_lam = nullptr;
+  cs_result* d_res = nullptr;
+  double* d_risk = nullptr;
+  auto cleanup = [&]() {
+    if (d_list) hipFree(d_list);
+    if (d_lam) hipFree(d_lam);
+    if (d_res) hipFree(d_res);
+    if (d_risk) hipFree(d_risk);
+  };
+  if (hipMalloc(&d_list, sizeof(int) * 2 * N) != hipSuccess ||
+      hipMalloc(&d_res, sizeof(cs_result) * N) != hipSuccess ||
+      (risk && (hipMalloc(&d_lam, sizeof(double) * n_comp) != hipSuccess ||
+                hipMalloc(&d_risk, sizeof(double) * n_comp) != hipSuccess))) {
+    cleanup();
+    return fail(CS_ENOMEM, "cs_screen: device allocation failed");
+  }
+  if (hipMemcpy(d_list, outages, sizeof(int) * 2 * N, hipMemcpyHostToDevice) != hipSuccess ||
+      (risk && hipMemcpy(d_lam, lambda, sizeof(double) * n_comp, hipMemcpyHostToDevice) != hipSuccess)) {
+    cleanup();
+    return fail(CS_EDEVICE, "cs_screen: copy to device failed");
+  }
+  rc = run_screen(c, n, d_list, N, d_lam, opts, d_res, d_risk, c->stream, nullptr);
+  if (rc == CS_OK) {
+    if (hipMemcpy(out, d_res, sizeof(cs_result) * N, hipMemcpyDeviceToHost) != hipSuccess ||
+        (risk && hipMemcpy(risk, d_risk, sizeof(double) * n_comp, hipMemcpyDeviceToHost) != hipSuccess))
+      rc = fail(CS_EDEVICE, "cs_screen: copy to host failed");
+  }
+  cleanup();
+  return rc;
+}
+
+extern "C" int cs_screen_device(cs_ctx* c, cs_net* n, const int32_t* d_outages, int64_t N,
+                                const double* d_lambda, const cs_opts* opts, cs_result* d_out,
+                                double* d_risk, void* stream) {
+  if (!c || !n || N < 0 || (N > 0 && (!d_outages || !d_out)))
+    return fail(CS_EINVAL, "cs_screen_device: NULL argument or negative n");
+  if (d_risk && !d_lambda) return fail(CS_EINVAL, "cs_screen_device: risk requested without lambda");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  const int n_comp = n->nl + n->ng + n->nd;
+  // validate the list and the rates on the device
+  HIPCHK(hipMemsetAsync(c->d_counter, 0, sizeof(int), st));
+  launch_validate(d_outages, N, n_comp, c->d_counter, st);
+  HIPCHK(hipMemcpyAsync(c->h_counter, c->d_counter, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (*c->h_counter) return fail(CS_EINVAL, "cs_screen_device: invalid outage row in the list");
+  if (d_lambda) {
+    std::vector<double> lam(n_comp);
+    HIPCHK(hipMemcpy(lam.data(), d_lambda, sizeof(double) * n_comp, hipMemcpyDeviceToHost));
+    for (int i = 0; i < n_comp; ++i)
+      if (!(lam[i] >= 0) || !std::isfinite(lam[i]))
+        return fail(CS_EINVAL, "failure rate " + std::to_string(i) + " must be finite and >= 0");
+  }
+  if (N == 0) {
+    if (d_risk) HIPCHK(hipMemsetAsync(d_risk, 0, sizeof(double) * n_comp, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return CS_OK;
+  }
+  return run_screen(c, n, d_outages, N, d_lambda, opts, d_out, d_risk, st, nullptr);
+}
+
+extern "C" int cs_detail(cs_ctx* c, cs_net* n, const int32_t outage[2], const cs_opts* opts,
+                         cs_result* rec, double* vm, double* va, double* pg, double* qg,
+                         double* eig_re, double* eig_im, int32_t* n_eig, int32_t* label) {
+  if (!c || !n || !outage || !rec) return fail(CS_EINVAL, "cs_detail: NULL argument");
+  int rc = validate_host(n, outage, 1, nullptr);
+  if (rc != CS_OK) return rc;
+  HIPCHK(hipSetDevice(c->device));
+  int* d_list = nullptr;
+  cs_result* d_res = nullptr;
+  if (hipMalloc(&d_list, sizeof(int) * 2) != hipSuccess ||
+      hipMalloc(&d_res, sizeof(cs_result)) != hipSuccess) {
+    if (d_list) hipFree(d_list);
+    return fail(CS_ENOMEM, "cs_detail: allocation failed");
+  }
+  cs_opts o;
+  cs_opts_default(&o);
+  if (opts) o = *opts;
+  o.batch = 1;
+  Plan p;
+  hipMemcpy(d_list, outage, sizeof(int) * 2, hipMemcpyHostToDevice);
+  rc = run_screen(c, n, d_list, 1, nullptr, &o, d_res, nullptr, c->stream, &p);
+  if (rc == CS_OK) {
+    const Slots& s = p.s;
+    const int nb = n->nb, ng = n->ng;
+    std::vector<double> x(s.nx), wr(std::max(s.na, 1)), wi(std::max(s.na, 1));
+    std::vector<uint8_t> bus_on(nb), gen_on(ng);
+    std::vector<int> lab(nb);
+    SlotState S;
+    bool ok = hipMemcpy(rec, d_res, sizeof(cs_result), hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(x.data(), s.x, sizeof(double) * s.nx, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(wr.data(), s.wr, sizeof(double) * s.na, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(wi.data(), s.wi, sizeof(double) * s.na, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(bus_on.data(), s.bus_on, nb, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(gen_on.data(), s.gen_on, ng, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(lab.data(), s.label, sizeof(int) * nb, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(&S, s.st, sizeof(SlotState), hipMemcpyDeviceToHost) == hipSuccess;
+    if (!ok) {
+      rc = fail(CS_EDEVICE, "cs_detail: copy to host failed");
+    } else {
+      const double nan = std::nan("");
+      const bool solved = rec->opf_status != CS_OPF_NOT_RUN;
+      for (int b = 0; b < nb; ++b) {
+        const bool on = solved && bus_on[b];
+        if (va) va[b] = on ? x[b] : nan;
+        if (vm) vm[b] = on ? x[nb + b] : nan;
+        if (label) label[b] = lab[b];
+      }
+      for (int g = 0; g < ng; ++g) {
+        const bool on = solved && gen_on[g];
+        if (pg) pg[g] = on ? x[2 * nb + g] : nan;
+        if (qg) qg[g] = on ? x[2 * nb + ng + g] : nan;
+      }
+      const int ne = (rec->opf_status == CS_OPF_CONVERGED && S.qr_fail == 0) ? rec->n_states : 0;
+      if (n_eig) *n_eig = ne;
+      for (int i = 0; i < ne; ++i) {
+        if (eig_re) eig_re[i] = wr[i];
+        if (eig_im) eig_im[i] = wi[i];
+      }
+    }
+  }
+  hipFree(d_list);
+  hipFree(d_res);
+  return rc;
+}
+
+extern "C" int cs_dense_solve_batched(const cs_ctx* c, double* d_A, int32_t n, int32_t nrhs,
+                                      int32_t lda, int32_t batch, int32_t* d_info, void* stream) {
+  if (!c || !d_A || n <= 0 || nrhs < 0 || lda < n || batch < 0)
+    return fail(CS_EINVAL, "cs_dense_solve_batched: bad arguments");
+  if (lu_lds_bytes(n) > c->lds_max)
+    return fail(CS_EUNSUPPORTED, "cs_dense_solve_batched: n = " + std::to_string(n) +
+                                     " needs more LDS than the device allows (" +
+                                     std::to_string(c->lds_max) + " bytes)");
+  if (batch == 0) return CS_OK;
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  int* piv = nullptr;
+  HIPCHK(hipMalloc(&piv, sizeof(int) * (size_t)n * batch));
+  launch_lu_solve(d_A, (size_t)lda * (n + nrhs), n, n + nrhs, lda, piv, n, nullptr, batch,
+                  d_info, st);
+  hipError_t e = hipGetLastError();
+  hipError_t e2 = hipStreamSynchronize(st);
+  hipFree(piv);
+  if (e != hipSuccess || e2 != hipSuccess)
+    return fail(CS_EDEVICE, std::string("cs_dense_solve_batched: ") +
+                                hipGetErrorString(e != hipSuccess ? e : e2));
+  return CS_OK;
+}
+
+extern "C" int cs_eigvals_batched(const cs_ctx* c, double* d_A, int32_t n, int32_t lda,
+                                  int32_t batch, double* d_wr, double* d_wi, int32_t* d_info,
+                                  void* stream) {
+  if (!c || !d_A || !d_wr || !d_wi || n <= 0 || lda < n || batch < 0)
+    return fail(CS_EINVAL, "cs_eigvals_batched: bad arguments");
+  if (n > 1024) return fail(CS_EUNSUPPORTED, "cs_eigvals_batched: n > 1024");
+  if (batch == 0) return CS_OK;
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  launch_eig(d_A, (size_t)lda * n, lda, nullptr, n, d_wr, d_wi, n, nullptr, batch, d_info, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return CS_OK;
+}
+
+extern "C" int cs_kkt_at(cs_ctx* c, cs_net* n, const int32_t outage[2], int32_t iters,
+                         double* K, double* x, double* lam, double* z, double* mu,
+                         double* metrics, int32_t* status, int32_t* order) {
+  if (!c || !n || !outage || iters < 0 || iters > 10000)
+    return fail(CS_EINVAL, "cs_kkt_at: bad arguments");
+  int rc = validate_host(n, outage, 1, nullptr);
+  if (rc != CS_OK) return rc;
+  HIPCHK(hipSetDevice(c->device));
+  Plan p = plan_sizes(n);
+  rc = bind_workspace(c, n, p, 1);
+  if (rc != CS_OK) return rc;
+  const Slots& s = p.s;
+  const DevNet& D = n->d;
+  hipStream_t st = c->stream;
+  int* d_list = nullptr;
+  HIPCHK(hipMalloc(&d_list, sizeof(int) * 2));
+  hipMemcpy(d_list, outage, sizeof(int) * 2, hipMemcpyHostToDevice);
+  const int big = iters + 100000;
+  const double tol = 1e-8;
+  launch_islands(D, s, d_list, 0, 1, st);
+  launch_setup_k(D, s, 1, d_list, 0, st);
+  for (int it = 0; it < iters; ++it) {
+    launch_opf_eval(D, s, 1, tol, big, st);
+    launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv, std::max(s.nk, s.ny), s.st, 1,
+                    nullptr, st);
+    launch_opf_update(D, s, 1, 1e10, st);
+  }
+  launch_opf_eval(D, s, 1, tol, big, st);
+  hipError_t e = hipStreamSynchronize(st);
+  hipFree(d_list);
+  if (e != hipSuccess) return fail(CS_EDEVICE, std::string("cs_kkt_at: ") + hipGetErrorString(e));
+  SlotState S;
+  HIPCHK(hipMemcpy(&S, s.st, sizeof(SlotState), hipMemcpyDeviceToHost));
+  const int nk = s.nk;
+  if (K) {
+    std::vector<double> buf((size_t)(nk + 1) * s.ldk);
+    HIPCHK(hipMemcpy(buf.data(), s.K, sizeof(double) * buf.size(), hipMemcpyDeviceToHost));
+    for (int col = 0; col <= nk; ++col)
+      for (int r = 0; r < nk; ++r) K[(size_t)col * nk + r] = buf[(size_t)col * s.ldk + r];
+  }
+  if (x) HIPCHK(hipMemcpy(x, s.x, sizeof(double) * s.nx, hipMemcpyDeviceToHost));
+  if (lam) HIPCHK(hipMemcpy(lam, s.lam, sizeof(double) * s.neq, hipMemcpyDeviceToHost));
+  if (z) HIPCHK(hipMemcpy(z, s.z, sizeof(double) * s.ni, hipMemcpyDeviceToHost));
+  if (mu) HIPCHK(hipMemcpy(mu, s.mu, sizeof(double) * s.ni, hipMemcpyDeviceToHost));
+  if (metrics) {
+    for (int k = 0; k < 4; ++k) metrics[k] = S.metrics[k];
+    metrics[4] = S.gamma;
+    metrics[5] = S.singular;
+    metrics[6] = S.f;
+    metrics[7] = S.iters;
+  }
+  if (status) *status = (S.phase == PH_IPM) ? CS_OPF_MAXIT : S.status;
+  if (order) *order = nk;
+  return CS_OK;
+}

@@ -1,0 +1,117 @@
+// Internal layouts shared by the HIP kernels and the host runtime.
+//
+// Device network: structure of arrays, resident for the lifetime of a cs_net.
+// Scenario slots: every per-scenario quantity is an array indexed
+// [slot * stride + i], so one workgroup per slot reads contiguous data.
+//
+// KKT layout (fixed positions, independent of the outage):
+//   x   = [theta (nb), V (nb), Pg (ng), Qg (ng)]            nx  = 2nb + 2ng
+//   lam = [P balance (nb), Q balance (nb)]                 neq = 2nb
+//   K is nk x nk, nk = nx + neq, stored column-major with one extra column
+//   holding the right-hand side and then the solution.  Variables and
+//   equations that the outage removes (buses outside the main island, the
+//   island's reference angle, generators out of service) become identity
+//   rows/columns with a zero right-hand side, so their Newton step is zero.
+// Inequalities (fixed positions): [|Sf|^2 (nl), |St|^2 (nl), Vmin (nb),
+//   Vmax (nb), Pmin (ng), Pmax (ng), Qmin (ng), Qmax (ng)]; masked entries
+//   have z = 1, mu = 0 and take no part in any sum.
+// Dynamic algebraic system (same buffer as K after the OPF):
+//   y = [Id (ng), Iq (ng), theta (nb), V (nb)], ny = 2ng + 2nb, followed by
+//   3ng right-hand-side columns: d g / d(delta_j, Eq'_j, Ed'_j).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cs {
+
+constexpr int kDyn = 14;     // H D Xd Xq Xdp Xqp Td0p Tq0p Rs KA TA R Tg Tt
+constexpr int kNsSg = 7;     // delta omega Eq' Ed' Efd Psv Pm
+
+enum Phase : int { PH_EMPTY = 0, PH_IPM = 1, PH_DYN = 2, PH_EIG = 3, PH_DONE = 4 };
+enum OpfStatus : int { OPF_CONVERGED = 0, OPF_MAXIT = 1, OPF_NUMERICAL = 2, OPF_NOT_RUN = 3 };
+enum Cause : int { C_ISLAND = 1, C_OPF = 2, C_LIMIT = 4, C_SSS = 8, C_NUMERICAL = 16 };
+enum Near : int { N_SSS = 1, N_OPF = 2, N_LIMIT = 4 };
+
+struct DevNet {
+  int nb, nl, ng, nd, ref_bus;
+  double base_mva, ws;
+  const int* br_f;
+  const int* br_t;
+  const double* yff_re; const double* yff_im;
+  const double* yft_re; const double* yft_im;
+  const double* ytf_re; const double* ytf_im;
+  const double* ytt_re; const double* ytt_im;
+  const double* rate;
+  const double* vmin; const double* vmax; const double* gs; const double* bs;
+  const int* bus_br_ptr; const int* bus_br;        // incident branches, ascending id
+  const int* bus_gen_ptr; const int* bus_gen;      // generators at each bus
+  const int* bus_load_ptr; const int* bus_load;    // loads at each bus
+  const int* gen_bus;
+  const double* pmin; const double* pmax; const double* qmin; const double* qmax;
+  const double* c2; const double* c1; const double* c0;
+  const double* dyn;                               // [ng][kDyn]
+  const int* load_bus; const double* pd; const double* qd;
+};
+
+struct SlotState {
+  int scen;        // scenario index within the call (-1 = empty)
+  int phase;       // Phase
+  int status;      // OpfStatus
+  int iters;       // Newton steps taken
+  int n_islands, main_label, ref_bus, n_ineq;
+  int job;         // 1 = factorise and solve this round
+  int singular;    // exactly zero pivot met in the last factorisation
+  int n_states;    // order of the reduced state matrix
+  int cause, near, qr_fail;
+  double gamma, f, f_prev, max_viol, alpha, zeta;
+  double metrics[4];
+};
+
+struct Slots {
+  int B;                        // slots
+  int nx, neq, nk, ldk, ni;     // KKT sizes
+  int ny, ldy, nyc;             // dynamic algebraic system: ny, lda, columns
+  int na, lda_a;                // state matrix max order and lda
+  size_t k_stride;              // doubles per slot in K
+  size_t a_stride;              // doubles per slot in A
+  double* K;
+  int* piv;                     // [B][max(nk, ny)]
+  double* x; double* lam; double* z; double* mu;
+  double* hv;                   // [B][ni] inequality values at the last evaluation
+  double* jh;                   // [B][nl][8] flow-limit gradients, both ends
+
+  int* label;                   // [B][nb]
+  uint8_t* bus_on; uint8_t* br_on; uint8_t* gen_on;
+  double* pd; double* qd;       // per-bus load in service [B][nb]
+  double* A;                    // [B][a_stride]
+  double* wr; double* wi;       // [B][na]
+  SlotState* st;
+};
+
+// Launch wrappers (one per kernel file).
+void launch_islands(const DevNet& net, const Slots& s, const int* outages,
+                    long long scen0, int count, hipStream_t st);
+void launch_opf_eval(const DevNet& net, const Slots& s, int count, double tol,
+                     int max_it, hipStream_t st);
+void launch_opf_update(const DevNet& net, const Slots& s, int count,
+                       double gamma_max, hipStream_t st);
+void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
+                     int* piv, int piv_stride, SlotState* st, int count,
+                     int* info, hipStream_t stream);
+void launch_dyn_assemble(const DevNet& net, const Slots& s, int count, hipStream_t st);
+void launch_form_state(const DevNet& net, const Slots& s, int count, hipStream_t st);
+void launch_eig(double* A, size_t stride, int lda, const int* n_per, int n_uniform,
+                double* wr, double* wi, int w_stride, SlotState* st, int count,
+                int* info, hipStream_t stream);
+void launch_classify(const Slots& s, int count, double near_eps, int max_it,
+                     void* results, hipStream_t st);
+void launch_risk(const int* outages, long long n, const uint8_t* severe_src,
+                 int sev_stride, const double* lam, int n_comp, double* risk,
+                 hipStream_t st);
+void launch_validate(const int* outages, long long n, int n_comp, int* bad,
+                     hipStream_t st);
+int count_active(const Slots& s, int count, int phase, int* d_counter,
+                 int* h_counter, hipStream_t st);
+int count_jobs(const Slots& s, int count, int* d_counter, int* h_counter, hipStream_t st);
+
+}  // namespace cs

@@ -1,0 +1,270 @@
+// Batched nonsymmetric eigenvalues (one workgroup per matrix).
+//
+// The small-signal test needs every eigenvalue of the state matrix.  Each
+// matrix is reduced to upper Hessenberg form by Householder reflections
+// (left update: one wavefront per column, lanes over rows; right update: one
+// thread per row), then Francis implicit double-shift QR sweeps run on the
+// active window [lo, hi] until every 1x1 or 2x2 diagonal block has split off
+// (eigenvalues only, so updates stay inside the window).  Deflation: a
+// subdiagonal entry is negligible when |h(k,k-1)| <= eps (|h(k-1,k-1)| +
+// |h(k,k)|).  Every tenth sweep without deflation uses an exceptional shift.
+// The matrix lives in global memory (column-major, lda), and the reflector
+// vectors and reduction scratch live in LDS.
+#include "cs_internal.h"
+#include <float.h>
+
+namespace cs {
+
+constexpr int EIG_THREADS = 256;
+constexpr int EIG_NMAX = 1024;
+
+__device__ inline double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < EIG_THREADS / 64; ++w) s += red[w];
+  return s;
+}
+
+__device__ inline int block_max_int(int v, int* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  int s = red[0];
+  for (int w = 1; w < EIG_THREADS / 64; ++w) s = max(s, red[w]);
+  return s;
+}
+
+// eigenvalues of [[a, b], [c, d]]
+__device__ inline void eig2x2(double a, double b, double c, double d,
+                              double& r1, double& i1, double& r2, double& i2) {
+  const double p = 0.5 * (a - d);
+  const double bc = b * c;
+  const double disc = p * p + bc;
+  if (disc >= 0.0) {
+    const double s = sqrt(disc);
+    const double zz = p + copysign(s, p);
+    if (zz == 0.0) {
+      r1 = r2 = d;
+    } else {
+      r1 = d + zz;
+      r2 = d - bc / zz;
+    }
+    i1 = i2 = 0.0;
+  } else {
+    r1 = r2 = d + p;
+    i1 = sqrt(-disc);
+    i2 = -i1;
+  }
+}
+
+__device__ void hessenberg(double* __restrict__ H, int n, int lda, double* u,
+                           double* w, double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;              // reflector length (rows k+1..n-1)
+    double* colk = H + (size_t)k * lda + k + 1;
+    double part = 0.0;
+    for (int i = tid; i < m; i += EIG_THREADS) {
+      double v = colk[i];
+      u[i] = v;
+      part += v * v;
+    }
+    const double sig2 = block_sum(part, red);
+    const double x0 = u[0];
+    if (sig2 == 0.0) { __syncthreads(); continue; }
+    const double sig = sqrt(sig2);
+    const double alpha = -copysign(sig, x0);
+    const double tau = 1.0 / (sig * (sig + fabs(x0)));
+    __syncthreads();
+    if (tid == 0) u[0] = x0 - alpha;
+    for (int i = tid; i < m; i += EIG_THREADS) colk[i] = (i == 0) ? alpha : 0.0;
+    __syncthreads();
+    // left: columns k+1..n-1, rows k+1..n-1
+    for (int j = k + 1 + wave; j < n; j += EIG_THREADS / 64) {
+      double* cj = H + (size_t)j * lda + k + 1;
+      double s = 0.0;
+      for (int i = lane; i < m; i += 64) s += u[i] * cj[i];
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      s *= tau;
+      for (int i = lane; i < m; i += 64) cj[i] -= s * u[i];
+    }
+    __syncthreads();
+    // right: rows 0..n-1, columns k+1..n-1
+    for (int i = tid; i < n; i += EIG_THREADS) {
+      double s = 0.0;
+      for (int j = 0; j < m; ++j) s += H[(size_t)(k + 1 + j) * lda + i] * u[j];
+      w[i] = s * tau;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += EIG_THREADS) {
+      const double wi = w[i];
+      for (int j = 0; j < m; ++j) H[(size_t)(k + 1 + j) * lda + i] -= wi * u[j];
+    }
+    __syncthreads();
+  }
+}
+
+// apply the reflector I - 2 v v^T / (v^T v) of length 3 (or 2) from the left
+// to rows k..k+len-1 over columns [c0, c1], and from the right to columns
+// k..k+len-1 over rows [r0, r1].
+__device__ inline void reflect(double* __restrict__ H, int lda, int k, int len,
+                               const double v0, const double v1, const double v2,
+                               int c0, int c1, int r0, int r1) {
+  const int tid = threadIdx.x;
+  const double vv = v0 * v0 + v1 * v1 + v2 * v2;
+  const double t = 2.0 / vv;
+  for (int c = c0 + tid; c <= c1; c += EIG_THREADS) {
+    double* p = H + (size_t)c * lda + k;
+    double a0 = p[0], a1 = p[1], a2 = (len == 3) ? p[2] : 0.0;
+    double s = t * (v0 * a0 + v1 * a1 + v2 * a2);
+    p[0] = a0 - s * v0;
+    p[1] = a1 - s * v1;
+    if (len == 3) p[2] = a2 - s * v2;
+  }
+  __syncthreads();
+  for (int r = r0 + tid; r <= r1; r += EIG_THREADS) {
+    double* p = H + (size_t)k * lda + r;
+    double a0 = p[0], a1 = p[lda], a2 = (len == 3) ? p[2 * (size_t)lda] : 0.0;
+    double s = t * (a0 * v0 + a1 * v1 + a2 * v2);
+    p[0] = a0 - s * v0;
+    p[lda] = a1 - s * v1;
+    if (len == 3) p[2 * (size_t)lda] = a2 - s * v2;
+  }
+  __syncthreads();
+}
+
+__device__ inline void house3(double x, double y, double z, double& v0,
+                              double& v1, double& v2, bool& ok) {
+  const double nv = sqrt(x * x + y * y + z * z);
+  ok = nv != 0.0;
+  v0 = x + copysign(nv, x);
+  v1 = y;
+  v2 = z;
+}
+
+// Francis double-shift QR on Hessenberg H; returns 0 on success.
+__device__ int francis(double* __restrict__ H, int n, int lda,
+                       double* __restrict__ wr, double* __restrict__ wi,
+                       int* ired) {
+  const int tid = threadIdx.x;
+  const double eps = DBL_EPSILON;
+  int hi = n - 1;
+  int its = 0;
+  int total = 0;
+  const int max_total = 40 * n + 100;
+#define HH(i, j) H[(size_t)(j) * lda + (i)]
+  while (hi >= 0) {
+    if (hi == 0) {
+      if (tid == 0) { wr[0] = HH(0, 0); wi[0] = 0.0; }
+      hi = -1;
+      break;
+    }
+    // deflation point: largest k in [1, hi] with a negligible subdiagonal
+    int cand = 0;
+    for (int k = 1 + tid; k <= hi; k += EIG_THREADS) {
+      double s = fabs(HH(k - 1, k - 1)) + fabs(HH(k, k));
+      double sub = fabs(HH(k, k - 1));
+      if (sub <= eps * s || sub == 0.0) cand = max(cand, k);
+    }
+    const int lo = block_max_int(cand, ired);
+    if (lo > 0 && tid == 0) HH(lo, lo - 1) = 0.0;
+    __syncthreads();
+    if (lo == hi) {
+      if (tid == 0) { wr[hi] = HH(hi, hi); wi[hi] = 0.0; }
+      hi -= 1;
+      its = 0;
+      __syncthreads();
+      continue;
+    }
+    if (lo == hi - 1) {
+      if (tid == 0) {
+        double r1, i1, r2, i2;
+        eig2x2(HH(hi - 1, hi - 1), HH(hi - 1, hi), HH(hi, hi - 1), HH(hi, hi), r1, i1, r2, i2);
+        wr[hi - 1] = r1; wi[hi - 1] = i1;
+        wr[hi] = r2; wi[hi] = i2;
+      }
+      hi -= 2;
+      its = 0;
+      __syncthreads();
+      continue;
+    }
+    ++its;
+    ++total;
+    if (total > max_total) return 1;
+    double s_sum, s_prod;
+    if (its % 10 == 0) {
+      const double w = fabs(HH(hi, hi - 1)) + fabs(HH(hi - 1, hi - 2));
+      s_sum = 1.5 * w;
+      s_prod = w * w;
+    } else {
+      const double a = HH(hi - 1, hi - 1), b = HH(hi - 1, hi);
+      const double c = HH(hi, hi - 1), d = HH(hi, hi);
+      s_sum = a + d;
+      s_prod = a * d - b * c;
+    }
+    double x = HH(lo, lo) * HH(lo, lo) + HH(lo, lo + 1) * HH(lo + 1, lo) - s_sum * HH(lo, lo) + s_prod;
+    double y = HH(lo + 1, lo) * (HH(lo, lo) + HH(lo + 1, lo + 1) - s_sum);
+    double z = HH(lo + 1, lo) * HH(lo + 2, lo + 1);
+    for (int k = lo; k <= hi - 2; ++k) {
+      double v0, v1, v2;
+      bool ok;
+      house3(x, y, z, v0, v1, v2, ok);
+      if (ok) reflect(H, lda, k, 3, v0, v1, v2, max(lo, k - 1), hi, lo, min(k + 3, hi));
+      x = HH(k + 1, k);
+      y = HH(k + 2, k);
+      if (k < hi - 2) z = HH(k + 3, k);
+      __syncthreads();
+    }
+    {
+      const double nv = sqrt(x * x + y * y);
+      if (nv != 0.0) {
+        const double v0 = x + copysign(nv, x), v1 = y;
+        reflect(H, lda, hi - 1, 2, v0, v1, 0.0, hi - 2, hi, lo, hi);
+      }
+    }
+    __syncthreads();
+  }
+#undef HH
+  return 0;
+}
+
+__global__ __launch_bounds__(EIG_THREADS) void k_eig(
+    double* __restrict__ Abase, size_t stride, int lda,
+    const SlotState* __restrict__ st, int n_uniform, double* __restrict__ wrb,
+    double* __restrict__ wib, int w_stride, int* __restrict__ info) {
+  const int slot = blockIdx.x;
+  int n = n_uniform;
+  if (st != nullptr) {
+    if (st[slot].phase != PH_EIG) return;
+    n = st[slot].n_states;
+  }
+  if (n <= 0 || n > EIG_NMAX) return;
+  __shared__ double u[EIG_NMAX];
+  __shared__ double w[EIG_NMAX];
+  __shared__ double red[EIG_THREADS / 64];
+  __shared__ int ired[EIG_THREADS / 64];
+  double* H = Abase + (size_t)slot * stride;
+  double* wr = wrb + (size_t)slot * w_stride;
+  double* wi = wib + (size_t)slot * w_stride;
+  hessenberg(H, n, lda, u, w, red);
+  // zero below the subdiagonal (the reduction leaves exact zeros already)
+  const int fail = francis(H, n, lda, wr, wi, ired);
+  if (threadIdx.x == 0 && info != nullptr) info[slot] = fail;
+  if (threadIdx.x == 0 && st != nullptr) const_cast<SlotState*>(st)[slot].qr_fail = fail;
+}
+
+void launch_eig(double* A, size_t stride, int lda, const int* /*n_per*/,
+                int n_uniform, double* wr, double* wi, int w_stride,
+                SlotState* st, int count, int* info, hipStream_t stream) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_eig, dim3(count), dim3(EIG_THREADS), 0, stream, A,
+                     stride, lda, st, n_uniform, wr, wi, w_stride, info);
+}
+
+}  // namespace cs

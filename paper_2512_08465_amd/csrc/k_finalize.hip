@@ -1,0 +1,157 @@
+// Severity and risk (Section II.B and Section II.C, eq. (1)-(3)).
+//
+// k_classify turns each scenario's islanding, OPF and eigenvalue outcome into
+// the binary severity S_c and its cause bits: islands > 1; OPF not converged;
+// a converged point violating a limit by more than 1e-6 p.u.; an eigenvalue
+// with Re >= 0.  It also reports the largest real part and the minimum damping
+// ratio -Re/|lambda| over oscillatory modes (|Im| > 1e-8 |lambda|; 1 if none).
+//
+// k_risk computes R_i = sum over the list of F_c S_c for every scenario c in
+// which component i takes part, F_c = lambda_i (N-1) or lambda_i lambda_j
+// (N-2).  One wavefront per component; each lane sums its strided share in
+// list order and the lanes combine in a fixed butterfly, so R is identical run
+// to run.
+#include "cs_internal.h"
+#include "../../include/cs.h"
+
+namespace cs {
+
+__global__ __launch_bounds__(64) void k_classify(Slots s, int count, double near_eps,
+                                                 int max_it, cs_result* __restrict__ out) {
+  const int slot = blockIdx.x;
+  if (slot >= count) return;
+  SlotState& S = s.st[slot];
+  const int lane = threadIdx.x;
+  const int phase = S.phase;
+  const bool have_eig = (phase == PH_EIG) && (S.qr_fail == 0);
+  double alpha = -__builtin_inf(), zeta = __builtin_inf();
+  bool osc_any = false;
+  if (have_eig) {
+    const double* wr = s.wr + (size_t)slot * s.na;
+    const double* wi = s.wi + (size_t)slot * s.na;
+    for (int i = lane; i < S.n_states; i += 64) {
+      const double re = wr[i], im = wi[i];
+      alpha = fmax(alpha, re);
+      const double mag = sqrt(re * re + im * im);
+      if (fabs(im) > 1e-8 * mag) {
+        osc_any = true;
+        zeta = fmin(zeta, -re / mag);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      alpha = fmax(alpha, __shfl_xor(alpha, off, 64));
+      zeta = fmin(zeta, __shfl_xor(zeta, off, 64));
+    }
+    osc_any = __any(osc_any);
+  }
+  if (lane != 0) return;
+  int cause = S.cause;
+  int nearf = 0;
+  const int status = S.status;
+  if (status != OPF_CONVERGED) cause |= C_OPF;
+  if (status == OPF_NUMERICAL) cause |= C_NUMERICAL;
+  if (status != OPF_NOT_RUN && S.iters >= max_it - 2) nearf |= N_OPF;
+  double mv = __builtin_nan(""), ar = __builtin_nan(""), zr = __builtin_nan("");
+  if (status == OPF_CONVERGED) {
+    mv = S.max_viol;
+    if (mv > 1e-6) cause |= C_LIMIT;
+    if (mv > 1e-7) nearf |= N_LIMIT;      // within a decade of the limit test
+    if (phase == PH_EIG && S.qr_fail) cause |= C_NUMERICAL;
+    if (have_eig) {
+      ar = alpha;
+      zr = osc_any ? zeta : 1.0;
+      if (alpha >= 0.0) cause |= C_SSS;
+      if (fabs(alpha) <= near_eps) nearf |= N_SSS;
+    }
+  }
+  cs_result r;
+  r.severe = cause != 0;
+  r.cause = (uint8_t)cause;
+  r.opf_status = (uint8_t)status;
+  r.near = (uint8_t)nearf;
+  r.n_islands = (int16_t)S.n_islands;
+  r.opf_iters = (int16_t)(status == OPF_NOT_RUN ? 0 : S.iters);
+  r.n_states = (status == OPF_CONVERGED) ? S.n_states : 0;
+  r.reserved = 0;
+  r.opf_cost = (status == OPF_NOT_RUN) ? __builtin_nan("") : S.f;
+  r.max_real_eig = ar;
+  r.min_damping = zr;
+  r.max_violation = mv;
+  out[S.scen] = r;
+  S.phase = PH_DONE;
+}
+
+void launch_classify(const Slots& s, int count, double near_eps, int max_it,
+                     void* results, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_classify, dim3(count), dim3(64), 0, st, s, count, near_eps,
+                     max_it, reinterpret_cast<cs_result*>(results));
+}
+
+__global__ __launch_bounds__(256) void k_risk(const int* __restrict__ outages, long long n,
+                                              const uint8_t* __restrict__ sev, int sev_stride,
+                                              const double* __restrict__ lam, int n_comp,
+                                              double* __restrict__ risk) {
+  const int comp = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (comp >= n_comp) return;
+  double acc = 0.0;
+  for (long long c = lane; c < n; c += 64) {
+    const int a = outages[2 * c], b = outages[2 * c + 1];
+    if ((a == comp || b == comp) && sev[c * sev_stride]) {
+      acc += (b < 0) ? lam[a] : lam[a] * lam[b];
+    }
+  }
+  for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) risk[comp] = acc;
+}
+
+void launch_risk(const int* outages, long long n, const uint8_t* severe_src,
+                 int sev_stride, const double* lam, int n_comp, double* risk,
+                 hipStream_t st) {
+  if (n_comp <= 0) return;
+  hipLaunchKernelGGL(k_risk, dim3((n_comp + 3) / 4), dim3(256), 0, st, outages, n,
+                     severe_src, sev_stride, lam, n_comp, risk);
+}
+
+__global__ void k_count_phase(const SlotState* __restrict__ st, int count, int phase,
+                              int* __restrict__ out) {
+  __shared__ int acc;
+  if (threadIdx.x == 0) acc = 0;
+  __syncthreads();
+  int c = 0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) c += (st[i].phase == phase);
+  atomicAdd(&acc, c);
+  __syncthreads();
+  if (threadIdx.x == 0) *out = acc;
+}
+
+__global__ void k_count_jobs(const SlotState* __restrict__ st, int count, int* __restrict__ out) {
+  __shared__ int acc;
+  if (threadIdx.x == 0) acc = 0;
+  __syncthreads();
+  int c = 0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) c += (st[i].job != 0);
+  atomicAdd(&acc, c);
+  __syncthreads();
+  if (threadIdx.x == 0) *out = acc;
+}
+
+int count_jobs(const Slots& s, int count, int* d_counter, int* h_counter, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_jobs, dim3(1), dim3(1024), 0, st, s.st, count, d_counter);
+  if (hipMemcpyAsync(h_counter, d_counter, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return -1;
+  if (hipStreamSynchronize(st) != hipSuccess) return -1;
+  return *h_counter;
+}
+
+int count_active(const Slots& s, int count, int phase, int* d_counter,
+                 int* h_counter, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_phase, dim3(1), dim3(1024), 0, st, s.st, count, phase, d_counter);
+  if (hipMemcpyAsync(h_counter, d_counter, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return -1;
+  if (hipStreamSynchronize(st) != hipSuccess) return -1;
+  return *h_counter;
+}
+
+}  // namespace cs

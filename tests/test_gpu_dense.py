@@ -1,0 +1,151 @@
+"""GPU parity of the dense kernels through the C-ABI: batched LU with partial
+pivoting + solve against SciPy/NumPy, and batched eigenvalues against LAPACK
+(including state matrices built by the oracle)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from helpers import match_eigs, load_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2512_08465_amd as cs
+    return cs.Context(0)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _run_lu(ctx, mats, rhs):
+    """mats [B][n][n], rhs [B][n][k] -> (factors, solutions, info)."""
+    import torch
+    B, n, _ = mats.shape
+    k = rhs.shape[2]
+    lda = n + (n % 2)
+    buf = np.zeros((B, n + k, lda))
+    buf[:, :n, :n] = np.transpose(mats, (0, 2, 1))       # column-major
+    buf[:, n:, :n] = np.transpose(rhs, (0, 2, 1))
+    d = _dev(buf)
+    info = torch.zeros(B, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    ctx.dense_solve_batched(d.data_ptr(), n, k, lda, B, info.data_ptr())
+    out = d.cpu().numpy()
+    fac = np.transpose(out[:, :n, :n], (0, 2, 1))
+    sol = np.transpose(out[:, n:, :n], (0, 2, 1))
+    return fac, sol, info.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,k,B", [(1, 1, 3), (5, 2, 4), (16, 1, 2), (17, 3, 5), (33, 1, 3),
+                                   (131, 1, 4), (344, 162, 2), (580, 1, 3)])
+def test_lu_solve_matches_scipy(ctx, n, k, B):
+    rng = np.random.default_rng(n * 100 + k)
+    A = rng.standard_normal((B, n, n))
+    X = rng.standard_normal((B, n, k))
+    Bm = A @ X
+    fac, sol, info = _run_lu(ctx, A, Bm)
+    assert np.all(info == 0)
+    for b in range(B):
+        lu, piv = sla.lu_factor(A[b])
+        # same pivots => same factors up to rounding
+        assert np.allclose(fac[b], lu, rtol=1e-9, atol=1e-9 * np.abs(lu).max())
+        ref = sla.lu_solve((lu, piv), Bm[b])
+        cond = np.linalg.cond(A[b])
+        assert np.max(np.abs(sol[b] - ref)) <= 1e-13 * cond * max(1.0, np.abs(ref).max())
+
+
+def test_lu_saddle_point_needs_pivoting(ctx):
+    rng = np.random.default_rng(7)
+    nx, ne, B = 60, 30, 3
+    mats, rhs = [], []
+    for _ in range(B):
+        M = rng.standard_normal((nx, nx))
+        M = M @ M.T + np.eye(nx)
+        J = rng.standard_normal((ne, nx))
+        K = np.block([[M, J.T], [J, np.zeros((ne, ne))]])
+        mats.append(K)
+        rhs.append(rng.standard_normal((nx + ne, 1)))
+    mats, rhs = np.array(mats), np.array(rhs)
+    _, sol, info = _run_lu(ctx, mats, rhs)
+    assert np.all(info == 0)
+    for b in range(B):
+        ref = np.linalg.solve(mats[b], rhs[b])
+        assert np.allclose(sol[b], ref, rtol=1e-9, atol=1e-10)
+
+
+def test_lu_singular_flag(ctx):
+    A = np.ones((2, 8, 8))
+    A[1] = np.eye(8)
+    _, _, info = _run_lu(ctx, A, np.ones((2, 8, 1)))
+    assert info[0] == 1 and info[1] == 0
+
+
+def _run_eig(ctx, mats):
+    import torch
+    B, n, _ = mats.shape
+    d = _dev(np.transpose(mats, (0, 2, 1)).copy())
+    wr = torch.zeros((B, n), dtype=torch.float64, device="cuda")
+    wi = torch.zeros((B, n), dtype=torch.float64, device="cuda")
+    info = torch.zeros(B, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    ctx.eigvals_batched(d.data_ptr(), n, n, B, wr.data_ptr(), wi.data_ptr(), info.data_ptr())
+    return wr.cpu().numpy() + 1j * wi.cpu().numpy(), info.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,B", [(1, 2), (2, 3), (3, 3), (6, 4), (17, 3), (41, 5), (100, 2), (377, 2)])
+def test_eigvals_random(ctx, n, B):
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((B, n, n))
+    lam, info = _run_eig(ctx, A)
+    assert np.all(info == 0)
+    for b in range(B):
+        assert match_eigs(np.linalg.eigvals(A[b]), lam[b]) < 1e-8
+
+
+def test_eigvals_known_spectrum(ctx):
+    rng = np.random.default_rng(3)
+    n = 40
+    d = np.concatenate([rng.uniform(-5, -0.1, 20)])
+    blocks = [(-0.2, 8.0), (-0.05, 3.0), (0.1, 12.0)] * 3 + [(-1.0, 0.5)]
+    Bm = np.zeros((n, n))
+    Bm[:20, :20] = np.diag(d)
+    k = 20
+    lam_ref = list(d)
+    for s, w in blocks:
+        Bm[k:k + 2, k:k + 2] = [[s, w], [-w, s]]
+        lam_ref += [complex(s, w), complex(s, -w)]
+        k += 2
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Q @ Bm @ Q.T)[None]
+    lam, info = _run_eig(ctx, A)
+    assert info[0] == 0
+    assert match_eigs(np.array(lam_ref), lam[0]) < 1e-9
+
+
+def test_eigvals_of_oracle_state_matrices(ctx):
+    """Same matrix on both sides: GPU eigenvalues within 1e-8 (relative to
+    max(|lambda|, 1)) of LAPACK on the oracle's 118-bus state matrices."""
+    from oracle import screen, network, islanding, opf, dynamics
+    net = load_case("c2_118")
+    mats = []
+    for o in [(-1, -1), (3, -1), (200, -1), (5, 40)]:
+        br_on, gen_on, load_on = screen.outage_masks(net, [c for c in o if c >= 0])
+        lab, _ = islanding.components_bfs(int(net["n_bus"]), net["br_from"], net["br_to"], br_on)
+        main = islanding.main_island(lab, net["gen_bus"], gen_on, net["pmax"])
+        ref = islanding.island_reference(lab, main, int(net["ref_bus"]), net["gen_bus"], gen_on)
+        sub = network.make_subsystem(net, np.flatnonzero(lab == main), br_on, gen_on, load_on, ref)
+        r = opf.solve_opf(net, sub)
+        if r.status != opf.CONVERGED:
+            continue
+        A = dynamics.DynModel(net, sub, r.vm, r.va, r.pg, r.qg).state_matrix()
+        if A.shape[0] == 377:
+            mats.append(A)
+    mats = np.array(mats)
+    lam, info = _run_eig(ctx, mats)
+    assert np.all(info == 0)
+    for b in range(len(mats)):
+        assert match_eigs(np.linalg.eigvals(mats[b]), lam[b]) < 1e-8

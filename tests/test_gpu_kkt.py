@@ -1,0 +1,100 @@
+"""GPU parity of the OPF Newton system (Section II.B.1).
+
+Both sides start from the same deterministic point, so the KKT matrix and
+right-hand side the GPU assembles at iteration 0 must equal the oracle's to
+rounding; after a few Newton steps the iterates must still agree closely.
+The GPU's fixed-position layout is mapped onto the oracle's compact one; the
+rows the GPU keeps for removed variables must be identity rows.
+"""
+import numpy as np
+import pytest
+
+from helpers import load_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2512_08465_amd as cs
+    return cs.Context(0)
+
+
+def _oracle_problem(net, outage):
+    from oracle import screen, islanding, network, opf
+    o = [c for c in outage if c >= 0]
+    br_on, gen_on, load_on = screen.outage_masks(net, o)
+    lab, _ = islanding.components_bfs(int(net["n_bus"]), net["br_from"], net["br_to"], br_on)
+    main = islanding.main_island(lab, net["gen_bus"], gen_on, net["pmax"])
+    ref = islanding.island_reference(lab, main, int(net["ref_bus"]), net["gen_bus"], gen_on)
+    sub = network.make_subsystem(net, np.flatnonzero(lab == main), br_on, gen_on, load_on, ref)
+    return sub, opf.OPFProblem(net, sub)
+
+
+def _index_map(net, sub):
+    nb, ng = int(net["n_bus"]), int(net["n_gen"])
+    nx = 2 * nb + 2 * ng
+    th = [b for j, b in enumerate(sub.bus) if j != sub.ref]
+    idx = list(th) + [nb + b for b in sub.bus] + [2 * nb + g for g in sub.gen] + \
+          [2 * nb + ng + g for g in sub.gen] + [nx + b for b in sub.bus] + \
+          [nx + nb + b for b in sub.bus]
+    return np.array(idx)
+
+
+CASES = [("c1_30", (0, -1)), ("c1_30", (15, -1)), ("c1_30", (3, 5)), ("c2_118", (0, -1)),
+         ("c2_118", (190, 250))]
+
+
+@pytest.mark.parametrize("name,outage", CASES)
+def test_kkt_at_start_matches_oracle(ctx, name, outage):
+    import paper_2512_08465_amd as cs
+    from oracle import opf
+    net = load_case(name)
+    h = cs.Network(ctx, net)
+    sub, P = _oracle_problem(net, outage)
+    x, lam, z, mu, gamma = opf.initial_state(P)
+    g, hh, Jg, Jh, aux = P.evaluate(x)
+    Lx = P.cost_grad(x) + Jg.T @ lam + Jh.T @ mu
+    Ko, ro = opf.kkt_system(P, x, lam, mu, z, gamma, g, hh, Jg, Jh, Lx, aux)
+    d = h.kkt_at(outage, 0)
+    idx = _index_map(net, sub)
+    Kg = d["K"][np.ix_(idx, idx)]
+    scale = np.abs(Ko).max()
+    err = np.abs(Kg - Ko)
+    i, j = np.unravel_index(np.argmax(err), err.shape)
+    print(f"{name} {outage}: max |dK| {err.max():.3e} at ({i},{j}) gpu {Kg[i, j]:.6e} "
+          f"oracle {Ko[i, j]:.6e}; max |K| {scale:.3e}")
+    assert err.max() <= 1e-12 * scale
+    rerr = np.abs(d["rhs"][idx] - ro)
+    print(f"  max |drhs| {rerr.max():.3e} (max |rhs| {np.abs(ro).max():.3e})")
+    assert rerr.max() <= 1e-12 * max(1.0, np.abs(ro).max())
+    # everything outside the mapped block: identity rows and columns
+    rest = np.setdiff1d(np.arange(d["K"].shape[0]), idx)
+    for r in rest:
+        row = d["K"][r].copy()
+        assert row[r] == 1.0
+        row[r] = 0.0
+        assert not np.any(row) and not np.any(np.delete(d["K"][:, r], r))
+        assert d["rhs"][r] == 0.0
+
+
+@pytest.mark.parametrize("name,outage", CASES)
+def test_newton_iterates_track_oracle(ctx, name, outage):
+    import paper_2512_08465_amd as cs
+    from oracle import opf
+    net = load_case(name)
+    h = cs.Network(ctx, net)
+    sub, P = _oracle_problem(net, outage)
+    r = opf.solve_opf(net, sub, keep_history=True)
+    idx = _index_map(net, sub)[:P.nx]
+    for k in (1, 2, 3, 5, 8):
+        if k >= len(r.history):
+            break
+        d = h.kkt_at(outage, k)
+        ho = r.history[k]
+        mg = d["metrics"]
+        print(f"{name} {outage} it {k}: oracle f {ho['f']:.10e} metrics "
+              f"{['%.3e' % m for m in ho['metrics']]} | gpu metrics {['%.3e' % m for m in mg]} "
+              f"status {d['status']}")
+        rel = np.abs(np.array(mg) - np.array(ho["metrics"])) / np.maximum(np.abs(ho["metrics"]), 1e-300)
+        assert rel[:3].max() < 1e-6, rel
