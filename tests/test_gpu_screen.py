@@ -124,7 +124,7 @@ def test_invalid_inputs_rejected(nets):
     import paper_2512_08465_amd as cs
     net = load_case("c1_30")
     h = nets["c1_30"]
-    for bad in ([[41, -1]], [[3, 3]], [[-2, -1]], [[0, 99]]):
+    for bad in ([[67, -1]], [[3, 3]], [[-2, -1]], [[0, 67]], [[5, -3]]):
         with pytest.raises(cs.CSError) as e:
             h.screen(np.array(bad), net["lam"])
         assert e.value.code == cs.CS_EINVAL
