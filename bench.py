@@ -20,6 +20,11 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# The host-side oracle baseline runs one BLAS thread in each of its (at most
+# 16) worker processes; set before NumPy loads so no BLAS thread pool exists
+# when the workers are forked.
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ[_v] = "1"
 
 METRIC = "N-2 scenarios/s (OPF+eigs) on 118-bus shape; p99 request latency; FP64 vs mixed"
 PEAK_FP64_TFLOPS = 78.6
@@ -31,39 +36,45 @@ def kkt_lu_flops(n: int) -> float:
     return 2.0 / 3.0 * n ** 3 + 2.0 * n ** 2
 
 
-def cpu_baseline(case, lst, n_sample=64, seed=7):
-    """The oracle timed on this host's cores on a seeded sample of the list."""
-    os.environ["OMP_NUM_THREADS"] = "1"
+def cpu_baseline(case, lst, n_sample=512, seed=7):
+    """The oracle timed on this host's cores on a seeded sample of the list.
+
+    Runs before the device is initialised; workers are forked from this
+    process, so they share its loaded modules and the network."""
     import numpy as np
     from multiprocessing import get_context
+    from oracle import screen  # noqa: F401  (warm import before the fork)
+    global _CPU_NET
+    _CPU_NET = case
     rng = np.random.default_rng(seed)
     idx = np.sort(rng.choice(len(lst), n_sample, replace=False))
-    cores = min(os.cpu_count() or 1, 16)
-    ctx = get_context("spawn")
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    ctx = get_context("fork")
     t0 = time.perf_counter()
-    with ctx.Pool(cores, initializer=_cpu_init) as p:
-        p.map(_cpu_one, [tuple(int(v) for v in lst[i]) for i in idx], chunksize=1)
+    done = 0
+    with ctx.Pool(cores) as p:
+        for _ in p.imap_unordered(_cpu_one, [tuple(int(v) for v in lst[i]) for i in idx]):
+            done += 1
+            if done % 16 == 0:
+                log(f"oracle: {done}/{n_sample} scenarios, {time.perf_counter() - t0:.1f} s")
     dt = time.perf_counter() - t0
     return dict(value=round(n_sample / dt, 3), unit="scenarios/s", cores=cores, kind="oracle",
                 sample=f"{n_sample} scenarios drawn uniformly (seed {seed}) from the 57,630-row "
-                       f"list, multiprocessing pool of {cores} single-threaded workers, "
-                       f"{dt:.1f} s wall")
+                       f"list, {cores} forked single-threaded worker processes, {dt:.1f} s wall")
 
 
 _CPU_NET = None
 
 
-def _cpu_init():
-    global _CPU_NET
+def _cpu_one(o):
     import warnings
     warnings.simplefilter("ignore")
-    from inputs import netgen
-    _CPU_NET = netgen.load_case(os.path.join(ROOT, "inputs", "cases", "c2_118.npz"))
-
-
-def _cpu_one(o):
     from oracle import screen
     return screen.evaluate(_CPU_NET, o).severe
+
+
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -82,17 +93,27 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
-    import paper_2512_08465_amd as cs
     from inputs import netgen, contingencies
 
     case = netgen.load_case(os.path.join(ROOT, "inputs", "cases", "c2_118.npz"))
     lst = contingencies.n1_n2(case["outage_set"]).astype(np.int32)
     n_all = len(lst)
     step = n_all if args.full else min(args.step_size, n_all)
+    base = None
+    if not args.no_cpu_baseline:
+        # before any device initialisation: worker processes are started here
+        log("timing the oracle on the host cores")
+        base = cpu_baseline(case, lst)
+        log(f"oracle: {base['value']} scenarios/s on {base['cores']} cores")
+
+    log("importing torch and the library")
+    import torch
+    import paper_2512_08465_amd as cs
 
     ctx = cs.Context(0)
+    log("device context ready")
     net = cs.Network(ctx, case)
+    log(f"network resident; {n_all} scenarios, {step} per step")
     dev = torch.device("cuda:0")
     d_list = torch.from_numpy(lst).to(dev)
     d_lam = torch.from_numpy(case["lam"]).to(dev)
@@ -113,12 +134,14 @@ def main():
     timed = cs.default_options(timing=1)
     for w in range(args.warmup):
         run_step(w, plain)
+        log(f"warmup step {w + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     ctx.reset_stats()
     done = 0
     t0 = time.perf_counter()
     for k in range(args.steps):
         done += run_step(args.warmup + k, timed)
+        log(f"timed step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = ctx.stats()
@@ -171,8 +194,8 @@ def main():
             "severe_fraction": round(float(np.mean(res["severe"][:min(n_all, done)])), 4),
         },
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case, lst)
+    if base is not None:
+        out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
 
 
