@@ -182,9 +182,10 @@ int cs_detail(cs_ctx* ctx, cs_net* net, const int32_t outage[2],
               int32_t* n_eig, int32_t* label);
 
 /* Kernel-level entry points (device buffers, for testing the dense kernels
- * alone).  Batched LU with partial pivoting of `batch` column-major n x n
+ * alone).  Batched LU with partial pivoting of `batch` row-major n x n
  * matrices followed by the solve of nrhs right-hand sides stored as extra
- * columns: A is [batch][ncols = n + nrhs][lda], overwritten by the factors
+ * columns: A is [batch][n][lda], lda >= n + nrhs, overwritten by the factors
+ * (unit lower L below the diagonal, U on and above, rows in pivoted order)
  * and the solutions.  info[b] = 1 if matrix b hit an exactly zero pivot. */
 int cs_dense_solve_batched(const cs_ctx* ctx, double* d_A, int32_t n,
                            int32_t nrhs, int32_t lda, int32_t batch,
@@ -199,7 +200,7 @@ int cs_eigvals_batched(const cs_ctx* ctx, double* d_A, int32_t n, int32_t lda,
 
 /* Parity/debug: run the OPF of one scenario for `iters` Newton steps, then
  * evaluate and assemble the KKT system at the point reached (Section II.B.1).
- * Host outputs, each may be NULL: K [nk + 1][nk] column-major (the last
+ * Host outputs, each may be NULL: K [nk][nk + 1] row-major (the last
  * column is the right-hand side; layout of the fixed-position KKT: theta,
  * V, Pg, Qg, then P and Q balance multipliers, with identity rows for
  * removed variables), x [2 n_bus + 2 n_gen], lam [2 n_bus],

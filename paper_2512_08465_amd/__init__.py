@@ -239,7 +239,7 @@ class Network:
         """KKT system and iterate after ``iters`` Newton steps (parity/debug)."""
         nb, nl, ng = self.n_bus, self.n_branch, self.n_gen
         nk = 4 * nb + 2 * ng
-        K = np.zeros((nk + 1, nk))
+        K = np.zeros((nk, nk + 1))
         x = np.zeros(2 * nb + 2 * ng)
         lam = np.zeros(2 * nb)
         z = np.zeros(2 * nl + 2 * nb + 4 * ng)
@@ -251,7 +251,7 @@ class Network:
         _check(library().cs_kkt_at(self.ctx.handle, self._h, _ptr(o2), int(iters), _ptr(K),
                                    _ptr(x), _ptr(lam), _ptr(z), _ptr(mu), _ptr(met),
                                    _ptr(status), _ptr(order)))
-        return dict(K=K[:nk].T.copy(), rhs=K[nk].copy(), x=x, lam=lam, z=z, mu=mu,
+        return dict(K=K[:, :nk].copy(), rhs=K[:, nk].copy(), x=x, lam=lam, z=z, mu=mu,
                     metrics=met, status=int(status[0]))
 
     def detail(self, outage, options: Options | None = None):

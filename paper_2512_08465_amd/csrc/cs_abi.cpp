@@ -21,7 +21,7 @@
 #include "cs_internal.h"
 
 namespace cs {
-size_t lu_lds_bytes(int n);
+size_t lu_lds_bytes(int n, int nrhs);
 size_t opf_eval_lds(int nb, int nl, int ng);
 size_t form_state_lds(int ng);
 void launch_setup_k(const DevNet& net, const Slots& s, int count, const int* outages,
@@ -259,7 +259,9 @@ extern "C" int cs_net_create(cs_ctx* ctx, const cs_net_desc* d, cs_net** out) {
   {
     const size_t nk = 4 * (size_t)nb + 2 * (size_t)ng;
     const size_t lim = ctx->lds_max;
-    if (lu_lds_bytes((int)nk) > lim || opf_eval_lds(nb, nl, ng) > lim ||
+    const int ny = 2 * ng + 2 * nb;
+    if (lu_lds_bytes((int)nk, 1) > lim || lu_lds_bytes(ny, 3 * ng) > lim ||
+        opf_eval_lds(nb, nl, ng) > lim ||
         form_state_lds(ng) > lim || 8 * (size_t)(2 * nl + 2 * nb + 4 * ng) > lim)
       return fail(CS_EUNSUPPORTED, "cs_net_create: network too large for the on-chip working set (KKT order " +
                                        std::to_string(nk) + ", " + std::to_string(lim) +
@@ -351,14 +353,14 @@ static Plan plan_sizes(const cs_net* n) {
   s.nx = 2 * nb + 2 * ng;
   s.neq = 2 * nb;
   s.nk = s.nx + s.neq;
-  s.ldk = (int)round_up(s.nk, 2);
+  s.ldk = (int)round_up(s.nk + 1, 2);      // row stride: matrix + right-hand side
   s.ni = 2 * nl + 2 * nb + 4 * ng;
   s.ny = 2 * ng + 2 * nb;
-  s.ldy = (int)round_up(s.ny, 2);
   s.nyc = s.ny + 3 * ng;
+  s.ldy = (int)round_up(s.nyc, 2);
   s.na = 7 * ng - 1;
   s.lda_a = (int)round_up(std::max(s.na, 1), 2);
-  s.k_stride = round_up(std::max((size_t)(s.nk + 1) * s.ldk, (size_t)s.nyc * s.ldy), 64);
+  s.k_stride = round_up(std::max((size_t)s.nk * s.ldk, (size_t)s.ny * s.ldy), 64);
   s.a_stride = round_up((size_t)s.lda_a * s.na, 64);
   const size_t piv = std::max(s.nk, s.ny);
   p.per_slot = 8 * (s.k_stride + s.a_stride + s.nx + s.neq + 3 * (size_t)s.ni + 8 * (size_t)nl +
@@ -669,9 +671,9 @@ extern "C" int cs_detail(cs_ctx* c, cs_net* n, const int32_t outage[2], const cs
 
 extern "C" int cs_dense_solve_batched(const cs_ctx* c, double* d_A, int32_t n, int32_t nrhs,
                                       int32_t lda, int32_t batch, int32_t* d_info, void* stream) {
-  if (!c || !d_A || n <= 0 || nrhs < 0 || lda < n || batch < 0)
+  if (!c || !d_A || n <= 0 || nrhs < 0 || lda < n + nrhs || batch < 0)
     return fail(CS_EINVAL, "cs_dense_solve_batched: bad arguments");
-  if (lu_lds_bytes(n) > c->lds_max)
+  if (lu_lds_bytes(n, nrhs) > c->lds_max)
     return fail(CS_EUNSUPPORTED, "cs_dense_solve_batched: n = " + std::to_string(n) +
                                      " needs more LDS than the device allows (" +
                                      std::to_string(c->lds_max) + " bytes)");
@@ -680,8 +682,7 @@ extern "C" int cs_dense_solve_batched(const cs_ctx* c, double* d_A, int32_t n, i
   hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
   int* piv = nullptr;
   HIPCHK(hipMalloc(&piv, sizeof(int) * (size_t)n * batch));
-  launch_lu_solve(d_A, (size_t)lda * (n + nrhs), n, n + nrhs, lda, piv, n, nullptr, batch,
-                  d_info, st);
+  launch_lu_solve(d_A, (size_t)lda * n, n, n + nrhs, lda, piv, n, nullptr, batch, d_info, st);
   hipError_t e = hipGetLastError();
   hipError_t e2 = hipStreamSynchronize(st);
   hipFree(piv);
@@ -741,10 +742,10 @@ extern "C" int cs_kkt_at(cs_ctx* c, cs_net* n, const int32_t outage[2], int32_t 
   HIPCHK(hipMemcpy(&S, s.st, sizeof(SlotState), hipMemcpyDeviceToHost));
   const int nk = s.nk;
   if (K) {
-    std::vector<double> buf((size_t)(nk + 1) * s.ldk);
+    std::vector<double> buf((size_t)nk * s.ldk);
     HIPCHK(hipMemcpy(buf.data(), s.K, sizeof(double) * buf.size(), hipMemcpyDeviceToHost));
-    for (int col = 0; col <= nk; ++col)
-      for (int r = 0; r < nk; ++r) K[(size_t)col * nk + r] = buf[(size_t)col * s.ldk + r];
+    for (int r = 0; r < nk; ++r)
+      for (int col = 0; col <= nk; ++col) K[(size_t)r * (nk + 1) + col] = buf[(size_t)r * s.ldk + col];
   }
   if (x) HIPCHK(hipMemcpy(x, s.x, sizeof(double) * s.nx, hipMemcpyDeviceToHost));
   if (lam) HIPCHK(hipMemcpy(lam, s.lam, sizeof(double) * s.neq, hipMemcpyDeviceToHost));

@@ -7,8 +7,8 @@
 // KKT layout (fixed positions, independent of the outage):
 //   x   = [theta (nb), V (nb), Pg (ng), Qg (ng)]            nx  = 2nb + 2ng
 //   lam = [P balance (nb), Q balance (nb)]                 neq = 2nb
-//   K is nk x nk, nk = nx + neq, stored column-major with one extra column
-//   holding the right-hand side and then the solution.  Variables and
+//   K is nk x nk, nk = nx + neq, stored row-major (row stride ldk) with one
+//   extra column holding the right-hand side and then the solution.  Variables and
 //   equations that the outage removes (buses outside the main island, the
 //   island's reference angle, generators out of service) become identity
 //   rows/columns with a zero right-hand side, so their Newton step is zero.
@@ -16,8 +16,8 @@
 //   Vmax (nb), Pmin (ng), Pmax (ng), Qmin (ng), Qmax (ng)]; masked entries
 //   have z = 1, mu = 0 and take no part in any sum.
 // Dynamic algebraic system (same buffer as K after the OPF):
-//   y = [Id (ng), Iq (ng), theta (nb), V (nb)], ny = 2ng + 2nb, followed by
-//   3ng right-hand-side columns: d g / d(delta_j, Eq'_j, Ed'_j).
+//   y = [Id (ng), Iq (ng), theta (nb), V (nb)], ny = 2ng + 2nb, row-major,
+//   followed by 3ng right-hand-side columns: d g / d(delta_j, Eq'_j, Ed'_j).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -2,20 +2,28 @@
 //
 // Each Newton step of the OPF solves one dense KKT system, and the state
 // matrix needs g_y^{-1} g_x; both go through this kernel.  The matrix is
-// column-major [lda][ncols] with the right-hand sides as columns n..ncols-1
-// (an augmented matrix), so the forward substitution falls out of the
+// row-major, rows of stride lda, with the right-hand sides stored as columns
+// n..ncols-1 (an augmented matrix): the forward substitution falls out of the
 // elimination and only the back substitution with U remains.
 //
-// Right-looking blocked LU, panel width NB:
-//   1. the m x NB panel is staged in LDS and factorised there (pivot = first
-//      largest |a| in the column, row swap, scale, rank-1 update);
-//   2. the panel's row interchanges are applied to every other column, and the
-//      NB x (ncols-k0-NB) block row is solved with the unit lower L11 (TRSM);
-//   3. the trailing matrix is updated, A22 -= L21 U12, with FP64 MFMA
-//      (v_mfma_f64_16x16x4f64), 16 x 16 tiles per wave, L21 read from LDS;
-//      each tile is formed transposed so its rows map onto lanes.
+// Right-looking blocked LU with panel width NB = 16 and one panel of
+// look-ahead.  Per panel k (its factors in LDS, pivots known):
+//   A. all waves: write the panel back, apply its row interchanges to every
+//      other column (one thread per column, coalesced along rows), then form
+//      the block row U12 = inv(L11) A12 with MFMA (inv(L11), the inverse of
+//      the panel's unit lower triangle, is built by wave 0 with the panel);
+//   B. all waves: update the next panel's NB columns with L21 U12;
+//   C. wave 0 stages the next panel in LDS and factorises it (pivot = first
+//      largest |a| in the column, row swap, scale, rank-1 update; wavefront
+//      shuffles only, no workgroup barrier), while the other waves update the
+//      rest of the trailing matrix, A22 -= L21 U12, with FP64 MFMA
+//      (v_mfma_f64_16x16x4f64) on 32 x 32 groups of four 16 x 16 tiles taken
+//      from a shared counter;
+//      wave 0 joins the tile loop when its panel is done.
 // After the last panel, U x = y is solved by 16-row blocks from the bottom.
 #include "cs_internal.h"
+
+#include <algorithm>
 
 namespace cs {
 
@@ -23,12 +31,182 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 constexpr int LU_NB = 16;
 constexpr int LU_THREADS = 256;
+constexpr int LU_WAVES = LU_THREADS / 64;
+constexpr int PLD = LU_NB + 1;        // LDS row stride of the panel (bank spread)
+
+__device__ inline void wave_sync() {
+  // LDS accesses of one wavefront complete in issue order; this only stops
+  // the compiler from moving memory operations across the point.
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
 
 __device__ inline void argmax_combine(double& v, int& i, double v2, int i2) {
   if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
 }
 
-__global__ __launch_bounds__(LU_THREADS) void k_lu_solve(
+// Stage rows [r0, n) x columns [r0, r0 + kb) in LDS and factorise them with
+// one wavefront.  Pivots (relative to r0) go to spiv[], absolute to piv[];
+// linv receives the inverse of the panel's unit lower triangle.
+__device__ void panel_factor(const double* __restrict__ A, int lda, int n, int r0, int kb,
+                             double* __restrict__ P, double* __restrict__ linv,
+                             int* __restrict__ spiv, int* __restrict__ piv, int* sing,
+                             int lane) {
+  const int m = n - r0;
+  for (int r = lane; r < m; r += 64) {
+    const double* src = A + (size_t)(r0 + r) * lda + r0;
+    double* dst = P + r * PLD;
+    for (int c = 0; c < kb; ++c) dst[c] = src[c];
+  }
+  wave_sync();
+  for (int j = 0; j < kb; ++j) {
+    double bv = -1.0;
+    int bi = j;
+    for (int r = j + lane; r < m; r += 64) {
+      const double a = fabs(P[r * PLD + j]);
+      if (a > bv) { bv = a; bi = r; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double v2 = __shfl_xor(bv, off, 64);
+      const int i2 = __shfl_xor(bi, off, 64);
+      argmax_combine(bv, bi, v2, i2);
+    }
+    const int p = bi;                 // uniform across the wavefront
+    if (lane == 0) {
+      spiv[j] = p;
+      piv[r0 + j] = r0 + p;
+    }
+    if (p != j && lane < kb) {
+      const double t = P[j * PLD + lane];
+      P[j * PLD + lane] = P[p * PLD + lane];
+      P[p * PLD + lane] = t;
+    }
+    wave_sync();
+    const double pv = P[j * PLD + j];
+    if (pv == 0.0) {
+      if (lane == 0) *sing = 1;
+    } else {
+      const double inv = 1.0 / pv;
+      for (int r = j + 1 + lane; r < m; r += 64) {
+        double* row = P + r * PLD;
+        const double l = row[j] * inv;
+        row[j] = l;
+        for (int c = j + 1; c < kb; ++c) row[c] -= l * P[j * PLD + c];
+      }
+    }
+    wave_sync();
+  }
+  // inverse of the unit lower triangle L11 (kb x kb, identity-padded to 16):
+  // lane j forms column j by forward substitution
+  if (lane < LU_NB) {
+    const int j = lane;
+    for (int i = 0; i < LU_NB; ++i) {
+      double v = (i == j) ? 1.0 : 0.0;
+      if (i > j && i < kb) {
+        v = 0.0;
+        for (int k = j; k < i; ++k) v -= P[i * PLD + k] * linv[k * LU_NB + j];
+      }
+      linv[i * LU_NB + j] = v;
+    }
+  }
+  wave_sync();
+}
+
+// C[i0:i0+16, j0:j0+16] -= L21[i0:, k0:k0+kb] U12[k0:k0+kb, j0:] (global
+// rows), restricted to rows < n and columns < ncols
+__device__ inline void update_tile(double* __restrict__ A, int lda, int n, int ncols,
+                                   int k0, int kb, int i0, int j0, int lane) {
+  const int li = lane & 15, lk = lane >> 4;
+  // accumulator layout of the f64 16x16x4 MFMA: lane l, register q holds
+  // D[l/16 + 4q][l%16]; D is the tile itself, so 16 lanes cover 16
+  // consecutive doubles of one row.
+  const int col = j0 + li;
+  const bool cok = col < ncols;
+  dbl4 acc;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int row = i0 + lk + 4 * q;
+    acc[q] = (cok && row < n) ? A[(size_t)row * lda + col] : 0.0;
+  }
+  const int arow = i0 + li;
+  const bool aok = arow < n;
+  const double* lrow = A + (size_t)arow * lda + k0;
+#pragma unroll
+  for (int kk = 0; kk < LU_NB / 4; ++kk) {
+    const int k = 4 * kk + lk;
+    double a = 0.0, b = 0.0;
+    if (k < kb) {
+      if (aok) a = -lrow[k];
+      if (cok) b = A[(size_t)(k0 + k) * lda + col];
+    }
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int row = i0 + lk + 4 * q;
+    if (cok && row < n) A[(size_t)row * lda + col] = acc[q];
+  }
+}
+
+// The same update on a 32 x 32 group of four tiles: all 32 loads of a lane
+// are issued together and every L21 / U12 operand feeds two MFMAs.
+__device__ inline void update_group(double* __restrict__ A, int lda, int n, int ncols,
+                                    int k0, int kb, int i0, int j0, int lane) {
+  const int li = lane & 15, lk = lane >> 4;
+  dbl4 acc[2][2];
+  int col[2];
+  bool cok[2];
+#pragma unroll
+  for (int tj = 0; tj < 2; ++tj) {
+    col[tj] = j0 + 16 * tj + li;
+    cok[tj] = col[tj] < ncols;
+  }
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = i0 + 16 * ti + lk + 4 * q;
+        acc[ti][tj][q] = (cok[tj] && row < n) ? A[(size_t)row * lda + col[tj]] : 0.0;
+      }
+  double a[2][LU_NB / 4], b[2][LU_NB / 4];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti) {
+    const int arow = i0 + 16 * ti + li;
+    const double* lrow = A + (size_t)arow * lda + k0;
+#pragma unroll
+    for (int kk = 0; kk < LU_NB / 4; ++kk) {
+      const int k = 4 * kk + lk;
+      a[ti][kk] = (k < kb && arow < n) ? -lrow[k] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+    for (int kk = 0; kk < LU_NB / 4; ++kk) {
+      const int k = 4 * kk + lk;
+      b[tj][kk] = (k < kb && cok[tj]) ? A[(size_t)(k0 + k) * lda + col[tj]] : 0.0;
+    }
+#pragma unroll
+  for (int kk = 0; kk < LU_NB / 4; ++kk)
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+        acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti][kk], b[tj][kk], acc[ti][tj], 0, 0, 0);
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = i0 + 16 * ti + lk + 4 * q;
+        if (cok[tj] && row < n) A[(size_t)row * lda + col[tj]] = acc[ti][tj][q];
+      }
+}
+
+__global__ __launch_bounds__(LU_THREADS, 2) void k_lu_solve(
     double* __restrict__ Abase, size_t stride, int n, int ncols, int lda,
     int* __restrict__ pivbase, int piv_stride, SlotState* __restrict__ st,
     int* __restrict__ info) {
@@ -40,191 +218,129 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_solve(
   const int lane = tid & 63;
   const int wave = tid >> 6;
 
-  extern __shared__ double P[];          // panel, column-major, ld = ldp
-  __shared__ double red_v[LU_THREADS / 64];
-  __shared__ int red_i[LU_THREADS / 64];
-  __shared__ int s_p;
+  extern __shared__ double P[];          // panel rows, stride PLD
   __shared__ int s_piv[LU_NB];
   __shared__ int s_sing;
+  __shared__ int s_tile;
   __shared__ double s_ub[LU_NB * LU_NB];
-  const int ldp = n + 1;
+  __shared__ double s_linv[LU_NB * LU_NB];
   if (tid == 0) s_sing = 0;
+  __syncthreads();
+
+  if (wave == 0) panel_factor(A, lda, n, 0, min(LU_NB, n), P, s_linv, s_piv, piv, &s_sing, lane);
+  __syncthreads();
 
   for (int k0 = 0; k0 < n; k0 += LU_NB) {
     const int kb = min(LU_NB, n - k0);
     const int m = n - k0;
-    // ---- 1. stage the panel A[k0:n, k0:k0+kb] in LDS
-    for (int c = 0; c < kb; ++c)
-      for (int r = tid; r < m; r += LU_THREADS)
-        P[r + ldp * c] = A[(size_t)(k0 + c) * lda + k0 + r];
-    __syncthreads();
-    // ---- factorise the panel
-    for (int j = 0; j < kb; ++j) {
-      double bv = -1.0;
-      int bi = j;
-      for (int r = j + tid; r < m; r += LU_THREADS) {
-        double a = fabs(P[r + ldp * j]);
-        if (a > bv) { bv = a; bi = r; }
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        double v2 = __shfl_xor(bv, off, 64);
-        int i2 = __shfl_xor(bi, off, 64);
-        argmax_combine(bv, bi, v2, i2);
-      }
-      if (lane == 0) { red_v[wave] = bv; red_i[wave] = bi; }
-      __syncthreads();
-      if (tid == 0) {
-        double v = red_v[0];
-        int i = red_i[0];
-        for (int w = 1; w < LU_THREADS / 64; ++w) argmax_combine(v, i, red_v[w], red_i[w]);
-        s_p = i;
-        s_piv[j] = i;
-        piv[k0 + j] = k0 + i;
-      }
-      __syncthreads();
-      const int p = s_p;
-      if (p != j && tid < kb) {
-        double t = P[j + ldp * tid];
-        P[j + ldp * tid] = P[p + ldp * tid];
-        P[p + ldp * tid] = t;
-      }
-      __syncthreads();
-      const double pv = P[j + ldp * j];
-      if (pv == 0.0) {
-        if (tid == 0) s_sing = 1;
-      } else {
-        const double inv = 1.0 / pv;
-        for (int r = j + 1 + tid; r < m; r += LU_THREADS) {
-          double l = P[r + ldp * j] * inv;
-          P[r + ldp * j] = l;
-          for (int c = j + 1; c < kb; ++c) P[r + ldp * c] -= l * P[j + ldp * c];
-        }
-      }
-      __syncthreads();
+    const int r0 = k0 + kb;
+    // ---- A: write the panel back, interchanges, TRSM of the block row
+    for (int e = tid; e < m * kb; e += LU_THREADS) {
+      const int r = e / kb, c = e % kb;
+      A[(size_t)(k0 + r) * lda + k0 + c] = P[r * PLD + c];
     }
-    // ---- write the factored panel back
-    for (int c = 0; c < kb; ++c)
-      for (int r = tid; r < m; r += LU_THREADS)
-        A[(size_t)(k0 + c) * lda + k0 + r] = P[r + ldp * c];
-    // ---- 2. interchanges on the other columns; TRSM on the block row
     for (int c = tid; c < ncols; c += LU_THREADS) {
-      if (c >= k0 && c < k0 + kb) continue;
-      double* col = A + (size_t)c * lda;
+      if (c >= k0 && c < r0) continue;
       for (int j = 0; j < kb; ++j) {
         const int p = s_piv[j];
         if (p != j) {
-          double t = col[k0 + j];
-          col[k0 + j] = col[k0 + p];
-          col[k0 + p] = t;
+          double* a = A + (size_t)(k0 + j) * lda + c;
+          double* b = A + (size_t)(k0 + p) * lda + c;
+          const double t = *a;
+          *a = *b;
+          *b = t;
         }
-      }
-      if (c >= k0 + kb) {
-        double u[LU_NB];
-#pragma unroll
-        for (int j = 0; j < LU_NB; ++j) u[j] = (j < kb) ? col[k0 + j] : 0.0;
-#pragma unroll
-        for (int j = 0; j < LU_NB; ++j) {
-#pragma unroll
-          for (int i = j + 1; i < LU_NB; ++i)
-            if (i < kb) u[i] -= P[i + ldp * j] * u[j];
-        }
-#pragma unroll
-        for (int j = 0; j < LU_NB; ++j)
-          if (j < kb) col[k0 + j] = u[j];
       }
     }
     __syncthreads();
-    // ---- 3. trailing update A22 -= L21 * U12 on MFMA
-    const int r0 = k0 + kb;
-    const int rows = n - r0;
-    const int cols = ncols - r0;
-    if (rows > 0 && cols > 0) {
-      const int tr = (rows + 15) >> 4;
-      const int tc = (cols + 15) >> 4;
-      const int ntiles = tr * tc;
-      // The tile is computed transposed, C^T -= U12^T L21^T, so that the
-      // accumulator layout of v_mfma_f64_16x16x4f64 (lane l, register q holds
-      // D[l/16 + 4q][l%16]) puts C rows on lanes: lane l owns row i0 + l%16
-      // of columns j0 + l/16 + 4q, and 16 lanes cover 16 consecutive doubles.
-      const int li = lane & 15;
-      const int lk = lane >> 4;
-      for (int t = wave; t < ntiles; t += LU_THREADS / 64) {
-        const int ti = t % tr;
-        const int tj = t / tr;
-        const int i0 = r0 + 16 * ti;
-        const int j0 = r0 + 16 * tj;
-        const int row = i0 + li;
-        const bool rok = row < n;
-        dbl4 acc;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int col = j0 + lk + 4 * q;
-          acc[q] = (rok && col < ncols) ? A[(size_t)col * lda + row] : 0.0;
-        }
-        const int ucol = j0 + li;           // column of the U12 entry
-        const bool uok = ucol < ncols;
-        const double* up = A + (size_t)ucol * lda + k0;
-        const double* lp = P + (row - k0);
+    // U12 = inv(L11) A12 on MFMA, one 16-column tile per wavefront pass
+    {
+      const int li = lane & 15, lk = lane >> 4;
+      const int ntc = (ncols - r0 + 15) >> 4;
+      for (int t = wave; t < ntc; t += LU_WAVES) {
+        const int col = r0 + 16 * t + li;
+        const bool cok = col < ncols;
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kk = 0; kk < LU_NB / 4; ++kk) {
           const int k = 4 * kk + lk;
-          double a = 0.0, b = 0.0;
-          if (k < kb) {
-            if (uok) a = -up[k];
-            if (rok) b = lp[(size_t)ldp * k];
-          }
+          const double a = s_linv[li * LU_NB + k];
+          const double b = (cok && k < kb) ? A[(size_t)(k0 + k) * lda + col] : 0.0;
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int col = j0 + lk + 4 * q;
-          if (rok && col < ncols) A[(size_t)col * lda + row] = acc[q];
+          const int row = lk + 4 * q;
+          if (cok && row < kb) A[(size_t)(k0 + row) * lda + col] = acc[q];
         }
+      }
+    }
+    if (tid == 0) s_tile = 0;
+    __syncthreads();
+    if (r0 >= n) break;     // last panel: the right-hand sides were done by TRSM
+    // ---- B: bring the next panel's columns up to date
+    const int kb2 = min(LU_NB, n - r0);
+    const int tr = (n - r0 + 15) >> 4;
+    for (int t = wave; t < tr; t += LU_WAVES)   // columns [r0, r0 + kb2) only
+      update_tile(A, lda, n, r0 + kb2, k0, kb, r0 + 16 * t, r0, lane);
+    __syncthreads();
+    // ---- C: wave 0 factorises the next panel; everyone updates the rest
+    if (wave == 0) panel_factor(A, lda, n, r0, kb2, P, s_linv, s_piv, piv, &s_sing, lane);
+    const int c2 = r0 + kb2;
+    if (c2 < ncols) {
+      const int gr = (n - r0 + 31) >> 5;
+      const int gc = (ncols - c2 + 31) >> 5;
+      const int ngroups = gr * gc;
+      while (true) {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(&s_tile, 1);
+        t = __shfl(t, 0, 64);
+        if (t >= ngroups) break;
+        const int ti = t % gr, tj = t / gr;
+        update_group(A, lda, n, ncols, k0, kb, r0 + 32 * ti, c2 + 32 * tj, lane);
       }
     }
     __syncthreads();
   }
 
-  // ---- back substitution U x = y for the right-hand-side columns
+  // ---- back substitution U x = y for the right-hand-side columns, by
+  // 16-row blocks from the bottom.  A wavefront solves a diagonal block for
+  // one right-hand side at a time (lane i holds row i; x_i is broadcast and
+  // eliminated from the rows above), the block solution is kept in LDS (the
+  // panel buffer is free now), then every row above is updated.
   const int nrhs = ncols - n;
   if (nrhs > 0) {
+    double* xs = P;                                 // [16][nrhs]
     const int nblk = (n + LU_NB - 1) / LU_NB;
     for (int b = nblk - 1; b >= 0; --b) {
       const int b0 = b * LU_NB;
       const int bs = min(LU_NB, n - b0);
       for (int e = tid; e < LU_NB * LU_NB; e += LU_THREADS) {
-        const int i = e % LU_NB, j = e / LU_NB;
-        s_ub[e] = (i < bs && j < bs) ? A[(size_t)(b0 + j) * lda + b0 + i] : 0.0;
+        const int i = e / LU_NB, j = e % LU_NB;
+        s_ub[e] = (i < bs && j < bs) ? A[(size_t)(b0 + i) * lda + b0 + j] : 0.0;
       }
       __syncthreads();
-      for (int rc = tid; rc < nrhs; rc += LU_THREADS) {
-        double* y = A + (size_t)(n + rc) * lda + b0;
-        double v[LU_NB];
-#pragma unroll
-        for (int i = 0; i < LU_NB; ++i) v[i] = (i < bs) ? y[i] : 0.0;
-#pragma unroll
-        for (int i = LU_NB - 1; i >= 0; --i) {
-          if (i < bs) {
-            double s = v[i];
-#pragma unroll
-            for (int j = i + 1; j < LU_NB; ++j)
-              if (j < bs) s -= s_ub[i + LU_NB * j] * v[j];
-            v[i] = s / s_ub[i + LU_NB * i];
-          }
+      for (int rc = wave; rc < nrhs; rc += LU_WAVES) {
+        double y = (lane < bs) ? A[(size_t)(b0 + lane) * lda + n + rc] : 0.0;
+        for (int i = bs - 1; i >= 0; --i) {
+          const double xi = __shfl(y, i, 64) / s_ub[i * LU_NB + i];
+          if (lane == i) y = xi;
+          if (lane < i) y -= s_ub[lane * LU_NB + i] * xi;
         }
-#pragma unroll
-        for (int i = 0; i < LU_NB; ++i)
-          if (i < bs) y[i] = v[i];
+        if (lane < bs) {
+          xs[lane * nrhs + rc] = y;
+          A[(size_t)(b0 + lane) * lda + n + rc] = y;
+        }
       }
       __syncthreads();
       // y[0:b0] -= U[0:b0, b0:b0+bs] x[b0:b0+bs]
       const int work = b0 * nrhs;
       for (int e = tid; e < work; e += LU_THREADS) {
-        const int i = e % b0, rc = e / b0;
-        double* y = A + (size_t)(n + rc) * lda;
-        double s = y[i];
-        for (int j = 0; j < bs; ++j) s -= A[(size_t)(b0 + j) * lda + i] * y[b0 + j];
-        y[i] = s;
+        const int i = e / nrhs, rc = e % nrhs;
+        const double* urow = A + (size_t)i * lda + b0;
+        double acc = A[(size_t)i * lda + n + rc];
+        for (int j = 0; j < bs; ++j) acc -= urow[j] * xs[j * nrhs + rc];
+        A[(size_t)i * lda + n + rc] = acc;
       }
       __syncthreads();
     }
@@ -235,16 +351,21 @@ __global__ __launch_bounds__(LU_THREADS) void k_lu_solve(
   }
 }
 
+// panel rows during the factorisation; a 16 x nrhs block during the solve
+size_t lu_lds_bytes(int n, int nrhs) {
+  return sizeof(double) * std::max((size_t)PLD * (size_t)n, (size_t)LU_NB * (size_t)nrhs);
+}
+
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
                      int* piv, int piv_stride, SlotState* st, int count,
                      int* info, hipStream_t stream) {
   if (count <= 0) return;
-  const size_t lds = sizeof(double) * (size_t)LU_NB * (size_t)(n + 1);
+  const size_t lds = lu_lds_bytes(n, ncols - n);
   hipLaunchKernelGGL(k_lu_solve, dim3(count), dim3(LU_THREADS), lds, stream,
                      A, stride, n, ncols, lda, piv, piv_stride, st, info);
 }
 
-size_t lu_lds_bytes(int n) { return sizeof(double) * (size_t)LU_NB * (size_t)(n + 1); }
+
 
 void lu_set_attrs(size_t bytes) {
   hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_solve),

@@ -79,11 +79,11 @@ __global__ __launch_bounds__(DYN_THREADS) void k_dyn_assemble(DevNet net, Slots 
   const double* qd = s.qd + (size_t)slot * nb;
   double* K = s.K + (size_t)slot * s.k_stride;
   {
-    const size_t total = (size_t)nyc * ldy;
+    const size_t total = (size_t)ny * ldy;
     for (size_t i = tid; i < total; i += DYN_THREADS) K[i] = 0.0;
   }
   __syncthreads();
-#define YY(r, c) K[(size_t)(c) * ldy + (r)]
+#define YY(r, c) K[(size_t)(r) * ldy + (c)]
   const int cth0 = 2 * ng, cv0 = 2 * ng + nb;
   // stator rows
   for (int g = tid; g < ng; g += DYN_THREADS) {
@@ -253,14 +253,17 @@ __global__ __launch_bounds__(DYN_THREADS) void k_form_state(DevNet net, Slots s,
       if (tc == 0 || tc == 2 || tc == 3) {
         const int gi = gl[i], gj = gl[j];
         const int m = (tc == 0) ? 0 : (tc == 2 ? 1 : 2);
-        const double* X = K + (size_t)(ny + 3 * gj + m) * ldy;   // column of X
+        // X = g_y^{-1} g_x sits in columns ny.. of the row-major system
+        const double* X = K + ny + 3 * gj + m;
+#define XR(row) X[(size_t)(row) * ldy]
         switch (sr) {
-          case 1: val -= r[M_fwId] * X[gi] + r[M_fwIq] * X[ng + gi]; break;
-          case 2: val -= r[M_fqId] * X[gi]; break;
-          case 3: val -= r[M_fdIq] * X[ng + gi]; break;
-          case 4: val -= r[M_feV] * X[2 * ng + nb + net.gen_bus[gi]]; break;
+          case 1: val -= r[M_fwId] * XR(gi) + r[M_fwIq] * XR(ng + gi); break;
+          case 2: val -= r[M_fqId] * XR(gi); break;
+          case 3: val -= r[M_fdIq] * XR(ng + gi); break;
+          case 4: val -= r[M_feV] * XR(2 * ng + nb + net.gen_bus[gi]); break;
           default: break;
         }
+#undef XR
       }
     }
     bad |= !__builtin_isfinite(val);

@@ -477,15 +477,15 @@ __global__ __launch_bounds__(OPF_THREADS) void k_opf_eval(DevNet net, Slots s,
   // ---- assemble the KKT system (column-major, rhs in column nk)
   double* K = v.K;
   {
-    const size_t total = (size_t)(nk + 1) * ldk;
+    const size_t total = (size_t)nk * ldk;
     double2* K2 = reinterpret_cast<double2*>(K);
     const double2 zero2 = {0.0, 0.0};
     for (size_t i = tid; i < total / 2; i += OPF_THREADS) K2[i] = zero2;
     if ((total & 1) && tid == 0) K[total - 1] = 0.0;
   }
   __syncthreads();
-  double* rhs = K + (size_t)nk * ldk;
-#define KK(r, c) K[(size_t)(c) * ldk + (r)]
+#define KK(r, c) K[(size_t)(r) * ldk + (c)]
+#define RHS(r) K[(size_t)(r) * ldk + nk]
   bool badw = false;
   for (int b = tid; b < nb; b += OPF_THREADS) {
     const int rt = b, rv = nb + b, rp = nx + b, rq = nx + nb + b;
@@ -536,10 +536,10 @@ __global__ __launch_bounds__(OPF_THREADS) void k_opf_eval(DevNet net, Slots s,
     }
     KK(rv, rv) = Hvv;
     KK(rp, rv) = Jpv; KK(rv, rp) = Jpv; KK(rq, rv) = Jqv; KK(rv, rq) = Jqv;
-    rhs[rt] = isref ? 0.0 : -gN[b];
-    rhs[rv] = -gN[nb + b];
-    rhs[rp] = -gv[b];
-    rhs[rq] = -gv[nb + b];
+    RHS(rt) = isref ? 0.0 : -gN[b];
+    RHS(rv) = -gN[nb + b];
+    RHS(rp) = -gv[b];
+    RHS(rq) = -gv[nb + b];
     badw |= !finite(Htt) || !finite(Htv) || !finite(Hvv);
   }
   for (int g = tid; g < ng; g += OPF_THREADS) {
@@ -554,8 +554,8 @@ __global__ __launch_bounds__(OPF_THREADS) void k_opf_eval(DevNet net, Slots s,
     KK(iq, iq) = dqq;
     KK(nx + k, ip) = -1.0; KK(ip, nx + k) = -1.0;
     KK(nx + nb + k, iq) = -1.0; KK(iq, nx + nb + k) = -1.0;
-    rhs[ip] = -gN[ip];
-    rhs[iq] = -gN[iq];
+    RHS(ip) = -gN[ip];
+    RHS(iq) = -gN[iq];
     badw |= !finite(dpp) || !finite(dqq);
   }
   for (int l = tid; l < nl; l += OPF_THREADS) {
@@ -563,6 +563,7 @@ __global__ __launch_bounds__(OPF_THREADS) void k_opf_eval(DevNet net, Slots s,
     for (int k = 0; k < 10; ++k) badw |= !finite(R[BR_H + k]);
   }
 #undef KK
+#undef RHS
   const double nbw = rmax(badw ? 1.0 : 0.0, red);
   if (tid == 0 && nbw > 0.0) {
     S.status = OPF_NUMERICAL;
@@ -584,9 +585,10 @@ __global__ __launch_bounds__(OPF_THREADS) void k_opf_update(DevNet net, Slots s,
   const int nx = s.nx, nk = s.nk, ldk = s.ldk, ni = s.ni;
   const int tid = threadIdx.x;
   __shared__ double red[OPF_THREADS / 64];
-  extern __shared__ double dz[];            // [ni]
+  extern __shared__ double dz[];            // [ni], then the solution [nk]
+  double* d = dz + ni;
   Views v = views(s, slot, nb, nl, ng);
-  const double* d = v.K + (size_t)nk * ldk; // solution [dx; dlam]
+  for (int i = tid; i < nk; i += OPF_THREADS) d[i] = v.K[(size_t)i * ldk + nk];
   const double gamma = S.gamma;
   const int ref = S.ref_bus;
   bool bad = S.singular != 0;
@@ -722,7 +724,7 @@ void launch_opf_update(const DevNet& net, const Slots& s, int count,
                        double gamma_max, hipStream_t st) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_opf_update, dim3(count), dim3(OPF_THREADS),
-                     sizeof(double) * (size_t)s.ni, st, net, s, count, gamma_max);
+                     sizeof(double) * (size_t)(s.ni + s.nk), st, net, s, count, gamma_max);
 }
 
 }  // namespace cs

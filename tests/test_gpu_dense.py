@@ -26,18 +26,16 @@ def _run_lu(ctx, mats, rhs):
     import torch
     B, n, _ = mats.shape
     k = rhs.shape[2]
-    lda = n + (n % 2)
-    buf = np.zeros((B, n + k, lda))
-    buf[:, :n, :n] = np.transpose(mats, (0, 2, 1))       # column-major
-    buf[:, n:, :n] = np.transpose(rhs, (0, 2, 1))
+    lda = n + k + ((n + k) % 2)
+    buf = np.zeros((B, n, lda))                          # row-major, rhs as columns
+    buf[:, :, :n] = mats
+    buf[:, :, n:n + k] = rhs
     d = _dev(buf)
     info = torch.zeros(B, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
     ctx.dense_solve_batched(d.data_ptr(), n, k, lda, B, info.data_ptr())
     out = d.cpu().numpy()
-    fac = np.transpose(out[:, :n, :n], (0, 2, 1))
-    sol = np.transpose(out[:, n:, :n], (0, 2, 1))
-    return fac, sol, info.cpu().numpy()
+    return out[:, :, :n], out[:, :, n:n + k], info.cpu().numpy()
 
 
 @pytest.mark.parametrize("n,k,B", [(1, 1, 3), (5, 2, 4), (16, 1, 2), (17, 3, 5), (33, 1, 3),
