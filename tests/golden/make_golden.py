@@ -7,6 +7,7 @@ island labels and the Risk Index over that list.
   c1_30:  every N-1 and N-2 branch outage of the 30-bus case (861 scenarios)
   c2_118: every N-1 outage plus a seeded sample of N-2 outages of the
           118-bus-shaped case (a stratified sample; the full list has 57,630)
+  c2_118_full: the whole 57,630-scenario list of the 118-bus-shaped case
 
 Usage: python tests/golden/make_golden.py [case ...]
 """
@@ -28,7 +29,8 @@ from inputs import netgen, contingencies          # noqa: E402
 from oracle import screen, risk                    # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SAMPLES = {"c1_30": None, "c2_118": 600}
+SAMPLES = {"c1_30": None, "c2_118": 600, "c2_118_full": None}
+CASE_OF = {"c2_118_full": "c2_118"}
 _NET = None
 
 
@@ -52,13 +54,17 @@ def case_list(net, name):
 
 
 def make(name, procs=8):
-    path = os.path.join(ROOT, "inputs", "cases", name + ".npz")
+    path = os.path.join(ROOT, "inputs", "cases", CASE_OF.get(name, name) + ".npz")
     net = netgen.load_case(path)
     lst = case_list(net, name)
     with Pool(procs, initializer=_init, initargs=(path,)) as p:
-        res = p.map(_one, list(lst), chunksize=2)
+        res = []
+        for k, r in enumerate(p.imap(_one, list(lst), chunksize=4)):
+            res.append(r)
+            if (k + 1) % 2000 == 0:
+                print(f"{name}: {k + 1}/{len(lst)}", flush=True)
     tab = screen.as_table(res)
-    labels = np.array([r.label for r in res], dtype=np.int32)
+    labels = np.array([r.label for r in res], dtype=np.int16)
     n_comp = int(net["n_branch"]) + int(net["n_gen"]) + int(net["n_load"])
     R = risk.risk_index(lst, tab["severe"], net["lam"], n_comp)
     out = os.path.join(HERE, name + "_oracle.npz")
@@ -67,5 +73,6 @@ def make(name, procs=8):
 
 
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or list(SAMPLES)):
-        make(name)
+    procs = int(os.environ.get("GOLDEN_PROCS", "8"))
+    for name in (sys.argv[1:] or ["c1_30", "c2_118"]):
+        make(name, procs)
