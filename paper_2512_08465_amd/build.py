@@ -3,6 +3,8 @@ from __future__ import annotations
 
 import os
 import subprocess
+
+COMPILE_TIMEOUT_S = 900
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -33,7 +35,12 @@ def build(verbose: bool = False) -> str:
         objs.append(obj)
     ok = True
     for cmd, p in procs:
-        out, _ = p.communicate()
+        try:
+            out, _ = p.communicate(timeout=COMPILE_TIMEOUT_S)
+        except subprocess.TimeoutExpired:
+            p.kill()
+            out, _ = p.communicate()
+            out += f"\ncompilation exceeded {COMPILE_TIMEOUT_S} s and was stopped\n"
         if p.returncode != 0 or verbose:
             sys.stderr.write(" ".join(cmd) + "\n" + out)
         ok &= p.returncode == 0

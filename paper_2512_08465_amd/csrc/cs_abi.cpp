@@ -22,6 +22,7 @@
 
 namespace cs {
 size_t lu_lds_bytes(int n, int nrhs);
+int lu_max_order();
 size_t opf_eval_lds(int nb, int nl, int ng);
 size_t form_state_lds(int ng);
 void launch_setup_k(const DevNet& net, const Slots& s, int count, const int* outages,
@@ -260,7 +261,8 @@ extern "C" int cs_net_create(cs_ctx* ctx, const cs_net_desc* d, cs_net** out) {
     const size_t nk = 4 * (size_t)nb + 2 * (size_t)ng;
     const size_t lim = ctx->lds_max;
     const int ny = 2 * ng + 2 * nb;
-    if (lu_lds_bytes((int)nk, 1) > lim || lu_lds_bytes(ny, 3 * ng) > lim ||
+    if ((int)nk > lu_max_order() || ny > lu_max_order() ||
+        lu_lds_bytes((int)nk, 1) > lim || lu_lds_bytes(ny, 3 * ng) > lim ||
         opf_eval_lds(nb, nl, ng) > lim ||
         form_state_lds(ng) > lim || 8 * (size_t)(2 * nl + 2 * nb + 4 * ng) > lim)
       return fail(CS_EUNSUPPORTED, "cs_net_create: network too large for the on-chip working set (KKT order " +
@@ -673,6 +675,10 @@ extern "C" int cs_dense_solve_batched(const cs_ctx* c, double* d_A, int32_t n, i
                                       int32_t lda, int32_t batch, int32_t* d_info, void* stream) {
   if (!c || !d_A || n <= 0 || nrhs < 0 || lda < n + nrhs || batch < 0)
     return fail(CS_EINVAL, "cs_dense_solve_batched: bad arguments");
+  if (n > lu_max_order())
+    return fail(CS_EUNSUPPORTED, "cs_dense_solve_batched: n = " + std::to_string(n) +
+                                     " above the largest supported order " +
+                                     std::to_string(lu_max_order()));
   if (lu_lds_bytes(n, nrhs) > c->lds_max)
     return fail(CS_EUNSUPPORTED, "cs_dense_solve_batched: n = " + std::to_string(n) +
                                      " needs more LDS than the device allows (" +

@@ -6,140 +6,258 @@
 // n..ncols-1 (an augmented matrix): the forward substitution falls out of the
 // elimination and only the back substitution with U remains.
 //
-// Right-looking blocked LU with panel width NB = 16 and one panel of
-// look-ahead, eight wavefronts per matrix.  The panel being factorised lives
-// in LDS.  Per panel k (its factors in LDS, pivots known):
-//   A. all waves: write the panel back, apply its row interchanges to every
-//      other column (the panel's swaps compose to one permutation of at most
-//      2 NB rows; each thread gathers its column's affected rows, then
-//      scatters them), then form the block row U12 = inv(L11) A12 with MFMA
-//      (inv(L11), the inverse of the panel's unit lower triangle, is built by
-//      wave 0 with the panel);
-//   B. all waves: update the next panel's NB columns with L21 U12, writing the
-//      result straight into the LDS panel buffer;
-//   C. wave 0 factorises that panel in LDS (pivot = first largest |a| in the
-//      column, row swap, scale, rank-1 update; wavefront shuffles only, no
-//      workgroup barrier), while the other waves update the rest of the
-//      trailing matrix, A22 -= L21 U12, with FP64 MFMA (v_mfma_f64_16x16x4f64)
-//      on 32 x 32 groups of four 16 x 16 tiles taken from a shared counter;
-//      wave 0 joins the tile loop when its panel is done.
+// Right-looking blocked LU, panel width NB = 32, eight wavefronts per matrix.
+// Per panel (columns k0 .. k0+kb, factors already in place, pivots known):
+//   A. row interchanges of the panel applied to every other column (the
+//      panel's swaps compose to one permutation of at most 2 NB rows: each
+//      thread gathers its column's affected rows, then scatters them); then
+//      the block row U12 = inv(L11) A12 on MFMA, inv(L11) being the inverse
+//      of the panel's unit lower triangle;
+//   B. the next panel's columns are brought up to date (A -= L21 U12 on
+//      MFMA), passed through LDS in 16-column chunks and loaded into
+//      registers: thread t holds panel rows t and t + 512;
+//   P. that panel is factorised in registers by all threads.  Rows are never
+//      moved while it runs: each keeps its LAPACK position (the position it
+//      would occupy after the interchanges so far) and a "pivoted" flag.  Per
+//      column: a wavefront argmax of |a| (ties to the lower position), one
+//      barrier, the eight wave candidates reduced by every thread, the pivot
+//      row published in LDS, a second barrier, then the rank-1 update of the
+//      rows not yet pivoted.  Finally every row is written to its position;
+//   C. the rest of the trailing matrix, A22 -= L21 U12, with FP64 MFMA
+//      (v_mfma_f64_16x16x4f64) on 32 x 32 groups of four 16 x 16 tiles taken
+//      from an LDS counter.
 // After the last panel, U x = y is solved by 16-row blocks from the bottom.
 #include "cs_internal.h"
 
 #include <algorithm>
+#include <climits>
 
 namespace cs {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int LU_NB = 16;
+constexpr int LU_NB = 32;             // panel width
+constexpr int LU_CW = 16;             // columns per LDS transposition chunk
 constexpr int LU_THREADS = 512;
 constexpr int LU_WAVES = LU_THREADS / 64;
-constexpr int PLD = LU_NB + 1;        // LDS row stride of the panel (bank spread)
-constexpr int LU_NSW = 2 * LU_NB;     // rows a panel's interchanges can touch
+constexpr int LU_R = 2;               // panel rows per thread: n <= LU_R * LU_THREADS
+// LDS chunk layout: row r, column c (< 16) at r * 17 + c (the padding
+// spreads a column over the banks for the row-wise reads)
+constexpr int PLD = LU_CW + 1;
+__device__ inline int chunk_at(int r, int c) { return r * PLD + c; }
+constexpr int LU_KK = LU_NB / 4;      // k-steps of the 16x16x4 MFMA per panel
+constexpr int LU_MAX_N = LU_R * LU_THREADS;
 
-__device__ inline void wave_sync() {
-  // LDS accesses of one wavefront complete in issue order; this only stops
-  // the compiler from moving memory operations across the point.
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+// static LDS of the kernel
+struct LuShared {
+  double rows[LU_NB * LU_NB];   // pivot rows of the panel: [L11 | U11]; U block in the solve
+  double linv[LU_NB * LU_NB];   // inv(L11), row-major
+  double cand_v[LU_WAVES];      // per column, each wavefront's pivot candidate
+  int cand_pos[LU_WAVES];
+  int cand_row[LU_WAVES];
+  int piv[LU_NB];               // relative pivot positions of the panel
+  int bq[LU_NB];                // interchanged rows below the panel's top: position, -1 unused
+  int bs[LU_NB];                //   and the position its new content comes from
+  int moved_row, moved_pos;     // row displaced by the last interchange and its new place
+  int sing, tile;
+};
+
+__device__ inline bool better(double v, int pos, double bv, int bpos) {
+  return v > bv || (v == bv && pos < bpos);
 }
 
-__device__ inline void argmax_combine(double& v, int& i, double v2, int i2) {
-  if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
-}
+// Per-thread state of the panel factorisation.
+struct PanelRows {
+  double v[LU_R][LU_NB];   // panel row tid + 512 s, columns of the panel
+  int pos[LU_R];           // its LAPACK position within the panel
+  bool live[LU_R];         // not yet chosen as a pivot
+};
 
-// Factorise the m x kb panel held in LDS (P, rows relative to the panel's
-// first row r0) with one wavefront.  Pivots (relative) go to spiv[], absolute
-// to piv[]; linv receives the inverse of the panel's unit lower triangle and
-// sw[] the panel's net row permutation as (destination << 16 | source) pairs
-// of relative rows, -1 for unused entries.  ridx[] is scratch of m ints.
-__device__ void panel_factor(double* __restrict__ P, int m, int r0, int kb,
-                             double* __restrict__ linv, int* __restrict__ spiv,
-                             int* __restrict__ piv, int* __restrict__ ridx,
-                             int* __restrict__ sw, int* sing, int lane) {
-  for (int r = lane; r < m; r += 64) ridx[r] = r;
-  wave_sync();
-  for (int j = 0; j < kb; ++j) {
-    double bv = -1.0;
-    int bi = j;
-    for (int r = j + lane; r < m; r += 64) {
-      const double a = fabs(P[r * PLD + j]);
-      if (a > bv) { bv = a; bi = r; }
+// One column J of the panel factorisation (J is a compile-time constant so
+// that every register index is static).  Two workgroup barriers: one after
+// each wavefront has published its best candidate, one after the winning
+// row has been published.
+template <int J>
+__device__ __attribute__((always_inline)) inline void panel_column(
+    PanelRows& R, int m, int r0, int* __restrict__ piv, int* __restrict__ ridx,
+    LuShared& S, int tid) {
+  const int lane = tid & 63, wave = tid >> 6;
+  // --- candidates: largest |a| in column J among rows not yet pivoted
+  double bv = -1.0;
+  int bp = INT_MAX, br = -1;
+#pragma unroll
+  for (int s = 0; s < LU_R; ++s) {
+    // a NaN entry ranks above every number, so a row is always chosen
+    const double x = R.v[s][J];
+    const double a = (x == x) ? fabs(x) : HUGE_VAL;
+    if (R.live[s] && better(a, R.pos[s], bv, bp)) {
+      bv = a;
+      bp = R.pos[s];
+      br = tid + LU_THREADS * s;
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double v2 = __shfl_xor(bv, off, 64);
-      const int i2 = __shfl_xor(bi, off, 64);
-      argmax_combine(bv, bi, v2, i2);
-    }
-    const int p = bi;                 // uniform across the wavefront
-    if (lane == 0) {
-      spiv[j] = p;
-      piv[r0 + j] = r0 + p;
-    }
-    if (p != j) {
-      if (lane < kb) {
-        const double t = P[j * PLD + lane];
-        P[j * PLD + lane] = P[p * PLD + lane];
-        P[p * PLD + lane] = t;
-      } else if (lane == LU_NB) {
-        const int t = ridx[j];
-        ridx[j] = ridx[p];
-        ridx[p] = t;
-      }
-    }
-    wave_sync();
-    const double pv = P[j * PLD + j];
-    if (pv == 0.0) {
-      if (lane == 0) *sing = 1;
-    } else {
-      const double inv = 1.0 / pv;
-      for (int r = j + 1 + lane; r < m; r += 64) {
-        double* row = P + r * PLD;
-        const double l = row[j] * inv;
-        row[j] = l;
-        for (int c = j + 1; c < kb; ++c) row[c] -= l * P[j * PLD + c];
-      }
-    }
-    wave_sync();
   }
-  // net permutation: position t < kb now holds original row ridx[t]; a pivot
-  // position q = spiv[t] >= kb holds ridx[q] (counted once if repeated)
-  if (lane < LU_NB) {
-    const int t = lane;
-    int e0 = -1, e1 = -1;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double v2 = __shfl_xor(bv, off, 64);
+    const int p2 = __shfl_xor(bp, off, 64);
+    const int r2 = __shfl_xor(br, off, 64);
+    if (better(v2, p2, bv, bp)) {
+      bv = v2;
+      bp = p2;
+      br = r2;
+    }
+  }
+  if (lane == 0) {
+    S.cand_v[wave] = bv;
+    S.cand_pos[wave] = bp;
+    S.cand_row[wave] = br;
+  }
+  __syncthreads();
+  bv = S.cand_v[0];
+  bp = S.cand_pos[0];
+  br = S.cand_row[0];
+#pragma unroll
+  for (int w = 1; w < LU_WAVES; ++w) {
+    const double v2 = S.cand_v[w];
+    const int p2 = S.cand_pos[w];
+    if (better(v2, p2, bv, bp)) {
+      bv = v2;
+      bp = p2;
+      br = S.cand_row[w];
+    }
+  }
+  // --- publish the pivot row; LAPACK interchanges positions J and bp
+#pragma unroll
+  for (int s = 0; s < LU_R; ++s) {
+    if (br == tid + LU_THREADS * s) {
+#pragma unroll
+      for (int c = 0; c < LU_NB; ++c) S.rows[J * LU_NB + c] = R.v[s][c];
+      R.live[s] = false;
+      R.pos[s] = J;
+    }
+  }
+  if (tid == 0 && bp >= J && bp < m) {
+    const int q = ridx[J];
+    ridx[J] = br;
+    ridx[bp] = q;
+    S.moved_row = q;
+    S.moved_pos = bp;
+    S.piv[J] = bp;
+    piv[r0 + J] = r0 + bp;
+    if (bv == 0.0) S.sing = 1;
+  }
+  __syncthreads();
+  const int q = S.moved_row;
+  const int qp = S.moved_pos;
+#pragma unroll
+  for (int s = 0; s < LU_R; ++s)
+    if (q == tid + LU_THREADS * s && R.live[s]) R.pos[s] = qp;
+  // --- scale and rank-1 update of the rows not yet pivoted
+  const double pv = S.rows[J * LU_NB + J];
+  if (pv != 0.0) {
+    const double inv = 1.0 / pv;
+#pragma unroll
+    for (int s = 0; s < LU_R; ++s) {
+      if (R.live[s]) {
+        const double l = R.v[s][J] * inv;
+        R.v[s][J] = l;
+#pragma unroll
+        for (int c = J + 1; c < LU_NB; ++c) R.v[s][c] -= l * S.rows[J * LU_NB + c];
+      }
+    }
+  }
+}
+
+template <int J>
+struct PanelColumns {
+  static __device__ __attribute__((always_inline)) inline void run(
+      PanelRows& R, int m, int r0, int kb, int* piv, int* ridx, LuShared& S, int tid) {
+    if (J < kb) {
+      panel_column<J>(R, m, r0, piv, ridx, S, tid);
+      PanelColumns<J + 1>::run(R, m, r0, kb, piv, ridx, S, tid);
+    }
+  }
+};
+template <>
+struct PanelColumns<LU_NB> {
+  static __device__ __attribute__((always_inline)) inline void run(
+      PanelRows&, int, int, int, int*, int*, LuShared&, int) {}
+};
+
+// Factorise the m x kb panel whose rows sit in R.v (row tid + 512 s of the
+// panel, relative to its first row r0) with all threads of the workgroup.
+// Rows are never moved while it runs: each keeps its LAPACK position (the
+// position it would occupy after the interchanges so far) and a "pivoted"
+// flag.  Writes the factored rows to A at their pivoted positions, the
+// pivots to piv[] (absolute) and S.piv (relative), L11/U11 to S.rows,
+// inv(L11) to S.linv and the rows interchanged below the panel's top to
+// S.bq / S.bs.  ridx[] is LDS scratch of m ints.
+__device__ __attribute__((always_inline)) inline void factor_panel(
+    PanelRows& R, int m, int r0, int kb, double* __restrict__ A, int lda,
+    int* __restrict__ piv, int* __restrict__ ridx, LuShared& S, int tid) {
+#pragma unroll
+  for (int s = 0; s < LU_R; ++s) {
+    R.pos[s] = tid + LU_THREADS * s;
+    R.live[s] = R.pos[s] < m;
+  }
+  for (int r = tid; r < m; r += LU_THREADS) ridx[r] = r;
+  __syncthreads();
+  PanelColumns<0>::run(R, m, r0, kb, piv, ridx, S, tid);
+  // every row to its pivoted position (columns r0 .. r0+kb)
+#pragma unroll
+  for (int s = 0; s < LU_R; ++s) {
+    const int r = tid + LU_THREADS * s;
+    if (r < m) {
+      double* dst = A + (size_t)(r0 + R.pos[s]) * lda + r0;
+#pragma unroll
+      for (int c = 0; c < LU_NB; ++c)
+        if (c < kb) dst[c] = R.v[s][c];
+    }
+  }
+  __syncthreads();
+  // net permutation: position t < kb now holds the row that was at
+  // position ridx[t]; a pivot position q = piv[t] >= kb holds ridx[q]
+  // (listed once if repeated)
+  if (tid < LU_NB) {
+    const int t = tid;
+    int q = -1, src = 0;
     if (t < kb) {
-      if (ridx[t] != t) e0 = (t << 16) | ridx[t];
-      const int q = spiv[t];
-      bool first = q >= kb;
-      for (int u = 0; u < t; ++u) first = first && spiv[u] != q;
-      if (first && ridx[q] != q) e1 = (q << 16) | ridx[q];
+      const int p = S.piv[t];
+      bool first = p >= kb;
+      for (int u = 0; u < t; ++u) first = first && S.piv[u] != p;
+      if (first && ridx[p] != p) {
+        q = p;
+        src = ridx[p];
+      }
     }
-    sw[2 * t] = e0;
-    sw[2 * t + 1] = e1;
+    S.bq[t] = q;
+    S.bs[t] = src;
   }
-  // inverse of the unit lower triangle L11 (kb x kb, identity-padded to 16):
-  // lane j forms column j by forward substitution
-  if (lane < LU_NB) {
-    const int j = lane;
+  // inv(L11), identity-padded to NB: thread j forms column j by forward
+  // substitution in registers
+  if (tid >= 64 && tid < 64 + LU_NB) {
+    const int j = tid - 64;
+    double x[LU_NB];
+#pragma unroll
     for (int i = 0; i < LU_NB; ++i) {
       double v = (i == j) ? 1.0 : 0.0;
-      if (i > j && i < kb) {
-        v = 0.0;
-        for (int k = j; k < i; ++k) v -= P[i * PLD + k] * linv[k * LU_NB + j];
+      if (i < kb) {
+#pragma unroll
+        for (int k = 0; k < i; ++k) v -= S.rows[i * LU_NB + k] * x[k];
       }
-      linv[i * LU_NB + j] = v;
+      x[i] = (i < j) ? 0.0 : v;
     }
+#pragma unroll
+    for (int i = 0; i < LU_NB; ++i) S.linv[i * LU_NB + j] = x[i];
   }
-  wave_sync();
 }
 
 // C[i0:i0+16, j0:j0+16] - L21[i0:, k0:k0+kb] U12[k0:k0+kb, j0:] (global
-// rows) for rows < n and columns < ncols; the result goes to the LDS panel
-// buffer P (rows relative to j0, which is also the panel's first row)
-__device__ inline void update_tile_to_panel(const double* __restrict__ A, int lda, int n,
-                                            int ncols, int k0, int kb, int i0, int j0,
-                                            double* __restrict__ P, int lane) {
+// rows) for rows < n and columns < ncols, written to the LDS chunk buffer
+// (rows relative to r0, columns relative to j0)
+__device__ inline void update_tile_to_lds(const double* __restrict__ A, int lda, int n,
+                                          int ncols, int k0, int kb, int i0, int j0, int r0,
+                                          double* __restrict__ P, int lane) {
   const int li = lane & 15, lk = lane >> 4;
   // accumulator layout of the f64 16x16x4 MFMA: lane l, register q holds
   // D[l/16 + 4q][l%16]; D is the tile itself, so 16 lanes cover 16
@@ -155,25 +273,25 @@ __device__ inline void update_tile_to_panel(const double* __restrict__ A, int ld
   const int arow = i0 + li;
   const bool aok = arow < n;
   const double* lrow = A + (size_t)arow * lda + k0;
-  double a[LU_NB / 4], b[LU_NB / 4];
+  double a[LU_KK], b[LU_KK];
 #pragma unroll
-  for (int kk = 0; kk < LU_NB / 4; ++kk) {
+  for (int kk = 0; kk < LU_KK; ++kk) {
     const int k = 4 * kk + lk;
     a[kk] = (k < kb && aok) ? -lrow[k] : 0.0;
     b[kk] = (k < kb && cok) ? A[(size_t)(k0 + k) * lda + col] : 0.0;
   }
 #pragma unroll
-  for (int kk = 0; kk < LU_NB / 4; ++kk)
+  for (int kk = 0; kk < LU_KK; ++kk)
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk], acc, 0, 0, 0);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int row = i0 + lk + 4 * q;
-    if (cok && row < n) P[(row - j0) * PLD + li] = acc[q];
+    if (cok && row < n) P[chunk_at(row - r0, li)] = acc[q];
   }
 }
 
-// The same update on a 32 x 32 group of four tiles: all 32 loads of a lane
-// are issued together and every L21 / U12 operand feeds two MFMAs.
+// The trailing update on a 32 x 32 group of four tiles, in place: all loads
+// of a lane are issued together and every L21 / U12 operand feeds two MFMAs.
 __device__ inline void update_group(double* __restrict__ A, int lda, int n, int ncols,
                                     int k0, int kb, int i0, int j0, int lane) {
   const int li = lane & 15, lk = lane >> 4;
@@ -194,13 +312,13 @@ __device__ inline void update_group(double* __restrict__ A, int lda, int n, int 
         const int row = i0 + 16 * ti + lk + 4 * q;
         acc[ti][tj][q] = (cok[tj] && row < n) ? A[(size_t)row * lda + col[tj]] : 0.0;
       }
-  double a[2][LU_NB / 4], b[2][LU_NB / 4];
+  double a[2][LU_KK], b[2][LU_KK];
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti) {
     const int arow = i0 + 16 * ti + li;
     const double* lrow = A + (size_t)arow * lda + k0;
 #pragma unroll
-    for (int kk = 0; kk < LU_NB / 4; ++kk) {
+    for (int kk = 0; kk < LU_KK; ++kk) {
       const int k = 4 * kk + lk;
       a[ti][kk] = (k < kb && arow < n) ? -lrow[k] : 0.0;
     }
@@ -208,12 +326,12 @@ __device__ inline void update_group(double* __restrict__ A, int lda, int n, int 
 #pragma unroll
   for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
-    for (int kk = 0; kk < LU_NB / 4; ++kk) {
+    for (int kk = 0; kk < LU_KK; ++kk) {
       const int k = 4 * kk + lk;
       b[tj][kk] = (k < kb && cok[tj]) ? A[(size_t)(k0 + k) * lda + col[tj]] : 0.0;
     }
 #pragma unroll
-  for (int kk = 0; kk < LU_NB / 4; ++kk)
+  for (int kk = 0; kk < LU_KK; ++kk)
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -242,130 +360,164 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
   const int lane = tid & 63;
   const int wave = tid >> 6;
 
-  extern __shared__ double P[];          // panel rows, stride PLD; then ridx
+  extern __shared__ double P[];          // a 16-column chunk (chunk_at); then ridx
   int* ridx = reinterpret_cast<int*>(P + (size_t)PLD * n);
-  __shared__ int s_piv[LU_NB];
-  __shared__ int s_sw[LU_NSW];
-  __shared__ int s_sing;
-  __shared__ int s_tile;
-  __shared__ double s_ub[LU_NB * LU_NB];
-  __shared__ double s_linv[LU_NB * LU_NB];
-  if (tid == 0) s_sing = 0;
-  {
-    const int kb = min(LU_NB, n);
-    for (int e = tid; e < n * kb; e += LU_THREADS) {
-      const int r = e / kb, c = e - r * kb;
-      P[r * PLD + c] = A[(size_t)r * lda + c];
-    }
+  __shared__ LuShared S;
+  if (tid == 0) {
+    S.sing = 0;
+    S.tile = 0;
   }
   __syncthreads();
-  if (wave == 0)
-    panel_factor(P, n, 0, min(LU_NB, n), s_linv, s_piv, piv, ridx, s_sw, &s_sing, lane);
-  __syncthreads();
-
+  PanelRows R;
+  int kp = 0, kbp = 0;                   // previous panel
   for (int k0 = 0; k0 < n; k0 += LU_NB) {
     const int kb = min(LU_NB, n - k0);
     const int m = n - k0;
     const int r0 = k0 + kb;
-    // ---- A: write the panel back, interchanges, TRSM of the block row
-    for (int e = tid; e < m * kb; e += LU_THREADS) {
-      const int r = e / kb, c = e - r * kb;
-      A[(size_t)(k0 + r) * lda + k0 + c] = P[r * PLD + c];
-    }
-    {
-      int sw[LU_NSW];
+    // ---- B: panel columns [k0, k0+kb) into registers: straight from memory
+    // for the first panel, else after the previous panel's update (MFMA),
+    // through LDS in 16-column chunks
+    if (k0 == 0) {
 #pragma unroll
-      for (int e = 0; e < LU_NSW; ++e) sw[e] = s_sw[e];
-      for (int c = tid; c < ncols; c += LU_THREADS) {
-        if (c >= k0 && c < r0) continue;
-        double* colp = A + (size_t)k0 * lda + c;
-        double v[LU_NSW];
+      for (int s = 0; s < LU_R; ++s) {
+        const int r = tid + LU_THREADS * s;
 #pragma unroll
-        for (int e = 0; e < LU_NSW; ++e)
-          v[e] = (sw[e] >= 0) ? colp[(size_t)(sw[e] & 0xffff) * lda] : 0.0;
-#pragma unroll
-        for (int e = 0; e < LU_NSW; ++e)
-          if (sw[e] >= 0) colp[(size_t)(sw[e] >> 16) * lda] = v[e];
+        for (int c = 0; c < LU_NB; ++c)
+          R.v[s][c] = (r < n && c < kb) ? A[(size_t)r * lda + c] : 0.0;
       }
-    }
-    __syncthreads();
-    // U12 = inv(L11) A12 on MFMA, one 16-column tile per wavefront pass
-    {
-      const int li = lane & 15, lk = lane >> 4;
-      const int ntc = (ncols - r0 + 15) >> 4;
-      for (int t = wave; t < ntc; t += LU_WAVES) {
-        const int col = r0 + 16 * t + li;
-        const bool cok = col < ncols;
-        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-        double a[LU_NB / 4], b[LU_NB / 4];
+    } else {
+      const int tr = (m + 15) >> 4;
 #pragma unroll
-        for (int kk = 0; kk < LU_NB / 4; ++kk) {
-          const int k = 4 * kk + lk;
-          a[kk] = s_linv[li * LU_NB + k];
-          b[kk] = (cok && k < kb) ? A[(size_t)(k0 + k) * lda + col] : 0.0;
-        }
+      for (int ch = 0; ch < LU_NB; ch += LU_CW) {
+        if (ch < kb) {
+          const int cend = k0 + min(kb, ch + LU_CW);
+          for (int t = wave; t < tr; t += LU_WAVES)
+            update_tile_to_lds(A, lda, n, cend, kp, kbp, k0 + 16 * t, k0 + ch, k0, P, lane);
+          __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < LU_NB / 4; ++kk)
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk], acc, 0, 0, 0);
+          for (int s = 0; s < LU_R; ++s) {
+            const int r = tid + LU_THREADS * s;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int row = lk + 4 * q;
-          if (cok && row < kb) A[(size_t)(k0 + row) * lda + col] = acc[q];
+            for (int c = 0; c < LU_CW; ++c)
+              R.v[s][ch + c] = (r < m && ch + c < kb) ? P[chunk_at(r, c)] : 0.0;
+          }
+          __syncthreads();
+        } else {
+#pragma unroll
+          for (int s = 0; s < LU_R; ++s)
+#pragma unroll
+            for (int c = 0; c < LU_CW; ++c) R.v[s][ch + c] = 0.0;
         }
       }
     }
-    if (tid == 0) s_tile = 0;
-    __syncthreads();
-    if (r0 >= n) break;     // last panel: the right-hand sides were done by TRSM
-    // ---- B: bring the next panel's columns up to date, into LDS
-    const int kb2 = min(LU_NB, n - r0);
-    const int tr = (n - r0 + 15) >> 4;
-    for (int t = wave; t < tr; t += LU_WAVES)   // columns [r0, r0 + kb2) only
-      update_tile_to_panel(A, lda, n, r0 + kb2, k0, kb, r0 + 16 * t, r0, P, lane);
-    __syncthreads();
-    // ---- C: wave 0 factorises the next panel; everyone updates the rest
-    if (wave == 0)
-      panel_factor(P, n - r0, r0, kb2, s_linv, s_piv, piv, ridx, s_sw, &s_sing, lane);
-    const int c2 = r0 + kb2;
-    if (c2 < ncols) {
-      const int gr = (n - r0 + 31) >> 5;
-      const int gc = (ncols - c2 + 31) >> 5;
+    // ---- P: factorise the panel
+    factor_panel(R, m, k0, kb, A, lda, piv, ridx, S, tid);
+    // ---- C: the rest of the previous panel's trailing update (columns
+    // right of this panel), independent of this panel's factors
+    if (k0 > 0 && r0 < ncols) {
+      const int gr = (m + 31) >> 5;
+      const int gc = (ncols - r0 + 31) >> 5;
       const int ngroups = gr * gc;
       while (true) {
         int t = 0;
-        if (lane == 0) t = atomicAdd(&s_tile, 1);
+        if (lane == 0) t = atomicAdd(&S.tile, 1);
         t = __shfl(t, 0, 64);
         if (t >= ngroups) break;
         const int ti = t % gr, tj = t / gr;
-        update_group(A, lda, n, ncols, k0, kb, r0 + 32 * ti, c2 + 32 * tj, lane);
+        update_group(A, lda, n, ncols, kp, kbp, k0 + 32 * ti, r0 + 32 * tj, lane);
       }
     }
     __syncthreads();
+    // ---- A: interchanges outside the panel, fused with U12 = inv(L11) A12.
+    // A wavefront takes 16 columns: it gathers the kb rows that end up on
+    // top (position t comes from position ridx[t]) and the interchanged rows
+    // below, then writes the latter back and the former either as they are
+    // (columns left of the panel) or multiplied by inv(L11) (to the right).
+    {
+      const int li = lane & 15, lk = lane >> 4;
+      const int ntl = k0 >> 4;                       // tiles left of the panel
+      const int ntr = (ncols - r0 + 15) >> 4;        // tiles right of it
+      int top[LU_KK], bq[LU_KK], bsrc[LU_KK];
+#pragma unroll
+      for (int kk = 0; kk < LU_KK; ++kk) {
+        const int k = 4 * kk + lk;
+        top[kk] = (k < kb) ? ridx[k] : k;
+        bq[kk] = S.bq[k];
+        bsrc[kk] = S.bs[k];
+      }
+      for (int t = wave; t < ntl + ntr; t += LU_WAVES) {
+        const bool right = t >= ntl;
+        const int col = right ? r0 + 16 * (t - ntl) + li : 16 * t + li;
+        const bool cok = col < ncols;
+        const double* colp = A + (size_t)k0 * lda + col;
+        double b[LU_KK], v[LU_KK];
+#pragma unroll
+        for (int kk = 0; kk < LU_KK; ++kk) {
+          const int k = 4 * kk + lk;
+          b[kk] = (cok && k < kb) ? colp[(size_t)top[kk] * lda] : 0.0;
+          v[kk] = (cok && bq[kk] >= 0) ? colp[(size_t)bsrc[kk] * lda] : 0.0;
+        }
+        // lanes write rows that other lanes of this wavefront read: every
+        // load has returned before the first store
+        __builtin_amdgcn_s_waitcnt(0);
+        double* colw = A + (size_t)k0 * lda + col;
+#pragma unroll
+        for (int kk = 0; kk < LU_KK; ++kk)
+          if (cok && bq[kk] >= 0) colw[(size_t)bq[kk] * lda] = v[kk];
+        if (!right) {
+#pragma unroll
+          for (int kk = 0; kk < LU_KK; ++kk) {
+            const int k = 4 * kk + lk;
+            if (cok && k < kb) colw[(size_t)k * lda] = b[kk];
+          }
+        } else {
+          dbl4 acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+          for (int kk = 0; kk < LU_KK; ++kk)
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti)
+              acc[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                  S.linv[(16 * ti + li) * LU_NB + 4 * kk + lk], b[kk], acc[ti], 0, 0, 0);
+#pragma unroll
+          for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int row = 16 * ti + lk + 4 * q;
+              if (cok && row < kb) colw[(size_t)row * lda] = acc[ti][q];
+            }
+        }
+      }
+    }
+    if (tid == 0) S.tile = 0;
+    __syncthreads();
+    kp = k0;
+    kbp = kb;
   }
 
   // ---- back substitution U x = y for the right-hand-side columns, by
   // 16-row blocks from the bottom.  A wavefront solves a diagonal block for
   // one right-hand side at a time (lane i holds row i; x_i is broadcast and
   // eliminated from the rows above), the block solution is kept in LDS (the
-  // panel buffer is free now), then every row above is updated.
+  // chunk buffer is free now), then every row above is updated.
   const int nrhs = ncols - n;
   if (nrhs > 0) {
     double* xs = P;                                 // [16][nrhs]
-    const int nblk = (n + LU_NB - 1) / LU_NB;
+    double* ub = S.rows;                            // [16][16]
+    const int nblk = (n + 15) / 16;
     for (int b = nblk - 1; b >= 0; --b) {
-      const int b0 = b * LU_NB;
-      const int bs = min(LU_NB, n - b0);
-      for (int e = tid; e < LU_NB * LU_NB; e += LU_THREADS) {
-        const int i = e / LU_NB, j = e % LU_NB;
-        s_ub[e] = (i < bs && j < bs) ? A[(size_t)(b0 + i) * lda + b0 + j] : 0.0;
+      const int b0 = b * 16;
+      const int bs = min(16, n - b0);
+      for (int e = tid; e < 256; e += LU_THREADS) {
+        const int i = e >> 4, j = e & 15;
+        ub[e] = (i < bs && j < bs) ? A[(size_t)(b0 + i) * lda + b0 + j] : 0.0;
       }
       __syncthreads();
       for (int rc = wave; rc < nrhs; rc += LU_WAVES) {
         double y = (lane < bs) ? A[(size_t)(b0 + lane) * lda + n + rc] : 0.0;
         for (int i = bs - 1; i >= 0; --i) {
-          const double xi = __shfl(y, i, 64) / s_ub[i * LU_NB + i];
+          const double xi = __shfl(y, i, 64) / ub[i * 16 + i];
           if (lane == i) y = xi;
-          if (lane < i) y -= s_ub[lane * LU_NB + i] * xi;
+          if (lane < i) y -= ub[lane * 16 + i] * xi;
         }
         if (lane < bs) {
           xs[lane * nrhs + rc] = y;
@@ -376,7 +528,7 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
       // y[0:b0] -= U[0:b0, b0:b0+bs] x[b0:b0+bs]
       const int work = b0 * nrhs;
       for (int e = tid; e < work; e += LU_THREADS) {
-        const int i = e / nrhs, rc = e % nrhs;
+        const int i = e / nrhs, rc = e - i * nrhs;
         const double* urow = A + (size_t)i * lda + b0;
         double acc = A[(size_t)i * lda + n + rc];
         for (int j = 0; j < bs; ++j) acc -= urow[j] * xs[j * nrhs + rc];
@@ -386,24 +538,26 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
     }
   }
   if (tid == 0) {
-    if (st != nullptr) st[slot].singular = s_sing;
-    if (info != nullptr) info[slot] = s_sing;
+    if (st != nullptr) st[slot].singular = S.sing;
+    if (info != nullptr) info[slot] = S.sing;
   }
 }
 
 // static LDS of k_lu_solve
-constexpr size_t LU_STATIC_LDS =
-    sizeof(int) * (LU_NB + LU_NSW + 2) + sizeof(double) * 2 * LU_NB * LU_NB;
+constexpr size_t LU_STATIC_LDS = sizeof(LuShared);
 
-// dynamic LDS: panel rows and their row-index scratch during the
-// factorisation; a 16 x nrhs block during the solve
+// dynamic LDS: a 16-column chunk of panel rows and the panel's row-index
+// scratch during the factorisation; a 16 x nrhs block during the solve
 static size_t lu_dynamic_lds(int n, int nrhs) {
   return std::max(sizeof(double) * (size_t)PLD * (size_t)n + sizeof(int) * (size_t)n,
-                  sizeof(double) * (size_t)LU_NB * (size_t)nrhs);
+                  sizeof(double) * (size_t)16 * (size_t)nrhs);
 }
 
 // total LDS one workgroup of k_lu_solve needs for order n and nrhs columns
 size_t lu_lds_bytes(int n, int nrhs) { return lu_dynamic_lds(n, nrhs) + LU_STATIC_LDS; }
+
+// largest order k_lu_solve handles (panel rows are held in registers)
+int lu_max_order() { return LU_MAX_N; }
 
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
                      int* piv, int piv_stride, SlotState* st, int count,
@@ -413,8 +567,6 @@ void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
   hipLaunchKernelGGL(k_lu_solve, dim3(count), dim3(LU_THREADS), lds, stream,
                      A, stride, n, ncols, lda, piv, piv_stride, st, info);
 }
-
-
 
 void lu_set_attrs(size_t bytes) {
   hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_solve),

@@ -38,8 +38,9 @@ def _run_lu(ctx, mats, rhs):
     return out[:, :, :n], out[:, :, n:n + k], info.cpu().numpy()
 
 
-@pytest.mark.parametrize("n,k,B", [(1, 1, 3), (5, 2, 4), (16, 1, 2), (17, 3, 5), (33, 1, 3),
-                                   (131, 1, 4), (344, 162, 2), (580, 1, 3)])
+@pytest.mark.parametrize("n,k,B", [(1, 1, 3), (5, 2, 4), (16, 1, 2), (17, 3, 5), (32, 1, 2),
+                                   (33, 1, 3), (64, 2, 2), (65, 1, 2), (131, 1, 4), (200, 7, 2),
+                                   (344, 162, 2), (513, 1, 2), (580, 1, 3), (1024, 1, 1)])
 def test_lu_solve_matches_scipy(ctx, n, k, B):
     rng = np.random.default_rng(n * 100 + k)
     A = rng.standard_normal((B, n, n))
@@ -54,6 +55,20 @@ def test_lu_solve_matches_scipy(ctx, n, k, B):
         ref = sla.lu_solve((lu, piv), Bm[b])
         cond = np.linalg.cond(A[b])
         assert np.max(np.abs(sol[b] - ref)) <= 1e-13 * cond * max(1.0, np.abs(ref).max())
+
+
+def test_lu_pivot_ties_go_to_the_first_row(ctx):
+    """Equal |a| in a column: the pivot is the first such row, as in LAPACK."""
+    rng = np.random.default_rng(11)
+    n, B = 150, 2
+    A = rng.standard_normal((B, n, n))
+    A[:, :, 0] = rng.choice([-1.0, 1.0, 0.5], size=(B, n))
+    X = rng.standard_normal((B, n, 1))
+    fac, sol, info = _run_lu(ctx, A, A @ X)
+    assert np.all(info == 0)
+    for b in range(B):
+        lu, piv = sla.lu_factor(A[b])
+        assert np.allclose(fac[b], lu, rtol=1e-9, atol=1e-9 * np.abs(lu).max())
 
 
 def test_lu_saddle_point_needs_pivoting(ctx):
