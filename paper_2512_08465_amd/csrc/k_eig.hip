@@ -5,7 +5,10 @@
 // (left update: one wavefront per column, lanes over rows; right update: one
 // thread per row), then Francis implicit double-shift QR sweeps run on the
 // active window [lo, hi] until every 1x1 or 2x2 diagonal block has split off
-// (eigenvalues only, so updates stay inside the window).  Deflation: a
+// (eigenvalues only, so updates stay inside the window).  A sweep chases its
+// bulge in blocks of 16 steps through a small diagonal block held in LDS and
+// applies the accumulated reflectors to the rest of the window once per
+// block.  Deflation: a
 // subdiagonal entry is negligible when |h(k,k-1)| <= eps (|h(k-1,k-1)| +
 // |h(k,k)|).  Every tenth sweep without deflation uses an exceptional shift.
 // The matrix lives in global memory (column-major, lda), and the reflector
@@ -110,48 +113,137 @@ __device__ void hessenberg(double* __restrict__ H, int n, int lda, double* u,
   }
 }
 
-// apply the reflector I - 2 v v^T / (v^T v) of length 3 (or 2) from the left
-// to rows k..k+len-1 over columns [c0, c1], and from the right to columns
-// k..k+len-1 over rows [r0, r1].
-__device__ inline void reflect(double* __restrict__ H, int lda, int k, int len,
-                               const double v0, const double v1, const double v2,
-                               int c0, int c1, int r0, int r1) {
-  const int tid = threadIdx.x;
-  const double vv = v0 * v0 + v1 * v1 + v2 * v2;
-  const double t = 2.0 / vv;
-  for (int c = c0 + tid; c <= c1; c += EIG_THREADS) {
-    double* p = H + (size_t)c * lda + k;
-    double a0 = p[0], a1 = p[1], a2 = (len == 3) ? p[2] : 0.0;
-    double s = t * (v0 * a0 + v1 * a1 + v2 * a2);
-    p[0] = a0 - s * v0;
-    p[1] = a1 - s * v1;
-    if (len == 3) p[2] = a2 - s * v2;
-  }
-  __syncthreads();
-  for (int r = r0 + tid; r <= r1; r += EIG_THREADS) {
-    double* p = H + (size_t)k * lda + r;
-    double a0 = p[0], a1 = p[lda], a2 = (len == 3) ? p[2 * (size_t)lda] : 0.0;
-    double s = t * (a0 * v0 + a1 * v1 + a2 * v2);
-    p[0] = a0 - s * v0;
-    p[lda] = a1 - s * v1;
-    if (len == 3) p[2 * (size_t)lda] = a2 - s * v2;
-  }
-  __syncthreads();
-}
+// Bulge chasing in blocks.  A block covers QR_NB consecutive bulge steps
+// k0 .. kend-1; every row and column those steps touch inside the window
+// lies in the index range [c0, c1] (plus the row c1 + 1, which the last
+// step's right-hand update reaches).  That diagonal block is chased in LDS by
+// one wavefront while the reflectors are accumulated into U (P_k0 ... P_kend-1);
+// afterwards the rest of the window gets them in one pass each:
+//   rows c0..c1, columns c1+1..hi:  H <- U^T H
+//   rows lo..c0-1, columns c0..c1:  H <- H U
+constexpr int QR_NB = 16;
+constexpr int QR_D = QR_NB + 3;      // block order
+constexpr int QR_LD = QR_D + 1;      // LDS row stride of the block and of U
 
-__device__ inline void house3(double x, double y, double z, double& v0,
-                              double& v1, double& v2, bool& ok) {
-  const double nv = sqrt(x * x + y * y + z * z);
-  ok = nv != 0.0;
-  v0 = x + copysign(nv, x);
-  v1 = y;
-  v2 = z;
+// one Francis double-shift sweep over the window [lo, hi] (hi - lo >= 2)
+__device__ void francis_sweep(double* __restrict__ H, int lda, int lo, int hi,
+                              double x, double y, double z,
+                              double* __restrict__ D, double* __restrict__ U) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#define HH(i, j) H[(size_t)(j) * lda + (i)]
+  for (int k0 = lo; k0 <= hi - 1; k0 += QR_NB) {
+    const int kend = min(k0 + QR_NB, hi);        // steps k0 .. kend-1
+    const int c0 = max(lo, k0 - 1);
+    const int c1 = min(kend + 1, hi);
+    const int d = c1 - c0 + 1;
+    const int dr = d + (c1 < hi ? 1 : 0);
+    for (int e = tid; e < dr * d; e += EIG_THREADS) {
+      const int r = e / d, c = e - r * d;
+      D[r * QR_LD + c] = HH(c0 + r, c0 + c);
+    }
+    // the whole QR_D x QR_D tile: the off-block products read every entry
+    for (int e = tid; e < QR_D * QR_D; e += EIG_THREADS) {
+      const int r = e / QR_D, c = e - r * QR_D;
+      U[r * QR_LD + c] = (r == c && r < d) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      for (int k = k0; k < kend; ++k) {
+        const int j = k - c0;
+        const bool three = k < hi - 1;
+        if (k > lo) {
+          x = D[j * QR_LD + j - 1];
+          y = D[(j + 1) * QR_LD + j - 1];
+          z = three ? D[(j + 2) * QR_LD + j - 1] : 0.0;
+        }
+        const double nv = three ? sqrt(x * x + y * y + z * z) : sqrt(x * x + y * y);
+        if (nv != 0.0) {
+          const double v0 = x + copysign(nv, x), v1 = y, v2 = three ? z : 0.0;
+          const double t = 2.0 / (v0 * v0 + v1 * v1 + v2 * v2);
+          // from the left: rows j..j+2, columns max(lo, k-1) .. c1; the
+          // bulge column k-1 becomes exactly (-sign(x) |(x,y,z)|, 0, 0)
+          const int q = max(lo, k - 1) - c0;
+          if (lane >= q && lane < d) {
+            double* p = D + j * QR_LD + lane;
+            const double a0 = p[0], a1 = p[QR_LD], a2 = three ? p[2 * QR_LD] : 0.0;
+            const double sv = t * (v0 * a0 + v1 * a1 + v2 * a2);
+            double b0 = a0 - sv * v0, b1 = a1 - sv * v1, b2 = a2 - sv * v2;
+            if (k > lo && lane == j - 1) {
+              b0 = -copysign(nv, x);
+              b1 = 0.0;
+              b2 = 0.0;
+            }
+            p[0] = b0;
+            p[QR_LD] = b1;
+            if (three) p[2 * QR_LD] = b2;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          // from the right: columns j..j+2, rows c0 .. min(k+3, hi); and U
+          const int rl = min(k + 3, hi) - c0;
+          if (lane <= rl) {
+            double* p = D + lane * QR_LD + j;
+            const double a0 = p[0], a1 = p[1], a2 = three ? p[2] : 0.0;
+            const double sv = t * (a0 * v0 + a1 * v1 + a2 * v2);
+            p[0] = a0 - sv * v0;
+            p[1] = a1 - sv * v1;
+            if (three) p[2] = a2 - sv * v2;
+          }
+          if (lane < d) {
+            double* p = U + lane * QR_LD + j;
+            const double a0 = p[0], a1 = p[1], a2 = three ? p[2] : 0.0;
+            const double sv = t * (a0 * v0 + a1 * v1 + a2 * v2);
+            p[0] = a0 - sv * v0;
+            p[1] = a1 - sv * v1;
+            if (three) p[2] = a2 - sv * v2;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < dr * d; e += EIG_THREADS) {
+      const int r = e / d, c = e - r * d;
+      HH(c0 + r, c0 + c) = D[r * QR_LD + c];
+    }
+    // rows c0..c1 right of the block: H <- U^T H, one thread per column
+    for (int cc = c1 + 1 + tid; cc <= hi; cc += EIG_THREADS) {
+      double* col = H + (size_t)cc * lda + c0;
+      double a[QR_D];
+#pragma unroll
+      for (int i = 0; i < QR_D; ++i) a[i] = (i < d) ? col[i] : 0.0;
+#pragma nounroll
+      for (int i = 0; i < d; ++i) {
+        double sv = 0.0;
+#pragma unroll
+        for (int r = 0; r < QR_D; ++r) sv += U[r * QR_LD + i] * a[r];
+        col[i] = sv;
+      }
+    }
+    // rows lo..c0-1 of the block's columns: H <- H U, one thread per row
+    for (int rr = lo + tid; rr < c0; rr += EIG_THREADS) {
+      double* row = H + (size_t)c0 * lda + rr;
+      double a[QR_D];
+#pragma unroll
+      for (int i = 0; i < QR_D; ++i) a[i] = (i < d) ? row[(size_t)i * lda] : 0.0;
+#pragma nounroll
+      for (int jj = 0; jj < d; ++jj) {
+        double sv = 0.0;
+#pragma unroll
+        for (int i = 0; i < QR_D; ++i) sv += a[i] * U[i * QR_LD + jj];
+        row[(size_t)jj * lda] = sv;
+      }
+    }
+    __syncthreads();
+  }
+#undef HH
 }
 
 // Francis double-shift QR on Hessenberg H; returns 0 on success.
 __device__ int francis(double* __restrict__ H, int n, int lda,
                        double* __restrict__ wr, double* __restrict__ wi,
-                       int* ired) {
+                       int* ired, double* D, double* U) {
   const int tid = threadIdx.x;
   const double eps = DBL_EPSILON;
   int hi = n - 1;
@@ -208,27 +300,11 @@ __device__ int francis(double* __restrict__ H, int n, int lda,
       s_sum = a + d;
       s_prod = a * d - b * c;
     }
-    double x = HH(lo, lo) * HH(lo, lo) + HH(lo, lo + 1) * HH(lo + 1, lo) - s_sum * HH(lo, lo) + s_prod;
-    double y = HH(lo + 1, lo) * (HH(lo, lo) + HH(lo + 1, lo + 1) - s_sum);
-    double z = HH(lo + 1, lo) * HH(lo + 2, lo + 1);
-    for (int k = lo; k <= hi - 2; ++k) {
-      double v0, v1, v2;
-      bool ok;
-      house3(x, y, z, v0, v1, v2, ok);
-      if (ok) reflect(H, lda, k, 3, v0, v1, v2, max(lo, k - 1), hi, lo, min(k + 3, hi));
-      x = HH(k + 1, k);
-      y = HH(k + 2, k);
-      if (k < hi - 2) z = HH(k + 3, k);
-      __syncthreads();
-    }
-    {
-      const double nv = sqrt(x * x + y * y);
-      if (nv != 0.0) {
-        const double v0 = x + copysign(nv, x), v1 = y;
-        reflect(H, lda, hi - 1, 2, v0, v1, 0.0, hi - 2, hi, lo, hi);
-      }
-    }
+    const double x = HH(lo, lo) * HH(lo, lo) + HH(lo, lo + 1) * HH(lo + 1, lo) - s_sum * HH(lo, lo) + s_prod;
+    const double y = HH(lo + 1, lo) * (HH(lo, lo) + HH(lo + 1, lo + 1) - s_sum);
+    const double z = HH(lo + 1, lo) * HH(lo + 2, lo + 1);
     __syncthreads();
+    francis_sweep(H, lda, lo, hi, x, y, z, D, U);
   }
 #undef HH
   return 0;
@@ -249,12 +325,14 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(
   __shared__ double w[EIG_NMAX];
   __shared__ double red[EIG_THREADS / 64];
   __shared__ int ired[EIG_THREADS / 64];
+  __shared__ double qd[(QR_D + 1) * QR_LD];
+  __shared__ double qu[QR_D * QR_LD];
   double* H = Abase + (size_t)slot * stride;
   double* wr = wrb + (size_t)slot * w_stride;
   double* wi = wib + (size_t)slot * w_stride;
   hessenberg(H, n, lda, u, w, red);
   // zero below the subdiagonal (the reduction leaves exact zeros already)
-  const int fail = francis(H, n, lda, wr, wi, ired);
+  const int fail = francis(H, n, lda, wr, wi, ired, qd, qu);
   if (threadIdx.x == 0 && info != nullptr) info[slot] = fail;
   if (threadIdx.x == 0 && st != nullptr) const_cast<SlotState*>(st)[slot].qr_fail = fail;
 }
