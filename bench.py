@@ -83,6 +83,10 @@ def main():
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--step-size", type=int, default=4096)
+    ap.add_argument("--batch", type=int, default=0,
+                    help="scenario slots resident at once (0: as many as the step)")
+    ap.add_argument("--overlap", type=int, default=0,
+                    help="1: dynamic stage on a second stream beside the OPF iterations")
     ap.add_argument("--full", action="store_true", help="one step = the whole 57,630 list")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -130,8 +134,8 @@ def main():
                           stream=stream.cuda_stream)
         return cnt
 
-    plain = cs.default_options()
-    timed = cs.default_options(timing=1)
+    plain = cs.default_options(batch=args.batch, overlap=args.overlap)
+    timed = cs.default_options(batch=args.batch, overlap=args.overlap, timing=1)
     for w in range(args.warmup):
         run_step(w, plain)
         log(f"warmup step {w + 1}/{args.warmup} done")
@@ -174,6 +178,8 @@ def main():
                         "N-1 + unordered N-2 over all 339 components = 57,630 scenarios; "
                         "FP64 plain method",
             "scenarios_per_step": step,
+            "slots": args.batch or step,
+            "overlap": args.overlap,
             "kkt_order": nk,
             "state_order": 7 * int(case["n_gen"]) - 1,
         },

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define CS_ABI_VERSION 1
+#define CS_ABI_VERSION 3
 
 enum {
   CS_OK = 0,
@@ -51,7 +51,9 @@ enum {
   CS_ENOMEM = -2,   /* host or device allocation failed                        */
   CS_EHBM = -3,     /* one scenario's workspace exceeds the HBM budget         */
   CS_EDEVICE = -4,  /* HIP runtime error                                       */
-  CS_EUNSUPPORTED = -5 /* a model or size this build does not support        */
+  CS_EUNSUPPORTED = -5, /* a model or size this build does not support       */
+  CS_EAGAIN = -6,       /* serving: no room for the request right now          */
+  CS_ETIMEDOUT = -7     /* serving: the request is not complete yet            */
 };
 
 enum { CS_PREC_FP64 = 0 };
@@ -102,10 +104,14 @@ typedef struct {
   double tol;          /* IPM termination tolerance (default 1e-8)            */
   double near_eps;     /* |max Re lambda| flagged as near (default 1e-6)      */
   size_t hbm_budget;   /* bytes of scenario workspace; 0 = context default    */
-  int32_t batch;       /* scenarios resident at once; 0 = from the budget     */
-  int32_t timing;      /* 1: time every kernel launch with HIP events on the
-                          launch stream and accumulate cs_stats (adds one
-                          synchronisation per OPF iteration)                 */
+  int32_t batch;       /* scenario slots resident at once (slots are refilled
+                          from the list as scenarios finish); 0 = as many as
+                          the budget allows, at most the list length        */
+  int32_t timing;      /* 1: time every kernel launch with HIP events on its
+                          stream and accumulate cs_stats when the call ends  */
+  int32_t overlap;     /* 1: the dynamic stage (state matrix, eigenvalues,
+                          records) runs on a second stream beside the OPF
+                          iterations of other slots; 0: one stream (default 0) */
 } cs_opts;
 
 /* Per-kernel accumulated device time of the calls made with opts.timing = 1
@@ -211,6 +217,42 @@ int cs_eigvals_batched(const cs_ctx* ctx, double* d_A, int32_t n, int32_t lda,
 int cs_kkt_at(cs_ctx* ctx, cs_net* net, const int32_t outage[2], int32_t iters,
               double* K, double* x, double* lam, double* z, double* mu,
               double* metrics, int32_t* status, int32_t* order);
+
+/* Serving (continuous batching).  A server owns B scenario slots of one
+ * network and a host thread that runs them; requests (each an outage list
+ * with its own failure rates) are admitted into a device ring of
+ * queue_capacity scenarios and their scenarios join the slots as slots free
+ * up, beside the work of every other request in flight.  Each scenario's
+ * record is computed exactly as by cs_screen; a request's R_i is eq. (3)
+ * over its own list.  opts (NULL = defaults) fixes tol, max_it, near_eps,
+ * batch (slots) and hbm_budget for all requests; timing is not available.
+ * Errors: CS_EHBM (one scenario's workspace exceeds the budget),
+ * CS_ENOMEM, CS_EDEVICE.  The server keeps ctx and net in use until
+ * destroyed; destroying it waits for the requests in flight. */
+typedef struct cs_server cs_server;
+typedef struct cs_req cs_req;
+int cs_server_create(cs_ctx* ctx, cs_net* net, const cs_opts* opts,
+                     int64_t queue_capacity, cs_server** out);
+void cs_server_destroy(cs_server* srv);
+
+/* Admit a request: outages [n][2] and lambda [n_comp] (may be NULL: no risk)
+ * are host buffers, copied before the call returns.  Returns CS_EAGAIN when
+ * the ring or the request table is full right now (retry later), CS_EINVAL
+ * on an invalid row or rate, or when n exceeds the ring capacity.  n = 0 is
+ * a valid, immediately complete request. */
+int cs_submit(cs_server* srv, const int32_t* outages, int64_t n, const double* lambda,
+              cs_req** out);
+
+/* Wait up to timeout_us microseconds (< 0: no limit) for a request; then
+ * copy its records (out [n]) and R_i (risk [n_comp], if lambda was given;
+ * either may be NULL) and its latency in seconds from admission to the last
+ * record (may be NULL).  CS_ETIMEDOUT if it is not complete yet. */
+int cs_wait(cs_req* req, int64_t timeout_us, cs_result* out, double* risk,
+            double* latency_s);
+
+/* Release a request (at any time; an unfinished one is dropped when it
+ * completes). */
+void cs_req_free(cs_req* req);
 
 /* Copy / clear the context's kernel timing counters. */
 int cs_stats_get(const cs_ctx* ctx, cs_stats* out);

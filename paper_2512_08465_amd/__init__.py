@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcs.so")
 
 CS_OK, CS_EINVAL, CS_ENOMEM, CS_EHBM, CS_EDEVICE, CS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+CS_EAGAIN, CS_ETIMEDOUT = -6, -7
 CAUSE_ISLAND, CAUSE_OPF, CAUSE_LIMIT, CAUSE_SSS, CAUSE_NUMERICAL = 1, 2, 4, 8, 16
 OPF_CONVERGED, OPF_MAXIT, OPF_NUMERICAL, OPF_NOT_RUN = 0, 1, 2, 3
 NEAR_SSS, NEAR_OPF, NEAR_LIMIT = 1, 2, 4
@@ -50,7 +51,7 @@ class Options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("max_it", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("near_eps", ctypes.c_double),
                 ("hbm_budget", ctypes.c_size_t), ("batch", ctypes.c_int32),
-                ("timing", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("overlap", ctypes.c_int32)]
 
 
 KERNELS = ("topology", "kkt_assemble", "kkt_lu", "ipm_update", "dyn_assemble", "dyn_lu",
@@ -99,6 +100,12 @@ def library():
         "cs_stats_reset": (ctypes.c_int, [vp]),
         "cs_last_error": (ctypes.c_char_p, []),
         "cs_abi_version": (ctypes.c_int, []),
+        "cs_server_create": (ctypes.c_int, [vp, vp, ctypes.POINTER(Options), i64,
+                                            ctypes.POINTER(vp)]),
+        "cs_server_destroy": (None, [vp]),
+        "cs_submit": (ctypes.c_int, [vp, vp, i64, dp, ctypes.POINTER(vp)]),
+        "cs_wait": (ctypes.c_int, [vp, i64, vp, dp, dp]),
+        "cs_req_free": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -111,7 +118,8 @@ def library():
 EXPORTED = ("cs_ctx_create", "cs_ctx_destroy", "cs_net_create", "cs_net_destroy",
             "cs_opts_default", "cs_screen", "cs_screen_device", "cs_detail",
             "cs_dense_solve_batched", "cs_eigvals_batched", "cs_kkt_at", "cs_stats_get",
-            "cs_stats_reset", "cs_last_error", "cs_abi_version")
+            "cs_stats_reset", "cs_last_error", "cs_abi_version", "cs_server_create",
+            "cs_server_destroy", "cs_submit", "cs_wait", "cs_req_free")
 
 
 def _check(rc):
@@ -272,3 +280,66 @@ class Network:
         k = int(ne[0])
         return dict(record=rec[0], vm=vm, va=va, pg=pg, qg=qg,
                     eig=er[:k] + 1j * ei[:k], label=lab)
+
+
+class Request:
+    """One submitted screening request (cs_req)."""
+
+    def __init__(self, server: "Server", handle, n: int, has_lam: bool):
+        self.server = server
+        self._h = handle
+        self.n = n
+        self.has_lam = has_lam
+
+    def wait(self, timeout_s: float | None = None):
+        """(records, risk or None, latency_s); raises CSError(CS_ETIMEDOUT)."""
+        res = np.zeros(self.n, dtype=RESULT_DTYPE)
+        risk = np.zeros(self.server.net.n_comp) if self.has_lam else None
+        lat = np.zeros(1)
+        us = -1 if timeout_s is None else int(timeout_s * 1e6)
+        _check(library().cs_wait(self._h, us, _ptr(res), _ptr(risk), _ptr(lat)))
+        return res, risk, float(lat[0])
+
+    def close(self):
+        if self._h:
+            library().cs_req_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """A serving engine for one network (cs_server): requests are admitted
+    as slots free up and run beside each other on the device."""
+
+    def __init__(self, ctx: Context, net: Network, options: Options | None = None,
+                 queue_capacity: int = 1 << 18):
+        self.ctx = ctx
+        self.net = net
+        self._h = ctypes.c_void_p()
+        o = options or default_options()
+        _check(library().cs_server_create(ctx.handle, net._h, ctypes.byref(o),
+                                          int(queue_capacity), ctypes.byref(self._h)))
+
+    def submit(self, outages, lam=None) -> Request:
+        out_list = np.ascontiguousarray(outages, dtype=np.int32).reshape(-1, 2)
+        lam_a = None if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(library().cs_submit(self._h, _ptr(out_list), len(out_list), _ptr(lam_a),
+                                   ctypes.byref(h)))
+        return Request(self, h, len(out_list), lam is not None)
+
+    def close(self):
+        if self._h:
+            library().cs_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libcs.so")
 SOURCES = ["k_topology.hip", "k_opf.hip", "k_dense.hip", "k_dyn.hip", "k_eig.hip",
            "k_finalize.hip", "cs_abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",
+FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall", "-pthread",
          # loadable by the HIP runtime that PyTorch ships (one runtime per process)
          "-mcode-object-version=5",
          "-Wno-unused-result",
@@ -48,7 +48,7 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc compilation failed")
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-mcode-object-version=5", "-shared", "-fPIC",
-           *objs, "-o", tmp]
+           "-pthread", *objs, "-o", tmp]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         sys.stderr.write(" ".join(cmd) + "\n" + r.stdout)

@@ -1,19 +1,30 @@
 // Host runtime and C-ABI of the screening library.
 //
-// A call screens its outage list in batches of B resident scenario slots
-// (B from the HBM budget).  Per batch, on one HIP stream:
-//   islands -> setup -> { OPF evaluate/assemble -> LU+solve -> step } until no
-//   slot is still iterating -> dynamic Jacobians -> LU+solve (g_y^{-1} g_x)
-//   -> state matrix -> Hessenberg + QR -> classify;
-// then one risk reduction over the whole list.  The network is resident on the
-// device from cs_net_create; per-call workspace is cached in the context and
-// grown when a larger network or batch needs it.
+// A call screens its outage list through B resident scenario slots (B from
+// the HBM budget) that are refilled as scenarios finish.  Two HIP streams:
+//   interior-point stream: refill free slots -> islands -> setup, and one
+//     Newton step per round for every iterating slot (OPF evaluate/assemble
+//     -> KKT LU + solve -> step), then a count of the slots per stage;
+//   dynamic stream: for the slots that left the OPF loop, claimed in one
+//     step: dynamic Jacobians -> LU + solve (g_y^{-1} g_x) -> state matrix ->
+//     Hessenberg + QR -> classify, which writes the record and frees the slot.
+// The two overlap: the eigenvalue work of early finishers runs beside the
+// Newton steps of the slow scenarios and of the next ones.  One risk
+// reduction over the whole list closes the call.  The network is resident on
+// the device from cs_net_create; per-call workspace is cached in the context
+// and grown when a larger network or batch needs it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <chrono>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
+#include <set>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -25,8 +36,6 @@ size_t lu_lds_bytes(int n, int nrhs);
 int lu_max_order();
 size_t opf_eval_lds(int nb, int nl, int ng);
 size_t form_state_lds(int ng);
-void launch_setup_k(const DevNet& net, const Slots& s, int count, const int* outages,
-                    long long scen0, hipStream_t st);
 void lu_set_attrs(size_t bytes);
 void opf_set_attrs(size_t bytes);
 void dyn_set_attrs(size_t bytes);
@@ -54,35 +63,78 @@ struct cs_ctx {
   int device = 0;
   size_t hbm_budget = 0;
   hipStream_t stream = nullptr;
+  hipStream_t stream_dyn = nullptr;     // dynamic stage of the screening loop
+  hipEvent_t ev_ipm = nullptr, ev_dyn = nullptr;   // cross-stream order (no timing)
   int* d_counter = nullptr;
   int* h_counter = nullptr;
+  int* d_sched = nullptr;               // [0..1] next scenario (64-bit), [2..] stage counts
+  int* h_sched = nullptr;
+  std::vector<hipEvent_t> ev_pool;      // timing events, reused across calls
+  int* d_units = nullptr;               // per-launch solve counts when timing
+  size_t units_cap = 0;
   // cached workspace
   void* ws = nullptr;
   size_t ws_bytes = 0;
   // kernel timing
   cs_stats stats{};
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
   size_t lds_max = 64 * 1024;   // dynamic LDS per workgroup this device allows
 };
 
-// Brackets one launch with events when timing is on and adds its duration.
-struct Timer {
+// Launch timing: events around each launch on its own stream, resolved when
+// the call ends (no synchronisation in between, so the two streams keep
+// overlapping).  units = work items of the launch, either known on the host
+// or counted on the device into d_units[uidx].
+struct TimedLaunches {
   cs_ctx* c;
   bool on;
-  hipStream_t st;
-  int k;
-  Timer(cs_ctx* c_, bool on_, hipStream_t st_, int k_) : c(c_), on(on_), st(st_), k(k_) {
-    if (on) hipEventRecord(c->ev0, st);
+  struct Rec { int kind; hipEvent_t a, b; int64_t units; int uidx; };
+  std::vector<Rec> recs;
+  size_t next_ev = 0;
+  int n_units = 0;
+  TimedLaunches(cs_ctx* c_, bool on_) : c(c_), on(on_) {}
+  hipEvent_t ev() {
+    if (next_ev == c->ev_pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[next_ev++];
   }
-  int done(int64_t units) {
+  // a device slot for a unit count, or -1 when timing is off / full
+  int unit_slot() {
+    if (!on || (size_t)n_units >= c->units_cap) return -1;
+    return n_units++;
+  }
+  template <class F>
+  int run(int kind, hipStream_t st, int64_t units, int uidx, F launch) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (on) {
+      a = ev();
+      b = ev();
+      if (!a || !b || hipEventRecord(a, st) != hipSuccess) return fail(CS_EDEVICE, "timing event failed");
+    }
+    launch();
+    if (on) {
+      if (hipEventRecord(b, st) != hipSuccess) return fail(CS_EDEVICE, "timing event failed");
+      recs.push_back(Rec{kind, a, b, units, uidx});
+    }
+    return CS_OK;
+  }
+  // after both streams have drained
+  int resolve() {
     if (!on) return CS_OK;
-    if (hipEventRecord(c->ev1, st) != hipSuccess || hipEventSynchronize(c->ev1) != hipSuccess)
-      return fail(CS_EDEVICE, "timing event failed");
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, c->ev0, c->ev1);
-    c->stats.ms[k] += ms;
-    c->stats.launches[k] += 1;
-    c->stats.units[k] += units;
+    std::vector<int> u(n_units);
+    if (n_units && hipMemcpy(u.data(), c->d_units, sizeof(int) * n_units,
+                             hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(CS_EDEVICE, "timing counts copy failed");
+    for (const Rec& r : recs) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+        return fail(CS_EDEVICE, "timing event query failed");
+      c->stats.ms[r.kind] += ms;
+      c->stats.launches[r.kind] += 1;
+      c->stats.units[r.kind] += (r.uidx >= 0) ? u[r.uidx] : r.units;
+    }
     return CS_OK;
   }
 };
@@ -126,6 +178,7 @@ void cs_opts_default(cs_opts* o) {
   o->hbm_budget = 0;
   o->batch = 0;
   o->timing = 0;
+  o->overlap = 0;
 }
 
 int cs_ctx_create(int device, size_t hbm_budget, cs_ctx** out) {
@@ -140,11 +193,16 @@ int cs_ctx_create(int device, size_t hbm_budget, cs_ctx** out) {
   cs_ctx* c = new cs_ctx();
   c->device = device;
   c->hbm_budget = hbm_budget ? hbm_budget : ((size_t)48 << 30);
+  // both streams at the default priority
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->stream_dyn, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_ipm, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_dyn, hipEventDisableTiming) != hipSuccess ||
       hipMalloc(&c->d_counter, sizeof(int)) != hipSuccess ||
-      hipHostMalloc(&c->h_counter, sizeof(int), hipHostMallocDefault) != hipSuccess) {
-    delete c;
+      hipHostMalloc(&c->h_counter, sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&c->d_sched, sizeof(int) * (PH_COUNT + 2)) != hipSuccess ||
+      hipHostMalloc(&c->h_sched, sizeof(int) * (PH_COUNT + 2), hipHostMallocDefault) != hipSuccess) {
+    cs_ctx_destroy(c);
     return fail(CS_EDEVICE, "cs_ctx_create: stream or counter allocation failed");
   }
   // kernels whose LDS may exceed the default dynamic limit
@@ -159,9 +217,14 @@ void cs_ctx_destroy(cs_ctx* c) {
   if (c->ws) hipFree(c->ws);
   if (c->d_counter) hipFree(c->d_counter);
   if (c->h_counter) hipHostFree(c->h_counter);
+  if (c->d_sched) hipFree(c->d_sched);
+  if (c->h_sched) hipHostFree(c->h_sched);
+  if (c->d_units) hipFree(c->d_units);
   if (c->stream) hipStreamDestroy(c->stream);
-  if (c->ev0) hipEventDestroy(c->ev0);
-  if (c->ev1) hipEventDestroy(c->ev1);
+  if (c->stream_dyn) hipStreamDestroy(c->stream_dyn);
+  if (c->ev_ipm) hipEventDestroy(c->ev_ipm);
+  if (c->ev_dyn) hipEventDestroy(c->ev_dyn);
+  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   delete c;
 }
 
@@ -373,7 +436,7 @@ static Plan plan_sizes(const cs_net* n) {
 }
 
 // carve the slot arrays out of one allocation
-static int bind_workspace(cs_ctx* c, const cs_net* n, Plan& p, int B) {
+static int bind_workspace(void** ws, size_t* ws_bytes, const cs_net* n, Plan& p, int B) {
   Slots& s = p.s;
   const size_t nb = n->nb, nl = n->nl, ng = n->ng;
   const size_t piv = std::max(s.nk, s.ny);
@@ -402,14 +465,14 @@ static int bind_workspace(cs_ctx* c, const cs_net* n, Plan& p, int B) {
   const size_t ogen = take(ng * B + 64);
   const size_t ost = take(sizeof(SlotState) * (size_t)B);
   const size_t need = off;
-  if (need > c->ws_bytes) {
-    if (c->ws) hipFree(c->ws);
-    c->ws = nullptr;
-    c->ws_bytes = 0;
-    if (hipMalloc(&c->ws, need) != hipSuccess) return fail(CS_ENOMEM, "workspace allocation failed");
-    c->ws_bytes = need;
+  if (need > *ws_bytes) {
+    if (*ws) hipFree(*ws);
+    *ws = nullptr;
+    *ws_bytes = 0;
+    if (hipMalloc(ws, need) != hipSuccess) return fail(CS_ENOMEM, "workspace allocation failed");
+    *ws_bytes = need;
   }
-  char* base = static_cast<char*>(c->ws);
+  char* base = static_cast<char*>(*ws);
   s.B = B;
   s.K = reinterpret_cast<double*>(base + oK);
   s.A = reinterpret_cast<double*>(base + oA);
@@ -433,16 +496,184 @@ static int bind_workspace(cs_ctx* c, const cs_net* n, Plan& p, int B) {
 }
 
 
+// ------------------------------------------------------------------ engine
+// The slot scheduler shared by the batch entry points and the server: B
+// slots over a stream of scenarios (a call's list, or a server's ring of
+// capacity q_cap), advanced one round at a time.  A round refills free slots,
+// takes one Newton step in every iterating slot, counts the slots per stage
+// and, when enough have left the OPF loop, claims them for the dynamic stage
+// (on the second stream when overlapping).
+struct Engine {
+  cs_ctx* c = nullptr;
+  const DevNet* D = nullptr;
+  Slots s{};
+  cs_opts opts{};
+  int nslots = 0, pstride = 0, dyn_min = 1;
+  bool eager = false;            // claim as soon as the OPF tail is shorter (serving)
+  hipStream_t st = nullptr, sd = nullptr;
+  hipEvent_t ev_ipm = nullptr, ev_dyn = nullptr;
+  unsigned long long* d_next = nullptr;
+  int* d_counts = nullptr;       // [PH_COUNT]
+  int* h_counts = nullptr;       // pinned [PH_COUNT]
+  unsigned long long* h_next = nullptr;   // pinned
+  const int* d_list = nullptr;   // outage pairs
+  cs_result* d_res = nullptr;
+  long long q_cap = 0;
+  const int* item_req = nullptr;
+  int* req_done = nullptr;
+  TimedLaunches* T = nullptr;
+  int cnt[PH_COUNT]{};
+  long long assigned = 0;        // scenarios handed to slots so far
+  bool dyn_busy = false;
+
+  int timed(int kind, hipStream_t stream, int64_t units, int uidx, const std::function<void()>& f) {
+    if (T) return T->run(kind, stream, units, uidx, f);
+    f();
+    return CS_OK;
+  }
+
+  int start() {
+    HIPCHK(hipMemsetAsync(s.st, 0, sizeof(SlotState) * (size_t)nslots, st));
+    HIPCHK(hipMemsetAsync(d_next, 0, sizeof(unsigned long long), st));
+    HIPCHK(hipEventRecord(ev_ipm, st));
+    HIPCHK(hipStreamWaitEvent(sd, ev_ipm, 0));
+    for (int k = 0; k < PH_COUNT; ++k) cnt[k] = 0;
+    cnt[PH_EMPTY] = nslots;
+    assigned = 0;
+    dyn_busy = false;
+    return CS_OK;
+  }
+
+  int count() {
+    launch_phase_counts(s, nslots, d_counts, st);
+    HIPCHK(hipMemcpyAsync(h_counts, d_counts, sizeof(int) * PH_COUNT, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_next, d_next, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int k = 0; k < PH_COUNT; ++k) cnt[k] = h_counts[k];
+    return CS_OK;
+  }
+
+  // One round with N scenarios available so far (absolute count).  idle is
+  // set when every available scenario has been recorded and no slot is busy.
+  int round(long long N, bool& idle) {
+    idle = false;
+    bool work = false;
+    int rc;
+    if (assigned < N && cnt[PH_EMPTY] > 0) {
+      const long long nnew = std::min<long long>(cnt[PH_EMPTY], N - assigned);
+      rc = timed(CS_K_TOPOLOGY, st, nnew, -1, [&] {
+        launch_refill(s, nslots, d_next, N, q_cap, st);
+        launch_islands(*D, s, d_list, nslots, st);
+        launch_setup_k(*D, s, nslots, d_list, st);
+      });
+      if (rc != CS_OK) return rc;
+      work = true;
+    }
+    if (work || cnt[PH_IPM] > 0) {
+      rc = timed(CS_K_KKT_ASSEMBLE, st, cnt[PH_IPM], -1,
+                 [&] { launch_opf_eval(*D, s, nslots, opts.tol, opts.max_it, st); });
+      if (rc != CS_OK) return rc;
+      const int u = T ? T->unit_slot() : -1;
+      if (u >= 0) launch_count_jobs(s, nslots, c->d_units + u, st);
+      rc = timed(CS_K_KKT_LU, st, 0, u, [&] {
+        launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv, pstride, s.st, PH_IPM,
+                        nslots, nullptr, st);
+      });
+      if (rc != CS_OK) return rc;
+      rc = timed(CS_K_IPM_UPDATE, st, 0, u, [&] { launch_opf_update(*D, s, nslots, 1e10, st); });
+      if (rc != CS_OK) return rc;
+    }
+    if ((rc = count()) != CS_OK) return rc;
+    assigned = std::min<long long>((long long)*h_next, N);
+    if (dyn_busy) {
+      const hipError_t q = hipEventQuery(ev_dyn);
+      if (q == hipSuccess) dyn_busy = false;
+      else if (q != hipErrorNotReady) return fail(CS_EDEVICE, "dynamic stage failed");
+    }
+    const int ready = cnt[PH_DYN] + cnt[PH_DONE];
+    const int ipm_left = cnt[PH_IPM] + cnt[PH_NEW];
+    // While more scenarios wait, the dynamic stage takes the ready slots in
+    // groups of dyn_min so that they can be refilled.  At the end of a list,
+    // one stream waits for the last OPF to finish (one large eigenvalue
+    // launch); two streams, or a server, start as soon as the OPF tail is
+    // smaller than what waits.
+    bool go = false;
+    if (!dyn_busy && ready > 0) {
+      if (ipm_left == 0) go = true;
+      else if (eager || (opts.overlap && assigned >= N)) go = ready >= dyn_min || ipm_left < ready;
+      else if (assigned < N) go = ready >= dyn_min;
+    }
+    if (go) {
+      const int ndyn = cnt[PH_DYN];
+      launch_claim(s, nslots, st);
+      HIPCHK(hipEventRecord(ev_ipm, st));
+      HIPCHK(hipStreamWaitEvent(sd, ev_ipm, 0));
+      rc = timed(CS_K_DYN_ASSEMBLE, sd, ndyn, -1, [&] { launch_dyn_assemble(*D, s, nslots, sd); });
+      if (rc != CS_OK) return rc;
+      rc = timed(CS_K_DYN_LU, sd, ndyn, -1, [&] {
+        launch_lu_solve(s.K, s.k_stride, s.ny, s.nyc, s.ldy, s.piv, pstride, s.st, PH_DYNB,
+                        nslots, nullptr, sd);
+      });
+      if (rc != CS_OK) return rc;
+      rc = timed(CS_K_STATE_MATRIX, sd, ndyn, -1, [&] { launch_form_state(*D, s, nslots, sd); });
+      if (rc != CS_OK) return rc;
+      rc = timed(CS_K_EIG, sd, ndyn, -1, [&] {
+        launch_eig(s.A, s.a_stride, s.lda_a, nullptr, 0, s.wr, s.wi, s.na, s.st, nslots,
+                   nullptr, sd);
+      });
+      if (rc != CS_OK) return rc;
+      rc = timed(CS_K_CLASSIFY, sd, ready, -1, [&] {
+        launch_classify(s, nslots, opts.near_eps, opts.max_it, d_res, item_req, req_done, sd);
+      });
+      if (rc != CS_OK) return rc;
+      HIPCHK(hipEventRecord(ev_dyn, sd));
+      if (T) c->stats.dyn_order = s.ny;
+      dyn_busy = true;
+      return CS_OK;
+    }
+    const bool can_refill = assigned < N && cnt[PH_EMPTY] > 0;
+    if (ipm_left == 0 && !can_refill) {
+      if (dyn_busy) {
+        // nothing to iterate: wait for the dynamic stage to free its slots
+        HIPCHK(hipEventSynchronize(ev_dyn));
+        dyn_busy = false;
+        return count();
+      }
+      if (ready == 0) {
+        if (assigned >= N) {
+          idle = true;
+          return CS_OK;
+        }
+        return fail(CS_EDEVICE, "scenario slots in an unexpected state");
+      }
+    }
+    return CS_OK;
+  }
+
+  // the given stream continues after both of the engine's streams
+  int join(hipStream_t after) {
+    HIPCHK(hipEventRecord(ev_dyn, sd));
+    HIPCHK(hipStreamWaitEvent(after, ev_dyn, 0));
+    return CS_OK;
+  }
+};
+
 // ------------------------------------------------------------------ screen
+static int check_opts(const cs_opts& opts, const char* who) {
+  if (opts.prec != CS_PREC_FP64) return fail(CS_EUNSUPPORTED, std::string(who) + ": only CS_PREC_FP64");
+  if (opts.max_it < 1 || opts.max_it > 10000) return fail(CS_EINVAL, std::string(who) + ": max_it out of range");
+  if (!(opts.tol > 0)) return fail(CS_EINVAL, std::string(who) + ": tol must be > 0");
+  return CS_OK;
+}
+
 static int run_screen(cs_ctx* c, cs_net* n, const int* d_out_list, long long N,
                       const double* d_lambda, const cs_opts* o, cs_result* d_res,
                       double* d_risk, hipStream_t st, Plan* keep) {
   cs_opts opts;
   cs_opts_default(&opts);
   if (o) opts = *o;
-  if (opts.prec != CS_PREC_FP64) return fail(CS_EUNSUPPORTED, "cs_screen: only CS_PREC_FP64");
-  if (opts.max_it < 1 || opts.max_it > 10000) return fail(CS_EINVAL, "cs_screen: max_it out of range");
-  if (!(opts.tol > 0)) return fail(CS_EINVAL, "cs_screen: tol must be > 0");
+  int rc = check_opts(opts, "cs_screen");
+  if (rc != CS_OK) return rc;
   HIPCHK(hipSetDevice(c->device));
   Plan p = plan_sizes(n);
   const size_t budget = opts.hbm_budget ? opts.hbm_budget : c->hbm_budget;
@@ -453,61 +684,60 @@ static int run_screen(cs_ctx* c, cs_net* n, const int* d_out_list, long long N,
   if (opts.batch > 0) B = std::min<long long>(B, opts.batch);
   B = std::max<long long>(1, std::min<long long>(B, std::max<long long>(N, 1)));
   B = std::min<long long>(B, 1 << 20);
-  int rc = bind_workspace(c, n, p, (int)B);
+  rc = bind_workspace(&c->ws, &c->ws_bytes, n, p, (int)B);
   if (rc != CS_OK) return rc;
-  const Slots& s = p.s;
-  const DevNet& D = n->d;
   const bool tm = opts.timing != 0;
-  const int pstride = std::max(s.nk, s.ny);
-#define TIMED(kind, units, launch)                     \
-  do {                                                 \
-    Timer t_(c, tm, st, kind);                         \
-    launch;                                            \
-    int r_ = t_.done(units);                           \
-    if (r_ != CS_OK) return r_;                        \
-  } while (0)
-  for (long long b0 = 0; b0 < N; b0 += B) {
-    const int cnt = (int)std::min<long long>(B, N - b0);
-    TIMED(CS_K_TOPOLOGY, cnt, (launch_islands(D, s, d_out_list, b0, cnt, st),
-                               launch_setup_k(D, s, cnt, d_out_list, b0, st)));
-    for (int it = 0; it <= opts.max_it; ++it) {
-      TIMED(CS_K_KKT_ASSEMBLE, cnt, launch_opf_eval(D, s, cnt, opts.tol, opts.max_it, st));
-      int nfac = 0;
-      if (tm) {
-        nfac = count_jobs(s, cnt, c->d_counter, c->h_counter, st);
-        if (nfac < 0) return fail(CS_EDEVICE, "cs_screen: device error in the OPF loop");
-        c->stats.kkt_order = s.nk;
-      }
-      TIMED(CS_K_KKT_LU, nfac, launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv,
-                                              pstride, s.st, cnt, nullptr, st));
-      TIMED(CS_K_IPM_UPDATE, nfac, launch_opf_update(D, s, cnt, 1e10, st));
-      const int act = count_active(s, cnt, PH_IPM, c->d_counter, c->h_counter, st);
-      if (act < 0) return fail(CS_EDEVICE, "cs_screen: device error in the OPF loop");
-      if (act == 0) break;
-    }
-    int ndyn = 0;
-    if (tm) {
-      ndyn = count_active(s, cnt, PH_DYN, c->d_counter, c->h_counter, st);
-      c->stats.dyn_order = s.ny;
-    }
-    TIMED(CS_K_DYN_ASSEMBLE, ndyn, launch_dyn_assemble(D, s, cnt, st));
-    TIMED(CS_K_DYN_LU, ndyn, launch_lu_solve(s.K, s.k_stride, s.ny, s.nyc, s.ldy, s.piv, pstride,
-                                            s.st, cnt, nullptr, st));
-    TIMED(CS_K_STATE_MATRIX, ndyn, launch_form_state(D, s, cnt, st));
-    TIMED(CS_K_EIG, ndyn, launch_eig(s.A, s.a_stride, s.lda_a, nullptr, 0, s.wr, s.wi, s.na,
-                                     s.st, cnt, nullptr, st));
-    TIMED(CS_K_CLASSIFY, cnt, launch_classify(s, cnt, opts.near_eps, opts.max_it, d_res, st));
-    HIPCHK(hipGetLastError());
+  if (tm && c->units_cap == 0) {
+    const size_t cap = 1 << 20;
+    HIPCHK(hipMalloc(&c->d_units, sizeof(int) * cap));
+    c->units_cap = cap;
   }
+  TimedLaunches T(c, tm);
+  Engine e;
+  e.c = c;
+  e.D = &n->d;
+  e.s = p.s;
+  e.opts = opts;
+  e.nslots = (int)B;
+  e.pstride = std::max(p.s.nk, p.s.ny);
+  e.dyn_min = std::max(1, std::min((int)B, 1024));
+  e.st = st;
+  e.sd = opts.overlap ? c->stream_dyn : st;
+  e.ev_ipm = c->ev_ipm;
+  e.ev_dyn = c->ev_dyn;
+  e.d_next = reinterpret_cast<unsigned long long*>(c->d_sched);
+  e.d_counts = c->d_sched + 2;
+  e.h_counts = c->h_sched + 2;
+  e.h_next = reinterpret_cast<unsigned long long*>(c->h_sched);
+  e.d_list = d_out_list;
+  e.d_res = d_res;
+  e.q_cap = std::max<long long>(N, 1);
+  e.T = tm ? &T : nullptr;
+  c->stats.kkt_order = p.s.nk;
+  if ((rc = e.start()) != CS_OK) return rc;
+  // every scenario needs at most max_it + 2 rounds in its slot, plus a few
+  // rounds per dynamic stage; a loop beyond this bound is an internal error
+  const long long max_rounds = ((N + B - 1) / B + 2) * (long long)(opts.max_it + 8) * 4 + 1000;
+  long long rounds = 0;
+  for (;;) {
+    bool idle = false;
+    if ((rc = e.round(N, idle)) != CS_OK) return rc;
+    if (idle) break;
+    if (++rounds > max_rounds) return fail(CS_EDEVICE, "cs_screen: scheduling did not finish");
+  }
+  if ((rc = e.join(st)) != CS_OK) return rc;
+  HIPCHK(hipGetLastError());
   if (d_risk) {
     const int n_comp = n->nl + n->ng + n->nd;
-    TIMED(CS_K_RISK, n_comp,
-          launch_risk(d_out_list, N, reinterpret_cast<const uint8_t*>(d_res),
-                      (int)sizeof(cs_result), d_lambda, n_comp, d_risk, st));
+    rc = T.run(CS_K_RISK, st, n_comp, -1, [&] {
+      launch_risk(d_out_list, N, reinterpret_cast<const uint8_t*>(d_res), (int)sizeof(cs_result),
+                  d_lambda, n_comp, d_risk, st);
+    });
+    if (rc != CS_OK) return rc;
   }
-#undef TIMED
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
+  if ((rc = T.resolve()) != CS_OK) return rc;
   if (keep) *keep = p;
   return CS_OK;
 }
@@ -606,6 +836,358 @@ extern "C" int cs_screen_device(cs_ctx* c, cs_net* n, const int32_t* d_outages, 
   return run_screen(c, n, d_outages, N, d_lambda, opts, d_out, d_risk, st, nullptr);
 }
 
+// ------------------------------------------------------------------ serving
+struct cs_req {
+  cs_server* srv = nullptr;
+  int slot = -1;                         // request table index
+  long long q0 = 0;                      // first ring position (absolute)
+  int64_t n = 0;
+  bool has_lam = false;
+  std::vector<double> lam;
+  std::vector<cs_result> res;
+  std::vector<double> risk;
+  bool done = false, freed = false;
+  int status = CS_OK;
+  std::string msg;
+  std::chrono::steady_clock::time_point t0, t1;
+};
+
+struct cs_server {
+  static constexpr int R = 1024;         // requests in flight at most
+  cs_ctx* c = nullptr;
+  cs_net* n = nullptr;
+  cs_opts opts{};
+  Plan p;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t st = nullptr, sd = nullptr, scopy = nullptr;
+  hipEvent_t ev_ipm = nullptr, ev_dyn = nullptr;
+  long long q_cap = 0;
+  int* q_out = nullptr;                  // ring of outage pairs
+  cs_result* q_res = nullptr;            // ring of records
+  int* item_req = nullptr;               // ring: request table index per scenario
+  int* req_done = nullptr;               // [R] records completed per request
+  int* h_req_done = nullptr;             // pinned copy
+  int* d_sched = nullptr;                // next (64-bit) + stage counts
+  int* h_sched = nullptr;
+  int* g_out = nullptr;                  // one request's list, contiguous
+  cs_result* g_res = nullptr;
+  double* g_lam = nullptr;
+  double* g_risk = nullptr;
+  std::vector<cs_req*> table;            // requests in flight
+  std::set<cs_req*> owned;               // every request not yet freed by the caller
+  long long submitted = 0;               // scenarios admitted (absolute)
+  std::mutex m;
+  std::condition_variable cv_work, cv_done;
+  bool stop = false;
+  int error = CS_OK;
+  std::string error_msg;
+  std::thread th;
+  Engine e;
+};
+
+// Finish every request whose records are all in: gather its slice of the
+// ring, reduce its R_i, copy to the host.  Called by the server thread.
+static int server_complete(cs_server* S) {
+  std::vector<cs_req*> live;
+  {
+    std::lock_guard<std::mutex> lk(S->m);
+    for (cs_req* r : S->table)
+      if (r && !r->done) live.push_back(r);
+  }
+  if (live.empty()) return CS_OK;
+  HIPCHK(hipMemcpyAsync(S->h_req_done, S->req_done, sizeof(int) * cs_server::R,
+                        hipMemcpyDeviceToHost, S->st));
+  HIPCHK(hipStreamSynchronize(S->st));
+  const int n_comp = S->n->nl + S->n->ng + S->n->nd;
+  for (cs_req* r : live) {
+    if (S->h_req_done[r->slot] < r->n) continue;
+    launch_gather_request(S->q_out, S->q_res, r->q0, (int)r->n, S->q_cap, S->g_out, S->g_res, S->st);
+    if (r->has_lam) {
+      HIPCHK(hipMemcpyAsync(S->g_lam, r->lam.data(), sizeof(double) * n_comp,
+                            hipMemcpyHostToDevice, S->st));
+      launch_risk(S->g_out, r->n, reinterpret_cast<const uint8_t*>(S->g_res),
+                  (int)sizeof(cs_result), S->g_lam, n_comp, S->g_risk, S->st);
+      r->risk.resize(n_comp);
+      HIPCHK(hipMemcpyAsync(r->risk.data(), S->g_risk, sizeof(double) * n_comp,
+                            hipMemcpyDeviceToHost, S->st));
+    }
+    r->res.resize(r->n);
+    HIPCHK(hipMemcpyAsync(r->res.data(), S->g_res, sizeof(cs_result) * r->n,
+                          hipMemcpyDeviceToHost, S->st));
+    HIPCHK(hipStreamSynchronize(S->st));
+    std::lock_guard<std::mutex> lk(S->m);
+    r->t1 = std::chrono::steady_clock::now();
+    r->done = true;
+    S->table[r->slot] = nullptr;
+    if (r->freed) {
+      S->owned.erase(r);
+      delete r;
+    }
+  }
+  S->cv_done.notify_all();
+  return CS_OK;
+}
+
+static void server_fail_all(cs_server* S, int code, const std::string& msg) {
+  std::lock_guard<std::mutex> lk(S->m);
+  S->error = code;
+  S->error_msg = msg;
+  for (cs_req*& r : S->table) {
+    if (!r) continue;
+    r->status = code;
+    r->msg = msg;
+    r->done = true;
+    r->t1 = std::chrono::steady_clock::now();
+    if (r->freed) {
+      S->owned.erase(r);
+      delete r;
+    }
+    r = nullptr;
+  }
+  S->cv_done.notify_all();
+}
+
+static void server_loop(cs_server* S) {
+  hipSetDevice(S->c->device);
+  int rc = S->e.start();
+  if (rc != CS_OK) {
+    server_fail_all(S, rc, g_err);
+    return;
+  }
+  for (;;) {
+    long long N;
+    {
+      std::lock_guard<std::mutex> lk(S->m);
+      N = S->submitted;
+    }
+    bool idle = false;
+    if ((rc = S->e.round(N, idle)) != CS_OK || (rc = server_complete(S)) != CS_OK) {
+      server_fail_all(S, rc, g_err);
+      return;
+    }
+    if (idle) {
+      std::unique_lock<std::mutex> lk(S->m);
+      S->cv_work.wait(lk, [&] { return S->stop || S->submitted > N; });
+      if (S->stop && S->submitted == N) return;
+    }
+  }
+}
+
+extern "C" int cs_server_create(cs_ctx* c, cs_net* n, const cs_opts* o,
+                                int64_t queue_capacity, cs_server** out) {
+  if (!c || !n || !out || queue_capacity <= 0 || queue_capacity > (1ll << 30))
+    return fail(CS_EINVAL, "cs_server_create: bad arguments");
+  *out = nullptr;
+  cs_opts opts;
+  cs_opts_default(&opts);
+  if (o) opts = *o;
+  opts.timing = 0;
+  int rc = check_opts(opts, "cs_server_create");
+  if (rc != CS_OK) return rc;
+  HIPCHK(hipSetDevice(c->device));
+  cs_server* S = new cs_server();
+  S->c = c;
+  S->n = n;
+  S->opts = opts;
+  S->q_cap = queue_capacity;
+  S->table.assign(cs_server::R, nullptr);
+  S->p = plan_sizes(n);
+  const size_t budget = opts.hbm_budget ? opts.hbm_budget : c->hbm_budget;
+  auto bail = [&](int code, const std::string& msg) {
+    cs_server_destroy(S);
+    return fail(code, msg);
+  };
+  if (S->p.per_slot > budget)
+    return bail(CS_EHBM, "cs_server_create: one scenario needs " + std::to_string(S->p.per_slot) +
+                             " bytes, over the budget of " + std::to_string(budget));
+  long long B = (long long)(budget / S->p.per_slot);
+  if (opts.batch > 0) B = std::min<long long>(B, opts.batch);
+  B = std::max<long long>(1, std::min<long long>(B, 1 << 20));
+  rc = bind_workspace(&S->ws, &S->ws_bytes, n, S->p, (int)B);
+  if (rc != CS_OK) return bail(rc, g_err);
+  const int n_comp = n->nl + n->ng + n->nd;
+  if (hipStreamCreateWithFlags(&S->st, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&S->sd, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&S->scopy, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&S->ev_ipm, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&S->ev_dyn, hipEventDisableTiming) != hipSuccess ||
+      hipMalloc(&S->q_out, sizeof(int) * 2 * queue_capacity) != hipSuccess ||
+      hipMalloc(&S->q_res, sizeof(cs_result) * queue_capacity) != hipSuccess ||
+      hipMalloc(&S->item_req, sizeof(int) * queue_capacity) != hipSuccess ||
+      hipMalloc(&S->req_done, sizeof(int) * cs_server::R) != hipSuccess ||
+      hipHostMalloc(&S->h_req_done, sizeof(int) * cs_server::R, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&S->d_sched, sizeof(int) * (PH_COUNT + 2)) != hipSuccess ||
+      hipHostMalloc(&S->h_sched, sizeof(int) * (PH_COUNT + 2), hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&S->g_out, sizeof(int) * 2 * queue_capacity) != hipSuccess ||
+      hipMalloc(&S->g_res, sizeof(cs_result) * queue_capacity) != hipSuccess ||
+      hipMalloc(&S->g_lam, sizeof(double) * std::max(n_comp, 1)) != hipSuccess ||
+      hipMalloc(&S->g_risk, sizeof(double) * std::max(n_comp, 1)) != hipSuccess)
+    return bail(CS_ENOMEM, "cs_server_create: allocation failed");
+  if (hipMemset(S->req_done, 0, sizeof(int) * cs_server::R) != hipSuccess)
+    return bail(CS_EDEVICE, "cs_server_create: device error");
+  Engine& e = S->e;
+  e.c = c;
+  e.D = &n->d;
+  e.s = S->p.s;
+  e.opts = opts;
+  e.nslots = (int)B;
+  e.pstride = std::max(S->p.s.nk, S->p.s.ny);
+  e.dyn_min = std::max(1, std::min((int)B, 1024));
+  e.eager = true;
+  e.st = S->st;
+  e.sd = opts.overlap ? S->sd : S->st;
+  e.ev_ipm = S->ev_ipm;
+  e.ev_dyn = S->ev_dyn;
+  e.d_next = reinterpret_cast<unsigned long long*>(S->d_sched);
+  e.d_counts = S->d_sched + 2;
+  e.h_counts = S->h_sched + 2;
+  e.h_next = reinterpret_cast<unsigned long long*>(S->h_sched);
+  e.d_list = S->q_out;
+  e.d_res = S->q_res;
+  e.q_cap = queue_capacity;
+  e.item_req = S->item_req;
+  e.req_done = S->req_done;
+  e.T = nullptr;
+  S->th = std::thread(server_loop, S);
+  *out = S;
+  return CS_OK;
+}
+
+extern "C" void cs_server_destroy(cs_server* S) {
+  if (!S) return;
+  if (S->th.joinable()) {
+    {
+      std::lock_guard<std::mutex> lk(S->m);
+      S->stop = true;
+    }
+    S->cv_work.notify_all();
+    S->th.join();
+  }
+  hipSetDevice(S->c->device);
+  // requests the caller still holds outlive the server, detached from it
+  for (cs_req* r : S->owned) {
+    if (r->freed) {
+      delete r;
+      continue;
+    }
+    if (!r->done) {
+      r->status = CS_EDEVICE;
+      r->msg = "server destroyed";
+      r->done = true;
+    }
+    r->srv = nullptr;
+  }
+  for (void* q : {(void*)S->q_out, (void*)S->q_res, (void*)S->item_req, (void*)S->req_done,
+                  (void*)S->d_sched, (void*)S->g_out, (void*)S->g_res, (void*)S->g_lam,
+                  (void*)S->g_risk, S->ws})
+    if (q) hipFree(q);
+  if (S->h_req_done) hipHostFree(S->h_req_done);
+  if (S->h_sched) hipHostFree(S->h_sched);
+  for (hipStream_t q : {S->st, S->sd, S->scopy})
+    if (q) hipStreamDestroy(q);
+  for (hipEvent_t q : {S->ev_ipm, S->ev_dyn})
+    if (q) hipEventDestroy(q);
+  delete S;
+}
+
+extern "C" int cs_submit(cs_server* S, const int32_t* outages, int64_t n, const double* lambda,
+                         cs_req** out) {
+  if (!S || !out || n < 0 || (n > 0 && !outages)) return fail(CS_EINVAL, "cs_submit: bad arguments");
+  *out = nullptr;
+  if (n > S->q_cap) return fail(CS_EINVAL, "cs_submit: request longer than the ring");
+  int rc = validate_host(S->n, outages, n, lambda);
+  if (rc != CS_OK) return rc;
+  const int n_comp = S->n->nl + S->n->ng + S->n->nd;
+  std::unique_lock<std::mutex> lk(S->m);
+  if (S->error != CS_OK) return fail(S->error, "cs_submit: server failed: " + S->error_msg);
+  long long oldest = S->submitted;
+  int slot = -1;
+  for (int i = 0; i < cs_server::R; ++i) {
+    const cs_req* r = S->table[i];
+    if (r) oldest = std::min(oldest, r->q0);
+    else if (slot < 0) slot = i;
+  }
+  if (slot < 0 || S->submitted + n - oldest > S->q_cap)
+    return fail(CS_EAGAIN, "cs_submit: no room for the request right now");
+  cs_req* r = new cs_req();
+  r->srv = S;
+  r->slot = slot;
+  r->q0 = S->submitted;
+  r->n = n;
+  r->has_lam = lambda != nullptr;
+  if (lambda) r->lam.assign(lambda, lambda + n_comp);
+  r->t0 = std::chrono::steady_clock::now();
+  S->owned.insert(r);
+  if (n == 0) {
+    r->done = true;
+    r->t1 = r->t0;
+    if (lambda) r->risk.assign(n_comp, 0.0);
+    *out = r;
+    return CS_OK;
+  }
+  hipSetDevice(S->c->device);
+  // copy into the ring (in two pieces when it wraps), tag the request
+  const long long p0 = r->q0 % S->q_cap;
+  const long long first = std::min<long long>(n, S->q_cap - p0);
+  bool ok = hipMemcpyAsync(S->q_out + 2 * p0, outages, sizeof(int) * 2 * first,
+                           hipMemcpyHostToDevice, S->scopy) == hipSuccess;
+  if (ok && first < n)
+    ok = hipMemcpyAsync(S->q_out, outages + 2 * first, sizeof(int) * 2 * (n - first),
+                        hipMemcpyHostToDevice, S->scopy) == hipSuccess;
+  if (ok) {
+    launch_fill_req(S->item_req, r->q0, (int)n, S->q_cap, slot, S->scopy);
+    ok = hipMemsetAsync(S->req_done + slot, 0, sizeof(int), S->scopy) == hipSuccess &&
+         hipStreamSynchronize(S->scopy) == hipSuccess;
+  }
+  if (!ok) {
+    S->owned.erase(r);
+    delete r;
+    return fail(CS_EDEVICE, "cs_submit: copy to the device failed");
+  }
+  S->table[slot] = r;
+  S->submitted += n;
+  lk.unlock();
+  S->cv_work.notify_all();
+  *out = r;
+  return CS_OK;
+}
+
+extern "C" int cs_wait(cs_req* r, int64_t timeout_us, cs_result* out, double* risk,
+                       double* latency_s) {
+  if (!r) return fail(CS_EINVAL, "cs_wait: NULL request");
+  cs_server* S = r->srv;
+  if (S) {
+    std::unique_lock<std::mutex> lk(S->m);
+    auto ready = [&] { return r->done; };
+    if (timeout_us < 0) S->cv_done.wait(lk, ready);
+    else if (!S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready))
+      return fail(CS_ETIMEDOUT, "cs_wait: request not complete");
+  }
+  if (!r->done) return fail(CS_ETIMEDOUT, "cs_wait: request not complete");
+  if (r->status != CS_OK) return fail(r->status, "cs_wait: " + r->msg);
+  if (out && r->n) std::memcpy(out, r->res.data(), sizeof(cs_result) * r->n);
+  if (risk && r->has_lam) std::memcpy(risk, r->risk.data(), sizeof(double) * r->risk.size());
+  if (latency_s) *latency_s = std::chrono::duration<double>(r->t1 - r->t0).count();
+  return CS_OK;
+}
+
+extern "C" void cs_req_free(cs_req* r) {
+  if (!r) return;
+  cs_server* S = r->srv;
+  if (!S) {
+    delete r;
+    return;
+  }
+  std::lock_guard<std::mutex> lk(S->m);
+  if (r->done) {
+    S->owned.erase(r);
+    delete r;
+  } else {
+    r->freed = true;
+  }
+}
+
 extern "C" int cs_detail(cs_ctx* c, cs_net* n, const int32_t outage[2], const cs_opts* opts,
                          cs_result* rec, double* vm, double* va, double* pg, double* qg,
                          double* eig_re, double* eig_im, int32_t* n_eig, int32_t* label) {
@@ -688,7 +1270,7 @@ extern "C" int cs_dense_solve_batched(const cs_ctx* c, double* d_A, int32_t n, i
   hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
   int* piv = nullptr;
   HIPCHK(hipMalloc(&piv, sizeof(int) * (size_t)n * batch));
-  launch_lu_solve(d_A, (size_t)lda * n, n, n + nrhs, lda, piv, n, nullptr, batch, d_info, st);
+  launch_lu_solve(d_A, (size_t)lda * n, n, n + nrhs, lda, piv, n, nullptr, 0, batch, d_info, st);
   hipError_t e = hipGetLastError();
   hipError_t e2 = hipStreamSynchronize(st);
   hipFree(piv);
@@ -722,7 +1304,7 @@ extern "C" int cs_kkt_at(cs_ctx* c, cs_net* n, const int32_t outage[2], int32_t 
   if (rc != CS_OK) return rc;
   HIPCHK(hipSetDevice(c->device));
   Plan p = plan_sizes(n);
-  rc = bind_workspace(c, n, p, 1);
+  rc = bind_workspace(&c->ws, &c->ws_bytes, n, p, 1);
   if (rc != CS_OK) return rc;
   const Slots& s = p.s;
   const DevNet& D = n->d;
@@ -732,12 +1314,13 @@ extern "C" int cs_kkt_at(cs_ctx* c, cs_net* n, const int32_t outage[2], int32_t 
   hipMemcpy(d_list, outage, sizeof(int) * 2, hipMemcpyHostToDevice);
   const int big = iters + 100000;
   const double tol = 1e-8;
-  launch_islands(D, s, d_list, 0, 1, st);
-  launch_setup_k(D, s, 1, d_list, 0, st);
+  launch_assign(s, 1, st);
+  launch_islands(D, s, d_list, 1, st);
+  launch_setup_k(D, s, 1, d_list, st);
   for (int it = 0; it < iters; ++it) {
     launch_opf_eval(D, s, 1, tol, big, st);
-    launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv, std::max(s.nk, s.ny), s.st, 1,
-                    nullptr, st);
+    launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv, std::max(s.nk, s.ny), s.st,
+                    PH_IPM, 1, nullptr, st);
     launch_opf_update(D, s, 1, 1e10, st);
   }
   launch_opf_eval(D, s, 1, tol, big, st);

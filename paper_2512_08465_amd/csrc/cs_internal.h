@@ -27,7 +27,16 @@ namespace cs {
 constexpr int kDyn = 14;     // H D Xd Xq Xdp Xqp Td0p Tq0p Rs KA TA R Tg Tt
 constexpr int kNsSg = 7;     // delta omega Eq' Ed' Efd Psv Pm
 
-enum Phase : int { PH_EMPTY = 0, PH_IPM = 1, PH_DYN = 2, PH_EIG = 3, PH_DONE = 4 };
+// Slot life cycle.  A free slot (EMPTY) is given the next scenario of the
+// list (NEW), islanded and set up (IPM), and leaves the interior-point loop
+// either converged (DYN) or finished without a dynamic model (DONE).  The
+// dynamic stage claims such slots in one step (DYN -> DYNB, DONE -> FIN),
+// forms the state matrix (DYNB -> EIG, or FIN on a numerical failure), takes
+// the eigenvalues, and writes the record, which frees the slot again.
+enum Phase : int {
+  PH_EMPTY = 0, PH_IPM = 1, PH_DYN = 2, PH_EIG = 3, PH_DONE = 4,
+  PH_NEW = 5, PH_DYNB = 6, PH_FIN = 7, PH_COUNT = 8
+};
 enum OpfStatus : int { OPF_CONVERGED = 0, OPF_MAXIT = 1, OPF_NUMERICAL = 2, OPF_NOT_RUN = 3 };
 enum Cause : int { C_ISLAND = 1, C_OPF = 2, C_LIMIT = 4, C_SSS = 8, C_NUMERICAL = 16 };
 enum Near : int { N_SSS = 1, N_OPF = 2, N_LIMIT = 4 };
@@ -90,28 +99,37 @@ struct Slots {
 
 // Launch wrappers (one per kernel file).
 void launch_islands(const DevNet& net, const Slots& s, const int* outages,
-                    long long scen0, int count, hipStream_t st);
+                    int count, hipStream_t st);
+void launch_setup_k(const DevNet& net, const Slots& s, int count, const int* outages,
+                    hipStream_t st);
 void launch_opf_eval(const DevNet& net, const Slots& s, int count, double tol,
                      int max_it, hipStream_t st);
 void launch_opf_update(const DevNet& net, const Slots& s, int count,
                        double gamma_max, hipStream_t st);
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
-                     int* piv, int piv_stride, SlotState* st, int count,
-                     int* info, hipStream_t stream);
+                     int* piv, int piv_stride, SlotState* st, int want_phase,
+                     int count, int* info, hipStream_t stream);
 void launch_dyn_assemble(const DevNet& net, const Slots& s, int count, hipStream_t st);
 void launch_form_state(const DevNet& net, const Slots& s, int count, hipStream_t st);
 void launch_eig(double* A, size_t stride, int lda, const int* n_per, int n_uniform,
                 double* wr, double* wi, int w_stride, SlotState* st, int count,
                 int* info, hipStream_t stream);
 void launch_classify(const Slots& s, int count, double near_eps, int max_it,
-                     void* results, hipStream_t st);
+                     void* results, const int* item_req, int* req_done, hipStream_t st);
 void launch_risk(const int* outages, long long n, const uint8_t* severe_src,
                  int sev_stride, const double* lam, int n_comp, double* risk,
                  hipStream_t st);
 void launch_validate(const int* outages, long long n, int n_comp, int* bad,
                      hipStream_t st);
-int count_active(const Slots& s, int count, int phase, int* d_counter,
-                 int* h_counter, hipStream_t st);
-int count_jobs(const Slots& s, int count, int* d_counter, int* h_counter, hipStream_t st);
+// slot scheduling
+void launch_refill(const Slots& s, int count, unsigned long long* next, long long n_scen,
+                   long long q_cap, hipStream_t st);
+void launch_assign(const Slots& s, int count, hipStream_t st);
+void launch_claim(const Slots& s, int count, hipStream_t st);
+void launch_phase_counts(const Slots& s, int count, int* out, hipStream_t st);
+void launch_gather_request(const int* q_out, const void* q_res, long long q0, int n,
+                           long long q_cap, int* out, void* res, hipStream_t st);
+void launch_fill_req(int* item_req, long long q0, int n, long long q_cap, int r, hipStream_t st);
+void launch_count_jobs(const Slots& s, int count, int* out, hipStream_t st);
 
 }  // namespace cs

@@ -351,9 +351,10 @@ __device__ inline void update_group(double* __restrict__ A, int lda, int n, int 
 __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
     double* __restrict__ Abase, size_t stride, int n, int ncols, int lda,
     int* __restrict__ pivbase, int piv_stride, SlotState* __restrict__ st,
-    int* __restrict__ info) {
+    int want_phase, int* __restrict__ info) {
   const int slot = blockIdx.x;
-  if (st != nullptr && st[slot].job == 0) return;
+  // with slot states: only the slots of one stage that asked for a solve
+  if (st != nullptr && (st[slot].job == 0 || st[slot].phase != want_phase)) return;
   double* __restrict__ A = Abase + (size_t)slot * stride;
   int* __restrict__ piv = pivbase + (size_t)slot * piv_stride;
   const int tid = threadIdx.x;
@@ -560,12 +561,12 @@ size_t lu_lds_bytes(int n, int nrhs) { return lu_dynamic_lds(n, nrhs) + LU_STATI
 int lu_max_order() { return LU_MAX_N; }
 
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
-                     int* piv, int piv_stride, SlotState* st, int count,
-                     int* info, hipStream_t stream) {
+                     int* piv, int piv_stride, SlotState* st, int want_phase,
+                     int count, int* info, hipStream_t stream) {
   if (count <= 0) return;
   const size_t lds = lu_dynamic_lds(n, ncols - n);
   hipLaunchKernelGGL(k_lu_solve, dim3(count), dim3(LU_THREADS), lds, stream,
-                     A, stride, n, ncols, lda, piv, piv_stride, st, info);
+                     A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, info);
 }
 
 void lu_set_attrs(size_t bytes) {

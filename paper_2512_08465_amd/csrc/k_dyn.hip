@@ -67,7 +67,7 @@ __global__ __launch_bounds__(DYN_THREADS) void k_dyn_assemble(DevNet net, Slots 
   const int slot = blockIdx.x;
   if (slot >= count) return;
   SlotState& S = s.st[slot];
-  if (S.phase != PH_DYN) return;
+  if (S.phase != PH_DYNB) return;
   const int nb = net.nb, nl = net.nl, ng = net.ng;
   const int ny = s.ny, ldy = s.ldy, nyc = s.nyc;
   const int tid = threadIdx.x;
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(DYN_THREADS) void k_form_state(DevNet net, Slots s,
   const int slot = blockIdx.x;
   if (slot >= count) return;
   SlotState& S = s.st[slot];
-  if (S.phase != PH_DYN) return;
+  if (S.phase != PH_DYNB) return;
   const int nb = net.nb, ng = net.ng;
   const int ny = s.ny, ldy = s.ldy, lda = s.lda_a;
   const int tid = threadIdx.x;
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(DYN_THREADS) void k_form_state(DevNet net, Slots s,
     S.job = 0;
     if (s_bad) {
       S.cause |= C_NUMERICAL;
-      S.phase = PH_DONE;
+      S.phase = PH_FIN;
     } else {
       S.phase = PH_EIG;
     }

@@ -17,12 +17,15 @@
 namespace cs {
 
 __global__ __launch_bounds__(64) void k_classify(Slots s, int count, double near_eps,
-                                                 int max_it, cs_result* __restrict__ out) {
+                                                 int max_it, cs_result* __restrict__ out,
+                                                 const int* __restrict__ item_req,
+                                                 int* __restrict__ req_done) {
   const int slot = blockIdx.x;
   if (slot >= count) return;
   SlotState& S = s.st[slot];
   const int lane = threadIdx.x;
   const int phase = S.phase;
+  if (phase != PH_EIG && phase != PH_FIN) return;     // only slots claimed and finished
   const bool have_eig = (phase == PH_EIG) && (S.qr_fail == 0);
   double alpha = -__builtin_inf(), zeta = __builtin_inf();
   bool osc_any = false;
@@ -78,14 +81,23 @@ __global__ __launch_bounds__(64) void k_classify(Slots s, int count, double near
   r.min_damping = zr;
   r.max_violation = mv;
   out[S.scen] = r;
-  S.phase = PH_DONE;
+  // serving: one more record of this scenario's request is complete (the
+  // record is visible device-wide before the count that announces it)
+  if (req_done != nullptr) {
+    __threadfence();
+    atomicAdd(&req_done[item_req[S.scen]], 1);
+  }
+  // the record and every read of this slot precede its release: a refill
+  // running on another stream may reuse the slot as soon as it sees EMPTY
+  __threadfence();
+  S.phase = PH_EMPTY;
 }
 
 void launch_classify(const Slots& s, int count, double near_eps, int max_it,
-                     void* results, hipStream_t st) {
+                     void* results, const int* item_req, int* req_done, hipStream_t st) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_classify, dim3(count), dim3(64), 0, st, s, count, near_eps,
-                     max_it, reinterpret_cast<cs_result*>(results));
+                     max_it, reinterpret_cast<cs_result*>(results), item_req, req_done);
 }
 
 __global__ __launch_bounds__(256) void k_risk(const int* __restrict__ outages, long long n,
@@ -114,44 +126,127 @@ void launch_risk(const int* outages, long long n, const uint8_t* severe_src,
                      severe_src, sev_stride, lam, n_comp, risk);
 }
 
-__global__ void k_count_phase(const SlotState* __restrict__ st, int count, int phase,
-                              int* __restrict__ out) {
-  __shared__ int acc;
-  if (threadIdx.x == 0) acc = 0;
-  __syncthreads();
-  int c = 0;
-  for (int i = threadIdx.x; i < count; i += blockDim.x) c += (st[i].phase == phase);
-  atomicAdd(&acc, c);
-  __syncthreads();
-  if (threadIdx.x == 0) *out = acc;
+// ------------------------------------------------------------- scheduling
+// Give every free slot the next scenario of the list (one thread per slot;
+// the order in which slots draw is irrelevant, each scenario's arithmetic
+// depends on its own data only).  Scenario k of the stream of work sits at
+// position k % q_cap of the list (a ring when serving).
+__global__ void k_refill(SlotState* __restrict__ st, int count,
+                         unsigned long long* __restrict__ next, long long n_scen, long long q_cap) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= count || st[slot].phase != PH_EMPTY) return;
+  const unsigned long long k = atomicAdd(next, 1ull);
+  if ((long long)k >= n_scen) {
+    // give the number back: scenarios admitted later (serving) start at
+    // n_scen, so the counter must end this launch at n_scen exactly
+    atomicSub(next, 1ull);
+    return;
+  }
+  st[slot].scen = (int)((long long)k % q_cap);
+  st[slot].job = 0;
+  st[slot].phase = PH_NEW;
 }
 
+// Slot i takes scenario i (single-scenario entry points).
+__global__ void k_assign(SlotState* __restrict__ st, int count) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= count) return;
+  st[slot].scen = slot;
+  st[slot].job = 0;
+  st[slot].phase = PH_NEW;
+}
+
+// Hand the slots that left the interior-point loop to the dynamic stage.
+__global__ void k_claim(SlotState* __restrict__ st, int count) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= count) return;
+  const int ph = st[slot].phase;
+  if (ph == PH_DYN) st[slot].phase = PH_DYNB;
+  else if (ph == PH_DONE) st[slot].phase = PH_FIN;
+}
+
+// out[p] = number of slots in phase p (p < PH_COUNT).
+__global__ void k_phase_counts(const SlotState* __restrict__ st, int count,
+                               int* __restrict__ out) {
+  __shared__ int acc[PH_COUNT];
+  if (threadIdx.x < PH_COUNT) acc[threadIdx.x] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    const int ph = st[i].phase;
+    if (ph >= 0 && ph < PH_COUNT) atomicAdd(&acc[ph], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < PH_COUNT) out[threadIdx.x] = acc[threadIdx.x];
+}
+
+// Number of interior-point slots that asked for a KKT solve this round.
 __global__ void k_count_jobs(const SlotState* __restrict__ st, int count, int* __restrict__ out) {
   __shared__ int acc;
   if (threadIdx.x == 0) acc = 0;
   __syncthreads();
   int c = 0;
-  for (int i = threadIdx.x; i < count; i += blockDim.x) c += (st[i].job != 0);
+  for (int i = threadIdx.x; i < count; i += blockDim.x)
+    c += (st[i].job != 0 && st[i].phase == PH_IPM);
   atomicAdd(&acc, c);
   __syncthreads();
   if (threadIdx.x == 0) *out = acc;
 }
 
-int count_jobs(const Slots& s, int count, int* d_counter, int* h_counter, hipStream_t st) {
-  hipLaunchKernelGGL(k_count_jobs, dim3(1), dim3(1024), 0, st, s.st, count, d_counter);
-  if (hipMemcpyAsync(h_counter, d_counter, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
-    return -1;
-  if (hipStreamSynchronize(st) != hipSuccess) return -1;
-  return *h_counter;
+void launch_refill(const Slots& s, int count, unsigned long long* next, long long n_scen,
+                   long long q_cap, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_refill, dim3((count + 255) / 256), dim3(256), 0, st, s.st, count, next,
+                     n_scen, q_cap);
 }
 
-int count_active(const Slots& s, int count, int phase, int* d_counter,
-                 int* h_counter, hipStream_t st) {
-  hipLaunchKernelGGL(k_count_phase, dim3(1), dim3(1024), 0, st, s.st, count, phase, d_counter);
-  if (hipMemcpyAsync(h_counter, d_counter, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
-    return -1;
-  if (hipStreamSynchronize(st) != hipSuccess) return -1;
-  return *h_counter;
+void launch_assign(const Slots& s, int count, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_assign, dim3((count + 255) / 256), dim3(256), 0, st, s.st, count);
+}
+
+void launch_claim(const Slots& s, int count, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_claim, dim3((count + 255) / 256), dim3(256), 0, st, s.st, count);
+}
+
+void launch_phase_counts(const Slots& s, int count, int* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_phase_counts, dim3(1), dim3(1024), 0, st, s.st, count, out);
+}
+
+// Copy ring positions [q0, q0 + n) (mod q_cap) of the list and its records
+// to contiguous buffers (a served request's risk reduction).
+__global__ void k_gather_request(const int* __restrict__ q_out, const cs_result* __restrict__ q_res,
+                                 long long q0, int n, long long q_cap, int* __restrict__ out,
+                                 cs_result* __restrict__ res) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const long long k = (q0 + i) % q_cap;
+  out[2 * i] = q_out[2 * k];
+  out[2 * i + 1] = q_out[2 * k + 1];
+  res[i] = q_res[k];
+}
+
+void launch_gather_request(const int* q_out, const void* q_res, long long q0, int n,
+                           long long q_cap, int* out, void* res, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gather_request, dim3((n + 255) / 256), dim3(256), 0, st, q_out,
+                     reinterpret_cast<const cs_result*>(q_res), q0, n, q_cap, out,
+                     reinterpret_cast<cs_result*>(res));
+}
+
+// Set list positions [q0, q0 + n) (mod q_cap) to request index r.
+__global__ void k_fill_req(int* __restrict__ item_req, long long q0, int n, long long q_cap, int r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) item_req[(q0 + i) % q_cap] = r;
+}
+
+void launch_fill_req(int* item_req, long long q0, int n, long long q_cap, int r, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_req, dim3((n + 255) / 256), dim3(256), 0, st, item_req, q0, n, q_cap, r);
+}
+
+void launch_count_jobs(const Slots& s, int count, int* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_jobs, dim3(1), dim3(1024), 0, st, s.st, count, out);
 }
 
 }  // namespace cs

@@ -108,16 +108,16 @@ __device__ inline int risum(int v, int* red) {
 
 // ---------------------------------------------------------------- setup
 __global__ __launch_bounds__(OPF_THREADS) void k_setup(DevNet net, Slots s,
-                                                       int count, const int* __restrict__ outages,
-                                                       long long scen0) {
+                                                       int count, const int* __restrict__ outages) {
   const int slot = blockIdx.x;
   if (slot >= count) return;
   SlotState& S = s.st[slot];
+  if (S.phase != PH_NEW) return;
   const int nb = net.nb, nl = net.nl, ng = net.ng;
   const int tid = threadIdx.x;
   __shared__ double red[OPF_THREADS / 64];
   __shared__ int ired[OPF_THREADS / 64];
-  const long long scen = scen0 + slot;
+  const long long scen = S.scen;
   const int o0 = outages[2 * scen], o1 = outages[2 * scen + 1];
   const int main = S.main_label;
   const int* label = s.label + (size_t)slot * nb;
@@ -213,6 +213,7 @@ __global__ __launch_bounds__(OPF_THREADS) void k_setup(DevNet net, Slots s,
         const int i = 2 * nl + 2 * nb + k * ng + g;
         v.mu[i] = 1.0 / v.z[i];
       }
+  __syncthreads();
   if (tid == 0) {
     S.n_ineq = n_ineq;
     S.gamma = 1.0;
@@ -706,10 +707,10 @@ void opf_set_attrs(size_t bytes) {
 }
 
 void launch_setup_k(const DevNet& net, const Slots& s, int count,
-                    const int* outages, long long scen0, hipStream_t st) {
+                    const int* outages, hipStream_t st) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_setup, dim3(count), dim3(OPF_THREADS), 0, st, net, s,
-                     count, outages, scen0);
+                     count, outages);
 }
 
 void launch_opf_eval(const DevNet& net, const Slots& s, int count, double tol,

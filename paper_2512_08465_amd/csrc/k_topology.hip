@@ -26,13 +26,13 @@ __device__ inline int uf_find(volatile int* parent, int x) {
 
 __global__ __launch_bounds__(64) void k_islands(DevNet net, Slots s,
                                                 const int* __restrict__ outages,
-                                                long long scen0, int count) {
+                                                int count) {
   const int slot = blockIdx.x;
-  if (slot >= count) return;
+  if (slot >= count || s.st[slot].phase != PH_NEW) return;
   extern __shared__ int parent[];
   __shared__ int roots_count;
   const int lane = threadIdx.x;
-  const long long scen = scen0 + slot;
+  const long long scen = s.st[slot].scen;
   const int o0 = outages[2 * scen], o1 = outages[2 * scen + 1];
   const int nb = net.nb, nl = net.nl, ng = net.ng;
   const int gen0 = nl, load0 = nl + ng;
@@ -94,8 +94,6 @@ __global__ __launch_bounds__(64) void k_islands(DevNet net, Slots s,
   (void)load0;
   if (lane == 0) {
     SlotState& S = s.st[slot];
-    S.scen = (int)scen;
-    S.phase = PH_IPM;
     S.status = OPF_NOT_RUN;
     S.iters = 0;
     S.n_islands = nroots;
@@ -117,10 +115,10 @@ __global__ __launch_bounds__(64) void k_islands(DevNet net, Slots s,
 }
 
 void launch_islands(const DevNet& net, const Slots& s, const int* outages,
-                    long long scen0, int count, hipStream_t st) {
+                    int count, hipStream_t st) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_islands, dim3(count), dim3(64), sizeof(int) * net.nb, st,
-                     net, s, outages, scen0, count);
+                     net, s, outages, count);
 }
 
 // outage list check: ids in range, j == -1 or a distinct id

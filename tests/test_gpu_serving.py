@@ -1,0 +1,130 @@
+"""Serving (continuous batching) through the C-ABI: requests admitted into a
+running server give, record for record, what cs_screen gives for the same
+list alone, whether they run alone or overlap with other requests; the ring
+refuses what does not fit (CS_EAGAIN) and a wait can time out."""
+import threading
+
+import numpy as np
+import pytest
+
+from helpers import load_case, load_golden
+
+pytestmark = pytest.mark.gpu
+
+FIELDS_EXACT = ("severe", "cause", "opf_status", "near", "n_islands", "opf_iters", "n_states")
+FIELDS_FLOAT = ("opf_cost", "max_real_eig", "min_damping", "max_violation")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2512_08465_amd as cs
+    return cs.Context(0)
+
+
+@pytest.fixture(scope="module")
+def nets(ctx):
+    import paper_2512_08465_amd as cs
+    return {k: (cs.Network(ctx, load_case(k)), load_case(k)) for k in ("c1_30", "c2_118")}
+
+
+def _same(a, b):
+    for k in FIELDS_EXACT:
+        assert np.array_equal(a[k], b[k]), k
+    for k in FIELDS_FLOAT:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+def _lists(name, sizes, seed):
+    g = load_golden(name)["outages"]
+    rng = np.random.default_rng(seed)
+    return [g[np.sort(rng.choice(len(g), k, replace=False))] for k in sizes]
+
+
+def test_requests_in_a_mix_equal_alone(nets):
+    import paper_2512_08465_amd as cs
+    net, case = nets["c1_30"]
+    lists = _lists("c1_30", [120, 7, 300, 1, 55], seed=1)
+    solo = [net.screen(l, case["lam"]) for l in lists]
+    srv = cs.Server(net.ctx, net, cs.default_options(batch=64), queue_capacity=4096)
+    reqs = [srv.submit(l, case["lam"]) for l in lists]
+    for (res_s, risk_s), r in zip(solo, reqs):
+        res, risk, lat = r.wait(timeout_s=100)
+        _same(res, res_s)
+        assert np.array_equal(risk, risk_s)
+        assert lat > 0
+    srv.close()
+
+
+def test_arrivals_while_running_118(nets):
+    """Requests submitted from another thread while earlier ones are on the
+    device; the second network size runs in its own server at the same time."""
+    import paper_2512_08465_amd as cs
+    net, case = nets["c2_118"]
+    net1, case1 = nets["c1_30"]
+    lists = _lists("c2_118", [200, 40, 90], seed=2)
+    lists1 = _lists("c1_30", [100, 100], seed=3)
+    solo = [net.screen(l, case["lam"]) for l in lists]
+    solo1 = [net1.screen(l, case1["lam"]) for l in lists1]
+    srv = cs.Server(net.ctx, net, cs.default_options(batch=128), queue_capacity=1024)
+    srv1 = cs.Server(net1.ctx, net1, cs.default_options(batch=32), queue_capacity=1024)
+    reqs = [srv.submit(lists[0], case["lam"])]
+    out = {}
+
+    def later():
+        out["r"] = [srv.submit(l, case["lam"]) for l in lists[1:]]
+        out["r1"] = [srv1.submit(l, case1["lam"]) for l in lists1]
+
+    t = threading.Thread(target=later)
+    t.start()
+    t.join()
+    reqs += out["r"]
+    for (res_s, risk_s), r in zip(solo, reqs):
+        res, risk, _ = r.wait(timeout_s=100)
+        _same(res, res_s)
+        assert np.array_equal(risk, risk_s)
+    for (res_s, risk_s), r in zip(solo1, out["r1"]):
+        res, risk, _ = r.wait(timeout_s=100)
+        _same(res, res_s)
+        assert np.array_equal(risk, risk_s)
+    srv.close()
+    srv1.close()
+
+
+def test_ring_full_and_timeout(nets):
+    import paper_2512_08465_amd as cs
+    net, case = nets["c2_118"]
+    lists = _lists("c2_118", [60, 30], seed=4)
+    srv = cs.Server(net.ctx, net, cs.default_options(batch=32), queue_capacity=80)
+    r0 = srv.submit(lists[0], case["lam"])
+    with pytest.raises(cs.CSError) as e:            # 60 + 30 > 80 positions
+        srv.submit(lists[1], case["lam"])
+    assert e.value.code == cs.CS_EAGAIN
+    with pytest.raises(cs.CSError) as e:            # 60 scenarios of the 118-bus case
+        r0.wait(timeout_s=0)
+    assert e.value.code == cs.CS_ETIMEDOUT
+    res0, _, _ = r0.wait(timeout_s=100)
+    r1 = srv.submit(lists[1], case["lam"])          # room again
+    res1, _, _ = r1.wait(timeout_s=100)
+    _same(res0, net.screen(lists[0], case["lam"])[0])
+    _same(res1, net.screen(lists[1], case["lam"])[0])
+    with pytest.raises(cs.CSError) as e:
+        srv.submit(np.array([[0, 0]]), case["lam"])
+    assert e.value.code == cs.CS_EINVAL
+    empty, risk, _ = srv.submit(np.zeros((0, 2), np.int32), case["lam"]).wait(timeout_s=1)
+    assert len(empty) == 0 and np.all(risk == 0)
+    srv.close()
+
+
+def test_overlapped_streams_and_refill_equal(nets):
+    """Two streams, and slots refilled many times over (batch much smaller
+    than the list), give the same records as one stream with every scenario
+    resident."""
+    import paper_2512_08465_amd as cs
+    net, case = nets["c2_118"]
+    lst = _lists("c2_118", [300], seed=5)[0]
+    a, Ra = net.screen(lst, case["lam"])
+    b, Rb = net.screen(lst, case["lam"], cs.default_options(batch=48, overlap=1))
+    c, Rc = net.screen(lst, case["lam"], cs.default_options(batch=100, overlap=0))
+    _same(a, b)
+    _same(a, c)
+    assert np.array_equal(Ra, Rb) and np.array_equal(Ra, Rc)
