@@ -28,6 +28,7 @@ for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
 
 METRIC = "N-2 scenarios/s (OPF+eigs) on 118-bus shape; p99 request latency; FP64 vs mixed"
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
 
 
 def kkt_lu_flops(n: int) -> float:
@@ -85,10 +86,17 @@ def main():
     ap.add_argument("--step-size", type=int, default=4096)
     ap.add_argument("--batch", type=int, default=0,
                     help="scenario slots resident at once (0: as many as the step)")
+    ap.add_argument("--prec", choices=("fp64", "mixed"), default="fp64",
+                    help="mixed: FP32 KKT factorisation + FP64 refinement")
     ap.add_argument("--overlap", type=int, default=0,
                     help="1: dynamic stage on a second stream beside the OPF iterations")
     ap.add_argument("--full", action="store_true", help="one step = the whole 57,630 list")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests in the serving measurement (0: skip it)")
+    ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-max-len", type=int, default=1000,
+                    help="request lengths are log-uniform integers in [1, this]")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -134,8 +142,9 @@ def main():
                           stream=stream.cuda_stream)
         return cnt
 
-    plain = cs.default_options(batch=args.batch, overlap=args.overlap)
-    timed = cs.default_options(batch=args.batch, overlap=args.overlap, timing=1)
+    prec = cs.PREC_MIXED if args.prec == "mixed" else cs.PREC_FP64
+    plain = cs.default_options(batch=args.batch, overlap=args.overlap, prec=prec)
+    timed = cs.default_options(batch=args.batch, overlap=args.overlap, prec=prec, timing=1)
     for w in range(args.warmup):
         run_step(w, plain)
         log(f"warmup step {w + 1}/{args.warmup} done")
@@ -156,6 +165,8 @@ def main():
     lu_avg_ms = lu["ms"] / max(lu["launches"], 1)
     lu_fact_per_launch = lu["units"] / max(lu["launches"], 1)
     achieved = lu_fact_per_launch * kkt_lu_flops(nk) / (lu_avg_ms * 1e-3) / 1e12 if lu["ms"] else 0.0
+    mixed = args.prec == "mixed"
+    peak = PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS
     total_ms = sum(v["ms"] for k, v in st.items() if isinstance(v, dict))
     breakdown = {k: round(v["ms"] / max(total_ms, 1e-9), 4) for k, v in st.items()
                  if isinstance(v, dict)}
@@ -170,13 +181,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {
             "workload": "c2_118: seeded synthetic 118-bus-shaped network (186 branches, "
                         "54 synchronous generators with AVR and governor, 99 loads); "
-                        "N-1 + unordered N-2 over all 339 components = 57,630 scenarios; "
-                        "FP64 plain method",
+                        "N-1 + unordered N-2 over all 339 components = 57,630 scenarios; " +
+                        ("KKT LU in FP32 with FP64 refinement, everything else FP64" if mixed
+                         else "FP64 plain method"),
             "scenarios_per_step": step,
             "slots": args.batch or step,
             "overlap": args.overlap,
@@ -184,25 +196,67 @@ def main():
             "state_order": 7 * int(case["n_gen"]) - 1,
         },
         "roofline": {
-            "kernel": "k_lu_solve (KKT LU + solve)",
+            "kernel": "k_lu_solve%s (KKT LU + solve)" % ("<float>" if mixed else "<double>"),
             "bound": "mfma",
             "achieved": round(achieved, 4),
-            "peak": PEAK_FP64_TFLOPS,
+            "peak": peak,
             "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP64_TFLOPS, 5),
+            "frac": round(achieved / peak, 5),
             "traffic": None,
             "avg_launch_ms": round(lu_avg_ms, 4),
             "factorisations_per_launch": round(lu_fact_per_launch, 1),
         },
         "kernel_time_share": breakdown,
+        "kkt_solves": {"factorisations": int(lu["units"]),
+                       "fp64_fallbacks": int(st["kkt_lu64"]["units"]) if mixed else None},
         "results": {
             "screened": int(done),
             "severe_fraction": round(float(np.mean(res["severe"][:min(n_all, done)])), 4),
         },
     }
+    if args.serve_requests > 0:
+        out["serving"] = serve(cs, ctx, net, case, lst, args)
     if base is not None:
         out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
+
+
+def serve(cs, ctx, net, case, lst, args):
+    """Requests arriving as a Poisson process, each a random slice of the
+    list with a log-uniform length, admitted into a running server; p50/p99
+    latency from admission to the last record."""
+    import numpy as np
+    rng = np.random.default_rng(5000)
+    gaps = rng.exponential(1.0 / args.serve_rate, args.serve_requests)
+    lens = np.floor(np.exp(rng.uniform(0, np.log(args.serve_max_len + 1), args.serve_requests)))
+    lens = np.clip(lens.astype(int), 1, args.serve_max_len)
+    lists = [lst[rng.choice(len(lst), k, replace=False)] for k in lens]
+    srv = cs.Server(ctx, net, cs.default_options(batch=2048), queue_capacity=1 << 16)
+    log(f"serving: {args.serve_requests} requests at {args.serve_rate}/s")
+    reqs = []
+    t0 = time.perf_counter()
+    due = t0
+    for k, (g, l) in enumerate(zip(gaps, lists)):
+        due += g
+        time.sleep(max(0.0, due - time.perf_counter()))
+        reqs.append(srv.submit(l, case["lam"]))
+        if (k + 1) % 10 == 0:
+            log(f"serving: {k + 1} submitted")
+    lat = []
+    for r in reqs:
+        _, _, l = r.wait(timeout_s=600)
+        lat.append(l)
+        r.close()
+    dt = time.perf_counter() - t0
+    srv.close()
+    lat = np.array(lat)
+    return dict(requests=int(args.serve_requests), rate_per_s=args.serve_rate,
+                length="log-uniform integer in [1, %d]" % args.serve_max_len,
+                scenarios=int(lens.sum()), slots=2048,
+                p50_latency_s=round(float(np.percentile(lat, 50)), 4),
+                p99_latency_s=round(float(np.percentile(lat, 99)), 4),
+                scenarios_per_s=round(float(lens.sum()) / dt, 2),
+                wall_s=round(dt, 2))
 
 
 if __name__ == "__main__":

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define CS_ABI_VERSION 3
+#define CS_ABI_VERSION 4
 
 enum {
   CS_OK = 0,
@@ -56,7 +56,12 @@ enum {
   CS_ETIMEDOUT = -7     /* serving: the request is not complete yet            */
 };
 
-enum { CS_PREC_FP64 = 0 };
+/* CS_PREC_FP64: every step in FP64.  CS_PREC_MIXED: the KKT systems are
+ * factorised in FP32 on the matrix cores and each Newton step refined in FP64
+ * to the backward error of an FP64 solve (FP64 factorisation when that is not
+ * reached); everything else, the state matrix and the eigenvalues included,
+ * stays FP64. */
+enum { CS_PREC_FP64 = 0, CS_PREC_MIXED = 1 };
 
 /* cause bits of cs_result.cause (severity criteria of Section II.B) */
 enum {
@@ -99,7 +104,7 @@ typedef struct {
 } cs_net_desc;
 
 typedef struct {
-  int32_t prec;        /* CS_PREC_FP64                                        */
+  int32_t prec;        /* CS_PREC_FP64 (default) or CS_PREC_MIXED             */
   int32_t max_it;      /* IPM iteration cap (default 150)                     */
   double tol;          /* IPM termination tolerance (default 1e-8)            */
   double near_eps;     /* |max Re lambda| flagged as near (default 1e-6)      */
@@ -118,7 +123,11 @@ typedef struct {
  * since the last cs_stats_reset.  units = matrices or scenarios processed. */
 enum { CS_K_TOPOLOGY = 0, CS_K_KKT_ASSEMBLE, CS_K_KKT_LU, CS_K_IPM_UPDATE,
        CS_K_DYN_ASSEMBLE, CS_K_DYN_LU, CS_K_STATE_MATRIX, CS_K_EIG, CS_K_CLASSIFY,
-       CS_K_RISK, CS_K_COUNT };
+       CS_K_RISK, CS_K_KKT_REFINE, CS_K_KKT_LU64, CS_K_COUNT };
+/* CS_K_KKT_LU is the KKT factorisation in the call's precision (FP32 for
+ * CS_PREC_MIXED); CS_K_KKT_REFINE the FP64 refinement (with the FP32
+ * conversion) and CS_K_KKT_LU64 the FP64 fallback factorisations of the
+ * mixed path (units = systems that needed one). */
 typedef struct {
   double ms[CS_K_COUNT];          /* summed launch durations                 */
   int64_t launches[CS_K_COUNT];

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libcs.so")
 
 CS_OK, CS_EINVAL, CS_ENOMEM, CS_EHBM, CS_EDEVICE, CS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 CS_EAGAIN, CS_ETIMEDOUT = -6, -7
+PREC_FP64, PREC_MIXED = 0, 1
 CAUSE_ISLAND, CAUSE_OPF, CAUSE_LIMIT, CAUSE_SSS, CAUSE_NUMERICAL = 1, 2, 4, 8, 16
 OPF_CONVERGED, OPF_MAXIT, OPF_NUMERICAL, OPF_NOT_RUN = 0, 1, 2, 3
 NEAR_SSS, NEAR_OPF, NEAR_LIMIT = 1, 2, 4
@@ -55,7 +56,7 @@ class Options(ctypes.Structure):
 
 
 KERNELS = ("topology", "kkt_assemble", "kkt_lu", "ipm_update", "dyn_assemble", "dyn_lu",
-           "state_matrix", "eig", "classify", "risk")
+           "state_matrix", "eig", "classify", "risk", "kkt_refine", "kkt_lu64")
 
 
 class Stats(ctypes.Structure):

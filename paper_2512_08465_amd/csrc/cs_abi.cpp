@@ -40,6 +40,7 @@ void lu_set_attrs(size_t bytes);
 void opf_set_attrs(size_t bytes);
 void dyn_set_attrs(size_t bytes);
 constexpr size_t kLdsMax = 160 * 1024;
+constexpr int kRefineMax = 10;     // FP64 refinement steps of a mixed-precision solve
 }  // namespace cs
 
 using namespace cs;
@@ -411,7 +412,7 @@ struct Plan {
   size_t per_slot = 0;
 };
 
-static Plan plan_sizes(const cs_net* n) {
+static Plan plan_sizes(const cs_net* n, bool mixed) {
   Plan p;
   Slots& s = p.s;
   const int nb = n->nb, nl = n->nl, ng = n->ng;
@@ -432,6 +433,14 @@ static Plan plan_sizes(const cs_net* n) {
                     2 * (size_t)nb +
                     2 * (size_t)s.na) +
                4 * ((size_t)nb + piv) + nb + nl + ng + sizeof(SlotState) + 16 * 64;
+  if (mixed) {
+    s.ld32 = (int)round_up(s.nk + 1, 4);
+    s.k32_stride = round_up((size_t)s.nk * s.ld32, 64);
+    p.per_slot += 4 * s.k32_stride;
+  } else {
+    s.ld32 = 0;
+    s.k32_stride = 0;
+  }
   return p;
 }
 
@@ -464,6 +473,7 @@ static int bind_workspace(void** ws, size_t* ws_bytes, const cs_net* n, Plan& p,
   const size_t obr = take(nl * B + 64);
   const size_t ogen = take(ng * B + 64);
   const size_t ost = take(sizeof(SlotState) * (size_t)B);
+  const size_t o32 = take(4 * s.k32_stride * B);
   const size_t need = off;
   if (need > *ws_bytes) {
     if (*ws) hipFree(*ws);
@@ -492,6 +502,7 @@ static int bind_workspace(void** ws, size_t* ws_bytes, const cs_net* n, Plan& p,
   s.br_on = reinterpret_cast<uint8_t*>(base + obr);
   s.gen_on = reinterpret_cast<uint8_t*>(base + ogen);
   s.st = reinterpret_cast<SlotState*>(base + ost);
+  s.K32 = s.k32_stride ? reinterpret_cast<float*>(base + o32) : nullptr;
   return CS_OK;
 }
 
@@ -574,13 +585,35 @@ struct Engine {
                  [&] { launch_opf_eval(*D, s, nslots, opts.tol, opts.max_it, st); });
       if (rc != CS_OK) return rc;
       const int u = T ? T->unit_slot() : -1;
-      if (u >= 0) launch_count_jobs(s, nslots, c->d_units + u, st);
-      rc = timed(CS_K_KKT_LU, st, 0, u, [&] {
-        launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv, pstride, s.st, PH_IPM,
-                        nslots, nullptr, st);
-      });
+      if (opts.prec == CS_PREC_MIXED) {
+        // (scenarios already on FP64 factorisations are switched to job 3 here)
+        rc = timed(CS_K_KKT_REFINE, st, 0, -1, [&] { launch_kkt_to_f32(s, nslots, st); });
+        if (rc != CS_OK) return rc;
+        if (u >= 0) launch_count_jobs(s, nslots, 1, c->d_units + u, st);
+        rc = timed(CS_K_KKT_LU, st, 0, u, [&] {
+          launch_lu_solve_f32(s.K32, s.k32_stride, s.nk, s.nk + 1, s.ld32, s.piv, pstride, s.st,
+                              PH_IPM, 1, nslots, nullptr, st);
+        });
+        if (rc != CS_OK) return rc;
+        rc = timed(CS_K_KKT_REFINE, st, 0, -1,
+                   [&] { launch_kkt_refine(s, nslots, pstride, kRefineMax, st); });
+        if (rc != CS_OK) return rc;
+        const int u3 = T ? T->unit_slot() : -1;
+        if (u3 >= 0) launch_count_jobs(s, nslots, 3, c->d_units + u3, st);
+        rc = timed(CS_K_KKT_LU64, st, 0, u3, [&] {
+          launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv, pstride, s.st, PH_IPM, 3,
+                          nslots, nullptr, st);
+        });
+      } else {
+        if (u >= 0) launch_count_jobs(s, nslots, 1, c->d_units + u, st);
+        rc = timed(CS_K_KKT_LU, st, 0, u, [&] {
+          launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv, pstride, s.st, PH_IPM, 1,
+                          nslots, nullptr, st);
+        });
+      }
       if (rc != CS_OK) return rc;
-      rc = timed(CS_K_IPM_UPDATE, st, 0, u, [&] { launch_opf_update(*D, s, nslots, 1e10, st); });
+      rc = timed(CS_K_IPM_UPDATE, st, cnt[PH_IPM], -1,
+                 [&] { launch_opf_update(*D, s, nslots, 1e10, st); });
       if (rc != CS_OK) return rc;
     }
     if ((rc = count()) != CS_OK) return rc;
@@ -611,7 +644,7 @@ struct Engine {
       rc = timed(CS_K_DYN_ASSEMBLE, sd, ndyn, -1, [&] { launch_dyn_assemble(*D, s, nslots, sd); });
       if (rc != CS_OK) return rc;
       rc = timed(CS_K_DYN_LU, sd, ndyn, -1, [&] {
-        launch_lu_solve(s.K, s.k_stride, s.ny, s.nyc, s.ldy, s.piv, pstride, s.st, PH_DYNB,
+        launch_lu_solve(s.K, s.k_stride, s.ny, s.nyc, s.ldy, s.piv, pstride, s.st, PH_DYNB, 1,
                         nslots, nullptr, sd);
       });
       if (rc != CS_OK) return rc;
@@ -660,7 +693,8 @@ struct Engine {
 
 // ------------------------------------------------------------------ screen
 static int check_opts(const cs_opts& opts, const char* who) {
-  if (opts.prec != CS_PREC_FP64) return fail(CS_EUNSUPPORTED, std::string(who) + ": only CS_PREC_FP64");
+  if (opts.prec != CS_PREC_FP64 && opts.prec != CS_PREC_MIXED)
+    return fail(CS_EINVAL, std::string(who) + ": prec must be CS_PREC_FP64 or CS_PREC_MIXED");
   if (opts.max_it < 1 || opts.max_it > 10000) return fail(CS_EINVAL, std::string(who) + ": max_it out of range");
   if (!(opts.tol > 0)) return fail(CS_EINVAL, std::string(who) + ": tol must be > 0");
   return CS_OK;
@@ -675,7 +709,7 @@ static int run_screen(cs_ctx* c, cs_net* n, const int* d_out_list, long long N,
   int rc = check_opts(opts, "cs_screen");
   if (rc != CS_OK) return rc;
   HIPCHK(hipSetDevice(c->device));
-  Plan p = plan_sizes(n);
+  Plan p = plan_sizes(n, opts.prec == CS_PREC_MIXED);
   const size_t budget = opts.hbm_budget ? opts.hbm_budget : c->hbm_budget;
   if (p.per_slot > budget)
     return fail(CS_EHBM, "cs_screen: one scenario needs " + std::to_string(p.per_slot) +
@@ -992,7 +1026,7 @@ extern "C" int cs_server_create(cs_ctx* c, cs_net* n, const cs_opts* o,
   S->opts = opts;
   S->q_cap = queue_capacity;
   S->table.assign(cs_server::R, nullptr);
-  S->p = plan_sizes(n);
+  S->p = plan_sizes(n, opts.prec == CS_PREC_MIXED);
   const size_t budget = opts.hbm_budget ? opts.hbm_budget : c->hbm_budget;
   auto bail = [&](int code, const std::string& msg) {
     cs_server_destroy(S);
@@ -1270,7 +1304,7 @@ extern "C" int cs_dense_solve_batched(const cs_ctx* c, double* d_A, int32_t n, i
   hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
   int* piv = nullptr;
   HIPCHK(hipMalloc(&piv, sizeof(int) * (size_t)n * batch));
-  launch_lu_solve(d_A, (size_t)lda * n, n, n + nrhs, lda, piv, n, nullptr, 0, batch, d_info, st);
+  launch_lu_solve(d_A, (size_t)lda * n, n, n + nrhs, lda, piv, n, nullptr, 0, 0, batch, d_info, st);
   hipError_t e = hipGetLastError();
   hipError_t e2 = hipStreamSynchronize(st);
   hipFree(piv);
@@ -1303,7 +1337,7 @@ extern "C" int cs_kkt_at(cs_ctx* c, cs_net* n, const int32_t outage[2], int32_t 
   int rc = validate_host(n, outage, 1, nullptr);
   if (rc != CS_OK) return rc;
   HIPCHK(hipSetDevice(c->device));
-  Plan p = plan_sizes(n);
+  Plan p = plan_sizes(n, false);
   rc = bind_workspace(&c->ws, &c->ws_bytes, n, p, 1);
   if (rc != CS_OK) return rc;
   const Slots& s = p.s;
@@ -1320,7 +1354,7 @@ extern "C" int cs_kkt_at(cs_ctx* c, cs_net* n, const int32_t outage[2], int32_t 
   for (int it = 0; it < iters; ++it) {
     launch_opf_eval(D, s, 1, tol, big, st);
     launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv, std::max(s.nk, s.ny), s.st,
-                    PH_IPM, 1, nullptr, st);
+                    PH_IPM, 1, 1, nullptr, st);
     launch_opf_update(D, s, 1, 1e10, st);
   }
   launch_opf_eval(D, s, 1, tol, big, st);

@@ -72,6 +72,7 @@ struct SlotState {
   int singular;    // exactly zero pivot met in the last factorisation
   int n_states;    // order of the reduced state matrix
   int cause, near, qr_fail;
+  int fp64_only;   // mixed precision: an FP32 solve of this scenario failed to refine
   double gamma, f, f_prev, max_viol, alpha, zeta;
   double metrics[4];
 };
@@ -84,6 +85,9 @@ struct Slots {
   size_t k_stride;              // doubles per slot in K
   size_t a_stride;              // doubles per slot in A
   double* K;
+  float* K32;                   // mixed precision: FP32 copy / factors of K, row stride ld32
+  int ld32;
+  size_t k32_stride;            // floats per slot in K32
   int* piv;                     // [B][max(nk, ny)]
   double* x; double* lam; double* z; double* mu;
   double* hv;                   // [B][ni] inequality values at the last evaluation
@@ -106,9 +110,14 @@ void launch_opf_eval(const DevNet& net, const Slots& s, int count, double tol,
                      int max_it, hipStream_t st);
 void launch_opf_update(const DevNet& net, const Slots& s, int count,
                        double gamma_max, hipStream_t st);
+// batched LU + solve; with slot states, only slots with st.job == want_job
+// in phase want_phase
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
-                     int* piv, int piv_stride, SlotState* st, int want_phase,
+                     int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
                      int count, int* info, hipStream_t stream);
+void launch_lu_solve_f32(float* A, size_t stride, int n, int ncols, int lda,
+                         int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
+                         int count, int* info, hipStream_t stream);
 void launch_dyn_assemble(const DevNet& net, const Slots& s, int count, hipStream_t st);
 void launch_form_state(const DevNet& net, const Slots& s, int count, hipStream_t st);
 void launch_eig(double* A, size_t stride, int lda, const int* n_per, int n_uniform,
@@ -121,6 +130,11 @@ void launch_risk(const int* outages, long long n, const uint8_t* severe_src,
                  hipStream_t st);
 void launch_validate(const int* outages, long long n, int n_comp, int* bad,
                      hipStream_t st);
+// mixed-precision KKT solve
+void launch_kkt_to_f32(const Slots& s, int count, hipStream_t st);
+void launch_kkt_refine(const Slots& s, int count, int pstride, int max_it, hipStream_t st);
+size_t kkt_refine_lds(int nk);
+
 // slot scheduling
 void launch_refill(const Slots& s, int count, unsigned long long* next, long long n_scen,
                    long long q_cap, hipStream_t st);
@@ -130,6 +144,6 @@ void launch_phase_counts(const Slots& s, int count, int* out, hipStream_t st);
 void launch_gather_request(const int* q_out, const void* q_res, long long q0, int n,
                            long long q_cap, int* out, void* res, hipStream_t st);
 void launch_fill_req(int* item_req, long long q0, int n, long long q_cap, int r, hipStream_t st);
-void launch_count_jobs(const Slots& s, int count, int* out, hipStream_t st);
+void launch_count_jobs(const Slots& s, int count, int want, int* out, hipStream_t st);
 
 }  // namespace cs

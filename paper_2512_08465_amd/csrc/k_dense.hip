@@ -23,9 +23,10 @@
 //      barrier, the eight wave candidates reduced by every thread, the pivot
 //      row published in LDS, a second barrier, then the rank-1 update of the
 //      rows not yet pivoted.  Finally every row is written to its position;
-//   C. the rest of the trailing matrix, A22 -= L21 U12, with FP64 MFMA
-//      (v_mfma_f64_16x16x4f64) on 32 x 32 groups of four 16 x 16 tiles taken
-//      from an LDS counter.
+//   C. the rest of the trailing matrix, A22 -= L21 U12, on the matrix cores
+//      (v_mfma_f64_16x16x4f64, or v_mfma_f32_16x16x4f32 for the FP32
+//      factorisation of the mixed-precision solve) on 32 x 32 groups of four
+//      16 x 16 tiles taken from an LDS counter.
 // After the last panel, U x = y is solved by 16-row blocks from the bottom.
 #include "cs_internal.h"
 
@@ -34,7 +35,27 @@
 
 namespace cs {
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+// The 16 x 16 x 4 matrix-core step for each element type.  Operands: lane
+// (li, lk) = (lane % 16, lane / 16) gives A[li][lk] and B[lk][li]; its four
+// accumulator registers hold column li of rows row(lk, 0..3).
+template <class T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef dvec4 acc;
+  static __device__ inline acc mac(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ constexpr int row(int lk, int q) { return lk + 4 * q; }
+};
+template <> struct Mfma<float> {
+  typedef fvec4 acc;
+  static __device__ inline acc mac(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ constexpr int row(int lk, int q) { return 4 * lk + q; }
+};
 
 constexpr int LU_NB = 32;             // panel width
 constexpr int LU_CW = 16;             // columns per LDS transposition chunk
@@ -49,10 +70,11 @@ constexpr int LU_KK = LU_NB / 4;      // k-steps of the 16x16x4 MFMA per panel
 constexpr int LU_MAX_N = LU_R * LU_THREADS;
 
 // static LDS of the kernel
+template <class T>
 struct LuShared {
-  double rows[LU_NB * LU_NB];   // pivot rows of the panel: [L11 | U11]; U block in the solve
-  double linv[LU_NB * LU_NB];   // inv(L11), row-major
-  double cand_v[LU_WAVES];      // per column, each wavefront's pivot candidate
+  T rows[LU_NB * LU_NB];        // pivot rows of the panel: [L11 | U11]; U block in the solve
+  T linv[LU_NB * LU_NB];        // inv(L11), row-major
+  T cand_v[LU_WAVES];           // per column, each wavefront's pivot candidate
   int cand_pos[LU_WAVES];
   int cand_row[LU_WAVES];
   int piv[LU_NB];               // relative pivot positions of the panel
@@ -62,13 +84,15 @@ struct LuShared {
   int sing, tile;
 };
 
-__device__ inline bool better(double v, int pos, double bv, int bpos) {
+template <class T>
+__device__ inline bool better(T v, int pos, T bv, int bpos) {
   return v > bv || (v == bv && pos < bpos);
 }
 
 // Per-thread state of the panel factorisation.
+template <class T>
 struct PanelRows {
-  double v[LU_R][LU_NB];   // panel row tid + 512 s, columns of the panel
+  T v[LU_R][LU_NB];        // panel row tid + 512 s, columns of the panel
   int pos[LU_R];           // its LAPACK position within the panel
   bool live[LU_R];         // not yet chosen as a pivot
 };
@@ -77,19 +101,19 @@ struct PanelRows {
 // that every register index is static).  Two workgroup barriers: one after
 // each wavefront has published its best candidate, one after the winning
 // row has been published.
-template <int J>
+template <class T, int J>
 __device__ __attribute__((always_inline)) inline void panel_column(
-    PanelRows& R, int m, int r0, int* __restrict__ piv, int* __restrict__ ridx,
-    LuShared& S, int tid) {
+    PanelRows<T>& R, int m, int r0, int* __restrict__ piv, int* __restrict__ ridx,
+    LuShared<T>& S, int tid) {
   const int lane = tid & 63, wave = tid >> 6;
   // --- candidates: largest |a| in column J among rows not yet pivoted
-  double bv = -1.0;
+  T bv = T(-1);
   int bp = INT_MAX, br = -1;
 #pragma unroll
   for (int s = 0; s < LU_R; ++s) {
     // a NaN entry ranks above every number, so a row is always chosen
-    const double x = R.v[s][J];
-    const double a = (x == x) ? fabs(x) : HUGE_VAL;
+    const T x = R.v[s][J];
+    const T a = (x == x) ? fabs(x) : T(HUGE_VAL);
     if (R.live[s] && better(a, R.pos[s], bv, bp)) {
       bv = a;
       bp = R.pos[s];
@@ -98,7 +122,7 @@ __device__ __attribute__((always_inline)) inline void panel_column(
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
-    const double v2 = __shfl_xor(bv, off, 64);
+    const T v2 = __shfl_xor(bv, off, 64);
     const int p2 = __shfl_xor(bp, off, 64);
     const int r2 = __shfl_xor(br, off, 64);
     if (better(v2, p2, bv, bp)) {
@@ -118,7 +142,7 @@ __device__ __attribute__((always_inline)) inline void panel_column(
   br = S.cand_row[0];
 #pragma unroll
   for (int w = 1; w < LU_WAVES; ++w) {
-    const double v2 = S.cand_v[w];
+    const T v2 = S.cand_v[w];
     const int p2 = S.cand_pos[w];
     if (better(v2, p2, bv, bp)) {
       bv = v2;
@@ -144,7 +168,7 @@ __device__ __attribute__((always_inline)) inline void panel_column(
     S.moved_pos = bp;
     S.piv[J] = bp;
     piv[r0 + J] = r0 + bp;
-    if (bv == 0.0) S.sing = 1;
+    if (bv == T(0)) S.sing = 1;
   }
   __syncthreads();
   const int q = S.moved_row;
@@ -153,13 +177,13 @@ __device__ __attribute__((always_inline)) inline void panel_column(
   for (int s = 0; s < LU_R; ++s)
     if (q == tid + LU_THREADS * s && R.live[s]) R.pos[s] = qp;
   // --- scale and rank-1 update of the rows not yet pivoted
-  const double pv = S.rows[J * LU_NB + J];
-  if (pv != 0.0) {
-    const double inv = 1.0 / pv;
+  const T pv = S.rows[J * LU_NB + J];
+  if (pv != T(0)) {
+    const T inv = T(1) / pv;
 #pragma unroll
     for (int s = 0; s < LU_R; ++s) {
       if (R.live[s]) {
-        const double l = R.v[s][J] * inv;
+        const T l = R.v[s][J] * inv;
         R.v[s][J] = l;
 #pragma unroll
         for (int c = J + 1; c < LU_NB; ++c) R.v[s][c] -= l * S.rows[J * LU_NB + c];
@@ -168,20 +192,20 @@ __device__ __attribute__((always_inline)) inline void panel_column(
   }
 }
 
-template <int J>
+template <class T, int J>
 struct PanelColumns {
   static __device__ __attribute__((always_inline)) inline void run(
-      PanelRows& R, int m, int r0, int kb, int* piv, int* ridx, LuShared& S, int tid) {
+      PanelRows<T>& R, int m, int r0, int kb, int* piv, int* ridx, LuShared<T>& S, int tid) {
     if (J < kb) {
-      panel_column<J>(R, m, r0, piv, ridx, S, tid);
-      PanelColumns<J + 1>::run(R, m, r0, kb, piv, ridx, S, tid);
+      panel_column<T, J>(R, m, r0, piv, ridx, S, tid);
+      PanelColumns<T, J + 1>::run(R, m, r0, kb, piv, ridx, S, tid);
     }
   }
 };
-template <>
-struct PanelColumns<LU_NB> {
+template <class T>
+struct PanelColumns<T, LU_NB> {
   static __device__ __attribute__((always_inline)) inline void run(
-      PanelRows&, int, int, int, int*, int*, LuShared&, int) {}
+      PanelRows<T>&, int, int, int, int*, int*, LuShared<T>&, int) {}
 };
 
 // Factorise the m x kb panel whose rows sit in R.v (row tid + 512 s of the
@@ -192,9 +216,10 @@ struct PanelColumns<LU_NB> {
 // pivots to piv[] (absolute) and S.piv (relative), L11/U11 to S.rows,
 // inv(L11) to S.linv and the rows interchanged below the panel's top to
 // S.bq / S.bs.  ridx[] is LDS scratch of m ints.
+template <class T>
 __device__ __attribute__((always_inline)) inline void factor_panel(
-    PanelRows& R, int m, int r0, int kb, double* __restrict__ A, int lda,
-    int* __restrict__ piv, int* __restrict__ ridx, LuShared& S, int tid) {
+    PanelRows<T>& R, int m, int r0, int kb, T* __restrict__ A, int lda,
+    int* __restrict__ piv, int* __restrict__ ridx, LuShared<T>& S, int tid) {
 #pragma unroll
   for (int s = 0; s < LU_R; ++s) {
     R.pos[s] = tid + LU_THREADS * s;
@@ -202,13 +227,13 @@ __device__ __attribute__((always_inline)) inline void factor_panel(
   }
   for (int r = tid; r < m; r += LU_THREADS) ridx[r] = r;
   __syncthreads();
-  PanelColumns<0>::run(R, m, r0, kb, piv, ridx, S, tid);
+  PanelColumns<T, 0>::run(R, m, r0, kb, piv, ridx, S, tid);
   // every row to its pivoted position (columns r0 .. r0+kb)
 #pragma unroll
   for (int s = 0; s < LU_R; ++s) {
     const int r = tid + LU_THREADS * s;
     if (r < m) {
-      double* dst = A + (size_t)(r0 + R.pos[s]) * lda + r0;
+      T* dst = A + (size_t)(r0 + R.pos[s]) * lda + r0;
 #pragma unroll
       for (int c = 0; c < LU_NB; ++c)
         if (c < kb) dst[c] = R.v[s][c];
@@ -237,15 +262,15 @@ __device__ __attribute__((always_inline)) inline void factor_panel(
   // substitution in registers
   if (tid >= 64 && tid < 64 + LU_NB) {
     const int j = tid - 64;
-    double x[LU_NB];
+    T x[LU_NB];
 #pragma unroll
     for (int i = 0; i < LU_NB; ++i) {
-      double v = (i == j) ? 1.0 : 0.0;
+      T v = (i == j) ? T(1) : T(0);
       if (i < kb) {
 #pragma unroll
         for (int k = 0; k < i; ++k) v -= S.rows[i * LU_NB + k] * x[k];
       }
-      x[i] = (i < j) ? 0.0 : v;
+      x[i] = (i < j) ? T(0) : v;
     }
 #pragma unroll
     for (int i = 0; i < LU_NB; ++i) S.linv[i * LU_NB + j] = x[i];
@@ -255,47 +280,48 @@ __device__ __attribute__((always_inline)) inline void factor_panel(
 // C[i0:i0+16, j0:j0+16] - L21[i0:, k0:k0+kb] U12[k0:k0+kb, j0:] (global
 // rows) for rows < n and columns < ncols, written to the LDS chunk buffer
 // (rows relative to r0, columns relative to j0)
-__device__ inline void update_tile_to_lds(const double* __restrict__ A, int lda, int n,
+template <class T>
+__device__ inline void update_tile_to_lds(const T* __restrict__ A, int lda, int n,
                                           int ncols, int k0, int kb, int i0, int j0, int r0,
-                                          double* __restrict__ P, int lane) {
+                                          T* __restrict__ P, int lane) {
   const int li = lane & 15, lk = lane >> 4;
-  // accumulator layout of the f64 16x16x4 MFMA: lane l, register q holds
-  // D[l/16 + 4q][l%16]; D is the tile itself, so 16 lanes cover 16
-  // consecutive doubles of one row.
+  // the accumulator is the tile itself: register q of lane (li, lk) holds
+  // column li of row Mfma<T>::row(lk, q)
   const int col = j0 + li;
   const bool cok = col < ncols;
-  dbl4 acc;
+  typename Mfma<T>::acc acc;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int row = i0 + lk + 4 * q;
-    acc[q] = (cok && row < n) ? A[(size_t)row * lda + col] : 0.0;
+    const int row = i0 + Mfma<T>::row(lk, q);
+    acc[q] = (cok && row < n) ? A[(size_t)row * lda + col] : T(0);
   }
   const int arow = i0 + li;
   const bool aok = arow < n;
-  const double* lrow = A + (size_t)arow * lda + k0;
-  double a[LU_KK], b[LU_KK];
+  const T* lrow = A + (size_t)arow * lda + k0;
+  T a[LU_KK], b[LU_KK];
 #pragma unroll
   for (int kk = 0; kk < LU_KK; ++kk) {
     const int k = 4 * kk + lk;
-    a[kk] = (k < kb && aok) ? -lrow[k] : 0.0;
-    b[kk] = (k < kb && cok) ? A[(size_t)(k0 + k) * lda + col] : 0.0;
+    a[kk] = (k < kb && aok) ? -lrow[k] : T(0);
+    b[kk] = (k < kb && cok) ? A[(size_t)(k0 + k) * lda + col] : T(0);
   }
 #pragma unroll
   for (int kk = 0; kk < LU_KK; ++kk)
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk], acc, 0, 0, 0);
+    acc = Mfma<T>::mac(a[kk], b[kk], acc);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int row = i0 + lk + 4 * q;
+    const int row = i0 + Mfma<T>::row(lk, q);
     if (cok && row < n) P[chunk_at(row - r0, li)] = acc[q];
   }
 }
 
 // The trailing update on a 32 x 32 group of four tiles, in place: all loads
 // of a lane are issued together and every L21 / U12 operand feeds two MFMAs.
-__device__ inline void update_group(double* __restrict__ A, int lda, int n, int ncols,
+template <class T>
+__device__ inline void update_group(T* __restrict__ A, int lda, int n, int ncols,
                                     int k0, int kb, int i0, int j0, int lane) {
   const int li = lane & 15, lk = lane >> 4;
-  dbl4 acc[2][2];
+  typename Mfma<T>::acc acc[2][2];
   int col[2];
   bool cok[2];
 #pragma unroll
@@ -309,18 +335,18 @@ __device__ inline void update_group(double* __restrict__ A, int lda, int n, int 
     for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int row = i0 + 16 * ti + lk + 4 * q;
-        acc[ti][tj][q] = (cok[tj] && row < n) ? A[(size_t)row * lda + col[tj]] : 0.0;
+        const int row = i0 + 16 * ti + Mfma<T>::row(lk, q);
+        acc[ti][tj][q] = (cok[tj] && row < n) ? A[(size_t)row * lda + col[tj]] : T(0);
       }
-  double a[2][LU_KK], b[2][LU_KK];
+  T a[2][LU_KK], b[2][LU_KK];
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti) {
     const int arow = i0 + 16 * ti + li;
-    const double* lrow = A + (size_t)arow * lda + k0;
+    const T* lrow = A + (size_t)arow * lda + k0;
 #pragma unroll
     for (int kk = 0; kk < LU_KK; ++kk) {
       const int k = 4 * kk + lk;
-      a[ti][kk] = (k < kb && arow < n) ? -lrow[k] : 0.0;
+      a[ti][kk] = (k < kb && arow < n) ? -lrow[k] : T(0);
     }
   }
 #pragma unroll
@@ -328,7 +354,7 @@ __device__ inline void update_group(double* __restrict__ A, int lda, int n, int 
 #pragma unroll
     for (int kk = 0; kk < LU_KK; ++kk) {
       const int k = 4 * kk + lk;
-      b[tj][kk] = (k < kb && cok[tj]) ? A[(size_t)(k0 + k) * lda + col[tj]] : 0.0;
+      b[tj][kk] = (k < kb && cok[tj]) ? A[(size_t)(k0 + k) * lda + col[tj]] : T(0);
     }
 #pragma unroll
   for (int kk = 0; kk < LU_KK; ++kk)
@@ -336,40 +362,42 @@ __device__ inline void update_group(double* __restrict__ A, int lda, int n, int 
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
       for (int tj = 0; tj < 2; ++tj)
-        acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti][kk], b[tj][kk], acc[ti][tj], 0, 0, 0);
+        acc[ti][tj] = Mfma<T>::mac(a[ti][kk], b[tj][kk], acc[ti][tj]);
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int row = i0 + 16 * ti + lk + 4 * q;
+        const int row = i0 + 16 * ti + Mfma<T>::row(lk, q);
         if (cok[tj] && row < n) A[(size_t)row * lda + col[tj]] = acc[ti][tj][q];
       }
 }
 
+template <class T>
 __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
-    double* __restrict__ Abase, size_t stride, int n, int ncols, int lda,
+    T* __restrict__ Abase, size_t stride, int n, int ncols, int lda,
     int* __restrict__ pivbase, int piv_stride, SlotState* __restrict__ st,
-    int want_phase, int* __restrict__ info) {
+    int want_phase, int want_job, int* __restrict__ info) {
   const int slot = blockIdx.x;
-  // with slot states: only the slots of one stage that asked for a solve
-  if (st != nullptr && (st[slot].job == 0 || st[slot].phase != want_phase)) return;
-  double* __restrict__ A = Abase + (size_t)slot * stride;
+  // with slot states: only the slots of one stage that asked for this solve
+  if (st != nullptr && (st[slot].job != want_job || st[slot].phase != want_phase)) return;
+  T* __restrict__ A = Abase + (size_t)slot * stride;
   int* __restrict__ piv = pivbase + (size_t)slot * piv_stride;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
 
-  extern __shared__ double P[];          // a 16-column chunk (chunk_at); then ridx
+  extern __shared__ __attribute__((aligned(16))) unsigned char lu_lds[];
+  T* P = reinterpret_cast<T*>(lu_lds);   // a 16-column chunk (chunk_at); then ridx
   int* ridx = reinterpret_cast<int*>(P + (size_t)PLD * n);
-  __shared__ LuShared S;
+  __shared__ LuShared<T> S;
   if (tid == 0) {
     S.sing = 0;
     S.tile = 0;
   }
   __syncthreads();
-  PanelRows R;
+  PanelRows<T> R;
   int kp = 0, kbp = 0;                   // previous panel
   for (int k0 = 0; k0 < n; k0 += LU_NB) {
     const int kb = min(LU_NB, n - k0);
@@ -384,7 +412,7 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
         const int r = tid + LU_THREADS * s;
 #pragma unroll
         for (int c = 0; c < LU_NB; ++c)
-          R.v[s][c] = (r < n && c < kb) ? A[(size_t)r * lda + c] : 0.0;
+          R.v[s][c] = (r < n && c < kb) ? A[(size_t)r * lda + c] : T(0);
       }
     } else {
       const int tr = (m + 15) >> 4;
@@ -400,14 +428,14 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
             const int r = tid + LU_THREADS * s;
 #pragma unroll
             for (int c = 0; c < LU_CW; ++c)
-              R.v[s][ch + c] = (r < m && ch + c < kb) ? P[chunk_at(r, c)] : 0.0;
+              R.v[s][ch + c] = (r < m && ch + c < kb) ? P[chunk_at(r, c)] : T(0);
           }
           __syncthreads();
         } else {
 #pragma unroll
           for (int s = 0; s < LU_R; ++s)
 #pragma unroll
-            for (int c = 0; c < LU_CW; ++c) R.v[s][ch + c] = 0.0;
+            for (int c = 0; c < LU_CW; ++c) R.v[s][ch + c] = T(0);
         }
       }
     }
@@ -450,18 +478,18 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
         const bool right = t >= ntl;
         const int col = right ? r0 + 16 * (t - ntl) + li : 16 * t + li;
         const bool cok = col < ncols;
-        const double* colp = A + (size_t)k0 * lda + col;
-        double b[LU_KK], v[LU_KK];
+        const T* colp = A + (size_t)k0 * lda + col;
+        T b[LU_KK], v[LU_KK];
 #pragma unroll
         for (int kk = 0; kk < LU_KK; ++kk) {
           const int k = 4 * kk + lk;
-          b[kk] = (cok && k < kb) ? colp[(size_t)top[kk] * lda] : 0.0;
-          v[kk] = (cok && bq[kk] >= 0) ? colp[(size_t)bsrc[kk] * lda] : 0.0;
+          b[kk] = (cok && k < kb) ? colp[(size_t)top[kk] * lda] : T(0);
+          v[kk] = (cok && bq[kk] >= 0) ? colp[(size_t)bsrc[kk] * lda] : T(0);
         }
         // lanes write rows that other lanes of this wavefront read: every
         // load has returned before the first store
         __builtin_amdgcn_s_waitcnt(0);
-        double* colw = A + (size_t)k0 * lda + col;
+        T* colw = A + (size_t)k0 * lda + col;
 #pragma unroll
         for (int kk = 0; kk < LU_KK; ++kk)
           if (cok && bq[kk] >= 0) colw[(size_t)bq[kk] * lda] = v[kk];
@@ -472,18 +500,17 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
             if (cok && k < kb) colw[(size_t)k * lda] = b[kk];
           }
         } else {
-          dbl4 acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+          typename Mfma<T>::acc acc[2] = {{T(0), T(0), T(0), T(0)}, {T(0), T(0), T(0), T(0)}};
 #pragma unroll
           for (int kk = 0; kk < LU_KK; ++kk)
 #pragma unroll
             for (int ti = 0; ti < 2; ++ti)
-              acc[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                  S.linv[(16 * ti + li) * LU_NB + 4 * kk + lk], b[kk], acc[ti], 0, 0, 0);
+              acc[ti] = Mfma<T>::mac(S.linv[(16 * ti + li) * LU_NB + 4 * kk + lk], b[kk], acc[ti]);
 #pragma unroll
           for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-              const int row = 16 * ti + lk + 4 * q;
+              const int row = 16 * ti + Mfma<T>::row(lk, q);
               if (cok && row < kb) colw[(size_t)row * lda] = acc[ti][q];
             }
         }
@@ -502,21 +529,21 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
   // chunk buffer is free now), then every row above is updated.
   const int nrhs = ncols - n;
   if (nrhs > 0) {
-    double* xs = P;                                 // [16][nrhs]
-    double* ub = S.rows;                            // [16][16]
+    T* xs = P;                                 // [16][nrhs]
+    T* ub = S.rows;                            // [16][16]
     const int nblk = (n + 15) / 16;
     for (int b = nblk - 1; b >= 0; --b) {
       const int b0 = b * 16;
       const int bs = min(16, n - b0);
       for (int e = tid; e < 256; e += LU_THREADS) {
         const int i = e >> 4, j = e & 15;
-        ub[e] = (i < bs && j < bs) ? A[(size_t)(b0 + i) * lda + b0 + j] : 0.0;
+        ub[e] = (i < bs && j < bs) ? A[(size_t)(b0 + i) * lda + b0 + j] : T(0);
       }
       __syncthreads();
       for (int rc = wave; rc < nrhs; rc += LU_WAVES) {
-        double y = (lane < bs) ? A[(size_t)(b0 + lane) * lda + n + rc] : 0.0;
+        T y = (lane < bs) ? A[(size_t)(b0 + lane) * lda + n + rc] : T(0);
         for (int i = bs - 1; i >= 0; --i) {
-          const double xi = __shfl(y, i, 64) / ub[i * 16 + i];
+          const T xi = __shfl(y, i, 64) / ub[i * 16 + i];
           if (lane == i) y = xi;
           if (lane < i) y -= ub[lane * 16 + i] * xi;
         }
@@ -530,8 +557,8 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
       const int work = b0 * nrhs;
       for (int e = tid; e < work; e += LU_THREADS) {
         const int i = e / nrhs, rc = e - i * nrhs;
-        const double* urow = A + (size_t)i * lda + b0;
-        double acc = A[(size_t)i * lda + n + rc];
+        const T* urow = A + (size_t)i * lda + b0;
+        T acc = A[(size_t)i * lda + n + rc];
         for (int j = 0; j < bs; ++j) acc -= urow[j] * xs[j * nrhs + rc];
         A[(size_t)i * lda + n + rc] = acc;
       }
@@ -545,33 +572,51 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
 }
 
 // static LDS of k_lu_solve
-constexpr size_t LU_STATIC_LDS = sizeof(LuShared);
+template <class T>
+constexpr size_t lu_static_lds() { return sizeof(LuShared<T>); }
 
 // dynamic LDS: a 16-column chunk of panel rows and the panel's row-index
 // scratch during the factorisation; a 16 x nrhs block during the solve
+template <class T>
 static size_t lu_dynamic_lds(int n, int nrhs) {
-  return std::max(sizeof(double) * (size_t)PLD * (size_t)n + sizeof(int) * (size_t)n,
-                  sizeof(double) * (size_t)16 * (size_t)nrhs);
+  return std::max(sizeof(T) * (size_t)PLD * (size_t)n + sizeof(int) * (size_t)n,
+                  sizeof(T) * (size_t)16 * (size_t)nrhs);
 }
 
-// total LDS one workgroup of k_lu_solve needs for order n and nrhs columns
-size_t lu_lds_bytes(int n, int nrhs) { return lu_dynamic_lds(n, nrhs) + LU_STATIC_LDS; }
+// total LDS one workgroup of the FP64 k_lu_solve needs for order n and nrhs
+// columns (the FP32 one needs less)
+size_t lu_lds_bytes(int n, int nrhs) {
+  return lu_dynamic_lds<double>(n, nrhs) + lu_static_lds<double>();
+}
 
 // largest order k_lu_solve handles (panel rows are held in registers)
 int lu_max_order() { return LU_MAX_N; }
 
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
-                     int* piv, int piv_stride, SlotState* st, int want_phase,
+                     int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
                      int count, int* info, hipStream_t stream) {
   if (count <= 0) return;
-  const size_t lds = lu_dynamic_lds(n, ncols - n);
-  hipLaunchKernelGGL(k_lu_solve, dim3(count), dim3(LU_THREADS), lds, stream,
-                     A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, info);
+  const size_t lds = lu_dynamic_lds<double>(n, ncols - n);
+  hipLaunchKernelGGL(k_lu_solve<double>, dim3(count), dim3(LU_THREADS), lds, stream,
+                     A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, info);
+}
+
+void launch_lu_solve_f32(float* A, size_t stride, int n, int ncols, int lda,
+                         int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
+                         int count, int* info, hipStream_t stream) {
+  if (count <= 0) return;
+  const size_t lds = lu_dynamic_lds<float>(n, ncols - n);
+  hipLaunchKernelGGL(k_lu_solve<float>, dim3(count), dim3(LU_THREADS), lds, stream,
+                     A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, info);
 }
 
 void lu_set_attrs(size_t bytes) {
-  hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_solve),
-                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)(bytes - LU_STATIC_LDS));
+  hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_solve<double>),
+                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)(bytes - lu_static_lds<double>()));
+  hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_solve<float>),
+                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)(bytes - lu_static_lds<float>()));
 }
 
 }  // namespace cs

@@ -179,14 +179,16 @@ __global__ void k_phase_counts(const SlotState* __restrict__ st, int count,
   if (threadIdx.x < PH_COUNT) out[threadIdx.x] = acc[threadIdx.x];
 }
 
-// Number of interior-point slots that asked for a KKT solve this round.
-__global__ void k_count_jobs(const SlotState* __restrict__ st, int count, int* __restrict__ out) {
+// Number of interior-point slots with job == want (1: a KKT solve this
+// round; 3: an FP64 fallback of the mixed-precision solve).
+__global__ void k_count_jobs(const SlotState* __restrict__ st, int count, int want,
+                             int* __restrict__ out) {
   __shared__ int acc;
   if (threadIdx.x == 0) acc = 0;
   __syncthreads();
   int c = 0;
   for (int i = threadIdx.x; i < count; i += blockDim.x)
-    c += (st[i].job != 0 && st[i].phase == PH_IPM);
+    c += (st[i].job == want && st[i].phase == PH_IPM);
   atomicAdd(&acc, c);
   __syncthreads();
   if (threadIdx.x == 0) *out = acc;
@@ -245,8 +247,8 @@ void launch_fill_req(int* item_req, long long q0, int n, long long q_cap, int r,
   hipLaunchKernelGGL(k_fill_req, dim3((n + 255) / 256), dim3(256), 0, st, item_req, q0, n, q_cap, r);
 }
 
-void launch_count_jobs(const Slots& s, int count, int* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_count_jobs, dim3(1), dim3(1024), 0, st, s.st, count, out);
+void launch_count_jobs(const Slots& s, int count, int want, int* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_jobs, dim3(1), dim3(1024), 0, st, s.st, count, want, out);
 }
 
 }  // namespace cs

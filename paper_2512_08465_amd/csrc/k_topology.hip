@@ -105,6 +105,7 @@ __global__ __launch_bounds__(64) void k_islands(DevNet net, Slots s,
     S.cause = (nroots > 1) ? C_ISLAND : 0;
     S.near = 0;
     S.qr_fail = 0;
+    S.fp64_only = 0;
     S.alpha = __builtin_nan("");
     S.zeta = __builtin_nan("");
     S.max_viol = __builtin_nan("");

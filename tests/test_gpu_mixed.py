@@ -1,0 +1,70 @@
+"""Mixed precision (FP32 KKT factorisation on the matrix cores + FP64
+refinement, FP64 fallback) against the oracle's stored records, to the same
+bars as the FP64 path, and against the FP64 GPU path.  The largest deviations
+from the oracle are printed (pytest -s) for the record."""
+import numpy as np
+import pytest
+
+from helpers import load_case, load_golden
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2512_08465_amd as cs
+    return cs.Context(0)
+
+
+@pytest.fixture(scope="module")
+def runs(ctx):
+    import paper_2512_08465_amd as cs
+    out = {}
+    for name in ("c1_30", "c2_118"):
+        case = load_case(name)
+        g = load_golden(name)
+        net = cs.Network(ctx, case)
+        ctx.reset_stats()
+        mixed = net.screen(g["outages"], case["lam"],
+                           cs.default_options(prec=cs.PREC_MIXED, timing=1))
+        st = ctx.stats()
+        plain = net.screen(g["outages"], case["lam"])
+        out[name] = (g, mixed, plain, st)
+    return out
+
+
+@pytest.mark.parametrize("name", ["c1_30", "c2_118"])
+def test_mixed_matches_oracle(runs, name):
+    g, (res, R), _, st = runs[name]
+    near = (g["near"] > 0) | (res["near"] > 0)
+    bad = np.flatnonzero(~near & ((res["severe"] != g["severe"]) | (res["cause"] != g["cause"])
+                                  | (res["opf_status"] != g["opf_status"])))
+    assert len(bad) == 0, bad[:10]
+    both = (g["opf_status"] == 0) & (res["opf_status"] == 0)
+    rel_cost = np.abs(res["opf_cost"][both] - g["opf_cost"][both]) / np.abs(g["opf_cost"][both])
+    d_alpha = np.abs(res["max_real_eig"][both] - g["max_real_eig"][both]) / \
+        np.maximum(np.abs(g["max_real_eig"][both]), 1.0)
+    d_zeta = np.abs(res["min_damping"][both] - g["min_damping"][both])
+    print(f"\n{name} mixed vs oracle: cost rel {rel_cost.max():.2e}, max Re rel "
+          f"{d_alpha.max():.2e}, damping {d_zeta.max():.2e}; FP64 fallbacks "
+          f"{st['kkt_lu64']['units']} of {st['kkt_lu']['units']} KKT solves")
+    assert rel_cost.max() < 1e-6
+    assert d_alpha.max() < 1e-6
+    assert d_zeta.max() < 1e-6
+    assert np.array_equal(res["n_states"][both], g["n_states"][both])
+    assert np.max(np.abs(res["opf_iters"][both].astype(int) - g["opf_iters"][both])) <= 2
+    assert st["kkt_lu"]["units"] > 0
+
+
+@pytest.mark.parametrize("name", ["c1_30", "c2_118"])
+def test_mixed_matches_fp64_path(runs, name):
+    _, (res, R), (ref, Rref), _ = runs[name]
+    conv = ref["opf_status"] == 0
+    same = conv & (res["opf_status"] == 0)
+    assert same.sum() >= 0.98 * conv.sum()
+    rel = np.abs(res["opf_cost"][same] - ref["opf_cost"][same]) / np.abs(ref["opf_cost"][same])
+    print(f"\n{name} mixed vs FP64 GPU: cost rel {rel.max():.2e}")
+    assert rel.max() < 1e-7
+    agree = res["severe"] == ref["severe"]
+    near = (res["near"] > 0) | (ref["near"] > 0)
+    assert np.all(agree | near)
