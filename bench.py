@@ -97,7 +97,13 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrivals per second")
     ap.add_argument("--serve-max-len", type=int, default=1000,
                     help="request lengths are log-uniform integers in [1, this]")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="run only a copy of known size and a batch of order-580 LUs "
+                         "(for hardware-counter passes), then exit")
     args = ap.parse_args()
+    if args.pmc_probe:
+        pmc_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(scenarios shard trivially across GPUs, but only the single-GPU path exists)",
@@ -167,6 +173,7 @@ def main():
     achieved = lu_fact_per_launch * kkt_lu_flops(nk) / (lu_avg_ms * 1e-3) / 1e12 if lu["ms"] else 0.0
     mixed = args.prec == "mixed"
     peak = PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS
+    lu_bytes = lu_traffic_per_factorisation()
     total_ms = sum(v["ms"] for k, v in st.items() if isinstance(v, dict))
     breakdown = {k: round(v["ms"] / max(total_ms, 1e-9), 4) for k, v in st.items()
                  if isinstance(v, dict)}
@@ -202,7 +209,11 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": round(achieved / peak, 5),
-            "traffic": None,
+            "traffic": (None if mixed or lu_bytes is None
+                        else round(lu_bytes * lu_fact_per_launch / 1e9, 3)),
+            "traffic_unit": "GB per launch (HBM, counters)",
+            "algorithmic_bytes_per_launch_gb": round(
+                2 * 8 * nk * (nk + 1) * lu_fact_per_launch / 1e9, 3),
             "avg_launch_ms": round(lu_avg_ms, 4),
             "factorisations_per_launch": round(lu_fact_per_launch, 1),
         },
@@ -219,6 +230,60 @@ def main():
     if base is not None:
         out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
+
+
+# HBM traffic of the FP64 KKT LU from two rocprofv3 counter passes over
+# `python bench.py --pmc-probe` (profiles/k_lu_solve_hbm_traffic_580.md):
+# FETCH_SIZE and WRITE_SIZE of the 512-system dispatch, each scaled by what the
+# same counter reads for the probe's 1 GiB device copy.  Valid only for the
+# kernel source it was measured on (hash below); otherwise traffic is null.
+LU_TRAFFIC = dict(source_sha256_16="6d317c0e579ce3d7", batch=512,
+                  fetch_kib=14150663.375, write_kib=10769236.09375,
+                  copy_fetch_kib=524308.1875, copy_write_kib=1048576.0,
+                  copy_bytes=1 << 30)
+
+
+def lu_traffic_per_factorisation():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2512_08465_amd", "csrc", "k_dense.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != LU_TRAFFIC["source_sha256_16"]:
+            return None
+    t = LU_TRAFFIC
+    kib = t["copy_bytes"] / 1024.0
+    fetch = t["fetch_kib"] * kib / t["copy_fetch_kib"]
+    write = t["write_kib"] * kib / t["copy_write_kib"]
+    return (fetch + write) * 1024.0 / t["batch"]
+
+
+PMC_COPY_BYTES = 1 << 30
+PMC_LU_BATCH = 512
+PMC_LU_ORDER = 580
+
+
+def pmc_probe():
+    """Workloads for the FETCH_SIZE / WRITE_SIZE counter passes: a plain
+    device copy of PMC_COPY_BYTES (the scale of the counters), then one batch
+    of PMC_LU_BATCH random order-580 systems through the library's LU kernel
+    (the KKT factorisation's kernel and shape)."""
+    import numpy as np
+    import torch
+    import paper_2512_08465_amd as cs
+    ctx = cs.Context(0)
+    src = torch.ones(PMC_COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    n, k = PMC_LU_ORDER, 1
+    lda = n + k + ((n + k) % 2)
+    rng = np.random.default_rng(0)
+    a = torch.from_numpy(rng.standard_normal((PMC_LU_BATCH, n, lda))).cuda()
+    info = torch.zeros(PMC_LU_BATCH, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    ctx.dense_solve_batched(a.data_ptr(), n, k, lda, PMC_LU_BATCH, info.data_ptr())
+    torch.cuda.synchronize()
+    log("pmc probe: copy and LU batch done")
 
 
 def serve(cs, ctx, net, case, lst, args):
