@@ -452,7 +452,9 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
         if (lane == 0) t = atomicAdd(&S.tile, 1);
         t = __shfl(t, 0, 64);
         if (t >= ngroups) break;
-        const int ti = t % gr, tj = t / gr;
+        // consecutive tickets walk along a row block: the waves working at
+        // the same time share its L21 rows in L2
+        const int ti = t / gc, tj = t % gc;
         update_group(A, lda, n, ncols, kp, kbp, k0 + 32 * ti, r0 + 32 * tj, lane);
       }
     }
