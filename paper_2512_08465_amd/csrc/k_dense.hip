@@ -374,6 +374,53 @@ __device__ inline void update_group(T* __restrict__ A, int lda, int n, int ncols
       }
 }
 
+// Back substitution U x = y for the right-hand-side columns n..ncols-1 (the
+// forward substitution was done on them during the elimination), by 16-row
+// blocks from the bottom.  A wavefront solves a diagonal block for one
+// right-hand side at a time (lane i holds row i; x_i is broadcast and
+// eliminated from the rows above), the block solution is kept in LDS (xs,
+// 16 x nrhs; ub, 16 x 16), then every row above is updated.
+template <class T>
+__device__ void back_substitute(T* __restrict__ A, int lda, int n, int ncols, T* xs, T* ub,
+                                int tid) {
+  const int lane = tid & 63, wave = tid >> 6;
+  const int nrhs = ncols - n;
+  if (nrhs <= 0) return;
+  const int nblk = (n + 15) / 16;
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int b0 = b * 16;
+    const int bs = min(16, n - b0);
+    for (int e = tid; e < 256; e += LU_THREADS) {
+      const int i = e >> 4, j = e & 15;
+      ub[e] = (i < bs && j < bs) ? A[(size_t)(b0 + i) * lda + b0 + j] : T(0);
+    }
+    __syncthreads();
+    for (int rc = wave; rc < nrhs; rc += LU_WAVES) {
+      T y = (lane < bs) ? A[(size_t)(b0 + lane) * lda + n + rc] : T(0);
+      for (int i = bs - 1; i >= 0; --i) {
+        const T xi = __shfl(y, i, 64) / ub[i * 16 + i];
+        if (lane == i) y = xi;
+        if (lane < i) y -= ub[lane * 16 + i] * xi;
+      }
+      if (lane < bs) {
+        xs[lane * nrhs + rc] = y;
+        A[(size_t)(b0 + lane) * lda + n + rc] = y;
+      }
+    }
+    __syncthreads();
+    // y[0:b0] -= U[0:b0, b0:b0+bs] x[b0:b0+bs]
+    const int work = b0 * nrhs;
+    for (int e = tid; e < work; e += LU_THREADS) {
+      const int i = e / nrhs, rc = e - i * nrhs;
+      const T* urow = A + (size_t)i * lda + b0;
+      T acc = A[(size_t)i * lda + n + rc];
+      for (int j = 0; j < bs; ++j) acc -= urow[j] * xs[j * nrhs + rc];
+      A[(size_t)i * lda + n + rc] = acc;
+    }
+    __syncthreads();
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
     T* __restrict__ Abase, size_t stride, int n, int ncols, int lda,
@@ -524,49 +571,7 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
     kbp = kb;
   }
 
-  // ---- back substitution U x = y for the right-hand-side columns, by
-  // 16-row blocks from the bottom.  A wavefront solves a diagonal block for
-  // one right-hand side at a time (lane i holds row i; x_i is broadcast and
-  // eliminated from the rows above), the block solution is kept in LDS (the
-  // chunk buffer is free now), then every row above is updated.
-  const int nrhs = ncols - n;
-  if (nrhs > 0) {
-    T* xs = P;                                 // [16][nrhs]
-    T* ub = S.rows;                            // [16][16]
-    const int nblk = (n + 15) / 16;
-    for (int b = nblk - 1; b >= 0; --b) {
-      const int b0 = b * 16;
-      const int bs = min(16, n - b0);
-      for (int e = tid; e < 256; e += LU_THREADS) {
-        const int i = e >> 4, j = e & 15;
-        ub[e] = (i < bs && j < bs) ? A[(size_t)(b0 + i) * lda + b0 + j] : T(0);
-      }
-      __syncthreads();
-      for (int rc = wave; rc < nrhs; rc += LU_WAVES) {
-        T y = (lane < bs) ? A[(size_t)(b0 + lane) * lda + n + rc] : T(0);
-        for (int i = bs - 1; i >= 0; --i) {
-          const T xi = __shfl(y, i, 64) / ub[i * 16 + i];
-          if (lane == i) y = xi;
-          if (lane < i) y -= ub[lane * 16 + i] * xi;
-        }
-        if (lane < bs) {
-          xs[lane * nrhs + rc] = y;
-          A[(size_t)(b0 + lane) * lda + n + rc] = y;
-        }
-      }
-      __syncthreads();
-      // y[0:b0] -= U[0:b0, b0:b0+bs] x[b0:b0+bs]
-      const int work = b0 * nrhs;
-      for (int e = tid; e < work; e += LU_THREADS) {
-        const int i = e / nrhs, rc = e - i * nrhs;
-        const T* urow = A + (size_t)i * lda + b0;
-        T acc = A[(size_t)i * lda + n + rc];
-        for (int j = 0; j < bs; ++j) acc -= urow[j] * xs[j * nrhs + rc];
-        A[(size_t)i * lda + n + rc] = acc;
-      }
-      __syncthreads();
-    }
-  }
+  back_substitute(A, lda, n, ncols, P, S.rows, tid);
   if (tid == 0) {
     if (st != nullptr) st[slot].singular = S.sing;
     if (info != nullptr) info[slot] = S.sing;
