@@ -49,6 +49,14 @@ class OPFOptions:
     xi: float = 0.99995
     sigma: float = 0.1
     gamma_max: float = 1e10     # barrier blow-up => diverged (NUMERICAL)
+    # Rounding probes, for the tests only (the method's solve is the dense LU,
+    # the default): "qr" solves each Newton system by Householder QR instead;
+    # row_scale_seed multiplies the rows of each system by powers of two drawn
+    # from that seed before the LU.  Both are exact reformulations of the same
+    # step, so a scenario whose outcome changes under them is decided by
+    # rounding, not by the method.
+    kkt_solve: str = "lu"
+    row_scale_seed: int | None = None
 
 
 @dataclasses.dataclass
@@ -283,6 +291,10 @@ def solve_opf(net, sub, opts: OPFOptions = OPFOptions(), keep_history=False) -> 
     it = 0
     status = MAXIT
     hist = []
+    if opts.kkt_solve not in ("lu", "qr"):
+        raise ValueError(f"kkt_solve must be 'lu' or 'qr', not {opts.kkt_solve!r}")
+    scale_rng = (np.random.default_rng(opts.row_scale_seed)
+                 if opts.row_scale_seed is not None else None)
     while True:
         Lx = P.cost_grad(x) + Jg.T @ lam + Jh.T @ mu
         xn = np.max(np.abs(x)) if nx else 0.0
@@ -305,11 +317,21 @@ def solve_opf(net, sub, opts: OPFOptions = OPFOptions(), keep_history=False) -> 
         if not np.all(np.isfinite(K)) or not np.all(np.isfinite(rhs)):
             status = NUMERICAL
             break
-        lu, piv = sla.lu_factor(K, check_finite=False)
-        if np.any(np.diag(lu) == 0.0):
-            status = NUMERICAL
-            break
-        d = sla.lu_solve((lu, piv), rhs, check_finite=False)
+        if opts.kkt_solve == "qr":
+            q, r = sla.qr(K, check_finite=False)
+            if np.any(np.diag(r) == 0.0):
+                status = NUMERICAL
+                break
+            d = sla.solve_triangular(r, q.T @ rhs, check_finite=False)
+        else:
+            if scale_rng is not None:
+                dscale = 2.0 ** scale_rng.integers(-2, 3, K.shape[0])
+                K, rhs = dscale[:, None] * K, dscale * rhs
+            lu, piv = sla.lu_factor(K, check_finite=False)
+            if np.any(np.diag(lu) == 0.0):
+                status = NUMERICAL
+                break
+            d = sla.lu_solve((lu, piv), rhs, check_finite=False)
         if not np.all(np.isfinite(d)):
             status = NUMERICAL
             break

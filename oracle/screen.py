@@ -24,6 +24,8 @@ class ScreenOptions:
     tol: float = 1e-8
     max_it: int = 150
     near_eps: float = 1e-6
+    kkt_solve: str = "lu"               # rounding probes of the OPF (tests only)
+    row_scale_seed: int | None = None
 
 
 @dataclasses.dataclass
@@ -91,7 +93,9 @@ def evaluate(net, outage, opts: ScreenOptions = ScreenOptions(),
         return res
     bus_ids = np.flatnonzero(label == main)
     sub = network.make_subsystem(net, bus_ids, br_on, gen_on, load_on, ref)
-    o = opf.solve_opf(net, sub, opf.OPFOptions(tol=opts.tol, max_it=opts.max_it))
+    o = opf.solve_opf(net, sub, opf.OPFOptions(tol=opts.tol, max_it=opts.max_it,
+                                               kkt_solve=opts.kkt_solve,
+                                               row_scale_seed=opts.row_scale_seed))
     res.opf_status, res.opf_iters = o.status, o.iters
     res.opf_cost, res.max_violation = o.cost, o.max_violation
     if o.iters >= opts.max_it - 2:

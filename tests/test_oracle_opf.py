@@ -158,3 +158,36 @@ def test_infeasible_load_is_not_converged():
     net = _two_bus(30.0, 5.0, 0.05, 0.3)
     o = opf.solve_opf(net, full_subsystem(net))
     assert o.status in (opf.MAXIT, opf.NUMERICAL)
+
+
+@pytest.mark.parametrize("probe", [dict(kkt_solve="qr"), dict(row_scale_seed=1),
+                                   dict(row_scale_seed=2)])
+@pytest.mark.parametrize("rate", [True, False])
+def test_rounding_probes_solve_the_same_steps(probe, rate):
+    """The QR and row-scaled LU probes are exact reformulations of the Newton
+    step: on a well-conditioned case they reach the same optimum in the same
+    number of steps (only the last bits differ)."""
+    net = _ring(rate=rate)
+    sub = full_subsystem(net)
+    ref = opf.solve_opf(net, sub)
+    o = opf.solve_opf(net, sub, opf.OPFOptions(**probe))
+    assert ref.status == o.status == opf.CONVERGED
+    assert abs(o.iters - ref.iters) <= 1
+    assert abs(o.cost - ref.cost) <= 1e-9 * abs(ref.cost)
+    assert np.max(np.abs(o.vm - ref.vm)) < 1e-7
+    assert np.max(np.abs(o.pg - ref.pg)) < 1e-7
+
+
+def test_rounding_probe_changes_the_arithmetic():
+    """The probes do change the rounding (else they would prove nothing)."""
+    net = _ring(rate=True)
+    sub = full_subsystem(net)
+    ref = opf.solve_opf(net, sub)
+    o = opf.solve_opf(net, sub, opf.OPFOptions(kkt_solve="qr"))
+    assert not np.array_equal(o.vm, ref.vm) or not np.array_equal(o.pg, ref.pg)
+
+
+def test_unknown_kkt_solve_rejected():
+    net = _ring()
+    with pytest.raises(ValueError):
+        opf.solve_opf(net, full_subsystem(net), opf.OPFOptions(kkt_solve="cholesky"))
