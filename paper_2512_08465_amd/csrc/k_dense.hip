@@ -68,6 +68,16 @@ constexpr int PLD = LU_CW + 1;
 __device__ inline int chunk_at(int r, int c) { return r * PLD + c; }
 constexpr int LU_KK = LU_NB / 4;      // k-steps of the 16x16x4 MFMA per panel
 constexpr int LU_MAX_N = LU_R * LU_THREADS;
+// elements of the chunk area of the dynamic LDS: a 16-column chunk of the
+// panel rows, and at least a 32 x 33 block of U12 for the trailing update
+__host__ __device__ inline int chunk_elems(int n) {
+  return PLD * n > (LU_NB + 1) * LU_NB ? PLD * n : (LU_NB + 1) * LU_NB;
+}
+// columns of U12 staged per pass of the trailing update (a multiple of 32;
+// the staged rows have a stride of cols + 1 elements)
+__device__ inline int u_stage_cols(int n) {
+  return ((chunk_elems(n) / LU_NB - 1) / 32) * 32;
+}
 
 // static LDS of the kernel
 template <class T>
@@ -302,12 +312,14 @@ __device__ inline void update_tile_to_lds(const T* __restrict__ A, int lda, int 
 #pragma unroll
   for (int kk = 0; kk < LU_KK; ++kk) {
     const int k = 4 * kk + lk;
-    a[kk] = (k < kb && aok) ? -lrow[k] : T(0);
+    a[kk] = (k < kb && aok) ? lrow[k] : T(0);
     b[kk] = (k < kb && cok) ? A[(size_t)(k0 + k) * lda + col] : T(0);
   }
+  // negated only once every load is in flight (a use right after each load
+  // would make it wait for that load alone)
 #pragma unroll
   for (int kk = 0; kk < LU_KK; ++kk)
-    acc = Mfma<T>::mac(a[kk], b[kk], acc);
+    acc = Mfma<T>::mac(-a[kk], b[kk], acc);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int row = i0 + Mfma<T>::row(lk, q);
@@ -317,9 +329,13 @@ __device__ inline void update_tile_to_lds(const T* __restrict__ A, int lda, int 
 
 // The trailing update on a 32 x 32 group of four tiles, in place: all loads
 // of a lane are issued together and every L21 / U12 operand feeds two MFMAs.
+// -U12 comes from its copy in LDS (Us: row k of the panel's U12 at k * ldu,
+// columns relative to the staged first column c0), so that the L21 operands
+// go from memory straight into the MFMAs.
 template <class T>
 __device__ inline void update_group(T* __restrict__ A, int lda, int n, int ncols,
-                                    int k0, int kb, int i0, int j0, int lane) {
+                                    int k0, int kb, int i0, int j0, const T* __restrict__ Us,
+                                    int ldu, int c0, int lane) {
   const int li = lane & 15, lk = lane >> 4;
   typename Mfma<T>::acc acc[2][2];
   int col[2];
@@ -346,7 +362,7 @@ __device__ inline void update_group(T* __restrict__ A, int lda, int n, int ncols
 #pragma unroll
     for (int kk = 0; kk < LU_KK; ++kk) {
       const int k = 4 * kk + lk;
-      a[ti][kk] = (k < kb && arow < n) ? -lrow[k] : T(0);
+      a[ti][kk] = (k < kb && arow < n) ? lrow[k] : T(0);
     }
   }
 #pragma unroll
@@ -354,7 +370,7 @@ __device__ inline void update_group(T* __restrict__ A, int lda, int n, int ncols
 #pragma unroll
     for (int kk = 0; kk < LU_KK; ++kk) {
       const int k = 4 * kk + lk;
-      b[tj][kk] = (k < kb && cok[tj]) ? A[(size_t)(k0 + k) * lda + col[tj]] : T(0);
+      b[tj][kk] = (k < kb && cok[tj]) ? Us[k * ldu + col[tj] - c0] : T(0);
     }
 #pragma unroll
   for (int kk = 0; kk < LU_KK; ++kk)
@@ -437,7 +453,7 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
 
   extern __shared__ __attribute__((aligned(16))) unsigned char lu_lds[];
   T* P = reinterpret_cast<T*>(lu_lds);   // a 16-column chunk (chunk_at); then ridx
-  int* ridx = reinterpret_cast<int*>(P + (size_t)PLD * n);
+  int* ridx = reinterpret_cast<int*>(P + chunk_elems(n));
   __shared__ LuShared<T> S;
   if (tid == 0) {
     S.sing = 0;
@@ -489,20 +505,35 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
     // ---- P: factorise the panel
     factor_panel(R, m, k0, kb, A, lda, piv, ridx, S, tid);
     // ---- C: the rest of the previous panel's trailing update (columns
-    // right of this panel), independent of this panel's factors
+    // right of this panel), independent of this panel's factors.  The
+    // previous panel's U12 rows are staged, negated, in the (now free) chunk
+    // area of the LDS, a block of columns per pass, so that every 32 x 32
+    // group reads them from there instead of from memory.
     if (k0 > 0 && r0 < ncols) {
       const int gr = (m + 31) >> 5;
-      const int gc = (ncols - r0 + 31) >> 5;
-      const int ngroups = gr * gc;
-      while (true) {
-        int t = 0;
-        if (lane == 0) t = atomicAdd(&S.tile, 1);
-        t = __shfl(t, 0, 64);
-        if (t >= ngroups) break;
-        // consecutive tickets walk along a row block: the waves working at
-        // the same time share its L21 rows in L2
-        const int ti = t / gc, tj = t % gc;
-        update_group(A, lda, n, ncols, kp, kbp, k0 + 32 * ti, r0 + 32 * tj, lane);
+      const int cap = u_stage_cols(n);
+      for (int c0 = r0; c0 < ncols; c0 += cap) {
+        const int w = min(cap, ncols - c0);
+        const int ldu = w + 1;
+        if (tid == 0) S.tile = 0;
+        for (int e = tid; e < kbp * w; e += LU_THREADS) {
+          const int r = e / w, c = e - r * w;
+          P[r * ldu + c] = -A[(size_t)(kp + r) * lda + c0 + c];
+        }
+        __syncthreads();
+        const int gc = (w + 31) >> 5;
+        const int ngroups = gr * gc;
+        while (true) {
+          int t = 0;
+          if (lane == 0) t = atomicAdd(&S.tile, 1);
+          t = __shfl(t, 0, 64);
+          if (t >= ngroups) break;
+          // consecutive tickets walk along a row block: the waves working at
+          // the same time share its L21 rows in L2
+          const int ti = t / gc, tj = t % gc;
+          update_group(A, lda, n, ncols, kp, kbp, k0 + 32 * ti, c0 + 32 * tj, P, ldu, c0, lane);
+        }
+        __syncthreads();
       }
     }
     __syncthreads();
@@ -582,11 +613,12 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
 template <class T>
 constexpr size_t lu_static_lds() { return sizeof(LuShared<T>); }
 
-// dynamic LDS: a 16-column chunk of panel rows and the panel's row-index
-// scratch during the factorisation; a 16 x nrhs block during the solve
+// dynamic LDS: the chunk area (a 16-column chunk of panel rows, or staged
+// U12 rows) and the panel's row-index scratch during the factorisation; a
+// 16 x nrhs block during the solve
 template <class T>
 static size_t lu_dynamic_lds(int n, int nrhs) {
-  return std::max(sizeof(T) * (size_t)PLD * (size_t)n + sizeof(int) * (size_t)n,
+  return std::max(sizeof(T) * (size_t)chunk_elems(n) + sizeof(int) * (size_t)n,
                   sizeof(T) * (size_t)16 * (size_t)nrhs);
 }
 
