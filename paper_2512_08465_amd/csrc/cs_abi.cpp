@@ -39,6 +39,7 @@ size_t form_state_lds(int ng);
 void lu_set_attrs(size_t bytes);
 void opf_set_attrs(size_t bytes);
 void dyn_set_attrs(size_t bytes);
+void eig_set_attrs(size_t bytes);
 constexpr size_t kLdsMax = 160 * 1024;
 constexpr int kRefineMax = 10;     // FP64 refinement steps of a mixed-precision solve
 }  // namespace cs
@@ -160,6 +161,7 @@ static size_t set_kernel_attrs(int device) {
     lu_set_attrs(lim);
     opf_set_attrs(lim);
     dyn_set_attrs(lim);
+    eig_set_attrs(lim);
   }
   (void)hipGetLastError();
   return lim;

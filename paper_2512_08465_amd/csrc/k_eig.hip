@@ -66,49 +66,123 @@ __device__ inline void eig2x2(double a, double b, double c, double d,
   }
 }
 
-__device__ void hessenberg(double* __restrict__ H, int n, int lda, double* u,
-                           double* w, double* red) {
+// Householder reduction to upper Hessenberg form with one read-write pass
+// over the matrix per reflector.  Step k uses P_k = I - tau u u^T on indices
+// k+1..n-1 (u from column k below the diagonal).  With B = H[:, k+1:],
+// p = B u and s = tau B[k+1:, :]^T u, both taken from H before the step, the
+// two-sided update P_k H P_k is the rank-2 change
+//   H[i][k+1+j] -= a_i s_j + w_i u_j,   a_i = u_{i-k-1} (i > k, else 0),
+//   w_i = tau (p_i - a_i (s . u)),
+// so one pass can apply step k and, on the values it has just written,
+// gather p and s for step k+1 (whose reflector comes from column k+1, which
+// is brought up to date first).  Columns are shared out to the wavefronts,
+// lanes run over the rows: s of a column is a wavefront sum, p a per-lane
+// partial per wavefront (kept in LDS), added in a fixed order.
+// LDS (dynamic, 9 n doubles): u, s, w of the current step, un, sn of the
+// next, and the NW partials of the next p.
+constexpr int EIG_NW = EIG_THREADS / 64;
+constexpr int EIG_CG = 8;                   // row chunks of 64 loaded together
+
+size_t eig_hess_lds(int nmax) { return sizeof(double) * 9 * (size_t)nmax; }
+
+__device__ void hessenberg(double* __restrict__ H, int n, int lda, double* __restrict__ lds,
+                           double* red) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;              // reflector length (rows k+1..n-1)
-    double* colk = H + (size_t)k * lda + k + 1;
+  double* u = lds;
+  double* sv = u + n;
+  double* w = sv + n;
+  double* un = w + n;
+  double* sn = un + n;
+  double* pn = sn + n;            // [EIG_NW][n]
+  double tau = 0.0;
+  __shared__ double s_x0;
+  for (int k = -1; k <= n - 3; ++k) {
+    const bool upd = k >= 0 && tau != 0.0;   // step k changes H
+    const bool nxt = k + 1 <= n - 3;         // a reflector for column k+1
+    // ---- column k+1: step k's update, then the next reflector from it
+    double* c1 = H + (size_t)(k + 1) * lda;
     double part = 0.0;
-    for (int i = tid; i < m; i += EIG_THREADS) {
-      double v = colk[i];
-      u[i] = v;
-      part += v * v;
-    }
-    const double sig2 = block_sum(part, red);
-    const double x0 = u[0];
-    if (sig2 == 0.0) { __syncthreads(); continue; }
-    const double sig = sqrt(sig2);
-    const double alpha = -copysign(sig, x0);
-    const double tau = 1.0 / (sig * (sig + fabs(x0)));
-    __syncthreads();
-    if (tid == 0) u[0] = x0 - alpha;
-    for (int i = tid; i < m; i += EIG_THREADS) colk[i] = (i == 0) ? alpha : 0.0;
-    __syncthreads();
-    // left: columns k+1..n-1, rows k+1..n-1
-    for (int j = k + 1 + wave; j < n; j += EIG_THREADS / 64) {
-      double* cj = H + (size_t)j * lda + k + 1;
-      double s = 0.0;
-      for (int i = lane; i < m; i += 64) s += u[i] * cj[i];
-      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-      s *= tau;
-      for (int i = lane; i < m; i += 64) cj[i] -= s * u[i];
-    }
-    __syncthreads();
-    // right: rows 0..n-1, columns k+1..n-1
     for (int i = tid; i < n; i += EIG_THREADS) {
-      double s = 0.0;
-      for (int j = 0; j < m; ++j) s += H[(size_t)(k + 1 + j) * lda + i] * u[j];
-      w[i] = s * tau;
+      double h = c1[i];
+      if (upd) h -= ((i > k) ? u[i - k - 1] * sv[0] : 0.0) + w[i] * u[0];
+      if (i >= k + 2 && nxt) {
+        un[i - k - 2] = h;
+        part += h * h;
+      } else {
+        c1[i] = h;
+      }
+    }
+    double taun = 0.0, alpha = 0.0;
+    if (nxt) {
+      const double sig2 = block_sum(part, red);   // barriers: un[] complete
+      if (tid == 0) s_x0 = un[0];
+      __syncthreads();
+      const double x0 = s_x0;
+      if (sig2 != 0.0) {
+        const double sig = sqrt(sig2);
+        alpha = -copysign(sig, x0);
+        taun = 1.0 / (sig * (sig + fabs(x0)));
+        if (tid == 0) un[0] = x0 - alpha;
+      }
+      for (int i = k + 2 + tid; i < n; i += EIG_THREADS) c1[i] = (i == k + 2) ? alpha : 0.0;
     }
     __syncthreads();
-    for (int i = tid; i < n; i += EIG_THREADS) {
-      const double wi = w[i];
-      for (int j = 0; j < m; ++j) H[(size_t)(k + 1 + j) * lda + i] -= wi * u[j];
+    // ---- one pass over columns k+2..n-1: apply step k, gather p and s of
+    // step k+1 from the updated values
+    if (upd || nxt) {
+      double* pw = pn + wave * n;   // this wavefront's partial p (lane-owned rows)
+      if (nxt)
+        for (int i = lane; i < n; i += 64) pw[i] = 0.0;
+      for (int j = k + 2 + wave; j < n; j += EIG_NW) {
+        double* cj = H + (size_t)j * lda;
+        const double sj = upd ? sv[j - k - 1] : 0.0, uj = upd ? u[j - k - 1] : 0.0;
+        const double unj = nxt ? un[j - k - 2] : 0.0;
+        double t = 0.0;
+        for (int i0 = 0; i0 < n; i0 += 64 * EIG_CG) {
+          double hv[EIG_CG];
+#pragma unroll
+          for (int c = 0; c < EIG_CG; ++c) {
+            const int i = i0 + 64 * c + lane;
+            hv[c] = (i < n) ? cj[i] : 0.0;
+          }
+#pragma unroll
+          for (int c = 0; c < EIG_CG; ++c) {
+            const int i = i0 + 64 * c + lane;
+            if (i < n) {
+              double h = hv[c];
+              if (upd) {
+                h -= ((i > k) ? u[i - k - 1] * sj : 0.0) + w[i] * uj;
+                cj[i] = h;
+              }
+              if (nxt) {
+                pw[i] += h * unj;
+                if (i >= k + 2) t += un[i - k - 2] * h;
+              }
+            }
+          }
+        }
+        if (nxt) {
+          for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+          if (lane == 0) sn[j - k - 2] = taun * t;
+        }
+      }
     }
+    __syncthreads();
+    if (!nxt) break;
+    // ---- step k+1's w from p (the partials in a fixed order) and s . u
+    double dot = 0.0;
+    for (int j = tid; j < n - k - 2; j += EIG_THREADS) dot += sn[j] * un[j];
+    const double cdot = block_sum(dot, red);
+    for (int i = tid; i < n; i += EIG_THREADS) {
+      double pi = 0.0;
+#pragma unroll
+      for (int v = 0; v < EIG_NW; ++v) pi += pn[v * n + i];
+      const double ai = (i > k + 1) ? un[i - k - 2] : 0.0;
+      w[i] = taun * (pi - ai * cdot);
+    }
+    double* t1 = u; u = un; un = t1;
+    double* t2 = sv; sv = sn; sn = t2;
+    tau = taun;
     __syncthreads();
   }
 }
@@ -312,7 +386,7 @@ __device__ int francis(double* __restrict__ H, int n, int lda,
 
 __global__ __launch_bounds__(EIG_THREADS) void k_eig(
     double* __restrict__ Abase, size_t stride, int lda,
-    const SlotState* __restrict__ st, int n_uniform, double* __restrict__ wrb,
+    const SlotState* __restrict__ st, int n_uniform, int nmax, double* __restrict__ wrb,
     double* __restrict__ wib, int w_stride, int* __restrict__ info) {
   const int slot = blockIdx.x;
   int n = n_uniform;
@@ -320,9 +394,8 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(
     if (st[slot].phase != PH_EIG) return;
     n = st[slot].n_states;
   }
-  if (n <= 0 || n > EIG_NMAX) return;
-  __shared__ double u[EIG_NMAX];
-  __shared__ double w[EIG_NMAX];
+  if (n <= 0 || n > EIG_NMAX || n > nmax) return;
+  extern __shared__ double eig_lds[];
   __shared__ double red[EIG_THREADS / 64];
   __shared__ int ired[EIG_THREADS / 64];
   __shared__ double qd[(QR_D + 1) * QR_LD];
@@ -330,7 +403,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(
   double* H = Abase + (size_t)slot * stride;
   double* wr = wrb + (size_t)slot * w_stride;
   double* wi = wib + (size_t)slot * w_stride;
-  hessenberg(H, n, lda, u, w, red);
+  hessenberg(H, n, lda, eig_lds, red);
   // zero below the subdiagonal (the reduction leaves exact zeros already)
   const int fail = francis(H, n, lda, wr, wi, ired, qd, qu);
   if (threadIdx.x == 0 && info != nullptr) info[slot] = fail;
@@ -341,8 +414,17 @@ void launch_eig(double* A, size_t stride, int lda, const int* /*n_per*/,
                 int n_uniform, double* wr, double* wi, int w_stride,
                 SlotState* st, int count, int* info, hipStream_t stream) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_eig, dim3(count), dim3(EIG_THREADS), 0, stream, A,
-                     stride, lda, st, n_uniform, wr, wi, w_stride, info);
+  // the dynamic LDS is sized for the largest order a slot can have (the
+  // eigenvalue arrays have that many entries per slot)
+  const int nmax = n_uniform > 0 ? n_uniform : w_stride;
+  hipLaunchKernelGGL(k_eig, dim3(count), dim3(EIG_THREADS), eig_hess_lds(nmax), stream, A,
+                     stride, lda, st, n_uniform, nmax, wr, wi, w_stride, info);
+}
+
+void eig_set_attrs(size_t bytes) {
+  hipFuncSetAttribute(reinterpret_cast<const void*>(k_eig),
+                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)std::min(bytes - 8 * 1024, eig_hess_lds(EIG_NMAX)));
 }
 
 }  // namespace cs
