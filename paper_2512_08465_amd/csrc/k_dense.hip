@@ -68,15 +68,17 @@ constexpr int PLD = LU_CW + 1;
 __device__ inline int chunk_at(int r, int c) { return r * PLD + c; }
 constexpr int LU_KK = LU_NB / 4;      // k-steps of the 16x16x4 MFMA per panel
 constexpr int LU_MAX_N = LU_R * LU_THREADS;
+constexpr int LU_KU = 2 * LU_NB;     // rank of the trailing update (a panel pair)
 // elements of the chunk area of the dynamic LDS: a 16-column chunk of the
-// panel rows, and at least a 32 x 33 block of U12 for the trailing update
+// panel rows; at least 64 staged U12 rows of 33 columns for the trailing
+// update, and two 32 x 32 blocks for the pair's coupling term
 __host__ __device__ inline int chunk_elems(int n) {
-  return PLD * n > (LU_NB + 1) * LU_NB ? PLD * n : (LU_NB + 1) * LU_NB;
+  return PLD * n > (LU_NB + 1) * LU_KU ? PLD * n : (LU_NB + 1) * LU_KU;
 }
 // columns of U12 staged per pass of the trailing update (a multiple of 32;
 // the staged rows have a stride of cols + 1 elements)
 __device__ inline int u_stage_cols(int n) {
-  return ((chunk_elems(n) / LU_NB - 1) / 32) * 32;
+  return ((chunk_elems(n) / LU_KU - 1) / 32) * 32;
 }
 
 // static LDS of the kernel
@@ -288,8 +290,8 @@ __device__ __attribute__((always_inline)) inline void factor_panel(
 }
 
 // C[i0:i0+16, j0:j0+16] - L21[i0:, k0:k0+kb] U12[k0:k0+kb, j0:] (global
-// rows) for rows < n and columns < ncols, written to the LDS chunk buffer
-// (rows relative to r0, columns relative to j0)
+// rows, kb <= 64) for rows < n and columns < ncols, written to the LDS chunk
+// buffer (rows relative to r0, columns relative to j0)
 template <class T>
 __device__ inline void update_tile_to_lds(const T* __restrict__ A, int lda, int n,
                                           int ncols, int k0, int kb, int i0, int j0, int r0,
@@ -307,19 +309,22 @@ __device__ inline void update_tile_to_lds(const T* __restrict__ A, int lda, int 
   }
   const int arow = i0 + li;
   const bool aok = arow < n;
-  const T* lrow = A + (size_t)arow * lda + k0;
-  T a[LU_KK], b[LU_KK];
+  // rank kb <= 64, by halves of 32
+  for (int h = 0; h < kb; h += LU_NB) {
+    const T* lrow = A + (size_t)arow * lda + k0 + h;
+    T a[LU_KK], b[LU_KK];
 #pragma unroll
-  for (int kk = 0; kk < LU_KK; ++kk) {
-    const int k = 4 * kk + lk;
-    a[kk] = (k < kb && aok) ? lrow[k] : T(0);
-    b[kk] = (k < kb && cok) ? A[(size_t)(k0 + k) * lda + col] : T(0);
+    for (int kk = 0; kk < LU_KK; ++kk) {
+      const int k = h + 4 * kk + lk;
+      a[kk] = (k < kb && aok) ? lrow[4 * kk + lk] : T(0);
+      b[kk] = (k < kb && cok) ? A[(size_t)(k0 + k) * lda + col] : T(0);
+    }
+    // negated only once every load is in flight (a use right after each load
+    // would make it wait for that load alone)
+#pragma unroll
+    for (int kk = 0; kk < LU_KK; ++kk)
+      acc = Mfma<T>::mac(-a[kk], b[kk], acc);
   }
-  // negated only once every load is in flight (a use right after each load
-  // would make it wait for that load alone)
-#pragma unroll
-  for (int kk = 0; kk < LU_KK; ++kk)
-    acc = Mfma<T>::mac(-a[kk], b[kk], acc);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int row = i0 + Mfma<T>::row(lk, q);
@@ -354,31 +359,34 @@ __device__ inline void update_group(T* __restrict__ A, int lda, int n, int ncols
         const int row = i0 + 16 * ti + Mfma<T>::row(lk, q);
         acc[ti][tj][q] = (cok[tj] && row < n) ? A[(size_t)row * lda + col[tj]] : T(0);
       }
-  T a[2][LU_KK], b[2][LU_KK];
+  // rank kb <= 64, by halves of 32
+  for (int h = 0; h < kb; h += LU_NB) {
+    T a[2][LU_KK], b[2][LU_KK];
 #pragma unroll
-  for (int ti = 0; ti < 2; ++ti) {
-    const int arow = i0 + 16 * ti + li;
-    const T* lrow = A + (size_t)arow * lda + k0;
+    for (int ti = 0; ti < 2; ++ti) {
+      const int arow = i0 + 16 * ti + li;
+      const T* lrow = A + (size_t)arow * lda + k0 + h;
 #pragma unroll
-    for (int kk = 0; kk < LU_KK; ++kk) {
-      const int k = 4 * kk + lk;
-      a[ti][kk] = (k < kb && arow < n) ? lrow[k] : T(0);
+      for (int kk = 0; kk < LU_KK; ++kk) {
+        const int k = h + 4 * kk + lk;
+        a[ti][kk] = (k < kb && arow < n) ? lrow[4 * kk + lk] : T(0);
+      }
     }
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int kk = 0; kk < LU_KK; ++kk) {
+        const int k = h + 4 * kk + lk;
+        b[tj][kk] = (k < kb && cok[tj]) ? Us[k * ldu + col[tj] - c0] : T(0);
+      }
+#pragma unroll
+    for (int kk = 0; kk < LU_KK; ++kk)
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = Mfma<T>::mac(a[ti][kk], b[tj][kk], acc[ti][tj]);
   }
-#pragma unroll
-  for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-    for (int kk = 0; kk < LU_KK; ++kk) {
-      const int k = 4 * kk + lk;
-      b[tj][kk] = (k < kb && cok[tj]) ? Us[k * ldu + col[tj] - c0] : T(0);
-    }
-#pragma unroll
-  for (int kk = 0; kk < LU_KK; ++kk)
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 2; ++tj)
-        acc[ti][tj] = Mfma<T>::mac(a[ti][kk], b[tj][kk], acc[ti][tj]);
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -437,6 +445,163 @@ __device__ void back_substitute(T* __restrict__ A, int lda, int n, int ncols, T*
   }
 }
 
+// Panel columns [k0, k0 + kb) of rows k0.. into the registers R: straight
+// from memory when no update is pending (kbp = 0), else after the update by
+// L21 / U12 of columns [kp, kp + kbp) (MFMA), passed through the LDS chunk
+// buffer P in 16-column chunks.
+template <class T>
+__device__ inline void load_panel(PanelRows<T>& R, const T* __restrict__ A, int lda, int n,
+                                  int k0, int kb, int kp, int kbp, T* __restrict__ P, int tid) {
+  const int lane = tid & 63, wave = tid >> 6;
+  const int m = n - k0;
+  if (kbp == 0) {
+#pragma unroll
+    for (int s = 0; s < LU_R; ++s) {
+      const int r = tid + LU_THREADS * s;
+#pragma unroll
+      for (int c = 0; c < LU_NB; ++c)
+        R.v[s][c] = (r < m && c < kb) ? A[(size_t)(k0 + r) * lda + k0 + c] : T(0);
+    }
+    return;
+  }
+  const int tr = (m + 15) >> 4;
+#pragma unroll
+  for (int ch = 0; ch < LU_NB; ch += LU_CW) {
+    if (ch < kb) {
+      const int cend = k0 + min(kb, ch + LU_CW);
+      for (int t = wave; t < tr; t += LU_WAVES)
+        update_tile_to_lds(A, lda, n, cend, kp, kbp, k0 + 16 * t, k0 + ch, k0, P, lane);
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < LU_R; ++s) {
+        const int r = tid + LU_THREADS * s;
+#pragma unroll
+        for (int c = 0; c < LU_CW; ++c)
+          R.v[s][ch + c] = (r < m && ch + c < kb) ? P[chunk_at(r, c)] : T(0);
+      }
+      __syncthreads();
+    } else {
+#pragma unroll
+      for (int s = 0; s < LU_R; ++s)
+#pragma unroll
+        for (int c = 0; c < LU_CW; ++c) R.v[s][ch + c] = T(0);
+    }
+  }
+}
+
+// Rows i0.. and columns c1.. of A take the update by L21 / U12 of columns
+// [kp, kp + kbp), kbp <= 64.  The U12 rows are staged, negated, in the LDS
+// chunk area P, a block of columns per pass, so that every 32 x 32 group
+// reads them from there and its L21 operands go from memory straight into
+// the MFMAs; groups are handed out by an LDS ticket counter.
+template <class T>
+__device__ inline void trailing_update(T* __restrict__ A, int lda, int n, int ncols, int kp,
+                                       int kbp, int i0, int c1, T* __restrict__ P,
+                                       LuShared<T>& S, int tid) {
+  const int lane = tid & 63;
+  const int gr = (n - i0 + 31) >> 5;
+  const int cap = u_stage_cols(n);
+  for (int c0 = c1; c0 < ncols; c0 += cap) {
+    const int w = min(cap, ncols - c0);
+    const int ldu = w + 1;
+    if (tid == 0) S.tile = 0;
+    for (int e = tid; e < kbp * w; e += LU_THREADS) {
+      const int r = e / w, c = e - r * w;
+      P[r * ldu + c] = -A[(size_t)(kp + r) * lda + c0 + c];
+    }
+    __syncthreads();
+    const int gc = (w + 31) >> 5;
+    const int ngroups = gr * gc;
+    while (true) {
+      int t = 0;
+      if (lane == 0) t = atomicAdd(&S.tile, 1);
+      t = __shfl(t, 0, 64);
+      if (t >= ngroups) break;
+      // consecutive tickets walk along a row block: the waves working at the
+      // same time share its L21 rows in L2
+      const int ti = t / gc, tj = t % gc;
+      update_group(A, lda, n, ncols, kp, kbp, i0 + 32 * ti, c0 + 32 * tj, P, ldu, c0, lane);
+    }
+    __syncthreads();
+  }
+}
+
+// The interchanges of the panel [k0, k0 + kb) outside its own columns, fused
+// with U12 = inv(L11) A12 right of it.  A wavefront takes 16 columns: it
+// gathers the kb rows that end up on top (position t comes from position
+// ridx[t]) and the interchanged rows below, then writes the latter back and
+// the former either as they are (columns left of the panel) or multiplied by
+// inv(L11) (to the right).  With Mneg (LDS, 32 x 32, row-major), the right
+// side also takes + Mneg U[kc .. kc + kbc) (rows of an earlier panel's U12).
+template <class T>
+__device__ inline void interchange_trsm(T* __restrict__ A, int lda, int ncols, int k0, int kb,
+                                        const int* __restrict__ ridx, const LuShared<T>& S,
+                                        const T* __restrict__ Mneg, int kc, int kbc, int tid) {
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int r0 = k0 + kb;
+  const int ntl = k0 >> 4;                       // tiles left of the panel
+  const int ntr = (ncols - r0 + 15) >> 4;        // tiles right of it
+  int top[LU_KK], bq[LU_KK], bsrc[LU_KK];
+#pragma unroll
+  for (int kk = 0; kk < LU_KK; ++kk) {
+    const int k = 4 * kk + lk;
+    top[kk] = (k < kb) ? ridx[k] : k;
+    bq[kk] = S.bq[k];
+    bsrc[kk] = S.bs[k];
+  }
+  for (int t = wave; t < ntl + ntr; t += LU_WAVES) {
+    const bool right = t >= ntl;
+    const int col = right ? r0 + 16 * (t - ntl) + li : 16 * t + li;
+    const bool cok = col < ncols;
+    const T* colp = A + (size_t)k0 * lda + col;
+    T b[LU_KK], v[LU_KK], uc[LU_KK];
+#pragma unroll
+    for (int kk = 0; kk < LU_KK; ++kk) {
+      const int k = 4 * kk + lk;
+      b[kk] = (cok && k < kb) ? colp[(size_t)top[kk] * lda] : T(0);
+      v[kk] = (cok && bq[kk] >= 0) ? colp[(size_t)bsrc[kk] * lda] : T(0);
+      uc[kk] = (Mneg != nullptr && right && cok && k < kbc) ? A[(size_t)(kc + k) * lda + col]
+                                                             : T(0);
+    }
+    // lanes write rows that other lanes of this wavefront read: every load
+    // has returned before the first store
+    __builtin_amdgcn_s_waitcnt(0);
+    T* colw = A + (size_t)k0 * lda + col;
+#pragma unroll
+    for (int kk = 0; kk < LU_KK; ++kk)
+      if (cok && bq[kk] >= 0) colw[(size_t)bq[kk] * lda] = v[kk];
+    if (!right) {
+#pragma unroll
+      for (int kk = 0; kk < LU_KK; ++kk) {
+        const int k = 4 * kk + lk;
+        if (cok && k < kb) colw[(size_t)k * lda] = b[kk];
+      }
+    } else {
+      typename Mfma<T>::acc acc[2] = {{T(0), T(0), T(0), T(0)}, {T(0), T(0), T(0), T(0)}};
+#pragma unroll
+      for (int kk = 0; kk < LU_KK; ++kk)
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+          acc[ti] = Mfma<T>::mac(S.linv[(16 * ti + li) * LU_NB + 4 * kk + lk], b[kk], acc[ti]);
+      if (Mneg != nullptr) {
+#pragma unroll
+        for (int kk = 0; kk < LU_KK; ++kk)
+#pragma unroll
+          for (int ti = 0; ti < 2; ++ti)
+            acc[ti] = Mfma<T>::mac(Mneg[(16 * ti + li) * LU_NB + 4 * kk + lk], uc[kk], acc[ti]);
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = 16 * ti + Mfma<T>::row(lk, q);
+          if (cok && row < kb) colw[(size_t)row * lda] = acc[ti][q];
+        }
+    }
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
     T* __restrict__ Abase, size_t stride, int n, int ncols, int lda,
@@ -461,145 +626,58 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
   }
   __syncthreads();
   PanelRows<T> R;
-  int kp = 0, kbp = 0;                   // previous panel
-  for (int k0 = 0; k0 < n; k0 += LU_NB) {
-    const int kb = min(LU_NB, n - k0);
-    const int m = n - k0;
-    const int r0 = k0 + kb;
-    // ---- B: panel columns [k0, k0+kb) into registers: straight from memory
-    // for the first panel, else after the previous panel's update (MFMA),
-    // through LDS in 16-column chunks
-    if (k0 == 0) {
-#pragma unroll
-      for (int s = 0; s < LU_R; ++s) {
-        const int r = tid + LU_THREADS * s;
-#pragma unroll
-        for (int c = 0; c < LU_NB; ++c)
-          R.v[s][c] = (r < n && c < kb) ? A[(size_t)r * lda + c] : T(0);
-      }
-    } else {
-      const int tr = (m + 15) >> 4;
-#pragma unroll
-      for (int ch = 0; ch < LU_NB; ch += LU_CW) {
-        if (ch < kb) {
-          const int cend = k0 + min(kb, ch + LU_CW);
-          for (int t = wave; t < tr; t += LU_WAVES)
-            update_tile_to_lds(A, lda, n, cend, kp, kbp, k0 + 16 * t, k0 + ch, k0, P, lane);
-          __syncthreads();
-#pragma unroll
-          for (int s = 0; s < LU_R; ++s) {
-            const int r = tid + LU_THREADS * s;
-#pragma unroll
-            for (int c = 0; c < LU_CW; ++c)
-              R.v[s][ch + c] = (r < m && ch + c < kb) ? P[chunk_at(r, c)] : T(0);
-          }
-          __syncthreads();
-        } else {
-#pragma unroll
-          for (int s = 0; s < LU_R; ++s)
-#pragma unroll
-            for (int c = 0; c < LU_CW; ++c) R.v[s][ch + c] = T(0);
-        }
-      }
-    }
-    // ---- P: factorise the panel
-    factor_panel(R, m, k0, kb, A, lda, piv, ridx, S, tid);
-    // ---- C: the rest of the previous panel's trailing update (columns
-    // right of this panel), independent of this panel's factors.  The
-    // previous panel's U12 rows are staged, negated, in the (now free) chunk
-    // area of the LDS, a block of columns per pass, so that every 32 x 32
-    // group reads them from there instead of from memory.
-    if (k0 > 0 && r0 < ncols) {
-      const int gr = (m + 31) >> 5;
-      const int cap = u_stage_cols(n);
-      for (int c0 = r0; c0 < ncols; c0 += cap) {
-        const int w = min(cap, ncols - c0);
-        const int ldu = w + 1;
-        if (tid == 0) S.tile = 0;
-        for (int e = tid; e < kbp * w; e += LU_THREADS) {
-          const int r = e / w, c = e - r * w;
-          P[r * ldu + c] = -A[(size_t)(kp + r) * lda + c0 + c];
+  // Panels are taken in pairs: the trailing update is applied once per pair
+  // with rank 64, which halves the passes over the trailing matrix.
+  int kp = 0, kbp = 0;                   // previous pair: columns [kp, kp + kbp)
+  for (int k0 = 0; k0 < n; k0 += LU_KU) {
+    const int kb1 = min(LU_NB, n - k0);
+    const int k1 = k0 + kb1;
+    const int kb2 = max(0, min(LU_NB, n - k1));
+    const int k2 = k1 + kb2;
+    // ---- B1: first panel's columns into registers, after the previous
+    // pair's update
+    load_panel(R, A, lda, n, k0, kb1, kp, kbp, P, tid);
+    // ---- P1
+    factor_panel(R, n - k0, k0, kb1, A, lda, piv, ridx, S, tid);
+    // ---- C: the rest of the previous pair's update (rows from k0, columns
+    // right of the first panel), independent of the first panel's factors
+    if (kbp > 0 && k1 < ncols) trailing_update(A, lda, n, ncols, kp, kbp, k0, k1, P, S, tid);
+    __syncthreads();
+    // ---- A1: the first panel's interchanges, U12 of its rows
+    interchange_trsm(A, lda, ncols, k0, kb1, ridx, S, (const T*)nullptr, 0, 0, tid);
+    __syncthreads();
+    if (kb2 > 0) {
+      // ---- B2, P2: the second panel after the first panel's update
+      load_panel(R, A, lda, n, k1, kb2, k0, kb1, P, tid);
+      factor_panel(R, n - k1, k1, kb2, A, lda, piv, ridx, S, tid);
+      __syncthreads();
+      // ---- A2: the second panel's interchanges; the U12 rows of its top
+      // rows right of the pair still lack the first panel's update, so
+      //   U12_2 = inv(L11_2) (A_top - L_top,1 U12_1)
+      //         = inv(L11_2) A_top - M U12_1,   M = inv(L11_2) L_top,1
+      // with L_top,1 the first panel's columns of the rows that the second
+      // panel brings to its top (read before A2 moves them).  -M goes to LDS.
+      T* Mneg = P + LU_NB * LU_NB;
+      if (k2 < ncols) {
+        for (int e = tid; e < LU_NB * LU_NB; e += LU_THREADS) {
+          const int t = e / LU_NB, c = e - t * LU_NB;
+          P[e] = (t < kb2 && c < kb1) ? A[(size_t)(k1 + ridx[t]) * lda + k0 + c] : T(0);
         }
         __syncthreads();
-        const int gc = (w + 31) >> 5;
-        const int ngroups = gr * gc;
-        while (true) {
-          int t = 0;
-          if (lane == 0) t = atomicAdd(&S.tile, 1);
-          t = __shfl(t, 0, 64);
-          if (t >= ngroups) break;
-          // consecutive tickets walk along a row block: the waves working at
-          // the same time share its L21 rows in L2
-          const int ti = t / gc, tj = t % gc;
-          update_group(A, lda, n, ncols, kp, kbp, k0 + 32 * ti, c0 + 32 * tj, P, ldu, c0, lane);
+        for (int e = tid; e < LU_NB * LU_NB; e += LU_THREADS) {
+          const int i = e / LU_NB, c = e - i * LU_NB;
+          T acc = T(0);
+#pragma unroll 8
+          for (int l = 0; l < LU_NB; ++l) acc += S.linv[i * LU_NB + l] * P[l * LU_NB + c];
+          Mneg[e] = -acc;
         }
         __syncthreads();
       }
+      interchange_trsm(A, lda, ncols, k1, kb2, ridx, S, (const T*)Mneg, k0, kb1, tid);
+      __syncthreads();
     }
-    __syncthreads();
-    // ---- A: interchanges outside the panel, fused with U12 = inv(L11) A12.
-    // A wavefront takes 16 columns: it gathers the kb rows that end up on
-    // top (position t comes from position ridx[t]) and the interchanged rows
-    // below, then writes the latter back and the former either as they are
-    // (columns left of the panel) or multiplied by inv(L11) (to the right).
-    {
-      const int li = lane & 15, lk = lane >> 4;
-      const int ntl = k0 >> 4;                       // tiles left of the panel
-      const int ntr = (ncols - r0 + 15) >> 4;        // tiles right of it
-      int top[LU_KK], bq[LU_KK], bsrc[LU_KK];
-#pragma unroll
-      for (int kk = 0; kk < LU_KK; ++kk) {
-        const int k = 4 * kk + lk;
-        top[kk] = (k < kb) ? ridx[k] : k;
-        bq[kk] = S.bq[k];
-        bsrc[kk] = S.bs[k];
-      }
-      for (int t = wave; t < ntl + ntr; t += LU_WAVES) {
-        const bool right = t >= ntl;
-        const int col = right ? r0 + 16 * (t - ntl) + li : 16 * t + li;
-        const bool cok = col < ncols;
-        const T* colp = A + (size_t)k0 * lda + col;
-        T b[LU_KK], v[LU_KK];
-#pragma unroll
-        for (int kk = 0; kk < LU_KK; ++kk) {
-          const int k = 4 * kk + lk;
-          b[kk] = (cok && k < kb) ? colp[(size_t)top[kk] * lda] : T(0);
-          v[kk] = (cok && bq[kk] >= 0) ? colp[(size_t)bsrc[kk] * lda] : T(0);
-        }
-        // lanes write rows that other lanes of this wavefront read: every
-        // load has returned before the first store
-        __builtin_amdgcn_s_waitcnt(0);
-        T* colw = A + (size_t)k0 * lda + col;
-#pragma unroll
-        for (int kk = 0; kk < LU_KK; ++kk)
-          if (cok && bq[kk] >= 0) colw[(size_t)bq[kk] * lda] = v[kk];
-        if (!right) {
-#pragma unroll
-          for (int kk = 0; kk < LU_KK; ++kk) {
-            const int k = 4 * kk + lk;
-            if (cok && k < kb) colw[(size_t)k * lda] = b[kk];
-          }
-        } else {
-          typename Mfma<T>::acc acc[2] = {{T(0), T(0), T(0), T(0)}, {T(0), T(0), T(0), T(0)}};
-#pragma unroll
-          for (int kk = 0; kk < LU_KK; ++kk)
-#pragma unroll
-            for (int ti = 0; ti < 2; ++ti)
-              acc[ti] = Mfma<T>::mac(S.linv[(16 * ti + li) * LU_NB + 4 * kk + lk], b[kk], acc[ti]);
-#pragma unroll
-          for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int row = 16 * ti + Mfma<T>::row(lk, q);
-              if (cok && row < kb) colw[(size_t)row * lda] = acc[ti][q];
-            }
-        }
-      }
-    }
-    if (tid == 0) S.tile = 0;
-    __syncthreads();
     kp = k0;
-    kbp = kb;
+    kbp = kb1 + kb2;
   }
 
   back_substitute(A, lda, n, ncols, P, S.rows, tid);
