@@ -70,10 +70,13 @@ constexpr int LU_KK = LU_NB / 4;      // k-steps of the 16x16x4 MFMA per panel
 constexpr int LU_MAX_N = LU_R * LU_THREADS;
 constexpr int LU_KU = 2 * LU_NB;     // rank of the trailing update (a panel pair)
 // elements of the chunk area of the dynamic LDS: a 16-column chunk of the
-// panel rows; at least 64 staged U12 rows of 33 columns for the trailing
+// panel rows below the first panel; at least 64 staged U12 rows of 33
+// columns for the trailing
 // update, and two 32 x 32 blocks for the pair's coupling term
 __host__ __device__ inline int chunk_elems(int n) {
-  return PLD * n > (LU_NB + 1) * LU_KU ? PLD * n : (LU_NB + 1) * LU_KU;
+  // the chunk holds the rows below the first panel (at most n - 32)
+  const int c = PLD * (n - LU_NB);
+  return c > (LU_NB + 1) * LU_KU ? c : (LU_NB + 1) * LU_KU;
 }
 // columns of U12 staged per pass of the trailing update (a multiple of 32;
 // the staged rows have a stride of cols + 1 elements)
@@ -86,13 +89,14 @@ template <class T>
 struct LuShared {
   T rows[LU_NB * LU_NB];        // pivot rows of the panel: [L11 | U11]; U block in the solve
   T linv[LU_NB * LU_NB];        // inv(L11), row-major
-  T cand_v[LU_WAVES];           // per column, each wavefront's pivot candidate
-  int cand_pos[LU_WAVES];
-  int cand_row[LU_WAVES];
+  // per panel column (two buffers, alternating): each wavefront's pivot
+  // candidate, |value| and LAPACK position, and the candidate's whole row
+  T slot[2][LU_WAVES][LU_NB];
+  T cand_v[2][LU_WAVES];
+  int cand_pos[2][LU_WAVES];
   int piv[LU_NB];               // relative pivot positions of the panel
   int bq[LU_NB];                // interchanged rows below the panel's top: position, -1 unused
   int bs[LU_NB];                //   and the position its new content comes from
-  int moved_row, moved_pos;     // row displaced by the last interchange and its new place
   int sing, tile;
 };
 
@@ -109,18 +113,62 @@ struct PanelRows {
   bool live[LU_R];         // not yet chosen as a pivot
 };
 
+// Cross-lane moves within a 16-lane row of the wavefront (DPP), for 32-bit
+// and 64-bit values.
+template <int CTRL>
+__device__ inline int dpp_move(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ inline float dpp_move(float v) {
+  return __builtin_bit_cast(float, dpp_move<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = dpp_move<CTRL>((int)(unsigned)(u & 0xffffffffu));
+  const int hi = dpp_move<CTRL>((int)(unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ inline int read_lane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ inline float read_lane(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ inline double read_lane(double v, int l) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffu), l);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+template <class T, int CTRL>
+__device__ inline void amax_step(T& bv, int& bp) {
+  const T v2 = dpp_move<CTRL>(bv);
+  const int p2 = dpp_move<CTRL>(bp);
+  if (better(v2, p2, bv, bp)) {
+    bv = v2;
+    bp = p2;
+  }
+}
+// DPP controls: lane pairs, lane quads, 8-lane halves mirrored, 16-lane rows
+// mirrored; after the four steps every lane of a row holds the row's best
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
+
 // One column J of the panel factorisation (J is a compile-time constant so
-// that every register index is static).  Two workgroup barriers: one after
-// each wavefront has published its best candidate, one after the winning
-// row has been published.
+// that every register index is static).  One workgroup barrier: each
+// wavefront publishes its best candidate (|value|, LAPACK position) and that
+// candidate's whole row in the column's LDS buffer; after the barrier every
+// thread picks the winner, applies the interchange to the positions of its
+// own rows (the winner takes position J, the row at position J takes the
+// winner's) and eliminates with the winner's row.  The two buffers alternate
+// between columns, so a buffer is rewritten only after the next barrier.
 template <class T, int J>
 __device__ __attribute__((always_inline)) inline void panel_column(
-    PanelRows<T>& R, int m, int r0, int* __restrict__ piv, int* __restrict__ ridx,
-    LuShared<T>& S, int tid) {
+    PanelRows<T>& R, int m, int r0, int* __restrict__ piv, LuShared<T>& S, int tid) {
   const int lane = tid & 63, wave = tid >> 6;
+  constexpr int BUF = J & 1;
   // --- candidates: largest |a| in column J among rows not yet pivoted
   T bv = T(-1);
-  int bp = INT_MAX, br = -1;
+  int bp = INT_MAX;
 #pragma unroll
   for (int s = 0; s < LU_R; ++s) {
     // a NaN entry ranks above every number, so a row is always chosen
@@ -129,67 +177,74 @@ __device__ __attribute__((always_inline)) inline void panel_column(
     if (R.live[s] && better(a, R.pos[s], bv, bp)) {
       bv = a;
       bp = R.pos[s];
-      br = tid + LU_THREADS * s;
     }
   }
+  amax_step<T, DPP_XOR1>(bv, bp);
+  amax_step<T, DPP_XOR2>(bv, bp);
+  amax_step<T, DPP_HALF_MIRROR>(bv, bp);
+  amax_step<T, DPP_MIRROR>(bv, bp);
+  {
+    T wv = read_lane(bv, 0);
+    int wp = read_lane(bp, 0);
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const T v2 = __shfl_xor(bv, off, 64);
-    const int p2 = __shfl_xor(bp, off, 64);
-    const int r2 = __shfl_xor(br, off, 64);
-    if (better(v2, p2, bv, bp)) {
-      bv = v2;
-      bp = p2;
-      br = r2;
+    for (int l = 16; l < 64; l += 16) {
+      const T v2 = read_lane(bv, l);
+      const int p2 = read_lane(bp, l);
+      if (better(v2, p2, wv, wp)) {
+        wv = v2;
+        wp = p2;
+      }
     }
+    bv = wv;
+    bp = wp;
   }
   if (lane == 0) {
-    S.cand_v[wave] = bv;
-    S.cand_pos[wave] = bp;
-    S.cand_row[wave] = br;
+    S.cand_v[BUF][wave] = bv;
+    S.cand_pos[BUF][wave] = bp;
+  }
+#pragma unroll
+  for (int s = 0; s < LU_R; ++s) {
+    if (R.live[s] && R.pos[s] == bp) {
+#pragma unroll
+      for (int c = 0; c < LU_NB; ++c) S.slot[BUF][wave][c] = R.v[s][c];
+    }
   }
   __syncthreads();
-  bv = S.cand_v[0];
-  bp = S.cand_pos[0];
-  br = S.cand_row[0];
+  // --- the winner (ties to the lower position, as LAPACK)
+  bv = S.cand_v[BUF][0];
+  bp = S.cand_pos[BUF][0];
+  int bw = 0;
 #pragma unroll
   for (int w = 1; w < LU_WAVES; ++w) {
-    const T v2 = S.cand_v[w];
-    const int p2 = S.cand_pos[w];
+    const T v2 = S.cand_v[BUF][w];
+    const int p2 = S.cand_pos[BUF][w];
     if (better(v2, p2, bv, bp)) {
       bv = v2;
       bp = p2;
-      br = S.cand_row[w];
+      bw = w;
     }
   }
-  // --- publish the pivot row; LAPACK interchanges positions J and bp
+  const T* prow = S.slot[BUF][bw];
+  // LAPACK interchanges positions J and bp
 #pragma unroll
   for (int s = 0; s < LU_R; ++s) {
-    if (br == tid + LU_THREADS * s) {
-#pragma unroll
-      for (int c = 0; c < LU_NB; ++c) S.rows[J * LU_NB + c] = R.v[s][c];
-      R.live[s] = false;
-      R.pos[s] = J;
+    if (R.live[s]) {
+      if (R.pos[s] == bp) {
+        R.live[s] = false;
+        R.pos[s] = J;
+      } else if (R.pos[s] == J) {
+        R.pos[s] = bp;
+      }
     }
   }
-  if (tid == 0 && bp >= J && bp < m) {
-    const int q = ridx[J];
-    ridx[J] = br;
-    ridx[bp] = q;
-    S.moved_row = q;
-    S.moved_pos = bp;
+  if (tid == 0) {
     S.piv[J] = bp;
     piv[r0 + J] = r0 + bp;
     if (bv == T(0)) S.sing = 1;
   }
-  __syncthreads();
-  const int q = S.moved_row;
-  const int qp = S.moved_pos;
-#pragma unroll
-  for (int s = 0; s < LU_R; ++s)
-    if (q == tid + LU_THREADS * s && R.live[s]) R.pos[s] = qp;
+  if (tid < LU_NB) S.rows[J * LU_NB + tid] = prow[tid];
   // --- scale and rank-1 update of the rows not yet pivoted
-  const T pv = S.rows[J * LU_NB + J];
+  const T pv = prow[J];
   if (pv != T(0)) {
     const T inv = T(1) / pv;
 #pragma unroll
@@ -198,7 +253,7 @@ __device__ __attribute__((always_inline)) inline void panel_column(
         const T l = R.v[s][J] * inv;
         R.v[s][J] = l;
 #pragma unroll
-        for (int c = J + 1; c < LU_NB; ++c) R.v[s][c] -= l * S.rows[J * LU_NB + c];
+        for (int c = J + 1; c < LU_NB; ++c) R.v[s][c] -= l * prow[c];
       }
     }
   }
@@ -207,17 +262,17 @@ __device__ __attribute__((always_inline)) inline void panel_column(
 template <class T, int J>
 struct PanelColumns {
   static __device__ __attribute__((always_inline)) inline void run(
-      PanelRows<T>& R, int m, int r0, int kb, int* piv, int* ridx, LuShared<T>& S, int tid) {
+      PanelRows<T>& R, int m, int r0, int kb, int* piv, LuShared<T>& S, int tid) {
     if (J < kb) {
-      panel_column<T, J>(R, m, r0, piv, ridx, S, tid);
-      PanelColumns<T, J + 1>::run(R, m, r0, kb, piv, ridx, S, tid);
+      panel_column<T, J>(R, m, r0, piv, S, tid);
+      PanelColumns<T, J + 1>::run(R, m, r0, kb, piv, S, tid);
     }
   }
 };
 template <class T>
 struct PanelColumns<T, LU_NB> {
   static __device__ __attribute__((always_inline)) inline void run(
-      PanelRows<T>&, int, int, int, int*, int*, LuShared<T>&, int) {}
+      PanelRows<T>&, int, int, int, int*, LuShared<T>&, int) {}
 };
 
 // Factorise the m x kb panel whose rows sit in R.v (row tid + 512 s of the
@@ -237,14 +292,15 @@ __device__ __attribute__((always_inline)) inline void factor_panel(
     R.pos[s] = tid + LU_THREADS * s;
     R.live[s] = R.pos[s] < m;
   }
-  for (int r = tid; r < m; r += LU_THREADS) ridx[r] = r;
   __syncthreads();
-  PanelColumns<T, 0>::run(R, m, r0, kb, piv, ridx, S, tid);
-  // every row to its pivoted position (columns r0 .. r0+kb)
+  PanelColumns<T, 0>::run(R, m, r0, kb, piv, S, tid);
+  // every row to its pivoted position (columns r0 .. r0+kb); ridx[t] = the
+  // row (relative to r0) that ends up at position t
 #pragma unroll
   for (int s = 0; s < LU_R; ++s) {
     const int r = tid + LU_THREADS * s;
     if (r < m) {
+      ridx[R.pos[s]] = r;
       T* dst = A + (size_t)(r0 + R.pos[s]) * lda + r0;
 #pragma unroll
       for (int c = 0; c < LU_NB; ++c)
