@@ -757,9 +757,10 @@ static size_t lu_dynamic_lds(int n, int nrhs) {
 }
 
 // total LDS one workgroup of the FP64 k_lu_solve needs for order n and nrhs
-// columns (the FP32 one needs less)
+// columns (the FP32 one needs less), with room for the compiler's padding of
+// the static part
 size_t lu_lds_bytes(int n, int nrhs) {
-  return lu_dynamic_lds<double>(n, nrhs) + lu_static_lds<double>();
+  return lu_dynamic_lds<double>(n, nrhs) + lu_static_lds<double>() + 256;
 }
 
 // largest order k_lu_solve handles (panel rows are held in registers)
@@ -783,13 +784,20 @@ void launch_lu_solve_f32(float* A, size_t stride, int n, int ncols, int lda,
                      A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, info);
 }
 
+// the dynamic LDS limit of a kernel: what is left of `bytes` beside its
+// static LDS as the compiler laid it out (which may pad the struct)
+template <class T>
+static void lu_set_attr(size_t bytes) {
+  const void* f = reinterpret_cast<const void*>(k_lu_solve<T>);
+  hipFuncAttributes fa;
+  size_t fixed = lu_static_lds<T>();
+  if (hipFuncGetAttributes(&fa, f) == hipSuccess) fixed = std::max(fixed, fa.sharedSizeBytes);
+  hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(bytes - fixed));
+}
+
 void lu_set_attrs(size_t bytes) {
-  hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_solve<double>),
-                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)(bytes - lu_static_lds<double>()));
-  hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_solve<float>),
-                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)(bytes - lu_static_lds<float>()));
+  lu_set_attr<double>(bytes);
+  lu_set_attr<float>(bytes);
 }
 
 }  // namespace cs
