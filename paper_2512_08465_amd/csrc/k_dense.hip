@@ -493,8 +493,14 @@ __device__ void back_substitute(T* __restrict__ A, int lda, int n, int ncols, T*
     for (int e = tid; e < work; e += LU_THREADS) {
       const int i = e / nrhs, rc = e - i * nrhs;
       const T* urow = A + (size_t)i * lda + b0;
+      // the block's U entries all in flight before the first is used
+      T u[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) u[j] = (j < bs) ? urow[j] : T(0);
       T acc = A[(size_t)i * lda + n + rc];
-      for (int j = 0; j < bs; ++j) acc -= urow[j] * xs[j * nrhs + rc];
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (j < bs) acc -= u[j] * xs[j * nrhs + rc];
       A[(size_t)i * lda + n + rc] = acc;
     }
     __syncthreads();
@@ -561,9 +567,22 @@ __device__ inline void trailing_update(T* __restrict__ A, int lda, int n, int nc
     const int w = min(cap, ncols - c0);
     const int ldu = w + 1;
     if (tid == 0) S.tile = 0;
-    for (int e = tid; e < kbp * w; e += LU_THREADS) {
-      const int r = e / w, c = e - r * w;
-      P[r * ldu + c] = -A[(size_t)(kp + r) * lda + c0 + c];
+    // eight loads in flight per thread before any of them is used
+    const int tot = kbp * w;
+    for (int e0 = 0; e0 < tot; e0 += 8 * LU_THREADS) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * LU_THREADS + tid;
+        const int r = e / w, c = e - r * w;
+        v[u] = (e < tot) ? A[(size_t)(kp + r) * lda + c0 + c] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * LU_THREADS + tid;
+        const int r = e / w, c = e - r * w;
+        if (e < tot) P[r * ldu + c] = -v[u];
+      }
     }
     __syncthreads();
     const int gc = (w + 31) >> 5;
@@ -715,9 +734,17 @@ __global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
       // panel brings to its top (read before A2 moves them).  -M goes to LDS.
       T* Mneg = P + LU_NB * LU_NB;
       if (k2 < ncols) {
-        for (int e = tid; e < LU_NB * LU_NB; e += LU_THREADS) {
-          const int t = e / LU_NB, c = e - t * LU_NB;
-          P[e] = (t < kb2 && c < kb1) ? A[(size_t)(k1 + ridx[t]) * lda + k0 + c] : T(0);
+        {
+          // both elements of a thread in flight together
+          T v[LU_NB * LU_NB / LU_THREADS];
+#pragma unroll
+          for (int u = 0; u < LU_NB * LU_NB / LU_THREADS; ++u) {
+            const int e = u * LU_THREADS + tid;
+            const int t = e / LU_NB, c = e - t * LU_NB;
+            v[u] = (t < kb2 && c < kb1) ? A[(size_t)(k1 + ridx[t]) * lda + k0 + c] : T(0);
+          }
+#pragma unroll
+          for (int u = 0; u < LU_NB * LU_NB / LU_THREADS; ++u) P[u * LU_THREADS + tid] = v[u];
         }
         __syncthreads();
         for (int e = tid; e < LU_NB * LU_NB; e += LU_THREADS) {
