@@ -109,7 +109,8 @@ def _run_eig(ctx, mats):
     return wr.cpu().numpy() + 1j * wi.cpu().numpy(), info.cpu().numpy()
 
 
-@pytest.mark.parametrize("n,B", [(1, 2), (2, 3), (3, 3), (6, 4), (17, 3), (41, 5), (100, 2), (377, 2)])
+@pytest.mark.parametrize("n,B", [(1, 2), (2, 3), (3, 3), (6, 4), (17, 3), (41, 5), (100, 2), (377, 2),
+                                 (700, 1), (1024, 1)])
 def test_eigvals_random(ctx, n, B):
     rng = np.random.default_rng(n)
     A = rng.standard_normal((B, n, n))
@@ -117,6 +118,25 @@ def test_eigvals_random(ctx, n, B):
     assert np.all(info == 0)
     for b in range(B):
         assert match_eigs(np.linalg.eigvals(A[b]), lam[b]) < 1e-8
+
+
+def test_eigvals_with_vanishing_reflectors(ctx):
+    """Columns that are already zero below the subdiagonal give no reflector
+    (an upper triangular matrix, a Hessenberg matrix, a block-diagonal matrix
+    with a zero block): the reduction must pass them through unchanged."""
+    rng = np.random.default_rng(11)
+    n = 60
+    T = np.triu(rng.standard_normal((n, n)))
+    H = np.triu(rng.standard_normal((n, n)), -1)
+    Z = np.zeros((n, n))
+    Z[:30, :30] = rng.standard_normal((30, 30))
+    Z[40:, 40:] = rng.standard_normal((20, 20))
+    mats = np.stack([T, H, Z])
+    lam, info = _run_eig(ctx, mats)
+    assert np.all(info == 0)
+    assert match_eigs(np.diag(T).astype(complex), lam[0]) < 1e-10
+    for b in (1, 2):
+        assert match_eigs(np.linalg.eigvals(mats[b]), lam[b]) < 1e-8
 
 
 def test_eigvals_known_spectrum(ctx):
