@@ -237,9 +237,9 @@ def main():
 # FETCH_SIZE and WRITE_SIZE of the 512-system dispatch, each scaled by what the
 # same counter reads for the probe's 1 GiB device copy.  Valid only for the
 # kernel source it was measured on (hash below); otherwise traffic is null.
-LU_TRAFFIC = dict(source_sha256_16="0f5590d12f099b2f", batch=512,
-                  fetch_kib=7027928.125, write_kib=6776008.3125,
-                  copy_fetch_kib=524308.875, copy_write_kib=1048576.0,
+LU_TRAFFIC = dict(source_sha256_16="11acd941c9c615fe", batch=512,
+                  fetch_kib=7048119.1875, write_kib=6766047.4375,
+                  copy_fetch_kib=524308.1875, copy_write_kib=1048576.0,
                   copy_bytes=1 << 30)
 
 
