@@ -133,37 +133,62 @@ __device__ void hessenberg(double* __restrict__ H, int n, int lda, double* __res
       double* pw = pn + wave * n;   // this wavefront's partial p (lane-owned rows)
       if (nxt)
         for (int i = lane; i < n; i += 64) pw[i] = 0.0;
-      for (int j = k + 2 + wave; j < n; j += EIG_NW) {
-        double* cj = H + (size_t)j * lda;
-        const double sj = upd ? sv[j - k - 1] : 0.0, uj = upd ? u[j - k - 1] : 0.0;
-        const double unj = nxt ? un[j - k - 2] : 0.0;
-        double t = 0.0;
-        for (int i0 = 0; i0 < n; i0 += 64 * EIG_CG) {
-          double hv[EIG_CG];
+      // two columns per pass of a wavefront (j and j + EIG_NW), all their
+      // loads in flight together
+      for (int j0 = k + 2 + wave; j0 < n; j0 += 2 * EIG_NW) {
+        double* cj[2];
+        double sj[2], uj[2], unj[2], t[2];
+        bool jok[2];
 #pragma unroll
-          for (int c = 0; c < EIG_CG; ++c) {
-            const int i = i0 + 64 * c + lane;
-            hv[c] = (i < n) ? cj[i] : 0.0;
-          }
+        for (int p = 0; p < 2; ++p) {
+          const int j = j0 + p * EIG_NW;
+          jok[p] = j < n;
+          cj[p] = H + (size_t)(jok[p] ? j : j0) * lda;
+          sj[p] = (upd && jok[p]) ? sv[j - k - 1] : 0.0;
+          uj[p] = (upd && jok[p]) ? u[j - k - 1] : 0.0;
+          unj[p] = (nxt && jok[p]) ? un[j - k - 2] : 0.0;
+          t[p] = 0.0;
+        }
+        for (int i0 = 0; i0 < n; i0 += 64 * EIG_CG) {
+          double hv[2][EIG_CG];
+#pragma unroll
+          for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int c = 0; c < EIG_CG; ++c) {
+              const int i = i0 + 64 * c + lane;
+              hv[p][c] = (jok[p] && i < n) ? cj[p][i] : 0.0;
+            }
 #pragma unroll
           for (int c = 0; c < EIG_CG; ++c) {
             const int i = i0 + 64 * c + lane;
             if (i < n) {
-              double h = hv[c];
-              if (upd) {
-                h -= ((i > k) ? u[i - k - 1] * sj : 0.0) + w[i] * uj;
-                cj[i] = h;
+              const double ai = (upd && i > k) ? u[i - k - 1] : 0.0;
+              const double wi = upd ? w[i] : 0.0;
+              const double uni = (nxt && i >= k + 2) ? un[i - k - 2] : 0.0;
+              double pacc = 0.0;
+#pragma unroll
+              for (int p = 0; p < 2; ++p) {
+                if (jok[p]) {
+                  double h = hv[p][c];
+                  if (upd) {
+                    h -= ai * sj[p] + wi * uj[p];
+                    cj[p][i] = h;
+                  }
+                  pacc += h * unj[p];
+                  t[p] += uni * h;
+                }
               }
-              if (nxt) {
-                pw[i] += h * unj;
-                if (i >= k + 2) t += un[i - k - 2] * h;
-              }
+              if (nxt) pw[i] += pacc;
             }
           }
         }
         if (nxt) {
-          for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-          if (lane == 0) sn[j - k - 2] = taun * t;
+#pragma unroll
+          for (int p = 0; p < 2; ++p) {
+            double tp = t[p];
+            for (int off = 32; off > 0; off >>= 1) tp += __shfl_xor(tp, off, 64);
+            if (lane == 0 && jok[p]) sn[j0 + p * EIG_NW - k - 2] = taun * tp;
+          }
         }
       }
     }
