@@ -5,6 +5,8 @@
   tied by a lossless line: the electromechanical pair is
   s = -D/(4H) +- j sqrt(ws Ks / H - (D/4H)^2), Ks = E1 E2 cos(d12) / Xt,
   with internal voltages E = V + j Xd' I from the textbook model.
+* A single machine against an infinite bus (the other machine's inertia and
+  damping scaled by 1e7): 2H s^2 + D s + ws Ks = 0.
 * The equilibrium built from the OPF point satisfies f = 0 and g = 0.
 * The analytic Jacobians match central differences of f and g.
 * The full matrix has one eigenvalue at 0 (uniform angle shift) that the
@@ -48,6 +50,30 @@ def test_two_machine_classical_closed_form():
     assert abs(lam[k] - s_expected) < 1e-6 * abs(s_expected)
     # common-mode speed deviation decays at -D/(2H)
     assert np.min(np.abs(lam - (-D / (2 * H)))) < 1e-6
+
+
+def test_single_machine_infinite_bus_closed_form():
+    """Machine 1 with an inertia 1e7 times larger acts as an infinite bus:
+    the electromechanical mode of machine 0 is the SMIB root of
+    2H s^2 + D s + ws Ks = 0, s = -D/(4H) +- j sqrt(ws Ks / (2H) - (D/4H)^2)."""
+    H, D, xl, xdp = 4.0, 3.0, 0.2, 0.3
+    net = _classical_pair(H, D, xl, xdp)
+    big = 1e7
+    net["dyn"][1, netgen.DYN_COLS.index("H")] = H * big
+    net["dyn"][1, netgen.DYN_COLS.index("D")] = D * big
+    sub = full_subsystem(net)
+    o = opf.solve_opf(net, sub)
+    assert o.status == opf.CONVERGED
+    V = o.vm * np.exp(1j * o.va)
+    I = np.conj((o.pg + 1j * o.qg) / V)
+    E = V + 1j * xdp * I
+    Ks = abs(E[0]) * abs(E[1]) * np.cos(np.angle(E[0]) - np.angle(E[1])) / (2 * xdp + xl)
+    ws = 2 * np.pi * 60.0
+    w = np.sqrt(ws * Ks / (2 * H) - (D / (4 * H)) ** 2)
+    s_expected = complex(-D / (4 * H), w)
+    lam = eigen.eigvals(dynamics.DynModel(net, sub, o.vm, o.va, o.pg, o.qg).state_matrix())
+    k = np.argmin(np.abs(lam - s_expected))
+    assert abs(lam[k] - s_expected) < 1e-5 * abs(s_expected)
 
 
 @pytest.fixture(scope="module")
