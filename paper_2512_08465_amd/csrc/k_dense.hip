@@ -677,8 +677,15 @@ __device__ inline void interchange_trsm(T* __restrict__ A, int lda, int ncols, i
   }
 }
 
+// Wavefronts per SIMD the register budget is cut for.  FP64: two (one
+// workgroup per CU; the panel rows fill the registers).  FP32: four (two
+// workgroups per CU), so that one workgroup's latency-bound panel steps
+// overlap the other's work.
 template <class T>
-__global__ __launch_bounds__(LU_THREADS, 1) void k_lu_solve(
+struct LuWavesPerEu { static constexpr int value = sizeof(T) == 4 ? 4 : 2; };
+
+template <class T>
+__global__ __launch_bounds__(LU_THREADS, LuWavesPerEu<T>::value) void k_lu_solve(
     T* __restrict__ Abase, size_t stride, int n, int ncols, int lda,
     int* __restrict__ pivbase, int piv_stride, SlotState* __restrict__ st,
     int want_phase, int want_job, int* __restrict__ info) {
