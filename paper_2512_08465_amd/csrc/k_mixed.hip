@@ -40,9 +40,24 @@ __global__ __launch_bounds__(256) void k_kkt_to_f32(Slots s, int count) {
   const int n = s.nk;
   const double* K = s.K + (size_t)slot * s.k_stride;
   float* F = s.K32 + (size_t)slot * s.k32_stride;
-  for (int r = 0; r < n; ++r)
-    for (int c = threadIdx.x; c <= n; c += blockDim.x)
-      F[(size_t)r * s.ld32 + c] = (float)K[(size_t)r * s.ldk + c];
+  // element e = r (n + 1) + c of the augmented system; eight loads of a
+  // thread in flight together
+  const int w = n + 1, tot = n * w;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += 8 * blockDim.x) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * blockDim.x;
+      const int r = e / w, c = e - r * w;
+      v[u] = (e < tot) ? K[(size_t)r * s.ldk + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * blockDim.x;
+      const int r = e / w, c = e - r * w;
+      if (e < tot) F[(size_t)r * s.ld32 + c] = (float)v[u];
+    }
+  }
 }
 
 // perm[i] = the row of the original system at position i after the
@@ -88,8 +103,14 @@ __device__ void forward_f32(const float* __restrict__ F, int ld, int n, float* y
     __syncthreads();
     for (int i = b0 + bs + tid; i < n; i += MX_THREADS) {
       const float* row = F + (size_t)i * ld + b0;
+      // the block's entries all in flight before the first is used
+      float f[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) f[j] = (j < bs) ? row[j] : 0.f;
       float acc = y[i];
-      for (int j = 0; j < bs; ++j) acc -= row[j] * y[b0 + j];
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (j < bs) acc -= f[j] * y[b0 + j];
       y[i] = acc;
     }
     __syncthreads();
@@ -121,8 +142,13 @@ __device__ void backward_f32(const float* __restrict__ F, int ld, int n, float* 
     __syncthreads();
     for (int i = tid; i < b0; i += MX_THREADS) {
       const float* row = F + (size_t)i * ld + b0;
+      float f[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) f[j] = (j < bs) ? row[j] : 0.f;
       float acc = y[i];
-      for (int j = 0; j < bs; ++j) acc -= row[j] * y[b0 + j];
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (j < bs) acc -= f[j] * y[b0 + j];
       y[i] = acc;
     }
     __syncthreads();
@@ -168,10 +194,20 @@ __global__ __launch_bounds__(MX_THREADS) void k_kkt_refine(Slots s, int count, i
     for (int i = wave; i < n; i += MX_WAVES) {
       const double* row = K + (size_t)i * s.ldk;
       double acc = 0.0, den = 0.0;
-      for (int j = lane; j < n; j += 64) {
-        const double a = row[j];
-        acc += a * x[j];
-        den += fabs(a) * fabs(x[j]);
+      // the row's entries in groups of 8 per lane, loads of a group in flight
+      // together
+      for (int j0 = lane; j0 < n; j0 += 8 * 64) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = (j0 + 64 * u < n) ? row[j0 + 64 * u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int j = j0 + 64 * u;
+          if (j < n) {
+            acc += a[u] * x[j];
+            den += fabs(a[u]) * fabs(x[j]);
+          }
+        }
       }
       for (int off = 32; off > 0; off >>= 1) {
         acc += __shfl_xor(acc, off, 64);
