@@ -164,3 +164,28 @@ def test_small_batches_give_same_records(nets):
         assert np.array_equal(a[k], b[k])
     assert np.array_equal(a["opf_cost"], b["opf_cost"], equal_nan=True)
     assert np.array_equal(Ra, Rb)
+
+
+def test_empty_and_single_scenario_lists(nets):
+    """An empty list gives no records and R_i = 0; a one-scenario list gives
+    the same record as that scenario inside a longer list."""
+    g = load_golden("c1_30")
+    net = load_case("c1_30")
+    res0, R0 = nets["c1_30"].screen(np.zeros((0, 2), np.int32), net["lam"])
+    assert len(res0) == 0
+    assert np.all(R0 == 0.0)
+    for i in (0, 45, 500):
+        r1, _ = nets["c1_30"].screen(g["outages"][i:i + 1], net["lam"])
+        assert len(r1) == 1
+        for k in ("severe", "cause", "opf_status", "opf_iters", "n_islands"):
+            assert r1[k][0] == g[k][i] or (g["near"][i] > 0 or r1["near"][0] > 0), (i, k)
+
+
+def test_dense_kernels_accept_an_empty_batch(ctx):
+    import torch
+    d = torch.zeros(16, dtype=torch.float64, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.dense_solve_batched(d.data_ptr(), 4, 0, 4, 0, info.data_ptr())
+    ctx.eigvals_batched(d.data_ptr(), 4, 4, 0, d.data_ptr(), d.data_ptr(), info.data_ptr())
+    torch.cuda.synchronize()
+    assert torch.all(d == 0)
