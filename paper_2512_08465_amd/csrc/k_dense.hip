@@ -455,32 +455,33 @@ __device__ inline void update_group(T* __restrict__ A, int lda, int n, int ncols
 }
 
 // Back substitution U x = y for the right-hand-side columns n..ncols-1 (the
-// forward substitution was done on them during the elimination), by 16-row
+// forward substitution was done on them during the elimination), by 32-row
 // blocks from the bottom.  A wavefront solves a diagonal block for one
 // right-hand side at a time (lane i holds row i; x_i is broadcast and
 // eliminated from the rows above), the block solution is kept in LDS (xs,
-// 16 x nrhs; ub, 16 x 16), then every row above is updated.
+// 32 x nrhs; ub, 32 x 32), then every row above is updated.
+constexpr int LU_BS = 32;
 template <class T>
 __device__ void back_substitute(T* __restrict__ A, int lda, int n, int ncols, T* xs, T* ub,
                                 int tid) {
   const int lane = tid & 63, wave = tid >> 6;
   const int nrhs = ncols - n;
   if (nrhs <= 0) return;
-  const int nblk = (n + 15) / 16;
+  const int nblk = (n + LU_BS - 1) / LU_BS;
   for (int b = nblk - 1; b >= 0; --b) {
-    const int b0 = b * 16;
-    const int bs = min(16, n - b0);
-    for (int e = tid; e < 256; e += LU_THREADS) {
-      const int i = e >> 4, j = e & 15;
+    const int b0 = b * LU_BS;
+    const int bs = min(LU_BS, n - b0);
+    for (int e = tid; e < LU_BS * LU_BS; e += LU_THREADS) {
+      const int i = e / LU_BS, j = e % LU_BS;
       ub[e] = (i < bs && j < bs) ? A[(size_t)(b0 + i) * lda + b0 + j] : T(0);
     }
     __syncthreads();
     for (int rc = wave; rc < nrhs; rc += LU_WAVES) {
       T y = (lane < bs) ? A[(size_t)(b0 + lane) * lda + n + rc] : T(0);
       for (int i = bs - 1; i >= 0; --i) {
-        const T xi = __shfl(y, i, 64) / ub[i * 16 + i];
+        const T xi = __shfl(y, i, 64) / ub[i * LU_BS + i];
         if (lane == i) y = xi;
-        if (lane < i) y -= ub[lane * 16 + i] * xi;
+        if (lane < i) y -= ub[lane * LU_BS + i] * xi;
       }
       if (lane < bs) {
         xs[lane * nrhs + rc] = y;
@@ -494,12 +495,12 @@ __device__ void back_substitute(T* __restrict__ A, int lda, int n, int ncols, T*
       const int i = e / nrhs, rc = e - i * nrhs;
       const T* urow = A + (size_t)i * lda + b0;
       // the block's U entries all in flight before the first is used
-      T u[16];
+      T u[LU_BS];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) u[j] = (j < bs) ? urow[j] : T(0);
+      for (int j = 0; j < LU_BS; ++j) u[j] = (j < bs) ? urow[j] : T(0);
       T acc = A[(size_t)i * lda + n + rc];
 #pragma unroll
-      for (int j = 0; j < 16; ++j)
+      for (int j = 0; j < LU_BS; ++j)
         if (j < bs) acc -= u[j] * xs[j * nrhs + rc];
       A[(size_t)i * lda + n + rc] = acc;
     }
@@ -783,11 +784,11 @@ constexpr size_t lu_static_lds() { return sizeof(LuShared<T>); }
 
 // dynamic LDS: the chunk area (a 16-column chunk of panel rows, or staged
 // U12 rows) and the panel's row-index scratch during the factorisation; a
-// 16 x nrhs block during the solve
+// 32 x nrhs block during the solve
 template <class T>
 static size_t lu_dynamic_lds(int n, int nrhs) {
   return std::max(sizeof(T) * (size_t)chunk_elems(n) + sizeof(int) * (size_t)n,
-                  sizeof(T) * (size_t)16 * (size_t)nrhs);
+                  sizeof(T) * (size_t)LU_BS * (size_t)nrhs);
 }
 
 // total LDS one workgroup of the FP64 k_lu_solve needs for order n and nrhs
