@@ -202,11 +202,13 @@ __device__ __attribute__((always_inline)) inline void panel_column(
     S.cand_v[BUF][wave] = bv;
     S.cand_pos[BUF][wave] = bp;
   }
+  // (only columns J.. are needed by the elimination; the whole pivot rows
+  // go to S.rows at the end of the panel)
 #pragma unroll
   for (int s = 0; s < LU_R; ++s) {
     if (R.live[s] && R.pos[s] == bp) {
 #pragma unroll
-      for (int c = 0; c < LU_NB; ++c) S.slot[BUF][wave][c] = R.v[s][c];
+      for (int c = J; c < LU_NB; ++c) S.slot[BUF][wave][c] = R.v[s][c];
     }
   }
   __syncthreads();
@@ -242,7 +244,6 @@ __device__ __attribute__((always_inline)) inline void panel_column(
     piv[r0 + J] = r0 + bp;
     if (bv == T(0)) S.sing = 1;
   }
-  if (tid < LU_NB) S.rows[J * LU_NB + tid] = prow[tid];
   // --- scale and rank-1 update of the rows not yet pivoted
   const T pv = prow[J];
   if (pv != T(0)) {
@@ -295,12 +296,17 @@ __device__ __attribute__((always_inline)) inline void factor_panel(
   __syncthreads();
   PanelColumns<T, 0>::run(R, m, r0, kb, piv, S, tid);
   // every row to its pivoted position (columns r0 .. r0+kb); ridx[t] = the
-  // row (relative to r0) that ends up at position t
+  // row (relative to r0) that ends up at position t; the pivot rows also to
+  // S.rows ([L11 | U11])
 #pragma unroll
   for (int s = 0; s < LU_R; ++s) {
     const int r = tid + LU_THREADS * s;
     if (r < m) {
       ridx[R.pos[s]] = r;
+      if (R.pos[s] < kb) {
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) S.rows[R.pos[s] * LU_NB + c] = R.v[s][c];
+      }
       T* dst = A + (size_t)(r0 + R.pos[s]) * lda + r0;
 #pragma unroll
       for (int c = 0; c < LU_NB; ++c)
