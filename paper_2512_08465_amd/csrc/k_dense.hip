@@ -115,19 +115,20 @@ struct PanelRows {
 
 // Cross-lane moves within a 16-lane row of the wavefront (DPP), for 32-bit
 // and 64-bit values.
-template <int CTRL>
+// (rows outside ROWS keep their own value)
+template <int CTRL, int ROWS = 0xF>
 __device__ inline int dpp_move(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWS, 0xF, false);
 }
-template <int CTRL>
+template <int CTRL, int ROWS = 0xF>
 __device__ inline float dpp_move(float v) {
-  return __builtin_bit_cast(float, dpp_move<CTRL>(__builtin_bit_cast(int, v)));
+  return __builtin_bit_cast(float, dpp_move<CTRL, ROWS>(__builtin_bit_cast(int, v)));
 }
-template <int CTRL>
+template <int CTRL, int ROWS = 0xF>
 __device__ inline double dpp_move(double v) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const int lo = dpp_move<CTRL>((int)(unsigned)(u & 0xffffffffu));
-  const int hi = dpp_move<CTRL>((int)(unsigned)(u >> 32));
+  const int lo = dpp_move<CTRL, ROWS>((int)(unsigned)(u & 0xffffffffu));
+  const int hi = dpp_move<CTRL, ROWS>((int)(unsigned)(u >> 32));
   return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 __device__ inline int read_lane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
@@ -140,18 +141,33 @@ __device__ inline double read_lane(double v, int l) {
   const int hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
   return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
-template <class T, int CTRL>
+template <class T, int CTRL, int ROWS = 0xF>
 __device__ inline void amax_step(T& bv, int& bp) {
-  const T v2 = dpp_move<CTRL>(bv);
-  const int p2 = dpp_move<CTRL>(bp);
+  const T v2 = dpp_move<CTRL, ROWS>(bv);
+  const int p2 = dpp_move<CTRL, ROWS>(bp);
   if (better(v2, p2, bv, bp)) {
     bv = v2;
     bp = p2;
   }
 }
 // DPP controls: lane pairs, lane quads, 8-lane halves mirrored, 16-lane rows
-// mirrored; after the four steps every lane of a row holds the row's best
+// mirrored (after these four every lane of a row holds the row's best); then
+// lane 15 of rows 0 and 2 to rows 1 and 3, and lane 31 to rows 2 and 3, after
+// which lane 63 holds the wavefront's best
 constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
+constexpr int DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143;
+// the same with the candidate's wavefront carried along
+template <class T, int CTRL>
+__device__ inline void choose_step(T& bv, int& bp, int& bw) {
+  const T v2 = dpp_move<CTRL>(bv);
+  const int p2 = dpp_move<CTRL>(bp);
+  const int w2 = dpp_move<CTRL>(bw);
+  if (better(v2, p2, bv, bp)) {
+    bv = v2;
+    bp = p2;
+    bw = w2;
+  }
+}
 
 // One column J of the panel factorisation (J is a compile-time constant so
 // that every register index is static).  One workgroup barrier: each
@@ -183,21 +199,10 @@ __device__ __attribute__((always_inline)) inline void panel_column(
   amax_step<T, DPP_XOR2>(bv, bp);
   amax_step<T, DPP_HALF_MIRROR>(bv, bp);
   amax_step<T, DPP_MIRROR>(bv, bp);
-  {
-    T wv = read_lane(bv, 0);
-    int wp = read_lane(bp, 0);
-#pragma unroll
-    for (int l = 16; l < 64; l += 16) {
-      const T v2 = read_lane(bv, l);
-      const int p2 = read_lane(bp, l);
-      if (better(v2, p2, wv, wp)) {
-        wv = v2;
-        wp = p2;
-      }
-    }
-    bv = wv;
-    bp = wp;
-  }
+  amax_step<T, DPP_BCAST15, 0xA>(bv, bp);
+  amax_step<T, DPP_BCAST31, 0xC>(bv, bp);
+  bv = read_lane(bv, 63);
+  bp = read_lane(bp, 63);
   if (lane == 0) {
     S.cand_v[BUF][wave] = bv;
     S.cand_pos[BUF][wave] = bp;
@@ -212,20 +217,21 @@ __device__ __attribute__((always_inline)) inline void panel_column(
     }
   }
   __syncthreads();
-  // --- the winner (ties to the lower position, as LAPACK)
-  bv = S.cand_v[BUF][0];
-  bp = S.cand_pos[BUF][0];
-  int bw = 0;
-#pragma unroll
-  for (int w = 1; w < LU_WAVES; ++w) {
-    const T v2 = S.cand_v[BUF][w];
-    const int p2 = S.cand_pos[BUF][w];
-    if (better(v2, p2, bv, bp)) {
-      bv = v2;
-      bp = p2;
-      bw = w;
-    }
+  // --- the winner (ties to the lower position, as LAPACK): lanes 0..7 of
+  // every wavefront take the eight candidates and reduce them on DPP
+  T cv = T(-1);
+  int cp = INT_MAX, cw = 0;
+  if (lane < LU_WAVES) {
+    cv = S.cand_v[BUF][lane];
+    cp = S.cand_pos[BUF][lane];
+    cw = lane;
   }
+  choose_step<T, DPP_XOR1>(cv, cp, cw);
+  choose_step<T, DPP_XOR2>(cv, cp, cw);
+  choose_step<T, DPP_HALF_MIRROR>(cv, cp, cw);
+  bv = read_lane(cv, 0);
+  bp = read_lane(cp, 0);
+  const int bw = read_lane(cw, 0);
   const T* prow = S.slot[BUF][bw];
   // LAPACK interchanges positions J and bp
 #pragma unroll
