@@ -237,9 +237,9 @@ def main():
 # FETCH_SIZE and WRITE_SIZE of the 512-system dispatch, each scaled by what the
 # same counter reads for the probe's 1 GiB device copy.  Valid only for the
 # kernel source it was measured on (hash below); otherwise traffic is null.
-LU_TRAFFIC = dict(source_sha256_16="13d8b3a3f57f6b50", batch=512,
-                  fetch_kib=7060926.0, write_kib=6780252.4375,
-                  copy_fetch_kib=524309.4375, copy_write_kib=1048576.0,
+LU_TRAFFIC = dict(source_sha256_16="263e7e1962b3bbd5", batch=512,
+                  fetch_kib=6945079.8125, write_kib=6693568.03125,
+                  copy_fetch_kib=524308.8125, copy_write_kib=1048576.0,
                   copy_bytes=1 << 30)
 
 
