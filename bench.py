@@ -237,7 +237,7 @@ def main():
 # FETCH_SIZE and WRITE_SIZE of the 512-system dispatch, each scaled by what the
 # same counter reads for the probe's 1 GiB device copy.  Valid only for the
 # kernel source it was measured on (hash below); otherwise traffic is null.
-LU_TRAFFIC = dict(source_sha256_16="263e7e1962b3bbd5", batch=512,
+LU_TRAFFIC = dict(source_sha256_16="0b5c9e997d5711ec", batch=512,
                   fetch_kib=6945079.8125, write_kib=6693568.03125,
                   copy_fetch_kib=524308.8125, copy_write_kib=1048576.0,
                   copy_bytes=1 << 30)

@@ -6,28 +6,32 @@
 // n..ncols-1 (an augmented matrix): the forward substitution falls out of the
 // elimination and only the back substitution with U remains.
 //
-// Right-looking blocked LU, panel width NB = 32, eight wavefronts per matrix.
-// Per panel (columns k0 .. k0+kb, factors already in place, pivots known):
-//   A. row interchanges of the panel applied to every other column (the
-//      panel's swaps compose to one permutation of at most 2 NB rows: each
-//      thread gathers its column's affected rows, then scatters them); then
-//      the block row U12 = inv(L11) A12 on MFMA, inv(L11) being the inverse
-//      of the panel's unit lower triangle;
-//   B. the next panel's columns are brought up to date (A -= L21 U12 on
-//      MFMA), passed through LDS in 16-column chunks and loaded into
-//      registers: thread t holds panel rows t and t + 512;
-//   P. that panel is factorised in registers by all threads.  Rows are never
-//      moved while it runs: each keeps its LAPACK position (the position it
-//      would occupy after the interchanges so far) and a "pivoted" flag.  Per
-//      column: a wavefront argmax of |a| (ties to the lower position), one
-//      barrier, the eight wave candidates reduced by every thread, the pivot
-//      row published in LDS, a second barrier, then the rank-1 update of the
-//      rows not yet pivoted.  Finally every row is written to its position;
-//   C. the rest of the trailing matrix, A22 -= L21 U12, on the matrix cores
-//      (v_mfma_f64_16x16x4f64, or v_mfma_f32_16x16x4f32 for the FP32
-//      factorisation of the mixed-precision solve) on 32 x 32 groups of four
-//      16 x 16 tiles taken from an LDS counter.
-// After the last panel, U x = y is solved by 16-row blocks from the bottom.
+// Right-looking blocked LU, panel width NB = 32, eight wavefronts per matrix,
+// panels taken in pairs so that the trailing matrix is updated once per pair
+// with rank 64.  Per pair (panels [k0, k1) and [k1, k2)):
+//   B1. the first panel's columns are brought up to date by the previous
+//       pair (A -= L21 U12 on MFMA), passed through LDS in 16-column chunks
+//       and loaded into registers: thread t holds panel rows t and t + 512;
+//   P1. that panel is factorised in registers by all threads.  Rows are never
+//       moved while it runs: each keeps its LAPACK position (the position it
+//       would occupy after the interchanges so far) and a "pivoted" flag.  Per
+//       column: a wavefront argmax of |a| on DPP (ties to the lower position),
+//       each wavefront publishes its candidate and the candidate's row in LDS,
+//       one barrier, every thread picks the winner and eliminates with that
+//       row.  Finally every row is written to its position;
+//   C.  the rest of the previous pair's trailing update (rows from k0,
+//       columns from k1) on the matrix cores (v_mfma_f64_16x16x4f64, or
+//       v_mfma_f32_16x16x4f32 for the FP32 factorisation of the mixed-
+//       precision solve), 32 x 32 groups of four 16 x 16 tiles taken from an
+//       LDS counter, -U12 staged in LDS;
+//   A1. the first panel's row interchanges applied to every other column (the
+//       swaps compose to one permutation of at most 2 NB rows: each wavefront
+//       gathers its columns' affected rows, then scatters them), fused with
+//       the block row U12 = inv(L11) A12 on MFMA;
+//   B2, P2. the second panel, brought up to date by the first, factorised;
+//   A2. its interchanges and U12 rows, which right of the pair still lack the
+//       first panel's update: that comes in through M = inv(L11_2) L_top,1.
+// After the last pair, U x = y is solved by 32-row blocks from the bottom.
 #include "cs_internal.h"
 
 #include <algorithm>
@@ -108,7 +112,7 @@ __device__ inline bool better(T v, int pos, T bv, int bpos) {
 // Per-thread state of the panel factorisation.
 template <class T>
 struct PanelRows {
-  T v[LU_R][LU_NB];        // panel row tid + 512 s, columns of the panel
+  T v[LU_R][LU_NB];        // panel row tid + LU_THREADS s, columns of the panel
   int pos[LU_R];           // its LAPACK position within the panel
   bool live[LU_R];         // not yet chosen as a pivot
 };
@@ -282,14 +286,15 @@ struct PanelColumns<T, LU_NB> {
       PanelRows<T>&, int, int, int, int*, LuShared<T>&, int) {}
 };
 
-// Factorise the m x kb panel whose rows sit in R.v (row tid + 512 s of the
+// Factorise the m x kb panel whose rows sit in R.v (row tid + LU_THREADS s of the
 // panel, relative to its first row r0) with all threads of the workgroup.
 // Rows are never moved while it runs: each keeps its LAPACK position (the
 // position it would occupy after the interchanges so far) and a "pivoted"
 // flag.  Writes the factored rows to A at their pivoted positions, the
 // pivots to piv[] (absolute) and S.piv (relative), L11/U11 to S.rows,
 // inv(L11) to S.linv and the rows interchanged below the panel's top to
-// S.bq / S.bs.  ridx[] is LDS scratch of m ints.
+// S.bq / S.bs, and in ridx[t] (LDS, m ints) the row, relative to r0, that
+// ends up at position t.
 template <class T>
 __device__ __attribute__((always_inline)) inline void factor_panel(
     PanelRows<T>& R, int m, int r0, int kb, T* __restrict__ A, int lda,
