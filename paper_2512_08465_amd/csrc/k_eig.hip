@@ -1,18 +1,19 @@
 // Batched nonsymmetric eigenvalues (one workgroup per matrix).
 //
 // The small-signal test needs every eigenvalue of the state matrix.  Each
-// matrix is reduced to upper Hessenberg form by Householder reflections
-// (left update: one wavefront per column, lanes over rows; right update: one
-// thread per row), then Francis implicit double-shift QR sweeps run on the
-// active window [lo, hi] until every 1x1 or 2x2 diagonal block has split off
-// (eigenvalues only, so updates stay inside the window).  A sweep chases its
-// bulge in blocks of 16 steps through a small diagonal block held in LDS and
-// applies the accumulated reflectors to the rest of the window once per
-// block.  Deflation: a
-// subdiagonal entry is negligible when |h(k,k-1)| <= eps (|h(k-1,k-1)| +
-// |h(k,k)|).  Every tenth sweep without deflation uses an exceptional shift.
-// The matrix lives in global memory (column-major, lda), and the reflector
-// vectors and reduction scratch live in LDS.
+// matrix is reduced to upper Hessenberg form by Householder reflections, one
+// read-write pass over the trailing columns per reflector (the two-sided
+// update of one step fused with the products the next step needs), then
+// Francis implicit double-shift QR sweeps run on the active window [lo, hi]
+// until every 1x1 or 2x2 diagonal block has split off (eigenvalues only, so
+// updates stay inside the window).  A sweep chases its bulge in blocks of 16
+// steps through a small diagonal block held in LDS and applies the
+// accumulated reflectors to the rest of the window once per block.
+// Deflation: a subdiagonal entry is negligible when |h(k,k-1)| <= eps
+// (|h(k-1,k-1)| + |h(k,k)|).  Every tenth sweep without deflation uses an
+// exceptional shift.  The matrix lives in global memory (column-major, lda);
+// the reflector vectors, the reduction's partial sums and the chased block
+// live in LDS.
 #include "cs_internal.h"
 #include <float.h>
 
