@@ -77,18 +77,19 @@ __device__ void pivots_to_perm(const int* piv, int n, int* perm) {
   __syncthreads();
 }
 
-// The triangular solves work by 16-row blocks: the diagonal block is staged
+// The triangular solves work by 32-row blocks: the diagonal block is staged
 // in LDS, one wavefront solves it (lane i holds y_i; each solved value is
 // broadcast and eliminated from the other rows of the block), then every
 // thread updates the rows outside the block.
+constexpr int MX_BS = 32;
 
 // y <- L^{-1} y, L unit lower triangular (row-major, below the diagonal of F)
 __device__ void forward_f32(const float* __restrict__ F, int ld, int n, float* y, float* blk) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int b0 = 0; b0 < n; b0 += 16) {
-    const int bs = min(16, n - b0);
-    for (int e = tid; e < 256; e += MX_THREADS) {
-      const int i = e >> 4, j = e & 15;
+  for (int b0 = 0; b0 < n; b0 += MX_BS) {
+    const int bs = min(MX_BS, n - b0);
+    for (int e = tid; e < MX_BS * MX_BS; e += MX_THREADS) {
+      const int i = e / MX_BS, j = e % MX_BS;
       blk[e] = (i < bs && j < bs) ? F[(size_t)(b0 + i) * ld + b0 + j] : 0.f;
     }
     __syncthreads();
@@ -96,7 +97,7 @@ __device__ void forward_f32(const float* __restrict__ F, int ld, int n, float* y
       float v = (lane < bs) ? y[b0 + lane] : 0.f;
       for (int i = 0; i < bs; ++i) {
         const float yi = __shfl(v, i, 64);
-        if (lane > i && lane < bs) v -= blk[lane * 16 + i] * yi;
+        if (lane > i && lane < bs) v -= blk[lane * MX_BS + i] * yi;
       }
       if (lane < bs) y[b0 + lane] = v;
     }
@@ -104,12 +105,12 @@ __device__ void forward_f32(const float* __restrict__ F, int ld, int n, float* y
     for (int i = b0 + bs + tid; i < n; i += MX_THREADS) {
       const float* row = F + (size_t)i * ld + b0;
       // the block's entries all in flight before the first is used
-      float f[16];
+      float f[MX_BS];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) f[j] = (j < bs) ? row[j] : 0.f;
+      for (int j = 0; j < MX_BS; ++j) f[j] = (j < bs) ? row[j] : 0.f;
       float acc = y[i];
 #pragma unroll
-      for (int j = 0; j < 16; ++j)
+      for (int j = 0; j < MX_BS; ++j)
         if (j < bs) acc -= f[j] * y[b0 + j];
       y[i] = acc;
     }
@@ -121,33 +122,33 @@ __device__ void forward_f32(const float* __restrict__ F, int ld, int n, float* y
 // the bottom block up
 __device__ void backward_f32(const float* __restrict__ F, int ld, int n, float* y, float* blk) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nblk = (n + 15) / 16;
+  const int nblk = (n + MX_BS - 1) / MX_BS;
   for (int b = nblk - 1; b >= 0; --b) {
-    const int b0 = b * 16;
-    const int bs = min(16, n - b0);
-    for (int e = tid; e < 256; e += MX_THREADS) {
-      const int i = e >> 4, j = e & 15;
+    const int b0 = b * MX_BS;
+    const int bs = min(MX_BS, n - b0);
+    for (int e = tid; e < MX_BS * MX_BS; e += MX_THREADS) {
+      const int i = e / MX_BS, j = e % MX_BS;
       blk[e] = (i < bs && j < bs) ? F[(size_t)(b0 + i) * ld + b0 + j] : 0.f;
     }
     __syncthreads();
     if (wave == 0) {
       float v = (lane < bs) ? y[b0 + lane] : 0.f;
       for (int i = bs - 1; i >= 0; --i) {
-        const float xi = __shfl(v, i, 64) / blk[i * 16 + i];
+        const float xi = __shfl(v, i, 64) / blk[i * MX_BS + i];
         if (lane == i) v = xi;
-        if (lane < i) v -= blk[lane * 16 + i] * xi;
+        if (lane < i) v -= blk[lane * MX_BS + i] * xi;
       }
       if (lane < bs) y[b0 + lane] = v;
     }
     __syncthreads();
     for (int i = tid; i < b0; i += MX_THREADS) {
       const float* row = F + (size_t)i * ld + b0;
-      float f[16];
+      float f[MX_BS];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) f[j] = (j < bs) ? row[j] : 0.f;
+      for (int j = 0; j < MX_BS; ++j) f[j] = (j < bs) ? row[j] : 0.f;
       float acc = y[i];
 #pragma unroll
-      for (int j = 0; j < 16; ++j)
+      for (int j = 0; j < MX_BS; ++j)
         if (j < bs) acc -= f[j] * y[b0 + j];
       y[i] = acc;
     }
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(MX_THREADS) void k_kkt_refine(Slots s, int count, i
   float* y = reinterpret_cast<float*>(r + n);          // [n]
   int* perm = reinterpret_cast<int*>(y + n);           // [n]
   __shared__ double red[MX_WAVES];
-  __shared__ float blk[256];
+  __shared__ float blk[MX_BS * MX_BS];
   __shared__ int s_ok;
   for (int i = tid; i < n; i += MX_THREADS) x[i] = (double)F[(size_t)i * s.ld32 + n];
   pivots_to_perm(piv, n, perm);
