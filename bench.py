@@ -259,13 +259,17 @@ def lu_traffic_per_factorisation():
 PMC_COPY_BYTES = 1 << 30
 PMC_LU_BATCH = 512
 PMC_LU_ORDER = 580
+PMC_EIG_BATCH = 1024
+PMC_EIG_ORDER = 377
 
 
 def pmc_probe():
     """Workloads for the FETCH_SIZE / WRITE_SIZE counter passes: a plain
     device copy of PMC_COPY_BYTES (the scale of the counters), then one batch
     of PMC_LU_BATCH random order-580 systems through the library's LU kernel
-    (the KKT factorisation's kernel and shape)."""
+    (the KKT factorisation's kernel and shape), then one batch of
+    PMC_EIG_BATCH random order-377 matrices through the eigenvalue kernel (the
+    state matrices' order)."""
     import numpy as np
     import torch
     import paper_2512_08465_amd as cs
@@ -283,7 +287,17 @@ def pmc_probe():
     torch.cuda.synchronize()
     ctx.dense_solve_batched(a.data_ptr(), n, k, lda, PMC_LU_BATCH, info.data_ptr())
     torch.cuda.synchronize()
-    log("pmc probe: copy and LU batch done")
+    del a
+    ne = PMC_EIG_ORDER
+    h = torch.from_numpy(rng.standard_normal((PMC_EIG_BATCH, ne, ne))).cuda()
+    wr = torch.zeros((PMC_EIG_BATCH, ne), dtype=torch.float64, device="cuda")
+    wi = torch.zeros_like(wr)
+    einfo = torch.zeros(PMC_EIG_BATCH, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    ctx.eigvals_batched(h.data_ptr(), ne, ne, PMC_EIG_BATCH, wr.data_ptr(), wi.data_ptr(),
+                        einfo.data_ptr())
+    torch.cuda.synchronize()
+    log("pmc probe: copy, LU batch and eigenvalue batch done")
 
 
 def serve(cs, ctx, net, case, lst, args):
