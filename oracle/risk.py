@@ -24,7 +24,10 @@ def scenario_frequency(outages, lam):
     out = np.asarray(outages)
     F = np.empty(len(out))
     for c, (i, j) in enumerate(out):
-        F[c] = lam[i] if j < 0 else lam[i] * lam[j]
+        if i < 0:
+            F[c] = 0.0              # the base case (-1, -1): nothing fails
+        else:
+            F[c] = lam[i] if j < 0 else lam[i] * lam[j]
     return F
 
 
@@ -33,7 +36,7 @@ def risk_index(outages, severe, lam, n_comp):
     F = scenario_frequency(outages, lam)
     R = np.zeros(n_comp)
     for c, (i, j) in enumerate(np.asarray(outages)):
-        if severe[c]:
+        if severe[c] and i >= 0:    # the base case involves no component
             R[i] += F[c]
             if j >= 0:
                 R[j] += F[c]

@@ -69,3 +69,15 @@ def test_total_risk_identity_and_ordered_doubling():
 
 def test_mttf_conversion():
     assert np.allclose(risk.failure_rate_from_mttf([20, 50, 10]), [0.05, 0.02, 0.10])
+
+
+def test_base_case_row_adds_no_risk():
+    """Eq. (3) sums over scenarios in which component i fails; the base case
+    (-1, -1) has none, so it adds nothing whatever its severity."""
+    from oracle import risk
+    lam = np.array([0.1, 0.2, 0.3])
+    lst = np.array([[0, -1], [1, 2], [-1, -1]])
+    R1 = risk.risk_index(lst, np.array([1, 1, 1]), lam, 3)
+    R0 = risk.risk_index(lst[:2], np.array([1, 1]), lam, 3)
+    assert np.array_equal(R1, R0)
+    assert risk.scenario_frequency(lst, lam)[2] == 0.0
