@@ -28,7 +28,8 @@
  *   - Per-unit quantities on base_mva; angles in radians; times in seconds.
  *   - Component ids: [0, n_branch) branches, then [n_branch, n_branch+n_gen)
  *     generators, then loads.  An outage row (i, j) outages i and j; j = -1
- *     marks an N-1 outage.
+ *     marks an N-1 outage, and (-1, -1) is the base case with nothing out
+ *     (the reference operating point of Section II.A).
  *   - Buffers passed in are owned by the caller and only read during the call
  *     (cs_net_create copies the network to the device).
  *   - All device work runs on one HIP device chosen at cs_ctx_create.

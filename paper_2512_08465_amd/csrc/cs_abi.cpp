@@ -782,6 +782,7 @@ static int validate_host(const cs_net* n, const int32_t* outages, int64_t N, con
   const int n_comp = n->nl + n->ng + n->nd;
   for (int64_t i = 0; i < N; ++i) {
     const int a = outages[2 * i], b = outages[2 * i + 1];
+    if (a == -1 && b == -1) continue;   // the base case: nothing out
     if (a < 0 || a >= n_comp)
       return fail(CS_EINVAL, "outage row " + std::to_string(i) + ": component id out of range");
     if (b != -1 && (b < 0 || b >= n_comp || b == a))

@@ -122,13 +122,15 @@ void launch_islands(const DevNet& net, const Slots& s, const int* outages,
                      net, s, outages, count);
 }
 
-// outage list check: ids in range, j == -1 or a distinct id
+// outage list check: ids in range, j == -1 or a distinct id; (-1, -1) is
+// the base case (the kernels only compare ids, never index with them)
 __global__ void k_validate(const int* __restrict__ outages, long long n,
                            int n_comp, int* __restrict__ bad) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int a = outages[2 * i], b = outages[2 * i + 1];
-  const bool ok = a >= 0 && a < n_comp && (b == -1 || (b >= 0 && b < n_comp && b != a));
+  const bool ok = (a == -1 && b == -1) ||
+                  (a >= 0 && a < n_comp && (b == -1 || (b >= 0 && b < n_comp && b != a)));
   if (!ok) atomicOr(bad, 1);
 }
 

@@ -189,3 +189,26 @@ def test_dense_kernels_accept_an_empty_batch(ctx):
     ctx.eigvals_batched(d.data_ptr(), 4, 4, 0, d.data_ptr(), d.data_ptr(), info.data_ptr())
     torch.cuda.synchronize()
     assert torch.all(d == 0)
+
+
+@pytest.mark.parametrize("name", ["c1_30", "c2_118"])
+def test_base_case_matches_oracle_and_adds_no_risk(nets, name):
+    """(-1, -1) is the base case with nothing out (the reference run): its
+    record matches the oracle's, and it adds nothing to R_i (eq. 3)."""
+    from oracle import screen
+    net = load_case(name)
+    g = load_golden(name)
+    ref = screen.evaluate(net, np.array([-1, -1]))
+    base = np.array([[-1, -1]], np.int32)
+    r, _ = nets[name].screen(base, net["lam"])
+    assert r["n_islands"][0] == ref.n_islands
+    assert r["opf_status"][0] == ref.opf_status
+    assert r["severe"][0] == ref.severe and r["cause"][0] == ref.cause
+    if ref.opf_status == 0:
+        assert abs(r["opf_cost"][0] - ref.opf_cost) < 1e-6 * abs(ref.opf_cost)
+        assert abs(r["opf_iters"][0] - ref.opf_iters) <= 2
+        assert abs(r["min_damping"][0] - ref.min_damping) < 1e-6
+    lst = g["outages"][:40]
+    _, R_without = nets[name].screen(lst, net["lam"])
+    _, R_with = nets[name].screen(np.concatenate([lst, base]), net["lam"])
+    assert np.array_equal(R_with, R_without)
