@@ -41,7 +41,7 @@ void opf_set_attrs(size_t bytes);
 void dyn_set_attrs(size_t bytes);
 void eig_set_attrs(size_t bytes);
 constexpr size_t kLdsMax = 160 * 1024;
-constexpr int kRefineMax = 10;     // FP64 refinement steps of a mixed-precision solve
+constexpr int kRefineMax = 4;     // FP64 refinement steps of a mixed-precision solve
 }  // namespace cs
 
 using namespace cs;
