@@ -105,7 +105,7 @@ def main():
         pmc_probe()
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(scenarios shard trivially across GPUs, but only the single-GPU path exists)",
               file=sys.stderr)
         sys.exit(2)

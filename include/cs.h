@@ -52,7 +52,7 @@ enum {
   CS_ENOMEM = -2,   /* host or device allocation failed                        */
   CS_EHBM = -3,     /* one scenario's workspace exceeds the HBM budget         */
   CS_EDEVICE = -4,  /* HIP runtime error                                       */
-  CS_EUNSUPPORTED = -5, /* a model or size this build does not support       */
+  CS_EUNSUPPORTED = -5, /* a model or size the library does not support      */
   CS_EAGAIN = -6,       /* serving: no room for the request right now          */
   CS_ETIMEDOUT = -7     /* serving: the request is not complete yet            */
 };
