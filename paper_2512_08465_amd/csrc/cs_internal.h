@@ -68,7 +68,7 @@ struct SlotState {
   int status;      // OpfStatus
   int iters;       // Newton steps taken
   int n_islands, main_label, ref_bus, n_ineq;
-  int job;         // 1 = factorise and solve this round
+  int job;         // 1 = factorise and solve in this scheduling step
   int singular;    // exactly zero pivot met in the last factorisation
   int n_states;    // order of the reduced state matrix
   int cause, near, qr_fail;
