@@ -2,13 +2,16 @@
 
 Workload: the 118-bus-shaped synthetic network (186 branches, 54 synchronous
 generators, 99 loads) with every N-1 and unordered N-2 outage of its 339
-components (57,630 scenarios), FP64.  One step screens the next slice of that
-list through the whole path (islanding, OPF with dense KKT LU, state matrix,
-eigenvalues, severity, Risk Index) with the outage list, failure rates and
-outputs resident in device memory.  Prints one JSON line.
+components (57,630 scenarios).  The timed steps screen that list exactly once
+(step k takes the k-th of K consecutive slices) through the whole path
+(islanding, OPF with dense KKT LU, state matrix, eigenvalues, severity, Risk
+Index) with the outage list, failure rates and outputs resident in device
+memory: first in FP64 (the headline), then in the mixed-precision form
+(FP32 KKT factorisation with FP64 refinement).  Then a serving sweep over
+arrival rates in both precisions.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--step-size S]
-                  [--full] [--no-cpu-baseline]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs fp64,mixed]
+                  [--no-cpu-baseline] [--serve-requests R] [--serve-rates 2,20,200]
 """
 from __future__ import annotations
 
@@ -60,8 +63,22 @@ def cpu_baseline(case, lst, n_sample=512, seed=7):
                 log(f"oracle: {done}/{n_sample} scenarios, {time.perf_counter() - t0:.1f} s")
     dt = time.perf_counter() - t0
     return dict(value=round(n_sample / dt, 3), unit="scenarios/s", cores=cores, kind="oracle",
+                nproc=os.cpu_count(), affinity=len(os.sched_getaffinity(0)),
+                cpu_model=cpu_model(),
                 sample=f"{n_sample} scenarios drawn uniformly (seed {seed}) from the 57,630-row "
-                       f"list, {cores} forked single-threaded worker processes, {dt:.1f} s wall")
+                       f"list, {cores} forked single-threaded worker processes (the host's "
+                       f"share of cores, at most 16), {dt:.1f} s wall")
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 _CPU_NET = None
@@ -81,22 +98,24 @@ def log(msg):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--step-size", type=int, default=4096)
-    ap.add_argument("--batch", type=int, default=0,
-                    help="scenario slots resident at once (0: as many as the step)")
-    ap.add_argument("--prec", choices=("fp64", "mixed"), default="fp64",
-                    help="mixed: FP32 KKT factorisation + FP64 refinement")
+    ap.add_argument("--steps", type=int, default=4,
+                    help="timed steps; together they screen the whole list exactly once")
+    ap.add_argument("--warmup", type=int, default=1,
+                    help="untimed steps, each over the first --warmup-size scenarios")
+    ap.add_argument("--warmup-size", type=int, default=4096)
+    ap.add_argument("--batch", type=int, default=4096,
+                    help="scenario slots resident at once (refilled as scenarios finish)")
+    ap.add_argument("--legs", default="fp64,mixed",
+                    help="precisions to time: fp64 (the headline) and/or mixed")
     ap.add_argument("--overlap", type=int, default=0,
                     help="1: dynamic stage on a second stream beside the OPF iterations")
-    ap.add_argument("--full", action="store_true", help="one step = the whole 57,630 list")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=40,
-                    help="requests in the serving measurement (0: skip it)")
-    ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrivals per second")
-    ap.add_argument("--serve-max-len", type=int, default=1000,
+    ap.add_argument("--serve-requests", type=int, default=12,
+                    help="requests per arrival rate in the serving sweep (0: skip it)")
+    ap.add_argument("--serve-rates", default="2,20,200", help="Poisson arrivals per second")
+    ap.add_argument("--serve-max-len", type=int, default=5000,
                     help="request lengths are log-uniform integers in [1, this]")
+    ap.add_argument("--serve-legs", default="fp64,mixed")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run only a copy of known size and a batch of order-580 LUs "
                          "(for hardware-counter passes), then exit")
@@ -116,7 +135,9 @@ def main():
     case = netgen.load_case(os.path.join(ROOT, "inputs", "cases", "c2_118.npz"))
     lst = contingencies.n1_n2(case["outage_set"]).astype(np.int32)
     n_all = len(lst)
-    step = n_all if args.full else min(args.step_size, n_all)
+    step = -(-n_all // args.steps)
+    legs = [v for v in args.legs.split(",") if v]
+    assert legs and legs[0] == "fp64" or legs == ["mixed"], "--legs: fp64 first"
     base = None
     if not args.no_cpu_baseline:
         # before any device initialisation: worker processes are started here
@@ -131,7 +152,7 @@ def main():
     ctx = cs.Context(0)
     log("device context ready")
     net = cs.Network(ctx, case)
-    log(f"network resident; {n_all} scenarios, {step} per step")
+    log(f"network resident; {n_all} scenarios, {step} per timed step")
     dev = torch.device("cuda:0")
     d_list = torch.from_numpy(lst).to(dev)
     d_lam = torch.from_numpy(case["lam"]).to(dev)
@@ -139,97 +160,166 @@ def main():
     d_risk = torch.zeros(len(case["lam"]), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
     rec = cs.RESULT_DTYPE.itemsize
+    golden = load_oracle_records()
 
-    def run_step(k, opts):
-        off = (k * step) % n_all
-        cnt = min(step, n_all - off)
+    def run(off, cnt, opts):
         net.screen_device(d_list.data_ptr() + off * 8, cnt, d_lam.data_ptr(),
                           d_res.data_ptr() + off * rec, d_risk.data_ptr(), opts,
                           stream=stream.cuda_stream)
         return cnt
 
-    prec = cs.PREC_MIXED if args.prec == "mixed" else cs.PREC_FP64
-    plain = cs.default_options(batch=args.batch, overlap=args.overlap, prec=prec)
-    timed = cs.default_options(batch=args.batch, overlap=args.overlap, prec=prec, timing=1)
-    for w in range(args.warmup):
-        run_step(w, plain)
-        log(f"warmup step {w + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    ctx.reset_stats()
-    done = 0
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        done += run_step(args.warmup + k, timed)
-        log(f"timed step {k + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    st = ctx.stats()
+    results = {}
+    for leg in legs:
+        prec = cs.PREC_MIXED if leg == "mixed" else cs.PREC_FP64
+        plain = cs.default_options(batch=args.batch, overlap=args.overlap, prec=prec)
+        timed = cs.default_options(batch=args.batch, overlap=args.overlap, prec=prec, timing=1)
+        for w in range(args.warmup):
+            run(0, min(args.warmup_size, n_all), plain)
+            log(f"{leg}: warmup step {w + 1}/{args.warmup} done")
+        torch.cuda.synchronize()
+        ctx.reset_stats()
+        done = 0
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            off = k * step
+            done += run(off, min(step, n_all - off), timed)
+            log(f"{leg}: timed step {k + 1}/{args.steps} done ({done} scenarios)")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res = d_res.cpu().numpy().view(cs.RESULT_DTYPE).copy()
+        results[leg] = leg_summary(leg, ctx.stats(), done, dt, args.steps, res, golden)
+        log(f"{leg}: {results[leg]['value']} scenarios/s")
 
-    res = d_res.cpu().numpy().view(cs.RESULT_DTYPE)
-    nk = int(st["kkt_order"])
-    lu = st["kkt_lu"]
-    lu_avg_ms = lu["ms"] / max(lu["launches"], 1)
-    lu_fact_per_launch = lu["units"] / max(lu["launches"], 1)
-    achieved = lu_fact_per_launch * kkt_lu_flops(nk) / (lu_avg_ms * 1e-3) / 1e12 if lu["ms"] else 0.0
-    mixed = args.prec == "mixed"
-    peak = PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS
-    lu_bytes = lu_traffic_per_factorisation()
-    total_ms = sum(v["ms"] for k, v in st.items() if isinstance(v, dict))
-    breakdown = {k: round(v["ms"] / max(total_ms, 1e-9), 4) for k, v in st.items()
-                 if isinstance(v, dict)}
+    head = results[legs[0]]
     out = {
         "metric": METRIC,
-        "value": round(done / dt, 3),
+        "value": head["value"],
         "unit": "scenarios/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * dt / args.steps, 3),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if mixed else "f64",
+        "dtype": "f64" if legs[0] == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": "c2_118: seeded synthetic 118-bus-shaped network (186 branches, "
                         "54 synchronous generators with AVR and governor, 99 loads); "
-                        "N-1 + unordered N-2 over all 339 components = 57,630 scenarios; " +
-                        ("KKT LU in FP32 with FP64 refinement, everything else FP64" if mixed
-                         else "FP64 plain method"),
+                        "N-1 + unordered N-2 over all 339 components = 57,630 scenarios, "
+                        "screened once across the timed steps; " +
+                        ("FP64 plain method" if legs[0] == "fp64" else
+                         "KKT LU in FP32 with FP64 refinement, everything else FP64"),
             "scenarios_per_step": step,
-            "slots": args.batch or step,
+            "slots": args.batch,
             "overlap": args.overlap,
-            "kkt_order": nk,
+            "kkt_order": head["kkt_order"],
             "state_order": 7 * int(case["n_gen"]) - 1,
         },
+        "roofline": head.pop("roofline"),
+        "kernel_time_share": head.pop("kernel_time_share"),
+        "kkt_solves": head.pop("kkt_solves"),
+        "results": head.pop("results"),
+        "vs_oracle": head.pop("vs_oracle"),
+    }
+    if "mixed" in results and legs[0] == "fp64":
+        out["mixed"] = results["mixed"]
+    if args.serve_requests > 0:
+        out["serving"] = serve_sweep(cs, ctx, net, case, lst, args)
+    if base is not None:
+        out["cpu_baseline"] = base
+    print(json.dumps(out), flush=True)
+
+
+def load_oracle_records():
+    """The oracle's stored records of the whole list (tests/golden), for the
+    deviation figures; None if absent."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "c2_118_full_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in ("severe", "opf_status", "opf_cost", "max_real_eig",
+                                  "min_damping", "n_islands")}
+
+
+def leg_summary(leg, st, done, dt, steps, res, golden):
+    import numpy as np
+    mixed = leg == "mixed"
+    nk = int(st["kkt_order"])
+    lu = st["kkt_lu"]
+    lu_avg_ms = lu["ms"] / max(lu["launches"], 1)
+    per_launch = lu["units"] / max(lu["launches"], 1)
+    achieved = per_launch * kkt_lu_flops(nk) / (lu_avg_ms * 1e-3) / 1e12 if lu["ms"] else 0.0
+    peak = PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS
+    lu_bytes = None if mixed else lu_traffic_per_factorisation()
+    total_ms = sum(v["ms"] for v in st.values() if isinstance(v, dict))
+    share = {k: round(v["ms"] / max(total_ms, 1e-9), 4) for k, v in st.items()
+             if isinstance(v, dict)}
+    status = res["opf_status"]
+    iters = res["opf_iters"].astype(np.int64)
+    out = {
+        "value": round(done / dt, 3),
+        "ms_per_step": round(1e3 * dt / steps, 3),
+        "kkt_order": nk,
         "roofline": {
-            "kernel": "k_lu_solve%s (KKT LU + solve)" % ("<float>" if mixed else "<double>"),
+            "kernel": "k_lu_solve<%s, LU_KKT> (KKT LU + solve)" % ("float" if mixed else "double"),
             "bound": "mfma",
             "achieved": round(achieved, 4),
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": round(achieved / peak, 5),
-            "traffic": (None if mixed or lu_bytes is None
-                        else round(lu_bytes * lu_fact_per_launch / 1e9, 3)),
+            "traffic": None if lu_bytes is None else round(lu_bytes * per_launch / 1e9, 3),
             "traffic_unit": "GB per launch (HBM, counters)",
             "algorithmic_bytes_per_launch_gb": round(
-                2 * 8 * nk * (nk + 1) * lu_fact_per_launch / 1e9, 3),
+                2 * (4 if mixed else 8) * nk * (nk + 1) * per_launch / 1e9, 3),
             "avg_launch_ms": round(lu_avg_ms, 4),
-            "factorisations_per_launch": round(lu_fact_per_launch, 1),
+            "launches": int(lu["launches"]),
+            "factorisations_per_launch": round(per_launch, 1),
         },
-        "kernel_time_share": breakdown,
+        "kernel_time_share": share,
         "kkt_solves": {"factorisations": int(lu["units"]),
-                       "fp64_fallbacks": int(st["kkt_lu64"]["units"]) if mixed else None},
+                       "fp64_fallbacks": int(st["kkt_lu64"]["units"]) if mixed else None,
+                       "fp64_fallback_share": (round(st["kkt_lu64"]["units"] / max(lu["units"], 1), 4)
+                                               if mixed else None)},
         "results": {
             "screened": int(done),
-            "severe_fraction": round(float(np.mean(res["severe"][:min(n_all, done)])), 4),
+            "severe_fraction": round(float(np.mean(res["severe"])), 4),
+            "opf_maxit_fraction": round(float(np.mean(status == 1)), 4),
+            "opf_diverged_fraction": round(float(np.mean(status == 2)), 4),
+            "newton_steps_at_maxit_share": round(float(iters[status == 1].sum() /
+                                                       max(iters.sum(), 1)), 4),
+            "newton_steps_histogram": np.histogram(iters[status != 3],
+                                                   bins=[0, 20, 30, 40, 60, 100, 149, 151]
+                                                   )[0].tolist(),
+            "newton_steps_bins": [0, 20, 30, 40, 60, 100, 149, 151],
         },
+        "vs_oracle": deviation(res, golden),
     }
-    if args.serve_requests > 0:
-        out["serving"] = serve(cs, ctx, net, case, lst, args)
-    if base is not None:
-        out["cpu_baseline"] = base
-    print(json.dumps(out), flush=True)
+    if mixed:
+        out["dtype"] = "f32+f64"
+    return out
+
+
+def deviation(res, g):
+    """Largest deviations of the screened records from the oracle's stored
+    ones: on scenarios converged on both sides, OPF cost (relative), the
+    largest real part (relative to max(|.|, 1)) and the minimum damping;
+    and the number of scenarios whose severity differs."""
+    import numpy as np
+    if g is None:
+        return None
+    both = (g["opf_status"] == 0) & (res["opf_status"] == 0)
+    rel = np.abs(res["opf_cost"][both] - g["opf_cost"][both]) / np.abs(g["opf_cost"][both])
+    da = np.abs(res["max_real_eig"][both] - g["max_real_eig"][both]) / np.maximum(
+        np.abs(g["max_real_eig"][both]), 1.0)
+    dz = np.abs(res["min_damping"][both] - g["min_damping"][both])
+    return {"converged_both": int(both.sum()),
+            "opf_cost_rel": float(rel.max()), "max_real_eig": float(da.max()),
+            "min_damping": float(dz.max()),
+            "islands_differ": int((res["n_islands"] != g["n_islands"]).sum()),
+            "severity_differs": int((res["severe"] != g["severe"]).sum())}
 
 
 # HBM traffic of the FP64 KKT LU from two rocprofv3 counter passes over
@@ -300,27 +390,41 @@ def pmc_probe():
     log("pmc probe: copy, LU batch and eigenvalue batch done")
 
 
-def serve(cs, ctx, net, case, lst, args):
-    """Requests arriving as a Poisson process, each a random slice of the
-    list with a log-uniform length, admitted into a running server; p50/p99
-    latency from admission to the last record."""
+def serve_sweep(cs, ctx, net, case, lst, args):
+    """Serving: for each precision and arrival rate, requests arriving as a
+    Poisson process, each a random slice of the list with a log-uniform
+    length, admitted into a running server; p50/p99 latency from admission
+    to the last record and the scenarios served per second."""
+    out = []
+    for leg in [v for v in args.serve_legs.split(",") if v]:
+        prec = cs.PREC_MIXED if leg == "mixed" else cs.PREC_FP64
+        for rate in [float(v) for v in args.serve_rates.split(",") if v]:
+            r = serve(cs, ctx, net, case, lst, args, rate, prec)
+            r["prec"] = leg
+            out.append(r)
+            log(f"serving {leg} at {rate}/s: p50 {r['p50_latency_s']} s, "
+                f"p99 {r['p99_latency_s']} s, {r['scenarios_per_s']} scenarios/s")
+    return out
+
+
+def serve(cs, ctx, net, case, lst, args, rate, prec):
     import numpy as np
-    rng = np.random.default_rng(5000)
-    gaps = rng.exponential(1.0 / args.serve_rate, args.serve_requests)
-    lens = np.floor(np.exp(rng.uniform(0, np.log(args.serve_max_len + 1), args.serve_requests)))
+    rng = np.random.default_rng(5000 + int(rate * 10))
+    nreq = args.serve_requests
+    gaps = rng.exponential(1.0 / rate, nreq)
+    lens = np.floor(np.exp(rng.uniform(0, np.log(args.serve_max_len + 1), nreq)))
     lens = np.clip(lens.astype(int), 1, args.serve_max_len)
     lists = [lst[rng.choice(len(lst), k, replace=False)] for k in lens]
-    srv = cs.Server(ctx, net, cs.default_options(batch=2048), queue_capacity=1 << 16)
-    log(f"serving: {args.serve_requests} requests at {args.serve_rate}/s")
+    slots = 4096
+    srv = cs.Server(ctx, net, cs.default_options(batch=slots, prec=prec),
+                    queue_capacity=1 << 17)
     reqs = []
     t0 = time.perf_counter()
     due = t0
-    for k, (g, l) in enumerate(zip(gaps, lists)):
+    for g, l in zip(gaps, lists):
         due += g
         time.sleep(max(0.0, due - time.perf_counter()))
         reqs.append(srv.submit(l, case["lam"]))
-        if (k + 1) % 10 == 0:
-            log(f"serving: {k + 1} submitted")
     lat = []
     for r in reqs:
         _, _, l = r.wait(timeout_s=600)
@@ -329,9 +433,9 @@ def serve(cs, ctx, net, case, lst, args):
     dt = time.perf_counter() - t0
     srv.close()
     lat = np.array(lat)
-    return dict(requests=int(args.serve_requests), rate_per_s=args.serve_rate,
+    return dict(requests=int(nreq), rate_per_s=rate,
                 length="log-uniform integer in [1, %d]" % args.serve_max_len,
-                scenarios=int(lens.sum()), slots=2048,
+                scenarios=int(lens.sum()), slots=slots,
                 p50_latency_s=round(float(np.percentile(lat, 50)), 4),
                 p99_latency_s=round(float(np.percentile(lat, 99)), 4),
                 scenarios_per_s=round(float(lens.sum()) / dt, 2),

@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define CS_ABI_VERSION 4
+#define CS_ABI_VERSION 5
 
 enum {
   CS_OK = 0,
@@ -76,9 +76,12 @@ enum {
 /* cs_result.opf_status */
 enum { CS_OPF_CONVERGED = 0, CS_OPF_MAXIT = 1, CS_OPF_NUMERICAL = 2, CS_OPF_NOT_RUN = 3 };
 
-/* cs_result.near: the decision lies close to a threshold */
-enum { CS_NEAR_SSS = 1 /* |max Re| <= near_eps */, CS_NEAR_OPF = 2 /* iters >= max_it-2 */,
-       CS_NEAR_LIMIT = 4 /* max violation above 1e-7 (a decade below the test) */ };
+/* cs_result.near: the decision lies close to a threshold (set only for a
+ * converged OPF) */
+enum { CS_NEAR_SSS = 1   /* |max Re| <= near_eps                              */,
+       CS_NEAR_OPF = 2   /* converged with iters >= max_it - 2                */,
+       CS_NEAR_LIMIT = 4 /* 1e-7 < max violation <= 1e-5: a decade either side
+                            of the 1e-6 p.u. limit test                      */ };
 
 #define CS_N_DYN 14  /* dyn row: H D Xd Xq Xd' Xq' Td0' Tq0' Rs KA TA R Tg Tt */
 
@@ -118,6 +121,11 @@ typedef struct {
   int32_t overlap;     /* 1: the dynamic stage (state matrix, eigenvalues,
                           records) runs on a second stream beside the OPF
                           iterations of other slots; 0: one stream (default 0) */
+  int32_t refine_steps; /* CS_PREC_MIXED: FP64 refinement steps a Newton solve
+                          may take to reach the backward error of an FP64
+                          solve before that system is factorised in FP64
+                          instead (default 4, 0..100; 0: the FP32 solution is
+                          tested as it is)                                   */
 } cs_opts;
 
 /* Per-kernel accumulated device time of the calls made with opts.timing = 1
@@ -227,6 +235,34 @@ int cs_eigvals_batched(const cs_ctx* ctx, double* d_A, int32_t n, int32_t lda,
 int cs_kkt_at(cs_ctx* ctx, cs_net* net, const int32_t outage[2], int32_t iters,
               double* K, double* x, double* lam, double* z, double* mu,
               double* metrics, int32_t* status, int32_t* order);
+
+/* Parity/debug: screen n outages (host buffers, as cs_screen, no risk) and
+ * also return every scenario's OPF operating point and spectrum
+ * (Section II.B.1-II.B.2): vm, va [n][n_bus] and pg, qg [n][n_gen] (NaN
+ * outside the solved island, for generators out of service, and for every
+ * entry when the OPF did not run; the point reached is reported also when
+ * the OPF did not converge), eig_re, eig_im [n][7 n_gen - 1] (NaN-padded)
+ * with n_eig [n] values each (0 unless the OPF converged and the state
+ * matrix was formed).  Errors as cs_screen. */
+int cs_screen_detail(cs_ctx* ctx, cs_net* net, const int32_t* outages, int64_t n,
+                     const cs_opts* opts, cs_result* out, double* vm, double* va,
+                     double* pg, double* qg, double* eig_re, double* eig_im,
+                     int32_t* n_eig);
+
+/* Parity/debug: the linearised state matrix of Section II.B.2 at a given
+ * operating point of one outage's main island, and its eigenvalues.  vm, va
+ * [n_bus], pg, qg [n_gen] are host buffers over the whole network; only the
+ * island's buses and its in-service generators are read (their values must
+ * be finite, vm > 0).  A (may be NULL): [n][n] row-major, n = *n_states =
+ * 7 (machines in the island) - 1, states per machine in ascending generator
+ * order [delta, omega, Eq', Ed', Efd, Psv, Pm] with angles relative to the
+ * first machine (its angle state removed).  eig_re, eig_im [n] (may be NULL:
+ * no eigenvalues computed).  Errors: CS_EINVAL (bad outage, no island with
+ * a generator, non-finite point), CS_EDEVICE (singular algebraic system,
+ * non-finite A, QR not converged; A is still written). */
+int cs_dyn_at(cs_ctx* ctx, cs_net* net, const int32_t outage[2], const double* vm,
+              const double* va, const double* pg, const double* qg, double* A,
+              int32_t* n_states, double* eig_re, double* eig_im);
 
 /* Serving (continuous batching).  A server owns B scenario slots of one
  * network and a host thread that runs them; requests (each an outage list

@@ -57,6 +57,10 @@ class OPFOptions:
     # rounding, not by the method.
     kkt_solve: str = "lu"
     row_scale_seed: int | None = None
+    # perm_seed: solve each system with its unknowns and equations permuted
+    # by one random permutation drawn from that seed (P K P^T) (P d) = P rhs,
+    # which changes the elimination order
+    perm_seed: int | None = None
 
 
 @dataclasses.dataclass
@@ -295,6 +299,8 @@ def solve_opf(net, sub, opts: OPFOptions = OPFOptions(), keep_history=False) -> 
         raise ValueError(f"kkt_solve must be 'lu' or 'qr', not {opts.kkt_solve!r}")
     scale_rng = (np.random.default_rng(opts.row_scale_seed)
                  if opts.row_scale_seed is not None else None)
+    perm = (np.random.default_rng(opts.perm_seed).permutation(nx + neq)
+            if opts.perm_seed is not None else None)
     while True:
         Lx = P.cost_grad(x) + Jg.T @ lam + Jh.T @ mu
         xn = np.max(np.abs(x)) if nx else 0.0
@@ -327,11 +333,15 @@ def solve_opf(net, sub, opts: OPFOptions = OPFOptions(), keep_history=False) -> 
             if scale_rng is not None:
                 dscale = 2.0 ** scale_rng.integers(-2, 3, K.shape[0])
                 K, rhs = dscale[:, None] * K, dscale * rhs
+            if perm is not None:
+                K, rhs = K[np.ix_(perm, perm)], rhs[perm]
             lu, piv = sla.lu_factor(K, check_finite=False)
             if np.any(np.diag(lu) == 0.0):
                 status = NUMERICAL
                 break
             d = sla.lu_solve((lu, piv), rhs, check_finite=False)
+            if perm is not None:
+                d = d[np.argsort(perm)]
         if not np.all(np.isfinite(d)):
             status = NUMERICAL
             break

@@ -17,6 +17,7 @@ from . import islanding, network, opf, dynamics, eigen, risk
 CAUSE_ISLAND, CAUSE_OPF, CAUSE_LIMIT, CAUSE_SSS, CAUSE_NUMERICAL = 1, 2, 4, 8, 16
 NEAR_SSS, NEAR_OPF, NEAR_LIMIT = 1, 2, 4
 LIMIT_TOL = 1e-6
+NEAR_LIMIT_LO, NEAR_LIMIT_HI = 1e-7, 1e-5     # a decade either side of LIMIT_TOL
 
 
 @dataclasses.dataclass
@@ -26,6 +27,7 @@ class ScreenOptions:
     near_eps: float = 1e-6
     kkt_solve: str = "lu"               # rounding probes of the OPF (tests only)
     row_scale_seed: int | None = None
+    perm_seed: int | None = None
 
 
 @dataclasses.dataclass
@@ -50,6 +52,7 @@ class ScenarioResult:
     eig: np.ndarray = None
     bus: np.ndarray = None
     gen: np.ndarray = None
+    A: np.ndarray = None
 
 
 def outage_masks(net, outage):
@@ -70,6 +73,56 @@ def outage_masks(net, outage):
     return br_on, gen_on, load_on
 
 
+def near_flags(opf_status, opf_iters, max_violation, alpha,
+               opts: ScreenOptions = ScreenOptions()):
+    """Decisions that lie close to a threshold (reading of the parity rules;
+    the paper's tests themselves are exact).
+
+    NEAR_OPF: the OPF converged within two steps of the iteration cap, so a
+      solve rounded differently may end at the cap instead.
+    NEAR_LIMIT: the largest limit excess of a converged OPF lies within a
+      decade either side of the 1e-6 p.u. test (1e-7 < excess <= 1e-5).
+    NEAR_SSS: |max Re lambda| <= near_eps.
+    Arguments that were not computed are NaN (and raise no flag)."""
+    near = 0
+    if opf_status == opf.CONVERGED:
+        if opf_iters >= opts.max_it - 2:
+            near |= NEAR_OPF
+        if NEAR_LIMIT_LO < max_violation <= NEAR_LIMIT_HI:
+            near |= NEAR_LIMIT
+        if abs(alpha) <= opts.near_eps:
+            near |= NEAR_SSS
+    return near
+
+
+def classify(n_islands, opf_status, max_violation, alpha, state_finite=True):
+    """Cause bits of one scenario (Section II.B).
+
+    ISLAND: more than one island after the outage (II.B.3).
+    OPF: the OPF on the main island did not converge, or could not be run
+      (no generator in service there); NUMERICAL in addition when it broke
+      down numerically (II.B.1: solver failures count as severe).
+    LIMIT: a converged OPF whose largest limit excess is above 1e-6 p.u.
+      (II.B.1, operational limits violated).
+    SSS: an eigenvalue of the state matrix with real part >= 0 (II.B.2; the
+      comparison with zero is inclusive).
+    NUMERICAL alone: a converged OPF whose state matrix is not finite.
+    The scenario is severe (S = 1) iff any bit is set."""
+    cause = CAUSE_ISLAND if n_islands > 1 else 0
+    if opf_status != opf.CONVERGED:
+        cause |= CAUSE_OPF
+        if opf_status == opf.NUMERICAL:
+            cause |= CAUSE_NUMERICAL
+        return cause
+    if max_violation > LIMIT_TOL:
+        cause |= CAUSE_LIMIT
+    if not state_finite:
+        cause |= CAUSE_NUMERICAL
+    elif alpha >= 0.0:
+        cause |= CAUSE_SSS
+    return cause
+
+
 def evaluate(net, outage, opts: ScreenOptions = ScreenOptions(),
              detail=False) -> ScenarioResult:
     """Evaluate one scenario (outage = (i, j), j = -1 for N-1)."""
@@ -79,8 +132,6 @@ def evaluate(net, outage, opts: ScreenOptions = ScreenOptions(),
     main = islanding.main_island(label, net["gen_bus"], gen_on, net["pmax"])
     ref = islanding.island_reference(label, main, int(net["ref_bus"]),
                                      net["gen_bus"], gen_on)
-    cause = CAUSE_ISLAND if n_isl > 1 else 0
-    near = 0
     nan = float("nan")
     res = ScenarioResult(severe=0, cause=0, opf_status=opf.NOT_RUN, near=0,
                          n_islands=n_isl, opf_iters=0, n_states=0,
@@ -88,48 +139,35 @@ def evaluate(net, outage, opts: ScreenOptions = ScreenOptions(),
                          max_violation=nan, label=label if detail else None)
     in_main = gen_on & (label[net["gen_bus"]] == main)
     if ref < 0 or not np.any(in_main):
-        res.cause = cause | CAUSE_OPF
-        res.severe = 1
+        res.cause = classify(n_isl, opf.NOT_RUN, nan, nan)
+        res.severe = int(res.cause != 0)
         return res
     bus_ids = np.flatnonzero(label == main)
     sub = network.make_subsystem(net, bus_ids, br_on, gen_on, load_on, ref)
     o = opf.solve_opf(net, sub, opf.OPFOptions(tol=opts.tol, max_it=opts.max_it,
                                                kkt_solve=opts.kkt_solve,
-                                               row_scale_seed=opts.row_scale_seed))
+                                               row_scale_seed=opts.row_scale_seed,
+                                               perm_seed=opts.perm_seed))
     res.opf_status, res.opf_iters = o.status, o.iters
     res.opf_cost, res.max_violation = o.cost, o.max_violation
-    if o.iters >= opts.max_it - 2:
-        near |= NEAR_OPF
     if detail:
         res.vm, res.va, res.pg, res.qg = o.vm, o.va, o.pg, o.qg
         res.bus, res.gen = sub.bus, sub.gen
-    if o.status != opf.CONVERGED:
-        cause |= CAUSE_OPF
-        if o.status == opf.NUMERICAL:
-            cause |= CAUSE_NUMERICAL
-    else:
-        if o.max_violation > LIMIT_TOL:
-            cause |= CAUSE_LIMIT
-        if o.max_violation > 0.1 * LIMIT_TOL:
-            near |= NEAR_LIMIT          # within a decade of the limit test
+    finite = True
+    if o.status == opf.CONVERGED:
         dm = dynamics.DynModel(net, sub, o.vm, o.va, o.pg, o.qg)
         A = dm.state_matrix()
         res.n_states = A.shape[0]
-        if not np.all(np.isfinite(A)):
-            cause |= CAUSE_NUMERICAL
-        else:
+        finite = bool(np.all(np.isfinite(A)))
+        if finite:
             lam = eigen.eigvals(A)
-            alpha, zeta = eigen.spectral_summary(lam)
-            res.max_real_eig, res.min_damping = alpha, zeta
-            if alpha >= 0.0:
-                cause |= CAUSE_SSS
-            if abs(alpha) <= opts.near_eps:
-                near |= NEAR_SSS
+            res.max_real_eig, res.min_damping = eigen.spectral_summary(lam)
             if detail:
                 res.eig = lam
-    res.cause = cause
-    res.near = near
-    res.severe = int(cause != 0)
+                res.A = A
+    res.cause = classify(n_isl, o.status, o.max_violation, res.max_real_eig, finite)
+    res.near = near_flags(o.status, o.iters, o.max_violation, res.max_real_eig, opts)
+    res.severe = int(res.cause != 0)
     return res
 
 

@@ -52,7 +52,8 @@ class Options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("max_it", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("near_eps", ctypes.c_double),
                 ("hbm_budget", ctypes.c_size_t), ("batch", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("overlap", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("overlap", ctypes.c_int32),
+                ("refine_steps", ctypes.c_int32)]
 
 
 KERNELS = ("topology", "kkt_assemble", "kkt_lu", "ipm_update", "dyn_assemble", "dyn_lu",
@@ -97,6 +98,9 @@ def library():
         "cs_dense_solve_batched": (ctypes.c_int, [vp, dp, i32, i32, i32, i32, vp, vp]),
         "cs_eigvals_batched": (ctypes.c_int, [vp, dp, i32, i32, i32, dp, dp, vp, vp]),
         "cs_kkt_at": (ctypes.c_int, [vp, vp, vp, i32, dp, dp, dp, dp, dp, dp, vp, vp]),
+        "cs_screen_detail": (ctypes.c_int, [vp, vp, vp, i64, ctypes.POINTER(Options), vp,
+                                            dp, dp, dp, dp, dp, dp, vp]),
+        "cs_dyn_at": (ctypes.c_int, [vp, vp, vp, dp, dp, dp, dp, dp, vp, dp, dp]),
         "cs_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(Stats)]),
         "cs_stats_reset": (ctypes.c_int, [vp]),
         "cs_last_error": (ctypes.c_char_p, []),
@@ -120,7 +124,8 @@ EXPORTED = ("cs_ctx_create", "cs_ctx_destroy", "cs_net_create", "cs_net_destroy"
             "cs_opts_default", "cs_screen", "cs_screen_device", "cs_detail",
             "cs_dense_solve_batched", "cs_eigvals_batched", "cs_kkt_at", "cs_stats_get",
             "cs_stats_reset", "cs_last_error", "cs_abi_version", "cs_server_create",
-            "cs_server_destroy", "cs_submit", "cs_wait", "cs_req_free")
+            "cs_server_destroy", "cs_submit", "cs_wait", "cs_req_free", "cs_screen_detail",
+            "cs_dyn_at")
 
 
 def _check(rc):
@@ -281,6 +286,42 @@ class Network:
         k = int(ne[0])
         return dict(record=rec[0], vm=vm, va=va, pg=pg, qg=qg,
                     eig=er[:k] + 1j * ei[:k], label=lab)
+
+
+    def screen_detail(self, outages, options: Options | None = None):
+        """Records plus each scenario's operating point and spectrum
+        (parity checks): dict of records, vm, va [n][n_bus], pg, qg
+        [n][n_gen], eig (list of complex arrays)."""
+        out_list = np.ascontiguousarray(outages, dtype=np.int32).reshape(-1, 2)
+        n = len(out_list)
+        nb, ng = self.n_bus, self.n_gen
+        na = 7 * ng - 1
+        res = np.zeros(n, dtype=RESULT_DTYPE)
+        vm, va = np.zeros((n, nb)), np.zeros((n, nb))
+        pg, qg = np.zeros((n, ng)), np.zeros((n, ng))
+        er, ei = np.zeros((n, na)), np.zeros((n, na))
+        ne = np.zeros(n, dtype=np.int32)
+        o = options or default_options()
+        _check(library().cs_screen_detail(self.ctx.handle, self._h, _ptr(out_list), n,
+                                          ctypes.byref(o), _ptr(res), _ptr(vm), _ptr(va),
+                                          _ptr(pg), _ptr(qg), _ptr(er), _ptr(ei), _ptr(ne)))
+        eig = [er[i, :ne[i]] + 1j * ei[i, :ne[i]] for i in range(n)]
+        return dict(records=res, vm=vm, va=va, pg=pg, qg=qg, eig=eig, n_eig=ne)
+
+    def dyn_at(self, outage, vm, va, pg, qg, eigenvalues: bool = True):
+        """State matrix (row-major) and its eigenvalues at a given operating
+        point over the whole network (only the island's entries are read)."""
+        na = 7 * self.n_gen - 1
+        A = np.zeros(na * na)
+        er, ei = np.zeros(na), np.zeros(na)
+        ns = np.zeros(1, dtype=np.int32)
+        o2 = np.ascontiguousarray(outage, dtype=np.int32).reshape(2)
+        arr = [np.ascontiguousarray(v, dtype=np.float64) for v in (vm, va, pg, qg)]
+        _check(library().cs_dyn_at(self.ctx.handle, self._h, _ptr(o2), *[_ptr(v) for v in arr],
+                                   _ptr(A), _ptr(ns), _ptr(er) if eigenvalues else None,
+                                   _ptr(ei) if eigenvalues else None))
+        k = int(ns[0])
+        return A[:k * k].reshape(k, k).copy(), (er[:k] + 1j * ei[:k]) if eigenvalues else None
 
 
 class Request:

@@ -41,7 +41,7 @@ void opf_set_attrs(size_t bytes);
 void dyn_set_attrs(size_t bytes);
 void eig_set_attrs(size_t bytes);
 constexpr size_t kLdsMax = 160 * 1024;
-constexpr int kRefineMax = 4;     // FP64 refinement steps of a mixed-precision solve
+constexpr int kRefineMax = 4;     // default FP64 refinement steps of a mixed-precision solve
 }  // namespace cs
 
 using namespace cs;
@@ -182,6 +182,7 @@ void cs_opts_default(cs_opts* o) {
   o->batch = 0;
   o->timing = 0;
   o->overlap = 0;
+  o->refine_steps = kRefineMax;
 }
 
 int cs_ctx_create(int device, size_t hbm_budget, cs_ctx** out) {
@@ -535,6 +536,7 @@ struct Engine {
   const int* item_req = nullptr;
   int* req_done = nullptr;
   TimedLaunches* T = nullptr;
+  const DetailOut* detail = nullptr;   // per-scenario detail (parity entry point)
   int cnt[PH_COUNT]{};
   long long assigned = 0;        // scenarios handed to slots so far
   bool dyn_busy = false;
@@ -598,13 +600,13 @@ struct Engine {
         });
         if (rc != CS_OK) return rc;
         rc = timed(CS_K_KKT_REFINE, st, 0, -1,
-                   [&] { launch_kkt_refine(s, nslots, pstride, kRefineMax, st); });
+                   [&] { launch_kkt_refine(s, nslots, pstride, opts.refine_steps, st); });
         if (rc != CS_OK) return rc;
         const int u3 = T ? T->unit_slot() : -1;
         if (u3 >= 0) launch_count_jobs(s, nslots, 3, c->d_units + u3, st);
         rc = timed(CS_K_KKT_LU64, st, 0, u3, [&] {
           launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv, pstride, s.st, PH_IPM, 3,
-                          nslots, nullptr, st);
+                          nslots, nullptr, st, LU_KKT_FALLBACK);
         });
       } else {
         if (u >= 0) launch_count_jobs(s, nslots, 1, c->d_units + u, st);
@@ -618,13 +620,18 @@ struct Engine {
                  [&] { launch_opf_update(*D, s, nslots, 1e10, st); });
       if (rc != CS_OK) return rc;
     }
-    if ((rc = count()) != CS_OK) return rc;
-    assigned = std::min<long long>((long long)*h_next, N);
+    // Ask whether the dynamic stage has finished before the slot counts are
+    // taken: if it finished between the two, its slots would be counted as
+    // still busy while it is marked idle, and nothing would free them.
+    bool dyn_finished = false;
     if (dyn_busy) {
       const hipError_t q = hipEventQuery(ev_dyn);
-      if (q == hipSuccess) dyn_busy = false;
+      if (q == hipSuccess) dyn_finished = true;
       else if (q != hipErrorNotReady) return fail(CS_EDEVICE, "dynamic stage failed");
     }
+    if ((rc = count()) != CS_OK) return rc;
+    if (dyn_finished) dyn_busy = false;
+    assigned = std::min<long long>((long long)*h_next, N);
     const int ready = cnt[PH_DYN] + cnt[PH_DONE];
     const int ipm_left = cnt[PH_IPM] + cnt[PH_NEW];
     // While more scenarios wait, the dynamic stage takes the ready slots in
@@ -647,7 +654,7 @@ struct Engine {
       if (rc != CS_OK) return rc;
       rc = timed(CS_K_DYN_LU, sd, ndyn, -1, [&] {
         launch_lu_solve(s.K, s.k_stride, s.ny, s.nyc, s.ldy, s.piv, pstride, s.st, PH_DYNB, 1,
-                        nslots, nullptr, sd);
+                        nslots, nullptr, sd, LU_DYN);
       });
       if (rc != CS_OK) return rc;
       rc = timed(CS_K_STATE_MATRIX, sd, ndyn, -1, [&] { launch_form_state(*D, s, nslots, sd); });
@@ -658,7 +665,8 @@ struct Engine {
       });
       if (rc != CS_OK) return rc;
       rc = timed(CS_K_CLASSIFY, sd, ready, -1, [&] {
-        launch_classify(s, nslots, opts.near_eps, opts.max_it, d_res, item_req, req_done, sd);
+        launch_classify(s, nslots, opts.near_eps, opts.max_it, d_res, item_req, req_done,
+                        detail, D->nb, D->ng, sd);
       });
       if (rc != CS_OK) return rc;
       HIPCHK(hipEventRecord(ev_dyn, sd));
@@ -699,12 +707,15 @@ static int check_opts(const cs_opts& opts, const char* who) {
     return fail(CS_EINVAL, std::string(who) + ": prec must be CS_PREC_FP64 or CS_PREC_MIXED");
   if (opts.max_it < 1 || opts.max_it > 10000) return fail(CS_EINVAL, std::string(who) + ": max_it out of range");
   if (!(opts.tol > 0)) return fail(CS_EINVAL, std::string(who) + ": tol must be > 0");
+  if (opts.refine_steps < 0 || opts.refine_steps > 100)
+    return fail(CS_EINVAL, std::string(who) + ": refine_steps must be in 0..100");
   return CS_OK;
 }
 
 static int run_screen(cs_ctx* c, cs_net* n, const int* d_out_list, long long N,
                       const double* d_lambda, const cs_opts* o, cs_result* d_res,
-                      double* d_risk, hipStream_t st, Plan* keep) {
+                      double* d_risk, hipStream_t st, Plan* keep,
+                      const DetailOut* detail = nullptr) {
   cs_opts opts;
   cs_opts_default(&opts);
   if (o) opts = *o;
@@ -749,6 +760,7 @@ static int run_screen(cs_ctx* c, cs_net* n, const int* d_out_list, long long N,
   e.d_res = d_res;
   e.q_cap = std::max<long long>(N, 1);
   e.T = tm ? &T : nullptr;
+  e.detail = detail;
   c->stats.kkt_order = p.s.nk;
   if ((rc = e.start()) != CS_OK) return rc;
   // every scenario needs at most max_it + 2 rounds in its slot, plus a few
@@ -1386,5 +1398,148 @@ extern "C" int cs_kkt_at(cs_ctx* c, cs_net* n, const int32_t outage[2], int32_t 
   }
   if (status) *status = (S.phase == PH_IPM) ? CS_OPF_MAXIT : S.status;
   if (order) *order = nk;
+  return CS_OK;
+}
+
+extern "C" int cs_screen_detail(cs_ctx* c, cs_net* n, const int32_t* outages, int64_t N,
+                                const cs_opts* opts, cs_result* out, double* vm, double* va,
+                                double* pg, double* qg, double* eig_re, double* eig_im,
+                                int32_t* n_eig) {
+  if (!c || !n || N < 0 || (N > 0 && (!outages || !out || !vm || !va || !pg || !qg ||
+                                      !eig_re || !eig_im || !n_eig)))
+    return fail(CS_EINVAL, "cs_screen_detail: NULL argument or negative n");
+  int rc = validate_host(n, outages, N, nullptr);
+  if (rc != CS_OK) return rc;
+  if (N == 0) return CS_OK;
+  HIPCHK(hipSetDevice(c->device));
+  const size_t nb = n->nb, ng = n->ng, na = 7 * (size_t)n->ng - 1;
+  const size_t per = 2 * nb + 2 * ng + 2 * na;
+  int* d_list = nullptr;
+  cs_result* d_res = nullptr;
+  double* d_det = nullptr;
+  int* d_ne = nullptr;
+  auto cleanup = [&]() {
+    if (d_list) hipFree(d_list);
+    if (d_res) hipFree(d_res);
+    if (d_det) hipFree(d_det);
+    if (d_ne) hipFree(d_ne);
+  };
+  if (hipMalloc(&d_list, sizeof(int) * 2 * N) != hipSuccess ||
+      hipMalloc(&d_res, sizeof(cs_result) * N) != hipSuccess ||
+      hipMalloc(&d_det, sizeof(double) * per * N) != hipSuccess ||
+      hipMalloc(&d_ne, sizeof(int) * N) != hipSuccess) {
+    cleanup();
+    return fail(CS_ENOMEM, "cs_screen_detail: device allocation failed");
+  }
+  DetailOut det;
+  det.vm = d_det;
+  det.va = det.vm + nb * N;
+  det.pg = det.va + nb * N;
+  det.qg = det.pg + ng * N;
+  det.eig_re = det.qg + ng * N;
+  det.eig_im = det.eig_re + na * N;
+  det.n_eig = d_ne;
+  if (hipMemcpy(d_list, outages, sizeof(int) * 2 * N, hipMemcpyHostToDevice) != hipSuccess) {
+    cleanup();
+    return fail(CS_EDEVICE, "cs_screen_detail: copy to device failed");
+  }
+  rc = run_screen(c, n, d_list, N, nullptr, opts, d_res, nullptr, c->stream, nullptr, &det);
+  if (rc == CS_OK) {
+    const struct { double* h; const double* d; size_t cnt; } cp[] = {
+        {vm, det.vm, nb * N}, {va, det.va, nb * N}, {pg, det.pg, ng * N},
+        {qg, det.qg, ng * N}, {eig_re, det.eig_re, na * N}, {eig_im, det.eig_im, na * N}};
+    bool ok = hipMemcpy(out, d_res, sizeof(cs_result) * N, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(n_eig, d_ne, sizeof(int) * N, hipMemcpyDeviceToHost) == hipSuccess;
+    for (const auto& e : cp)
+      ok = ok && hipMemcpy(e.h, e.d, sizeof(double) * e.cnt, hipMemcpyDeviceToHost) == hipSuccess;
+    if (!ok) rc = fail(CS_EDEVICE, "cs_screen_detail: copy to host failed");
+  }
+  cleanup();
+  return rc;
+}
+
+extern "C" int cs_dyn_at(cs_ctx* c, cs_net* n, const int32_t outage[2], const double* vm,
+                         const double* va, const double* pg, const double* qg, double* A,
+                         int32_t* n_states, double* eig_re, double* eig_im) {
+  if (!c || !n || !outage || !vm || !va || !pg || !qg || !n_states)
+    return fail(CS_EINVAL, "cs_dyn_at: NULL argument");
+  int rc = validate_host(n, outage, 1, nullptr);
+  if (rc != CS_OK) return rc;
+  HIPCHK(hipSetDevice(c->device));
+  Plan p = plan_sizes(n, false);
+  rc = bind_workspace(&c->ws, &c->ws_bytes, n, p, 1);
+  if (rc != CS_OK) return rc;
+  const Slots& s = p.s;
+  const DevNet& D = n->d;
+  const int nb = n->nb, ng = n->ng;
+  hipStream_t st = c->stream;
+  int* d_list = nullptr;
+  HIPCHK(hipMalloc(&d_list, sizeof(int) * 2));
+  if (hipMemcpy(d_list, outage, sizeof(int) * 2, hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(d_list);
+    return fail(CS_EDEVICE, "cs_dyn_at: copy to device failed");
+  }
+  launch_assign(s, 1, st);
+  launch_islands(D, s, d_list, 1, st);
+  launch_setup_k(D, s, 1, d_list, st);
+  hipError_t e = hipStreamSynchronize(st);
+  hipFree(d_list);
+  if (e != hipSuccess) return fail(CS_EDEVICE, std::string("cs_dyn_at: ") + hipGetErrorString(e));
+  SlotState S;
+  HIPCHK(hipMemcpy(&S, s.st, sizeof(SlotState), hipMemcpyDeviceToHost));
+  if (S.phase != PH_IPM)
+    return fail(CS_EINVAL, "cs_dyn_at: the outage leaves no island with a generator to linearise");
+  // the given operating point on the island's buses and in-service machines
+  std::vector<double> x(s.nx);
+  std::vector<uint8_t> bus_on(nb), gen_on(ng);
+  HIPCHK(hipMemcpy(x.data(), s.x, sizeof(double) * s.nx, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(bus_on.data(), s.bus_on, nb, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(gen_on.data(), s.gen_on, ng, hipMemcpyDeviceToHost));
+  for (int b = 0; b < nb; ++b)
+    if (bus_on[b]) {
+      if (!std::isfinite(va[b]) || !std::isfinite(vm[b]) || !(vm[b] > 0))
+        return fail(CS_EINVAL, "cs_dyn_at: bus " + std::to_string(b) +
+                                   " of the island needs a finite angle and a positive voltage");
+      x[b] = va[b];
+      x[nb + b] = vm[b];
+    }
+  for (int g = 0; g < ng; ++g)
+    if (gen_on[g]) {
+      if (!std::isfinite(pg[g]) || !std::isfinite(qg[g]))
+        return fail(CS_EINVAL, "cs_dyn_at: generator " + std::to_string(g) + " needs finite P and Q");
+      x[2 * nb + g] = pg[g];
+      x[2 * nb + ng + g] = qg[g];
+    }
+  HIPCHK(hipMemcpy(s.x, x.data(), sizeof(double) * s.nx, hipMemcpyHostToDevice));
+  S.phase = PH_DYNB;
+  S.status = OPF_CONVERGED;
+  S.job = 0;
+  S.singular = 0;
+  HIPCHK(hipMemcpy(s.st, &S, sizeof(SlotState), hipMemcpyHostToDevice));
+  const int pstride = std::max(s.nk, s.ny);
+  launch_dyn_assemble(D, s, 1, st);
+  launch_lu_solve(s.K, s.k_stride, s.ny, s.nyc, s.ldy, s.piv, pstride, s.st, PH_DYNB, 1, 1,
+                  nullptr, st, LU_DYN);
+  launch_form_state(D, s, 1, st);
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipMemcpy(&S, s.st, sizeof(SlotState), hipMemcpyDeviceToHost));
+  const int ns = S.n_states;
+  *n_states = ns;
+  if (A) {
+    std::vector<double> a((size_t)s.lda_a * std::max(ns, 1));
+    HIPCHK(hipMemcpy(a.data(), s.A, sizeof(double) * a.size(), hipMemcpyDeviceToHost));
+    for (int r = 0; r < ns; ++r)
+      for (int col = 0; col < ns; ++col) A[(size_t)r * ns + col] = a[(size_t)col * s.lda_a + r];
+  }
+  if (S.phase != PH_EIG)
+    return fail(CS_EDEVICE, "cs_dyn_at: the algebraic system is singular or the state matrix is not finite");
+  if (eig_re || eig_im) {
+    launch_eig(s.A, s.a_stride, s.lda_a, nullptr, 0, s.wr, s.wi, s.na, s.st, 1, nullptr, st);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(&S, s.st, sizeof(SlotState), hipMemcpyDeviceToHost));
+    if (S.qr_fail) return fail(CS_EDEVICE, "cs_dyn_at: QR iteration did not converge");
+    if (eig_re) HIPCHK(hipMemcpy(eig_re, s.wr, sizeof(double) * ns, hipMemcpyDeviceToHost));
+    if (eig_im) HIPCHK(hipMemcpy(eig_im, s.wi, sizeof(double) * ns, hipMemcpyDeviceToHost));
+  }
   return CS_OK;
 }

@@ -101,6 +101,16 @@ struct Slots {
   SlotState* st;
 };
 
+// Per-scenario detail written by k_classify when requested (parity checks):
+// the operating point over the whole network (NaN outside the solved island or
+// when the OPF did not run) and the spectrum (NaN-padded to na).
+struct DetailOut {
+  double* vm; double* va;       // [n][nb]
+  double* pg; double* qg;       // [n][ng]
+  double* eig_re; double* eig_im;   // [n][na]
+  int* n_eig;                   // [n]
+};
+
 // Launch wrappers (one per kernel file).
 void launch_islands(const DevNet& net, const Slots& s, const int* outages,
                     int count, hipStream_t st);
@@ -111,10 +121,11 @@ void launch_opf_eval(const DevNet& net, const Slots& s, int count, double tol,
 void launch_opf_update(const DevNet& net, const Slots& s, int count,
                        double gamma_max, hipStream_t st);
 // batched LU + solve; with slot states, only slots with st.job == want_job
-// in phase want_phase
+// in phase want_phase.  role (LuRole) picks the kernel symbol only.
+enum LuRole : int { LU_KKT = 0, LU_DYN = 1, LU_KKT_FALLBACK = 2 };
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
                      int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
-                     int count, int* info, hipStream_t stream);
+                     int count, int* info, hipStream_t stream, int role = LU_KKT);
 void launch_lu_solve_f32(float* A, size_t stride, int n, int ncols, int lda,
                          int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
                          int count, int* info, hipStream_t stream);
@@ -124,7 +135,8 @@ void launch_eig(double* A, size_t stride, int lda, const int* n_per, int n_unifo
                 double* wr, double* wi, int w_stride, SlotState* st, int count,
                 int* info, hipStream_t stream);
 void launch_classify(const Slots& s, int count, double near_eps, int max_it,
-                     void* results, const int* item_req, int* req_done, hipStream_t st);
+                     void* results, const int* item_req, int* req_done,
+                     const DetailOut* detail, int nb, int ng, hipStream_t st);
 void launch_risk(const int* outages, long long n, const uint8_t* severe_src,
                  int sev_stride, const double* lam, int n_comp, double* risk,
                  hipStream_t st);

@@ -702,7 +702,11 @@ __device__ inline void interchange_trsm(T* __restrict__ A, int lda, int ncols, i
 template <class T>
 struct LuWavesPerEu { static constexpr int value = sizeof(T) == 4 ? 4 : 2; };
 
-template <class T>
+// ROLE only names the instantiation (LuRole): the KKT systems, the dynamic
+// algebraic systems and the FP64 fallback of the mixed-precision solve run
+// the same code under their own kernel symbols, so that a profiler's
+// per-kernel statistics separate them.
+template <class T, int ROLE>
 __global__ __launch_bounds__(LU_THREADS, LuWavesPerEu<T>::value) void k_lu_solve(
     T* __restrict__ Abase, size_t stride, int n, int ncols, int lda,
     int* __restrict__ pivbase, int piv_stride, SlotState* __restrict__ st,
@@ -820,10 +824,13 @@ int lu_max_order() { return LU_MAX_N; }
 
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
                      int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
-                     int count, int* info, hipStream_t stream) {
+                     int count, int* info, hipStream_t stream, int role) {
   if (count <= 0) return;
   const size_t lds = lu_dynamic_lds<double>(n, ncols - n);
-  hipLaunchKernelGGL(k_lu_solve<double>, dim3(count), dim3(LU_THREADS), lds, stream,
+  auto k = role == LU_DYN ? k_lu_solve<double, LU_DYN>
+           : role == LU_KKT_FALLBACK ? k_lu_solve<double, LU_KKT_FALLBACK>
+                                     : k_lu_solve<double, LU_KKT>;
+  hipLaunchKernelGGL(k, dim3(count), dim3(LU_THREADS), lds, stream,
                      A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, info);
 }
 
@@ -832,15 +839,15 @@ void launch_lu_solve_f32(float* A, size_t stride, int n, int ncols, int lda,
                          int count, int* info, hipStream_t stream) {
   if (count <= 0) return;
   const size_t lds = lu_dynamic_lds<float>(n, ncols - n);
-  hipLaunchKernelGGL(k_lu_solve<float>, dim3(count), dim3(LU_THREADS), lds, stream,
+  hipLaunchKernelGGL((k_lu_solve<float, LU_KKT>), dim3(count), dim3(LU_THREADS), lds, stream,
                      A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, info);
 }
 
 // the dynamic LDS limit of a kernel: what is left of `bytes` beside its
 // static LDS as the compiler laid it out (which may pad the struct)
-template <class T>
+template <class T, int ROLE>
 static void lu_set_attr(size_t bytes) {
-  const void* f = reinterpret_cast<const void*>(k_lu_solve<T>);
+  const void* f = reinterpret_cast<const void*>(k_lu_solve<T, ROLE>);
   hipFuncAttributes fa;
   size_t fixed = lu_static_lds<T>();
   if (hipFuncGetAttributes(&fa, f) == hipSuccess) fixed = std::max(fixed, fa.sharedSizeBytes);
@@ -848,8 +855,10 @@ static void lu_set_attr(size_t bytes) {
 }
 
 void lu_set_attrs(size_t bytes) {
-  lu_set_attr<double>(bytes);
-  lu_set_attr<float>(bytes);
+  lu_set_attr<double, LU_KKT>(bytes);
+  lu_set_attr<double, LU_DYN>(bytes);
+  lu_set_attr<double, LU_KKT_FALLBACK>(bytes);
+  lu_set_attr<float, LU_KKT>(bytes);
 }
 
 }  // namespace cs

@@ -19,7 +19,8 @@ namespace cs {
 __global__ __launch_bounds__(64) void k_classify(Slots s, int count, double near_eps,
                                                  int max_it, cs_result* __restrict__ out,
                                                  const int* __restrict__ item_req,
-                                                 int* __restrict__ req_done) {
+                                                 int* __restrict__ req_done, DetailOut det,
+                                                 int nb, int ng) {
   const int slot = blockIdx.x;
   if (slot >= count) return;
   SlotState& S = s.st[slot];
@@ -47,18 +48,48 @@ __global__ __launch_bounds__(64) void k_classify(Slots s, int count, double near
     }
     osc_any = __any(osc_any);
   }
+  if (det.vm != nullptr) {
+    // detail of this scenario, before the record releases the slot
+    const int sc = S.scen;
+    const int status = S.status;
+    const bool solved = status != OPF_NOT_RUN;
+    const double nan = __builtin_nan("");
+    const double* x = s.x + (size_t)slot * s.nx;
+    const uint8_t* bus_on = s.bus_on + (size_t)slot * nb;
+    const uint8_t* gen_on = s.gen_on + (size_t)slot * ng;
+    for (int b = lane; b < nb; b += 64) {
+      const bool on = solved && bus_on[b];
+      det.va[(size_t)sc * nb + b] = on ? x[b] : nan;
+      det.vm[(size_t)sc * nb + b] = on ? x[nb + b] : nan;
+    }
+    for (int g = lane; g < ng; g += 64) {
+      const bool on = solved && gen_on[g];
+      det.pg[(size_t)sc * ng + g] = on ? x[2 * nb + g] : nan;
+      det.qg[(size_t)sc * ng + g] = on ? x[2 * nb + ng + g] : nan;
+    }
+    const int ne = (have_eig && status == OPF_CONVERGED) ? S.n_states : 0;
+    const double* wr = s.wr + (size_t)slot * s.na;
+    const double* wi = s.wi + (size_t)slot * s.na;
+    for (int i = lane; i < s.na; i += 64) {
+      det.eig_re[(size_t)sc * s.na + i] = i < ne ? wr[i] : nan;
+      det.eig_im[(size_t)sc * s.na + i] = i < ne ? wi[i] : nan;
+    }
+    if (lane == 0) det.n_eig[sc] = ne;
+  }
   if (lane != 0) return;
   int cause = S.cause;
   int nearf = 0;
   const int status = S.status;
   if (status != OPF_CONVERGED) cause |= C_OPF;
   if (status == OPF_NUMERICAL) cause |= C_NUMERICAL;
-  if (status != OPF_NOT_RUN && S.iters >= max_it - 2) nearf |= N_OPF;
   double mv = __builtin_nan(""), ar = __builtin_nan(""), zr = __builtin_nan("");
   if (status == OPF_CONVERGED) {
+    // converged within two steps of the cap: a solve rounded differently may
+    // have ended at the cap instead
+    if (S.iters >= max_it - 2) nearf |= N_OPF;
     mv = S.max_viol;
     if (mv > 1e-6) cause |= C_LIMIT;
-    if (mv > 1e-7) nearf |= N_LIMIT;      // within a decade of the limit test
+    if (mv > 1e-7 && mv <= 1e-5) nearf |= N_LIMIT;   // a decade either side of the test
     if (phase == PH_EIG && S.qr_fail) cause |= C_NUMERICAL;
     if (have_eig) {
       ar = alpha;
@@ -94,10 +125,14 @@ __global__ __launch_bounds__(64) void k_classify(Slots s, int count, double near
 }
 
 void launch_classify(const Slots& s, int count, double near_eps, int max_it,
-                     void* results, const int* item_req, int* req_done, hipStream_t st) {
+                     void* results, const int* item_req, int* req_done,
+                     const DetailOut* detail, int nb, int ng, hipStream_t st) {
   if (count <= 0) return;
+  DetailOut det{};
+  if (detail) det = *detail;
   hipLaunchKernelGGL(k_classify, dim3(count), dim3(64), 0, st, s, count, near_eps,
-                     max_it, reinterpret_cast<cs_result*>(results), item_req, req_done);
+                     max_it, reinterpret_cast<cs_result*>(results), item_req, req_done, det,
+                     nb, ng);
 }
 
 __global__ __launch_bounds__(256) void k_risk(const int* __restrict__ outages, long long n,

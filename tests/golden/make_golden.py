@@ -9,6 +9,16 @@ island labels and the Risk Index over that list.
           118-bus-shaped case (a stratified sample; the full list has 57,630)
   c2_118_full: the whole 57,630-scenario list of the 118-bus-shaped case
 
+c1_30 and c2_118 also hold each scenario's operating point (vm, va over the
+buses, pg, qg over the generators; NaN outside the solved island or when the
+OPF did not run) and its full spectrum (eig_re, eig_im, NaN-padded, n_eig
+values).
+
+  python tests/golden/make_golden.py --refresh-near [case ...]
+
+recomputes only the stored near-threshold flags from the stored records with
+the oracle's own rule (oracle.screen.near_flags), without solving again.
+
 Usage: python tests/golden/make_golden.py [case ...]
 """
 from __future__ import annotations
@@ -30,6 +40,7 @@ from oracle import screen, risk                    # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SAMPLES = {"c1_30": None, "c2_118": 600, "c2_118_full": None}
+WITH_DETAIL = {"c1_30", "c2_118"}
 CASE_OF = {"c2_118_full": "c2_118"}
 _NET = None
 
@@ -67,12 +78,51 @@ def make(name, procs=8):
     labels = np.array([r.label for r in res], dtype=np.int16)
     n_comp = int(net["n_branch"]) + int(net["n_gen"]) + int(net["n_load"])
     R = risk.risk_index(lst, tab["severe"], net["lam"], n_comp)
+    extra = detail_arrays(net, res) if name in WITH_DETAIL else {}
     out = os.path.join(HERE, name + "_oracle.npz")
-    np.savez_compressed(out, outages=lst, labels=labels, risk=R, **tab)
+    np.savez_compressed(out, outages=lst, labels=labels, risk=R, **tab, **extra)
     print(f"{name}: {len(lst)} scenarios, {int(tab['severe'].sum())} severe -> {out}")
+
+
+def detail_arrays(net, res):
+    nb, ng = int(net["n_bus"]), int(net["n_gen"])
+    na = 7 * ng - 1
+    n = len(res)
+    d = {k: np.full((n, nb), np.nan) for k in ("vm", "va")}
+    d.update({k: np.full((n, ng), np.nan) for k in ("pg", "qg")})
+    d.update({k: np.full((n, na), np.nan) for k in ("eig_re", "eig_im")})
+    d["n_eig"] = np.zeros(n, np.int32)
+    for i, r in enumerate(res):
+        if r.vm is not None and r.opf_status != screen.opf.NOT_RUN:
+            d["vm"][i, r.bus], d["va"][i, r.bus] = r.vm, r.va
+            d["pg"][i, r.gen], d["qg"][i, r.gen] = r.pg, r.qg
+        if r.eig is not None:
+            d["eig_re"][i, :len(r.eig)] = r.eig.real
+            d["eig_im"][i, :len(r.eig)] = r.eig.imag
+            d["n_eig"][i] = len(r.eig)
+    return d
+
+
+def refresh_near(name):
+    """Rewrite the stored near flags with the oracle's rule applied to the
+    stored status, iteration count, limit excess and largest real part."""
+    out = os.path.join(HERE, name + "_oracle.npz")
+    with np.load(out, allow_pickle=False) as z:
+        g = {k: z[k] for k in z.files}
+    g["near"] = np.array([screen.near_flags(int(s), int(it), float(v), float(a))
+                          for s, it, v, a in zip(g["opf_status"], g["opf_iters"],
+                                                 g["max_violation"], g["max_real_eig"])],
+                         dtype=g["near"].dtype)
+    np.savez_compressed(out, **g)
+    print(f"{name}: near flags refreshed, {int((g['near'] > 0).sum())} flagged -> {out}")
 
 
 if __name__ == "__main__":
     procs = int(os.environ.get("GOLDEN_PROCS", "8"))
-    for name in (sys.argv[1:] or ["c1_30", "c2_118"]):
+    args = sys.argv[1:]
+    if args and args[0] == "--refresh-near":
+        for name in (args[1:] or ["c2_118_full"]):
+            refresh_near(name)
+        sys.exit(0)
+    for name in (args or ["c1_30", "c2_118"]):
         make(name, procs)

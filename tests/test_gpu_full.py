@@ -2,27 +2,29 @@
 unordered N-2 over the 339 components: 57,630 scenarios) against the oracle's
 stored records (tests/golden/c2_118_full_oracle.npz, written by make_golden.py
 from the oracle only), in the launch configuration the benchmark times: the
-outage list, the load-loss weights and the outputs resident on the device, and
-the device entry point called on consecutive slices of 4,096 scenarios.
+outage list, the failure rates and the outputs resident on the device, and
+the device entry point called on consecutive slices of the list.
 
-Bars: island counts bit-exact.  Severity bit-exact except (a) scenarios that
-the oracle or the device flags as near a threshold (the OPF within two steps
-of its iteration limit, a limit excess within a decade of the test, the
-largest real part within 1e-6 of zero) and (b) at most MAX_FLIPS scenarios
-where one side's OPF converges and the other's does not, with everything
-before the OPF identical.  On such hard cases (the post-contingency OPF is
-infeasible or nearly so and the interior-point path wanders for dozens of
-steps) the outcome is decided by rounding: the oracle itself flips on them
-when its Newton systems are solved by an exact reformulation (QR, or LU of the
-system with power-of-two row scaling; tests/test_oracle_sensitivity.py pins
-this on listed scenarios).  Where both OPFs fail, the failure may be reported
-as the iteration limit by one side and as divergence by the other.  For every
-scenario converged on both sides: OPF cost within 1e-6 relative, the
-spectrum summary within 1e-6, and iteration counts within 2 except on at most
-MAX_FLIPS scenarios (the same optimum reached by a different path).  The Risk Index of every
-component not touched by a scenario whose severity differs within 1e-12
-relative (Section II.C, eq. 1-3).  The mixed-precision form is held to the
-same bars.
+Bars (Section II.B decisions, helpers.outcome_mismatches):
+  - island counts bit-exact;
+  - severity, cause and OPF status bit-exact, except
+      * a decision next to its threshold on either side, explained by its
+        own near flag (OPF converged within two steps of the cap, a limit
+        excess within a decade of 1e-6 p.u., |max Re| <= 1e-6);
+      * an OPF that converges on one side only, on the scenarios listed in
+        tests/golden/c2_118_rounding_probes.json ("outcome"), each shown by
+        tests/test_oracle_sensitivity.py to flip in the oracle itself under
+        an exact reformulation of its Newton solves;
+      * where both OPFs fail, whether by the iteration cap or by divergence
+        (the same severity for the same reason; sampled evidence under
+        "kind" in the same file);
+  - on every scenario converged on both sides: OPF cost within 1e-6
+    relative, the largest real part and the minimum damping within 1e-6 (end
+    to end: the operating points agree to the OPF tolerance), iteration
+    counts within 2 except on listed scenarios ("path" or "outcome");
+  - R_i of every component not touched by a scenario whose severity differs
+    within 1e-12 relative (Section II.C, eq. 1-3).
+The mixed-precision form is held to the same bars.
 """
 import numpy as np
 import pytest
@@ -31,7 +33,10 @@ from helpers import load_case, load_golden
 
 pytestmark = pytest.mark.gpu
 
-STEP = 4096
+# the benchmark's default launch configuration: four consecutive slices of
+# the list, 4,096 resident slots refilled as scenarios finish
+STEP = -(-57630 // 4)
+SLOTS = 4096
 
 
 @pytest.fixture(scope="module")
@@ -56,7 +61,7 @@ def _screen_full(setup, prec):
     d_res = torch.zeros(n * rec, dtype=torch.uint8, device=dev)
     d_risk = torch.zeros(len(case["lam"]), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
-    opts = cs.default_options(prec=prec)
+    opts = cs.default_options(prec=prec, batch=SLOTS)
     # eq. (3) is a sum over the scenarios of the list, so R_i of the whole
     # list is the sum of the slices' R_i
     R = np.zeros(len(case["lam"]))
@@ -83,38 +88,27 @@ def full_mixed(setup):
     return _screen_full(setup, setup[0].PREC_MIXED)
 
 
-MAX_FLIPS = 20
-CAUSE_NUMERICAL = 16
+def _rounding_lists():
+    import json
+    from helpers import GOLDEN
+    import os
+    data = json.load(open(os.path.join(GOLDEN, "c2_118_rounding_probes.json")))
+    return ({int(i) for i in data.get("outcome", {})}, {int(i) for i in data.get("path", {})})
 
 
 def _check(g, res, R, tag):
+    from helpers import outcome_mismatches
     assert len(res) == len(g["outages"]) == 57630
     assert np.array_equal(res["n_islands"], g["n_islands"])
+    flip_ok, path_ok = _rounding_lists()
+    bad, flips, kind = outcome_mismatches(g, res, flip_ok)
     near = (g["near"] > 0) | (res["near"] > 0)
-    conv_g, conv_d = g["opf_status"] == 0, res["opf_status"] == 0
-    ran_g, ran_d = g["opf_status"] != 3, res["opf_status"] != 3
-    assert np.array_equal(ran_g, ran_d)
-    sev_differ = res["severe"] != g["severe"]
-    flip = ran_g & (conv_g != conv_d)
-    print(f"{tag}: {int(near.sum())} near-threshold scenarios, severity differs on "
-          f"{np.flatnonzero(near & sev_differ).tolist()}")
-    print(f"{tag}: OPF converged on one side only (not near a threshold): "
-          f"{np.flatnonzero(~near & flip).tolist()}")
-    bad = np.flatnonzero(~near & sev_differ & ~flip)
+    print(f"{tag}: {int(near.sum())} scenarios near a threshold; OPF converged on one side "
+          f"only: {flips.tolist()}; both failed, different kind: {len(kind)}")
     for i in bad[:10]:
         print("mismatch", i, g["outages"][i], "device", res[i], "oracle",
-              {k: g[k][i] for k in ("severe", "cause", "opf_status", "opf_iters")})
-    assert len(bad) == 0
-    assert int((~near & flip).sum()) <= MAX_FLIPS
-    # same outcome: same cause, except the kind of OPF failure where both failed
-    same = ~near & ~flip
-    mask = np.where(~conv_g & ~conv_d & ran_g, ~CAUSE_NUMERICAL, -1)
-    cause_bad = np.flatnonzero(same & ((res["cause"] & mask) != (g["cause"] & mask)))
-    assert len(cause_bad) == 0, cause_bad[:10]
-    fail_kind = int((same & ~conv_g & ~conv_d & ran_g
-                     & (res["opf_status"] != g["opf_status"])).sum())
-    print(f"{tag}: both OPFs failed, one by the iteration limit and one by divergence: "
-          f"{fail_kind}")
+              {k: g[k][i] for k in ("severe", "cause", "opf_status", "opf_iters", "near")})
+    assert len(bad) == 0, bad[:20]
 
     both = (g["opf_status"] == 0) & (res["opf_status"] == 0)
     assert both.sum() > 0.5 * len(res)
@@ -128,8 +122,10 @@ def _check(g, res, R, tag):
           f"equal on {int((dit == 0).sum())}, more than 2 apart on "
           f"{np.flatnonzero(both)[dit > 2].tolist()}")
     assert rel.max() < 1e-6
-    # the same optimum, reached by a different path on a few hard cases
-    assert (dit > 2).sum() <= MAX_FLIPS
+    # the same optimum, reached by a different path on listed hard cases
+    other_path = np.flatnonzero(both)[dit > 2]
+    unlisted = [int(i) for i in other_path if int(i) not in path_ok | flip_ok]
+    assert not unlisted, unlisted
     assert np.array_equal(res["n_states"][both], g["n_states"][both])
     assert da.max() < 1e-6
     assert dz.max() < 1e-6

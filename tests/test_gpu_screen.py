@@ -51,11 +51,16 @@ def test_islanding_bit_exact(screened, name):
 
 @pytest.mark.parametrize("name", ["c1_30", "c2_118"])
 def test_severity_and_status(screened, name):
+    """Bit-exact except what helpers.outcome_mismatches explains (near flags,
+    listed rounding-decided OPF outcomes, the kind of failure where both
+    OPFs failed)."""
+    from helpers import outcome_mismatches, rounding_listed
     g, res, _ = screened[name]
-    near = _near(g, res)
-    bad = np.flatnonzero(~near & ((res["severe"] != g["severe"]) | (res["cause"] != g["cause"])
-                                  | (res["opf_status"] != g["opf_status"])))
-    print(f"{name}: near-threshold scenarios excluded: {np.flatnonzero(near).tolist()}")
+    flip_ok = rounding_listed(g["outages"]) if name == "c2_118" else []
+    bad, flips, kind = outcome_mismatches(g, res, flip_ok)
+    print(f"{name}: near-threshold scenarios: {np.flatnonzero(_near(g, res)).tolist()}; "
+          f"OPF converged on one side only: {flips.tolist()}; both failed, other kind: "
+          f"{kind.tolist()}")
     for i in bad[:10]:
         print("mismatch", i, g["outages"][i], "gpu", res[i], "oracle",
               {k: g[k][i] for k in ("severe", "cause", "opf_status", "opf_iters")})
@@ -69,7 +74,11 @@ def test_opf_cost_iters_and_spectrum_summary(screened, name):
     assert both.sum() > 0
     rel = np.abs(res["opf_cost"][both] - g["opf_cost"][both]) / np.abs(g["opf_cost"][both])
     assert rel.max() < 1e-6
-    assert np.max(np.abs(res["opf_iters"][both].astype(int) - g["opf_iters"][both])) <= 2
+    from helpers import rounding_listed
+    listed = np.zeros(len(res), bool)
+    listed[rounding_listed(g["outages"], ("outcome", "path"))] = True
+    dit = np.abs(res["opf_iters"].astype(int) - g["opf_iters"])
+    assert np.all(dit[both & ~listed] <= 2), np.flatnonzero(both & ~listed & (dit > 2))
     assert np.array_equal(res["n_states"][both], g["n_states"][both])
     da = np.abs(res["max_real_eig"][both] - g["max_real_eig"][both])
     assert np.max(da / np.maximum(np.abs(g["max_real_eig"][both]), 1.0)) < 1e-6
@@ -118,6 +127,108 @@ def test_detail_against_live_oracle(nets, name, rows):
         assert np.max(np.abs(d["pg"][ref.gen] - ref.pg)) < 1e-6
         assert len(d["eig"]) == len(ref.eig)
         assert match_eigs(ref.eig, d["eig"]) < 1e-6
+
+
+@pytest.fixture(scope="module")
+def detailed(nets):
+    out = {}
+    for name in ("c1_30", "c2_118"):
+        g = load_golden(name)
+        print(f"screening {name} with detail: {len(g['outages'])} scenarios", flush=True)
+        out[name] = (g, nets[name].screen_detail(g["outages"]))
+    return out
+
+
+@pytest.mark.parametrize("name", ["c1_30", "c2_118"])
+def test_operating_point_every_scenario(detailed, name):
+    """V within 1e-6 p.u. (angles, P and Q within 1e-6) on every scenario
+    whose OPF converged on both sides; NaN exactly where the oracle has no
+    value (outside the island, generators out of service)."""
+    g, d = detailed[name]
+    rec = d["records"]
+    both = (g["opf_status"] == 0) & (rec["opf_status"] == 0)
+    assert both.sum() > 0.5 * len(rec)
+    worst = {}
+    for k in ("vm", "va", "pg", "qg"):
+        ref, got = g[k][both], d[k][both]
+        assert np.array_equal(np.isnan(ref), np.isnan(got)), k
+        m = ~np.isnan(ref)
+        worst[k] = float(np.max(np.abs(ref[m] - got[m])))
+    print(f"{name}: {int(both.sum())} scenarios, largest deviations {worst}")
+    assert max(worst.values()) < 1e-6
+
+
+@pytest.mark.parametrize("name", ["c1_30", "c2_118"])
+def test_full_spectrum_every_scenario(detailed, name):
+    """Every eigenvalue of every scenario whose OPF converged on both sides,
+    after matching, within 1e-6 max(|lambda|, 1).  End to end the two
+    operating points agree only to the OPF tolerance, and an eigenvalue moves
+    by its condition number times the change of A; the 1e-8 bar applies to the
+    same operating point (test_state_matrix_at_oracle_point)."""
+    g, d = detailed[name]
+    rec = d["records"]
+    both = np.flatnonzero((g["opf_status"] == 0) & (rec["opf_status"] == 0))
+    worst, at = 0.0, -1
+    for i in both:
+        ne = int(g["n_eig"][i])
+        assert int(d["n_eig"][i]) == ne
+        ref = g["eig_re"][i, :ne] + 1j * g["eig_im"][i, :ne]
+        w = match_eigs(ref, d["eig"][i])
+        if w > worst:
+            worst, at = w, int(i)
+    print(f"{name}: {len(both)} spectra, worst matched deviation {worst:.2e} (scenario {at})")
+    assert worst < 1e-6
+
+
+@pytest.mark.parametrize("name,rows", [("c1_30", [0, 7, 41, 100, 500, 860]),
+                                       ("c2_118", [0, 120, 250, 339, 450, 599])])
+def test_state_matrix_at_oracle_point(nets, name, rows):
+    """Rows a8-a11 alone: from the oracle's own OPF point, the device's state
+    matrix equals the oracle's entry by entry (1e-12 of its largest entry) and
+    its eigenvalues match within 1e-8 max(|lambda|, 1)."""
+    from oracle import dynamics, eigen, network, screen
+    net = load_case(name)
+    g = load_golden(name)
+    nb, ng = int(net["n_bus"]), int(net["n_gen"])
+    checked = 0
+    worst_a, worst_l = 0.0, 0.0
+    for r in rows:
+        if g["opf_status"][r] != 0:
+            continue
+        o = g["outages"][r]
+        ref = screen.evaluate(net, o, detail=True)
+        vm, va = np.full(nb, np.nan), np.full(nb, np.nan)
+        pg, qg = np.full(ng, np.nan), np.full(ng, np.nan)
+        vm[ref.bus], va[ref.bus], pg[ref.gen], qg[ref.gen] = ref.vm, ref.va, ref.pg, ref.qg
+        A, lam = nets[name].dyn_at(o, vm, va, pg, qg)
+        assert A.shape == ref.A.shape
+        da = np.max(np.abs(A - ref.A)) / np.max(np.abs(ref.A))
+        dl = match_eigs(ref.eig, lam)
+        worst_a, worst_l = max(worst_a, da), max(worst_l, dl)
+        assert da < 1e-12, (r, da)
+        assert dl < 1e-8, (r, dl)
+        checked += 1
+    print(f"{name}: {checked} state matrices, A within {worst_a:.2e}, eigenvalues {worst_l:.2e}")
+    assert checked >= 3
+
+
+def test_state_matrix_entry_point_rejects_bad_points(nets):
+    import paper_2512_08465_amd as cs
+    net = load_case("c1_30")
+    nb, ng, nl = int(net["n_bus"]), int(net["n_gen"]), int(net["n_branch"])
+    h = nets["c1_30"]
+    vm, va = np.ones(nb), np.zeros(nb)
+    pg, qg = np.full(ng, 0.3), np.zeros(ng)
+    # a NaN inside the island
+    bad = vm.copy()
+    bad[3] = np.nan
+    with pytest.raises(cs.CSError) as e:
+        h.dyn_at([-1, -1], bad, va, pg, qg)
+    assert e.value.code == cs.CS_EINVAL
+    # an outage id out of range
+    with pytest.raises(cs.CSError) as e:
+        h.dyn_at([nl + ng + int(net["n_load"]), -1], vm, va, pg, qg)
+    assert e.value.code == cs.CS_EINVAL
 
 
 def test_invalid_inputs_rejected(nets):

@@ -126,3 +126,95 @@ def test_structural_zero_removed(c1_base):
     shift = np.zeros(Af.shape[0])
     shift[::dynamics.NS_SG] = 1.0
     assert np.allclose(np.abs(v), shift, atol=1e-6)
+
+
+# --- single machine against an infinite bus, every model row live -----------
+#
+# Bus 1 holds the machine under test (two-axis with transient saliency, AVR,
+# governor and turbine, no time constant frozen); bus 0 holds machine 0 with
+# Xd' = Xq' = Xp0, which is a constant EMF E_inf behind Xp0 while its own
+# states are held (A's entries are partial derivatives).  With a lossless line
+# x and no loads, machine 1 sees E_inf behind Xe = x + Xp0, and in its own dq
+# frame the network reduces to
+#     Vd = E_b sin d - Xe Iq,   Vq = E_b cos d + Xe Id     (d = delta - arg E_inf)
+# which with the stator (Rs = 0) Vd = Ed' + Xq' Iq, Vq = Eq' - Xd' Id gives
+#     Id = (Eq' - E_b cos d) / (Xe + Xd'),   Iq = (E_b sin d - Ed') / (Xe + Xq').
+# Linearising Pe = Ed' Id + Eq' Iq + (Xq' - Xd') Id Iq and |V| gives the
+# Heffron-Phillips constants (deMello and Concordia 1969; Kundur, Power
+# System Stability and Control, Section 12.3) extended by the q-axis EMF:
+#     dPe = K1 dd + K2 dEq' + K2d dEd',   dV = K5 dd + K6 dEq' + K6d dEd',
+#     1/K3 = (Xd + Xe)/(Xd' + Xe),  K4 = (Xd - Xd') E_b sin d / (Xd' + Xe),
+#     1/K3d = (Xq + Xe)/(Xq' + Xe), K4d = (Xq - Xq') E_b cos d / (Xq' + Xe).
+
+def _smib_case(V0=1.0, V1=1.03, th1=0.25, x=0.3, Xp0=0.05):
+    row0 = base_dyn_row(Xd=0.9, Xq=0.8, Xdp=Xp0, Xqp=Xp0)
+    row1 = base_dyn_row()            # H 4, D 2, Xd 1.5, Xq 1.4, Xd' 0.3, Xq' 0.5, ...
+    gens = [dict(bus=0, pmin=-5, pmax=5, qmin=-5, qmax=5, dyn=row0),
+            dict(bus=1, pmin=-5, pmax=5, qmin=-5, qmax=5, dyn=row1)]
+    net = make_net(2, [(0, 1, 0.0, x, 0.0)], gens, [])
+    Vb = np.array([V0 + 0j, V1 * np.exp(1j * th1)])
+    I1 = (Vb[1] - Vb[0]) / (1j * x)             # injected by machine 1
+    S = Vb * np.conj(np.array([-I1, I1]))
+    return net, Vb, I1, S, x + Xp0, dict(zip(netgen.DYN_COLS, row1))
+
+
+def _smib_closed_form(Vb, I1, Xe, p, ws):
+    Xd, Xq, Xdp, Xqp = p["Xd"], p["Xq"], p["Xdp"], p["Xqp"]
+    H, D, KA, TA, R, Tg, Tt = p["H"], p["D"], p["KA"], p["TA"], p["R"], p["Tg"], p["Tt"]
+    Td0p, Tq0p = p["Td0p"], p["Tq0p"]
+    Einf = Vb[1] - 1j * Xe * I1
+    delta = np.angle(Vb[1] + 1j * Xq * I1)
+    rot = np.exp(-1j * (delta - np.pi / 2))
+    Idq, Vdq = I1 * rot, Vb[1] * rot
+    Id, Iq, Vd, Vq = Idq.real, Idq.imag, Vdq.real, Vdq.imag
+    Edp, Eqp = Vd - Xqp * Iq, Vq + Xdp * Id
+    Eb, d = abs(Einf), delta - np.angle(Einf)
+    # the reduced network reproduces the operating point
+    assert abs(Id - (Eqp - Eb * np.cos(d)) / (Xe + Xdp)) < 1e-12
+    assert abs(Iq - (Eb * np.sin(d) - Edp) / (Xe + Xqp)) < 1e-12
+    dId_dd, dIq_dd = Eb * np.sin(d) / (Xe + Xdp), Eb * np.cos(d) / (Xe + Xqp)
+    ad, aq = Edp + (Xqp - Xdp) * Iq, Eqp + (Xqp - Xdp) * Id
+    K1 = ad * dId_dd + aq * dIq_dd
+    K2 = Iq + ad / (Xe + Xdp)
+    K2d = Id - aq / (Xe + Xqp)
+    K3 = (Xdp + Xe) / (Xd + Xe)
+    K4 = (Xd - Xdp) * Eb * np.sin(d) / (Xdp + Xe)
+    K3d = (Xqp + Xe) / (Xq + Xe)
+    K4d = (Xq - Xqp) * Eb * np.cos(d) / (Xqp + Xe)
+    V = abs(Vb[1])
+    K5 = (Vd * Xqp * dIq_dd - Vq * Xdp * dId_dd) / V
+    K6 = Vq / V * Xe / (Xe + Xdp)
+    K6d = Vd / V * Xe / (Xe + Xqp)
+    H2 = 2 * H
+    # states: delta, omega, Eq', Ed', Efd, Psv, Pm
+    return np.array([
+        [0, ws, 0, 0, 0, 0, 0],
+        [-K1 / H2, -D / H2, -K2 / H2, -K2d / H2, 0, 0, 1 / H2],
+        [-K4 / Td0p, 0, -1 / (K3 * Td0p), 0, 1 / Td0p, 0, 0],
+        [K4d / Tq0p, 0, 0, -1 / (K3d * Tq0p), 0, 0, 0],
+        [-KA * K5 / TA, 0, -KA * K6 / TA, -KA * K6d / TA, -1 / TA, 0, 0],
+        [0, -1 / (R * Tg), 0, 0, 0, -1 / Tg, 0],
+        [0, 0, 0, 0, 0, 1 / Tt, -1 / Tt]])
+
+
+@pytest.mark.parametrize("V1,th1,x", [(1.03, 0.25, 0.3), (0.97, -0.4, 0.2), (1.05, 0.6, 0.45)])
+def test_smib_two_axis_avr_governor_heffron_phillips(V1, th1, x):
+    """Machine 1's 7 x 7 block of the oracle's state matrix, entry by entry,
+    against the Heffron-Phillips form above (rotor angle, speed, both
+    transient EMFs, exciter, governor and turbine rows)."""
+    net, Vb, I1, S, Xe, p = _smib_case(V1=V1, th1=th1, x=x)
+    sub = full_subsystem(net)
+    dm = dynamics.DynModel(net, sub, np.abs(Vb), np.angle(Vb), S.real, S.imag)
+    # the equilibrium is one (f = 0, g = 0 at the given point)
+    assert np.max(np.abs(dm.f(dm.x0, dm.y0))) < 1e-12
+    assert np.max(np.abs(dm.g(dm.x0, dm.y0))) < 1e-12
+    A = dm.state_matrix()
+    assert A.shape == (13, 13)
+    blk = A[6:13, 6:13]               # [delta1 - delta0, omega1, Eq1', Ed1', Efd1, Psv1, Pm1]
+    ref = _smib_closed_form(Vb, I1, Xe, p, dm.ws)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(blk - ref)) < 1e-11 * scale, np.abs(blk - ref).max()
+    # eigenvalues of the block are the roots of its characteristic polynomial
+    lam_ref = np.roots(np.poly(ref))
+    from helpers import match_eigs
+    assert match_eigs(eigen.eigvals(blk), lam_ref) < 1e-8
