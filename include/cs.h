@@ -195,6 +195,25 @@ int cs_screen_device(cs_ctx* ctx, cs_net* net, const int32_t* d_outages,
                      int64_t n, const double* d_lambda, const cs_opts* opts,
                      cs_result* d_out, double* d_risk, void* stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): cs_screen_device with the scenario
+ * workspace in a static device array of CS_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on until the process ends, instead of
+ * the context's workspace.  Same arguments, results and validation as
+ * cs_screen_device; as many scenario slots as the array holds (refilled from
+ * the list, so any list length works), further capped by opts->batch and
+ * opts->hbm_budget.  No device or pinned memory is allocated and nothing is
+ * freed.  Errors as cs_screen_device, plus CS_EHBM when one scenario's
+ * workspace exceeds half the array (a network too large for it) and
+ * CS_EINVAL for opts->timing = 1 (timing allocates).  Every call on one GPU
+ * uses that GPU's single array, whatever the context: calls that overlap on
+ * one GPU (other threads, other streams) race and must be serialised by the
+ * caller. */
+#define CS_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int cs_screen_device_noalloc(cs_ctx* ctx, cs_net* net, const int32_t* d_outages,
+                             int64_t n, const double* d_lambda, const cs_opts* opts,
+                             cs_result* d_out, double* d_risk, void* stream);
+
 /* One scenario in full detail, for parity checks.  Host buffers:
  * vm, va [n_bus] (NaN outside the solved island), pg, qg [n_gen] (NaN when
  * out of service), eig_re, eig_im [7 n_gen] with *n_eig set to the number

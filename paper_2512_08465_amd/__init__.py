@@ -101,6 +101,8 @@ def library():
         "cs_screen_detail": (ctypes.c_int, [vp, vp, vp, i64, ctypes.POINTER(Options), vp,
                                             dp, dp, dp, dp, dp, dp, vp]),
         "cs_dyn_at": (ctypes.c_int, [vp, vp, vp, dp, dp, dp, dp, dp, vp, dp, dp]),
+        "cs_screen_device_noalloc": (ctypes.c_int, [vp, vp, vp, i64, dp,
+                                                    ctypes.POINTER(Options), vp, dp, vp]),
         "cs_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(Stats)]),
         "cs_stats_reset": (ctypes.c_int, [vp]),
         "cs_last_error": (ctypes.c_char_p, []),
@@ -125,7 +127,7 @@ EXPORTED = ("cs_ctx_create", "cs_ctx_destroy", "cs_net_create", "cs_net_destroy"
             "cs_dense_solve_batched", "cs_eigvals_batched", "cs_kkt_at", "cs_stats_get",
             "cs_stats_reset", "cs_last_error", "cs_abi_version", "cs_server_create",
             "cs_server_destroy", "cs_submit", "cs_wait", "cs_req_free", "cs_screen_detail",
-            "cs_dyn_at")
+            "cs_dyn_at", "cs_screen_device_noalloc")
 
 
 def _check(rc):
@@ -248,6 +250,15 @@ class Network:
         o = options or default_options()
         _check(library().cs_screen_device(self.ctx.handle, self._h, d_outages, n, d_lambda,
                                           ctypes.byref(o), d_results, d_risk, stream))
+
+    def screen_device_noalloc(self, d_outages, n, d_lambda, d_results, d_risk,
+                              options: Options | None = None, stream=None):
+        """As screen_device, with the workspace in the library's static
+        device scratch array: the call allocates no device memory."""
+        o = options or default_options()
+        _check(library().cs_screen_device_noalloc(self.ctx.handle, self._h, d_outages, n,
+                                                  d_lambda, ctypes.byref(o), d_results, d_risk,
+                                                  stream))
 
     def kkt_at(self, outage, iters: int):
         """KKT system and iterate after ``iters`` Newton steps (parity/debug)."""

@@ -49,6 +49,12 @@ using namespace cs;
 static thread_local std::string g_err;
 static size_t set_kernel_attrs(int device);
 
+// Scenario workspace of cs_screen_device_noalloc: a static device array, one
+// per GPU the library runs on, held until the process ends.  Its address on a
+// device comes from hipGetSymbolAddress at cs_ctx_create (the name itself is
+// a host-side stand-in and is never passed to a kernel).
+static __device__ __align__(256) unsigned char scratch[CS_NOALLOC_SCRATCH_BYTES];
+
 static int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
@@ -80,6 +86,7 @@ struct cs_ctx {
   // kernel timing
   cs_stats stats{};
   size_t lds_max = 64 * 1024;   // dynamic LDS per workgroup this device allows
+  void* scratch = nullptr;      // this device's copy of the static scratch array
 };
 
 // Launch timing: events around each launch on its own stream, resolved when
@@ -211,6 +218,12 @@ int cs_ctx_create(int device, size_t hbm_budget, cs_ctx** out) {
   }
   // kernels whose LDS may exceed the default dynamic limit
   c->lds_max = set_kernel_attrs(device);
+  // the device address of the static scratch array on this device
+  const hipError_t se = hipGetSymbolAddress(&c->scratch, HIP_SYMBOL(scratch));
+  if (se != hipSuccess || c->scratch == nullptr) {
+    cs_ctx_destroy(c);
+    return fail(CS_EDEVICE, std::string("cs_ctx_create: scratch address: ") + hipGetErrorString(se));
+  }
   *out = c;
   return CS_OK;
 }
@@ -447,8 +460,11 @@ static Plan plan_sizes(const cs_net* n, bool mixed) {
   return p;
 }
 
-// carve the slot arrays out of one allocation
-static int bind_workspace(void** ws, size_t* ws_bytes, const cs_net* n, Plan& p, int B) {
+// carve the slot arrays out of one allocation.  With fixed != nullptr the
+// arrays go into that region of fixed_bytes (nothing is allocated; a layout
+// that does not fit fails with CS_EHBM); else into *ws, grown on demand.
+static int bind_workspace(void** ws, size_t* ws_bytes, const cs_net* n, Plan& p, int B,
+                          void* fixed = nullptr, size_t fixed_bytes = 0) {
   Slots& s = p.s;
   const size_t nb = n->nb, nl = n->nl, ng = n->ng;
   const size_t piv = std::max(s.nk, s.ny);
@@ -478,14 +494,23 @@ static int bind_workspace(void** ws, size_t* ws_bytes, const cs_net* n, Plan& p,
   const size_t ost = take(sizeof(SlotState) * (size_t)B);
   const size_t o32 = take(4 * s.k32_stride * B);
   const size_t need = off;
-  if (need > *ws_bytes) {
-    if (*ws) hipFree(*ws);
-    *ws = nullptr;
-    *ws_bytes = 0;
-    if (hipMalloc(ws, need) != hipSuccess) return fail(CS_ENOMEM, "workspace allocation failed");
-    *ws_bytes = need;
+  char* base = nullptr;
+  if (fixed) {
+    if (need > fixed_bytes)
+      return fail(CS_EHBM, "workspace of " + std::to_string(B) + " slots needs " +
+                               std::to_string(need) + " bytes, above the " +
+                               std::to_string(fixed_bytes) + " bytes of the scratch region");
+    base = static_cast<char*>(fixed);
+  } else {
+    if (need > *ws_bytes) {
+      if (*ws) hipFree(*ws);
+      *ws = nullptr;
+      *ws_bytes = 0;
+      if (hipMalloc(ws, need) != hipSuccess) return fail(CS_ENOMEM, "workspace allocation failed");
+      *ws_bytes = need;
+    }
+    base = static_cast<char*>(*ws);
   }
-  char* base = static_cast<char*>(*ws);
   s.B = B;
   s.K = reinterpret_cast<double*>(base + oK);
   s.A = reinterpret_cast<double*>(base + oA);
@@ -715,7 +740,7 @@ static int check_opts(const cs_opts& opts, const char* who) {
 static int run_screen(cs_ctx* c, cs_net* n, const int* d_out_list, long long N,
                       const double* d_lambda, const cs_opts* o, cs_result* d_res,
                       double* d_risk, hipStream_t st, Plan* keep,
-                      const DetailOut* detail = nullptr) {
+                      const DetailOut* detail = nullptr, bool in_scratch = false) {
   cs_opts opts;
   cs_opts_default(&opts);
   if (o) opts = *o;
@@ -731,7 +756,21 @@ static int run_screen(cs_ctx* c, cs_net* n, const int* d_out_list, long long N,
   if (opts.batch > 0) B = std::min<long long>(B, opts.batch);
   B = std::max<long long>(1, std::min<long long>(B, std::max<long long>(N, 1)));
   B = std::min<long long>(B, 1 << 20);
-  rc = bind_workspace(&c->ws, &c->ws_bytes, n, p, (int)B);
+  if (in_scratch) {
+    // as many slots as the static scratch holds (the layout pads each array)
+    if (p.per_slot > CS_NOALLOC_SCRATCH_BYTES / 2)
+      return fail(CS_EHBM, "cs_screen_device_noalloc: one scenario needs " +
+                               std::to_string(p.per_slot) + " bytes of workspace, above half the " +
+                               std::to_string((size_t)CS_NOALLOC_SCRATCH_BYTES) +
+                               "-byte static scratch");
+    B = std::min<long long>(B, (long long)(CS_NOALLOC_SCRATCH_BYTES / p.per_slot) - 1);
+    while (B > 1 && bind_workspace(nullptr, nullptr, n, p, (int)B, c->scratch,
+                                   CS_NOALLOC_SCRATCH_BYTES) != CS_OK)
+      B = B * 15 / 16;
+    rc = bind_workspace(nullptr, nullptr, n, p, (int)B, c->scratch, CS_NOALLOC_SCRATCH_BYTES);
+  } else {
+    rc = bind_workspace(&c->ws, &c->ws_bytes, n, p, (int)B);
+  }
   if (rc != CS_OK) return rc;
   const bool tm = opts.timing != 0;
   if (tm && c->units_cap == 0) {
@@ -855,34 +894,47 @@ extern "C" int cs_screen(cs_ctx* c, cs_net* n, const int32_t* outages, int64_t N
   return rc;
 }
 
-extern "C" int cs_screen_device(cs_ctx* c, cs_net* n, const int32_t* d_outages, int64_t N,
-                                const double* d_lambda, const cs_opts* opts, cs_result* d_out,
-                                double* d_risk, void* stream) {
+static int screen_device(const char* who, cs_ctx* c, cs_net* n, const int32_t* d_outages,
+                         int64_t N, const double* d_lambda, const cs_opts* opts,
+                         cs_result* d_out, double* d_risk, void* stream, bool in_scratch) {
   if (!c || !n || N < 0 || (N > 0 && (!d_outages || !d_out)))
-    return fail(CS_EINVAL, "cs_screen_device: NULL argument or negative n");
-  if (d_risk && !d_lambda) return fail(CS_EINVAL, "cs_screen_device: risk requested without lambda");
+    return fail(CS_EINVAL, std::string(who) + ": NULL argument or negative n");
+  if (d_risk && !d_lambda) return fail(CS_EINVAL, std::string(who) + ": risk requested without lambda");
+  if (in_scratch && opts && opts->timing)
+    return fail(CS_EINVAL, std::string(who) + ": kernel timing is not available (it allocates)");
   HIPCHK(hipSetDevice(c->device));
   hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
   const int n_comp = n->nl + n->ng + n->nd;
-  // validate the list and the rates on the device
+  // validate the list (bit 1) and the rates (bit 2) on the device
   HIPCHK(hipMemsetAsync(c->d_counter, 0, sizeof(int), st));
   launch_validate(d_outages, N, n_comp, c->d_counter, st);
+  if (d_lambda) launch_validate_rates(d_lambda, n_comp, c->d_counter, st);
   HIPCHK(hipMemcpyAsync(c->h_counter, c->d_counter, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  if (*c->h_counter) return fail(CS_EINVAL, "cs_screen_device: invalid outage row in the list");
-  if (d_lambda) {
-    std::vector<double> lam(n_comp);
-    HIPCHK(hipMemcpy(lam.data(), d_lambda, sizeof(double) * n_comp, hipMemcpyDeviceToHost));
-    for (int i = 0; i < n_comp; ++i)
-      if (!(lam[i] >= 0) || !std::isfinite(lam[i]))
-        return fail(CS_EINVAL, "failure rate " + std::to_string(i) + " must be finite and >= 0");
-  }
+  if (*c->h_counter & 1) return fail(CS_EINVAL, std::string(who) + ": invalid outage row in the list");
+  if (*c->h_counter & 2)
+    return fail(CS_EINVAL, std::string(who) + ": every failure rate must be finite and >= 0");
   if (N == 0) {
     if (d_risk) HIPCHK(hipMemsetAsync(d_risk, 0, sizeof(double) * n_comp, st));
     HIPCHK(hipStreamSynchronize(st));
     return CS_OK;
   }
-  return run_screen(c, n, d_outages, N, d_lambda, opts, d_out, d_risk, st, nullptr);
+  return run_screen(c, n, d_outages, N, d_lambda, opts, d_out, d_risk, st, nullptr, nullptr,
+                    in_scratch);
+}
+
+extern "C" int cs_screen_device(cs_ctx* c, cs_net* n, const int32_t* d_outages, int64_t N,
+                                const double* d_lambda, const cs_opts* opts, cs_result* d_out,
+                                double* d_risk, void* stream) {
+  return screen_device("cs_screen_device", c, n, d_outages, N, d_lambda, opts, d_out, d_risk,
+                       stream, false);
+}
+
+extern "C" int cs_screen_device_noalloc(cs_ctx* c, cs_net* n, const int32_t* d_outages,
+                                        int64_t N, const double* d_lambda, const cs_opts* opts,
+                                        cs_result* d_out, double* d_risk, void* stream) {
+  return screen_device("cs_screen_device_noalloc", c, n, d_outages, N, d_lambda, opts, d_out,
+                       d_risk, stream, true);
 }
 
 // ------------------------------------------------------------------ serving

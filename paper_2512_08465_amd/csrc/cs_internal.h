@@ -142,6 +142,8 @@ void launch_risk(const int* outages, long long n, const uint8_t* severe_src,
                  hipStream_t st);
 void launch_validate(const int* outages, long long n, int n_comp, int* bad,
                      hipStream_t st);
+// sets bit 2 of *bad when a failure rate is negative or not finite
+void launch_validate_rates(const double* lam, int n_comp, int* bad, hipStream_t st);
 // mixed-precision KKT solve
 void launch_kkt_to_f32(const Slots& s, int count, hipStream_t st);
 void launch_kkt_refine(const Slots& s, int count, int pstride, int max_it, hipStream_t st);

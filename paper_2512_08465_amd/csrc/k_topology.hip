@@ -143,4 +143,20 @@ void launch_validate(const int* outages, long long n, int n_comp, int* bad,
                      outages, n, n_comp, bad);
 }
 
+// failure-rate check: finite and >= 0 (eq. (1)-(2) take them as frequencies)
+__global__ void k_validate_rates(const double* __restrict__ lam, int n,
+                                 int* __restrict__ bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = lam[i];
+  if (!(v >= 0.0) || !__builtin_isfinite(v)) atomicOr(bad, 2);
+}
+
+void launch_validate_rates(const double* lam, int n_comp, int* bad, hipStream_t st) {
+  if (n_comp <= 0) return;
+  const int threads = 256;
+  hipLaunchKernelGGL(k_validate_rates, dim3((n_comp + threads - 1) / threads), dim3(threads), 0,
+                     st, lam, n_comp, bad);
+}
+
 }  // namespace cs
