@@ -116,6 +116,9 @@ def main():
     ap.add_argument("--serve-max-len", type=int, default=5000,
                     help="request lengths are log-uniform integers in [1, this]")
     ap.add_argument("--serve-legs", default="fp64,mixed")
+    ap.add_argument("--pmc-copy", action="store_true",
+                    help="begin with a device copy of known size (the scale of the HBM "
+                         "counters in a counter pass over this run)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run only a copy of known size and a batch of order-580 LUs "
                          "(for hardware-counter passes), then exit")
@@ -151,6 +154,14 @@ def main():
 
     ctx = cs.Context(0)
     log("device context ready")
+    if args.pmc_copy:
+        src = torch.ones(PMC_COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"pmc copy of {PMC_COPY_BYTES} bytes done")
     net = cs.Network(ctx, case)
     log(f"network resident; {n_all} scenarios, {step} per timed step")
     dev = torch.device("cuda:0")
@@ -323,13 +334,15 @@ def deviation(res, g):
 
 
 # HBM traffic of the FP64 KKT LU from two rocprofv3 counter passes over
-# `python bench.py --pmc-probe` (profiles/k_lu_solve_hbm_traffic_580.md):
-# FETCH_SIZE and WRITE_SIZE of the 512-system dispatch, each scaled by what the
-# same counter reads for the probe's 1 GiB device copy.  Valid only for the
-# kernel source it was measured on (hash below); otherwise traffic is null.
-LU_TRAFFIC = dict(source_sha256_16="0b5c9e997d5711ec", batch=512,
-                  fetch_kib=6945079.8125, write_kib=6693568.03125,
-                  copy_fetch_kib=524308.8125, copy_write_kib=1048576.0,
+# `python bench.py --warmup 0 --no-cpu-baseline --serve-requests 0 --pmc-copy
+# --legs fp64` (profiles/k_lu_solve_hbm_traffic_c2_118.md): FETCH_SIZE and
+# WRITE_SIZE summed over the run's KKT LU dispatches, each scaled by what the
+# same counter reads for the run's 1 GiB device copy, divided by the
+# factorisations those dispatches performed.  Valid only for the kernel source
+# it was measured on (hash below); otherwise traffic is null.
+LU_TRAFFIC = dict(source_sha256_16="b94ad6cbe92548d0", factorisations=2217483,
+                  fetch_kib=27399876139.875, write_kib=24583685875.6875,
+                  copy_fetch_kib=524307.5625, copy_write_kib=1048576.0,
                   copy_bytes=1 << 30)
 
 
@@ -343,7 +356,7 @@ def lu_traffic_per_factorisation():
     kib = t["copy_bytes"] / 1024.0
     fetch = t["fetch_kib"] * kib / t["copy_fetch_kib"]
     write = t["write_kib"] * kib / t["copy_write_kib"]
-    return (fetch + write) * 1024.0 / t["batch"]
+    return (fetch + write) * 1024.0 / t["factorisations"]
 
 
 PMC_COPY_BYTES = 1 << 30
