@@ -283,6 +283,54 @@ int cs_dyn_at(cs_ctx* ctx, cs_net* net, const int32_t outage[2], const double* v
               const double* va, const double* pg, const double* qg, double* A,
               int32_t* n_states, double* eig_re, double* eig_im);
 
+/* Risk Index variants over a screened list (Section II.C, eq. (1)-(3), with
+ * the extensions Section V.C lists as future work).
+ *   severity = CS_SEV_BINARY: S_c is the record's binary severity (eq. (3)).
+ *   severity = CS_SEV_DAMPING: non-binary severity from the damping ratio:
+ *     a scenario severe by any criterion keeps S_c = 1; a secure one gets
+ *     S_c = clip((zeta_ref - min_damping) / zeta_ref, 0, 1).
+ *   Common-cause failures: each tagged pair (i, j) adds its common-cause
+ *     frequency to the N-2 frequency, F_ij = lambda_i lambda_j + rate(i, j)
+ *     (both orders of the pair; a pair tagged twice adds both rates). */
+enum { CS_SEV_BINARY = 0, CS_SEV_DAMPING = 1 };
+typedef struct {
+  int32_t severity;          /* CS_SEV_BINARY (default) or CS_SEV_DAMPING       */
+  double zeta_ref;           /* CS_SEV_DAMPING: damping ratio at which a secure
+                                scenario's severity reaches 0 (default 0.05, > 0) */
+  int64_t n_cc;              /* common-cause pairs (default 0)                  */
+  const int32_t* cc_pairs;   /* host [n_cc][2]: distinct valid component ids    */
+  const double* cc_rate;     /* host [n_cc]: frequency of the common cause, 1/yr,
+                                finite and >= 0                                 */
+} cs_risk_opts;
+void cs_risk_opts_default(cs_risk_opts* ropts);
+
+/* R_i over a screened list from its records, with the severity and
+ * common-cause options above (ropts NULL = binary, independent: the R_i of
+ * cs_screen).  Device buffers: d_outages [n][2] and d_records [n] as given
+ * to and returned by cs_screen_device, d_lambda [n_comp], d_risk [n_comp]
+ * out; stream as cs_screen_device.  Sums run in list order (identical run to
+ * run).  Errors: CS_EINVAL (bad row, rate or option), CS_ENOMEM, CS_EDEVICE. */
+int cs_risk(cs_ctx* ctx, cs_net* net, const int32_t* d_outages, int64_t n,
+            const cs_result* d_records, const double* d_lambda,
+            const cs_risk_opts* ropts, double* d_risk, void* stream);
+
+/* Monte-Carlo over the failure rates (Section V.C, uncertainty analysis):
+ * R_i for each of n_samples rate vectors d_lambda_samples [n_samples][n_comp]
+ * (device, drawn by the caller; finite and >= 0), as
+ * R(lambda) = lambda o (S1 + S2 lambda) + C with the list's severities folded
+ * into S1 (N-1), the symmetric S2 (N-2) and C (common-cause terms), the
+ * product over all samples on the FP64 matrix cores.  Outputs (device, each
+ * may be NULL): d_risk [n_samples][n_comp]; d_moments [n_comp][2] mean and
+ * sample standard deviation of R_i; d_rank_q [n_comp][3] the 5%, 50% and 95%
+ * quantiles of the component's rank over the samples (rank 0 = the largest
+ * R; equal R ranked by component id; quantile q = the smallest rank whose
+ * cumulative count reaches ceil(q n_samples / 100)).  n_comp <= 16384.
+ * Errors as cs_risk. */
+int cs_risk_mc(cs_ctx* ctx, cs_net* net, const int32_t* d_outages, int64_t n,
+               const cs_result* d_records, const double* d_lambda_samples,
+               int64_t n_samples, const cs_risk_opts* ropts, double* d_risk,
+               double* d_moments, int32_t* d_rank_q, void* stream);
+
 /* Serving (continuous batching).  A server owns B scenario slots of one
  * network and a host thread that runs them; requests (each an outage list
  * with its own failure rates) are admitted into a device ring of

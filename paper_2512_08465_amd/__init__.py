@@ -48,6 +48,15 @@ class _NetDesc(ctypes.Structure):
                    "load_bus", "pd", "qd")]
 
 
+class RiskOptions(ctypes.Structure):
+    _fields_ = [("severity", ctypes.c_int32), ("zeta_ref", ctypes.c_double),
+                ("n_cc", ctypes.c_int64), ("cc_pairs", ctypes.c_void_p),
+                ("cc_rate", ctypes.c_void_p)]
+
+
+SEV_BINARY, SEV_DAMPING = 0, 1
+
+
 class Options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("max_it", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("near_eps", ctypes.c_double),
@@ -103,6 +112,11 @@ def library():
         "cs_dyn_at": (ctypes.c_int, [vp, vp, vp, dp, dp, dp, dp, dp, vp, dp, dp]),
         "cs_screen_device_noalloc": (ctypes.c_int, [vp, vp, vp, i64, dp,
                                                     ctypes.POINTER(Options), vp, dp, vp]),
+        "cs_risk_opts_default": (None, [ctypes.POINTER(RiskOptions)]),
+        "cs_risk": (ctypes.c_int, [vp, vp, vp, i64, vp, dp, ctypes.POINTER(RiskOptions), dp,
+                                   vp]),
+        "cs_risk_mc": (ctypes.c_int, [vp, vp, vp, i64, vp, dp, i64, ctypes.POINTER(RiskOptions),
+                                      dp, dp, vp, vp]),
         "cs_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(Stats)]),
         "cs_stats_reset": (ctypes.c_int, [vp]),
         "cs_last_error": (ctypes.c_char_p, []),
@@ -127,7 +141,8 @@ EXPORTED = ("cs_ctx_create", "cs_ctx_destroy", "cs_net_create", "cs_net_destroy"
             "cs_dense_solve_batched", "cs_eigvals_batched", "cs_kkt_at", "cs_stats_get",
             "cs_stats_reset", "cs_last_error", "cs_abi_version", "cs_server_create",
             "cs_server_destroy", "cs_submit", "cs_wait", "cs_req_free", "cs_screen_detail",
-            "cs_dyn_at", "cs_screen_device_noalloc")
+            "cs_dyn_at", "cs_screen_device_noalloc", "cs_risk_opts_default", "cs_risk",
+            "cs_risk_mc")
 
 
 def _check(rc):
@@ -259,6 +274,40 @@ class Network:
         _check(library().cs_screen_device_noalloc(self.ctx.handle, self._h, d_outages, n,
                                                   d_lambda, ctypes.byref(o), d_results, d_risk,
                                                   stream))
+
+    @staticmethod
+    def _risk_opts(severity, zeta_ref, cc_pairs, cc_rate):
+        r = RiskOptions()
+        library().cs_risk_opts_default(ctypes.byref(r))
+        r.severity = severity
+        if zeta_ref is not None:
+            r.zeta_ref = zeta_ref
+        keep = []
+        if cc_pairs is not None and len(cc_pairs):
+            p = np.ascontiguousarray(cc_pairs, dtype=np.int32).reshape(-1, 2)
+            q = np.ascontiguousarray(cc_rate, dtype=np.float64).reshape(-1)
+            keep = [p, q]
+            r.n_cc, r.cc_pairs, r.cc_rate = len(p), p.ctypes.data, q.ctypes.data
+        return r, keep
+
+    def risk(self, d_outages, n, d_records, d_lambda, d_risk, severity=SEV_BINARY,
+             zeta_ref=None, cc_pairs=None, cc_rate=None, stream=None):
+        """R_i from screened records (device pointers), with the non-binary
+        severity and common-cause options."""
+        r, keep = self._risk_opts(severity, zeta_ref, cc_pairs, cc_rate)
+        _check(library().cs_risk(self.ctx.handle, self._h, d_outages, n, d_records, d_lambda,
+                                 ctypes.byref(r), d_risk, stream))
+        del keep
+
+    def risk_mc(self, d_outages, n, d_records, d_samples, n_samples, d_risk=None,
+                d_moments=None, d_rank_q=None, severity=SEV_BINARY, zeta_ref=None,
+                cc_pairs=None, cc_rate=None, stream=None):
+        """Monte-Carlo over sampled failure rates (device pointers)."""
+        r, keep = self._risk_opts(severity, zeta_ref, cc_pairs, cc_rate)
+        _check(library().cs_risk_mc(self.ctx.handle, self._h, d_outages, n, d_records,
+                                    d_samples, n_samples, ctypes.byref(r), d_risk, d_moments,
+                                    d_rank_q, stream))
+        del keep
 
     def kkt_at(self, outage, iters: int):
         """KKT system and iterate after ``iters`` Newton steps (parity/debug)."""

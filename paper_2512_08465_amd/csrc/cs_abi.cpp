@@ -1595,3 +1595,135 @@ extern "C" int cs_dyn_at(cs_ctx* c, cs_net* n, const int32_t outage[2], const do
   }
   return CS_OK;
 }
+
+// ------------------------------------------------------------- risk variants
+extern "C" void cs_risk_opts_default(cs_risk_opts* r) {
+  if (!r) return;
+  r->severity = CS_SEV_BINARY;
+  r->zeta_ref = 0.05;
+  r->n_cc = 0;
+  r->cc_pairs = nullptr;
+  r->cc_rate = nullptr;
+}
+
+// Device temporaries of one risk call, freed on every exit path.
+struct RiskTemps {
+  std::vector<void*> p;
+  ~RiskTemps() {
+    for (void* q : p) hipFree(q);
+  }
+  template <class T>
+  T* take(size_t count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess) return nullptr;
+    p.push_back(q);
+    return static_cast<T*>(q);
+  }
+};
+
+// Validate the list (and, when given, n_vals rate values) on the device,
+// check the options on the host, and build the per-scenario severity
+// weights and the common-cause table.
+static int risk_prepare(const char* who, cs_ctx* c, cs_net* n, const int32_t* d_outages,
+                        int64_t N, const cs_result* d_records, const double* d_vals,
+                        long long n_vals, const cs_risk_opts* ro, hipStream_t st, RiskTemps& T,
+                        double** w, double** cc) {
+  const int n_comp = n->nl + n->ng + n->nd;
+  cs_risk_opts r;
+  cs_risk_opts_default(&r);
+  if (ro) r = *ro;
+  if (r.severity != CS_SEV_BINARY && r.severity != CS_SEV_DAMPING)
+    return fail(CS_EINVAL, std::string(who) + ": severity must be CS_SEV_BINARY or CS_SEV_DAMPING");
+  if (!(r.zeta_ref > 0) || !std::isfinite(r.zeta_ref))
+    return fail(CS_EINVAL, std::string(who) + ": zeta_ref must be finite and > 0");
+  if (r.n_cc < 0 || (r.n_cc > 0 && (!r.cc_pairs || !r.cc_rate)))
+    return fail(CS_EINVAL, std::string(who) + ": common-cause pairs need cc_pairs and cc_rate");
+  for (int64_t k = 0; k < r.n_cc; ++k) {
+    const int a = r.cc_pairs[2 * k], b = r.cc_pairs[2 * k + 1];
+    if (a < 0 || a >= n_comp || b < 0 || b >= n_comp || a == b)
+      return fail(CS_EINVAL, std::string(who) + ": common-cause pair " + std::to_string(k) +
+                                 " needs two distinct valid component ids");
+    if (!(r.cc_rate[k] >= 0) || !std::isfinite(r.cc_rate[k]))
+      return fail(CS_EINVAL, std::string(who) + ": common-cause rate " + std::to_string(k) +
+                                 " must be finite and >= 0");
+  }
+  HIPCHK(hipMemsetAsync(c->d_counter, 0, sizeof(int), st));
+  launch_validate(d_outages, N, n_comp, c->d_counter, st);
+  if (d_vals) launch_validate_values(d_vals, n_vals, c->d_counter, st);
+  HIPCHK(hipMemcpyAsync(c->h_counter, c->d_counter, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (*c->h_counter & 1) return fail(CS_EINVAL, std::string(who) + ": invalid outage row in the list");
+  if (*c->h_counter & 2)
+    return fail(CS_EINVAL, std::string(who) + ": every failure rate must be finite and >= 0");
+  *w = T.take<double>(N);
+  if (!*w) return fail(CS_ENOMEM, std::string(who) + ": device allocation failed");
+  launch_sev_weights(d_records, N, r.severity, r.zeta_ref, *w, st);
+  *cc = nullptr;
+  if (r.n_cc > 0) {
+    double* tab = T.take<double>((size_t)n_comp * n_comp);
+    int* dp = T.take<int>(2 * (size_t)r.n_cc);
+    double* dr = T.take<double>((size_t)r.n_cc);
+    if (!tab || !dp || !dr) return fail(CS_ENOMEM, std::string(who) + ": device allocation failed");
+    HIPCHK(hipMemsetAsync(tab, 0, sizeof(double) * (size_t)n_comp * n_comp, st));
+    HIPCHK(hipMemcpyAsync(dp, r.cc_pairs, sizeof(int) * 2 * r.n_cc, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dr, r.cc_rate, sizeof(double) * r.n_cc, hipMemcpyHostToDevice, st));
+    launch_cc_table(dp, dr, r.n_cc, n_comp, tab, st);
+    *cc = tab;
+  }
+  return CS_OK;
+}
+
+extern "C" int cs_risk(cs_ctx* c, cs_net* n, const int32_t* d_outages, int64_t N,
+                       const cs_result* d_records, const double* d_lambda,
+                       const cs_risk_opts* ro, double* d_risk, void* stream) {
+  if (!c || !n || N < 0 || !d_lambda || !d_risk || (N > 0 && (!d_outages || !d_records)))
+    return fail(CS_EINVAL, "cs_risk: NULL argument or negative n");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  const int n_comp = n->nl + n->ng + n->nd;
+  RiskTemps T;
+  double *w = nullptr, *cc = nullptr;
+  int rc = risk_prepare("cs_risk", c, n, d_outages, N, d_records, d_lambda, n_comp, ro, st, T,
+                        &w, &cc);
+  if (rc != CS_OK) return rc;
+  launch_risk_weighted(d_outages, N, w, d_lambda, cc, n_comp, d_risk, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return CS_OK;
+}
+
+extern "C" int cs_risk_mc(cs_ctx* c, cs_net* n, const int32_t* d_outages, int64_t N,
+                          const cs_result* d_records, const double* d_samples, int64_t M,
+                          const cs_risk_opts* ro, double* d_risk, double* d_moments,
+                          int32_t* d_rank_q, void* stream) {
+  if (!c || !n || N < 0 || M <= 0 || !d_samples || (N > 0 && (!d_outages || !d_records)))
+    return fail(CS_EINVAL, "cs_risk_mc: NULL argument, negative n or no samples");
+  const int n_comp = n->nl + n->ng + n->nd;
+  if (n_comp > 16384) return fail(CS_EUNSUPPORTED, "cs_risk_mc: more than 16384 components");
+  if (M > (1ll << 24)) return fail(CS_EINVAL, "cs_risk_mc: more than 2^24 samples");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  RiskTemps T;
+  double *w = nullptr, *cc = nullptr;
+  int rc = risk_prepare("cs_risk_mc", c, n, d_outages, N, d_records, d_samples,
+                        (long long)M * n_comp, ro, st, T, &w, &cc);
+  if (rc != CS_OK) return rc;
+  double* S1 = T.take<double>(n_comp);
+  double* S2 = T.take<double>((size_t)n_comp * n_comp);
+  double* C = T.take<double>(n_comp);
+  double* R = d_risk ? d_risk : T.take<double>((size_t)M * n_comp);
+  int* hist = d_rank_q ? T.take<int>((size_t)n_comp * n_comp) : nullptr;
+  if (!S1 || !S2 || !C || !R || (d_rank_q && !hist))
+    return fail(CS_ENOMEM, "cs_risk_mc: device allocation failed");
+  HIPCHK(hipMemsetAsync(S2, 0, sizeof(double) * (size_t)n_comp * n_comp, st));
+  launch_risk_split(d_outages, N, w, cc, n_comp, n_comp, S1, S2, C, st);
+  launch_risk_mc_gemm(d_samples, M, n_comp, S1, S2, n_comp, C, R, st);
+  if (hist) {
+    HIPCHK(hipMemsetAsync(hist, 0, sizeof(int) * (size_t)n_comp * n_comp, st));
+    launch_rank_hist(R, M, n_comp, hist, st);
+  }
+  if (d_moments || d_rank_q) launch_risk_summary(R, M, n_comp, hist, d_moments, d_rank_q, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return CS_OK;
+}

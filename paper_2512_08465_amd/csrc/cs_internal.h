@@ -144,6 +144,23 @@ void launch_validate(const int* outages, long long n, int n_comp, int* bad,
                      hipStream_t st);
 // sets bit 2 of *bad when a failure rate is negative or not finite
 void launch_validate_rates(const double* lam, int n_comp, int* bad, hipStream_t st);
+// Risk Index extensions (k_risk.hip)
+void launch_sev_weights(const void* rec, long long n, int mode, double zeta_ref, double* w,
+                        hipStream_t st);
+void launch_cc_table(const int* pairs, const double* rate, long long n_cc, int n_comp, double* T,
+                     hipStream_t st);
+void launch_risk_weighted(const int* outages, long long n, const double* w, const double* lam,
+                          const double* cc, int n_comp, double* risk, hipStream_t st);
+void launch_risk_split(const int* outages, long long n, const double* w, const double* cc,
+                       int n_comp, int ld, double* S1, double* S2, double* C, hipStream_t st);
+void launch_risk_mc_gemm(const double* L, long long M, int n, const double* S1, const double* S2,
+                         int ld, const double* C, double* R, hipStream_t st);
+void launch_rank_hist(const double* R, long long M, int n, int* hist, hipStream_t st);
+void launch_risk_summary(const double* R, long long M, int n, const int* hist, double* moments,
+                         int* rank_q, hipStream_t st);
+// sets bit 2 of *bad when one of n values is negative or not finite
+void launch_validate_values(const double* v, long long n, int* bad, hipStream_t st);
+
 // mixed-precision KKT solve
 void launch_kkt_to_f32(const Slots& s, int count, hipStream_t st);
 void launch_kkt_refine(const Slots& s, int count, int pstride, int max_it, hipStream_t st);

@@ -144,19 +144,23 @@ void launch_validate(const int* outages, long long n, int n_comp, int* bad,
 }
 
 // failure-rate check: finite and >= 0 (eq. (1)-(2) take them as frequencies)
-__global__ void k_validate_rates(const double* __restrict__ lam, int n,
+__global__ void k_validate_rates(const double* __restrict__ lam, long long n,
                                  int* __restrict__ bad) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double v = lam[i];
   if (!(v >= 0.0) || !__builtin_isfinite(v)) atomicOr(bad, 2);
 }
 
-void launch_validate_rates(const double* lam, int n_comp, int* bad, hipStream_t st) {
-  if (n_comp <= 0) return;
+void launch_validate_values(const double* v, long long n, int* bad, hipStream_t st) {
+  if (n <= 0) return;
   const int threads = 256;
-  hipLaunchKernelGGL(k_validate_rates, dim3((n_comp + threads - 1) / threads), dim3(threads), 0,
-                     st, lam, n_comp, bad);
+  hipLaunchKernelGGL(k_validate_rates, dim3((unsigned)((n + threads - 1) / threads)),
+                     dim3(threads), 0, st, v, n, bad);
+}
+
+void launch_validate_rates(const double* lam, int n_comp, int* bad, hipStream_t st) {
+  launch_validate_values(lam, n_comp, bad, st);
 }
 
 }  // namespace cs

@@ -81,3 +81,94 @@ def test_base_case_row_adds_no_risk():
     R0 = risk.risk_index(lst[:2], np.array([1, 1]), lam, 3)
     assert np.array_equal(R1, R0)
     assert risk.scenario_frequency(lst, lam)[2] == 0.0
+
+
+# --- extensions: non-binary severity, common cause, Monte-Carlo on lambda ---
+
+def test_damping_severity_values():
+    from oracle.risk import severity_weights, SEV_DAMPING, SEV_BINARY
+    severe = np.array([1, 0, 0, 0, 0, 0, 0, 1])
+    zeta = np.array([0.3, 0.0, 0.05, 0.025, 0.2, np.nan, 0.0125, np.nan])
+    w = severity_weights(severe, zeta, SEV_DAMPING, zeta_ref=0.05)
+    assert np.allclose(w, [1.0, 1.0, 0.0, 0.5, 0.0, 0.0, 0.75, 1.0], rtol=1e-15, atol=1e-15)
+    assert severity_weights(severe, zeta, SEV_BINARY).tolist() == severe.tolist()
+    # another reference damping
+    assert severity_weights([0], [0.05], SEV_DAMPING, zeta_ref=0.1)[0] == 0.5
+
+
+def _all_severe(n=12, seed=0):
+    rng = np.random.default_rng(seed)
+    lam = rng.uniform(0.001, 0.1, n)
+    lst = contingencies.n1_n2(np.arange(n))
+    return lam, lst
+
+
+def test_weighted_risk_closed_form_all_severe():
+    """Every N-1 and unordered N-2 scenario severe: R_k = lam_k (1 + Lambda -
+    lam_k); a tagged common-cause pair adds its rate to both members; a
+    half-weight severity halves everything."""
+    lam, lst = _all_severe()
+    n = len(lam)
+    L = lam.sum()
+    ones = np.ones(len(lst))
+    R = risk.risk_index_weighted(lst, ones, lam, n)
+    assert np.allclose(R, lam * (1 + L - lam), rtol=1e-14)
+    cc = risk.common_cause_table([[2, 5], [5, 7], [2, 5]], [0.01, 0.003, 0.002], n)
+    Rc = risk.risk_index_weighted(lst, ones, lam, n, cc)
+    extra = np.zeros(n)
+    extra[[2, 5]] += 0.012
+    extra[[5, 7]] += 0.003
+    assert np.allclose(Rc, lam * (1 + L - lam) + extra, rtol=1e-14)
+    assert np.allclose(risk.risk_index_weighted(lst, 0.5 * ones, lam, n), 0.5 * R, rtol=1e-15)
+
+
+def test_monte_carlo_closed_form_ranks():
+    """All scenarios severe: R_k = lam_k (1 + Lambda - lam_k) is increasing in
+    lam_k (every rate is below (1 + Lambda) / 2), so in every sample the rank
+    order of R is that of the sampled rates."""
+    from inputs.rate_samples import lognormal_rates
+    lam, lst = _all_severe(10, 3)
+    n = len(lam)
+    S = lognormal_rates(lam, 40, seed=9)
+    R, mean, std, hist, quant = risk.risk_monte_carlo(lst, np.ones(len(lst)), S, n)
+    L = S.sum(axis=1, keepdims=True)
+    assert np.allclose(R, S * (1 + L - S), rtol=1e-13)
+    assert np.allclose(mean, (S * (1 + L - S)).mean(axis=0), rtol=1e-13)
+    assert np.allclose(std, (S * (1 + L - S)).std(axis=0, ddof=1), rtol=1e-12)
+    want = np.zeros((n, n), np.int64)
+    for m in range(len(S)):
+        order = np.argsort(-S[m], kind="stable")
+        want[order, np.arange(n)] += 1
+    assert np.array_equal(hist, want)
+    assert np.all(hist.sum(axis=1) == len(S)) and np.all(hist.sum(axis=0) == len(S))
+
+
+def test_monte_carlo_one_sample_is_eq3():
+    lam, lst = _all_severe(9, 5)
+    rng = np.random.default_rng(1)
+    severe = rng.integers(0, 2, len(lst))
+    R, *_ = risk.risk_monte_carlo(lst, severe.astype(float), lam[None, :], len(lam))
+    ref = np.zeros(len(lam))
+    for (i, j), s in zip(lst, severe):       # eq. (3) written out
+        if s:
+            f = lam[i] if j < 0 else lam[i] * lam[j]
+            ref[i] += f
+            if j >= 0:
+                ref[j] += f
+    assert np.allclose(R[0], ref, rtol=1e-14)
+
+
+def test_rank_quantile_definition():
+    """20 samples with ranks 0 (once), 1 (9 times), 2 (10 times): the 5%
+    quantile needs 1 sample (rank 0), the median 10 (rank 1), the 95% 19
+    (rank 2)."""
+    n = 3
+    lst = np.array([[0, -1], [1, -1], [2, -1]])
+    # component 0's rank set through its rate relative to the others
+    S = []
+    for r in [0] + [1] * 9 + [2] * 10:
+        v = {0: [0.9, 0.5, 0.1], 1: [0.5, 0.9, 0.1], 2: [0.1, 0.5, 0.9]}[r]
+        S.append(v)
+    _, _, _, hist, quant = risk.risk_monte_carlo(lst, np.ones(3), np.array(S), n)
+    assert hist[0].tolist() == [1, 9, 10]
+    assert quant[0].tolist() == [0, 1, 2]
