@@ -70,7 +70,9 @@ enum {
   CS_CAUSE_OPF = 2,         /* OPF not converged (or not solvable)            */
   CS_CAUSE_LIMIT = 4,       /* converged OPF violates a limit by > 1e-6 p.u.  */
   CS_CAUSE_SSS = 8,         /* an eigenvalue with Re >= 0                     */
-  CS_CAUSE_NUMERICAL = 16   /* singular/non-finite KKT, divergence, QR failure */
+  CS_CAUSE_NUMERICAL = 16,  /* singular/non-finite KKT, divergence, QR failure */
+  CS_CAUSE_PRUNED = 32      /* N-3 row taken as severe because a screened
+                               sub-scenario is severe (cs_screen_n3_device) */
 };
 
 /* cs_result.opf_status */
@@ -282,6 +284,36 @@ int cs_screen_detail(cs_ctx* ctx, cs_net* net, const int32_t* outages, int64_t n
 int cs_dyn_at(cs_ctx* ctx, cs_net* net, const int32_t outage[2], const double* vm,
               const double* va, const double* pg, const double* qg, double* A,
               int32_t* n_states, double* eig_re, double* eig_im);
+
+/* Higher-order contingencies (Section VI, N-k with k > 2).  Rows of three
+ * ids: (i, j, k) outages three components, (i, j, -1) and (i, -1, -1) are
+ * N-2 and N-1 rows, (-1, -1, -1) the base case; ids distinct, -1 only as
+ * trailing padding.  Each row is screened exactly as by cs_screen_device
+ * (Section II.B criteria on the main island); R_i adds F = lambda_i
+ * lambda_j lambda_k for every severe triple containing i (independent
+ * failures, as eq. (2)).  Arguments, validation and errors as
+ * cs_screen_device with d_outages [n][3]. */
+int cs_screen3_device(cs_ctx* ctx, cs_net* net, const int32_t* d_outages, int64_t n,
+                      const double* d_lambda, const cs_opts* opts, cs_result* d_out,
+                      double* d_risk, void* stream);
+
+/* N-3 screening with pruning (Section V.C: reduce the search space before
+ * the full AC evaluation).  A row of d_rows [n][3] is pruned, taken as severe
+ * without being solved, when one of its singles or pairs is severe in an
+ * already screened N-1/N-2 list (d_sub [n_sub][2] with its records
+ * d_sub_rec): more outaged elements are read as never making a severe
+ * contingency secure (exact for islanding by branches, the screening
+ * assumption for the OPF and stability criteria).  Sub-scenarios absent from
+ * the screened list prune nothing.  The other rows are screened as by
+ * cs_screen3_device.  d_out [n] records in list order; a pruned row's record
+ * has severe 1, cause CS_CAUSE_PRUNED, opf_status CS_OPF_NOT_RUN, n_islands
+ * 0 and NaN values.  *n_solved (host, may be NULL) = rows solved.  d_risk
+ * [n_comp] (may be NULL) sums F_c S_c over all rows, pruned ones included.
+ * Errors as cs_screen3_device. */
+int cs_screen_n3_device(cs_ctx* ctx, cs_net* net, const int32_t* d_rows, int64_t n,
+                        const int32_t* d_sub, int64_t n_sub, const cs_result* d_sub_rec,
+                        const double* d_lambda, const cs_opts* opts, cs_result* d_out,
+                        double* d_risk, int64_t* n_solved, void* stream);
 
 /* Risk Index variants over a screened list (Section II.C, eq. (1)-(3), with
  * the extensions Section V.C lists as future work).

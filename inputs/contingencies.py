@@ -30,6 +30,21 @@ def n1_n2(components, ordered: bool = False) -> np.ndarray:
     return np.concatenate([n1, pairs.astype(np.int32)], axis=0)
 
 
+def n3(components) -> np.ndarray:
+    """Every unordered triple of ``components`` (rows of three ids, a before
+    b before c in ``components`` order, lexicographic)."""
+    c = np.asarray(components, dtype=np.int32)
+    m = len(c)
+    if m < 3:
+        return np.zeros((0, 3), np.int32)
+    out = []
+    for a in range(m - 2):
+        for b in range(a + 1, m - 1):
+            k = np.arange(b + 1, m)
+            out.append(np.stack([np.full(len(k), c[a]), np.full(len(k), c[b]), c[k]], axis=1))
+    return np.concatenate(out).astype(np.int32)
+
+
 def random_list(components, n: int, seed: int, p_n1: float = 0.1) -> np.ndarray:
     """``n`` random outages: N-1 with probability ``p_n1``, else a uniform
     random distinct pair."""

@@ -20,14 +20,20 @@ def failure_rate_from_mttf(mttf_years):
 
 
 def scenario_frequency(outages, lam):
-    """F_c for every row of the outage list (eq. 1 and eq. 2)."""
+    """F_c for every row of the outage list: the product of the outaged
+    components' rates (eq. 1 for N-1, eq. 2 for N-2, and the same
+    independence for rows of three); -1 entries pad a row."""
     out = np.asarray(outages)
     F = np.empty(len(out))
-    for c, (i, j) in enumerate(out):
-        if i < 0:
-            F[c] = 0.0              # the base case (-1, -1): nothing fails
-        else:
-            F[c] = lam[i] if j < 0 else lam[i] * lam[j]
+    for c, row in enumerate(out):
+        ids = [int(v) for v in row if v >= 0]
+        if not ids:
+            F[c] = 0.0              # the base case: nothing fails
+            continue
+        f = lam[ids[0]]
+        for k in ids[1:]:
+            f = f * lam[k]
+        F[c] = f
     return F
 
 
@@ -35,11 +41,12 @@ def risk_index(outages, severe, lam, n_comp):
     """R_i of eq. (3), summed over the list in scenario order."""
     F = scenario_frequency(outages, lam)
     R = np.zeros(n_comp)
-    for c, (i, j) in enumerate(np.asarray(outages)):
-        if severe[c] and i >= 0:    # the base case involves no component
-            R[i] += F[c]
-            if j >= 0:
-                R[j] += F[c]
+    for c, row in enumerate(np.asarray(outages)):
+        if not severe[c]:
+            continue
+        for k in row:               # the base case involves no component
+            if k >= 0:
+                R[k] += F[c]
     return R
 
 

@@ -180,6 +180,31 @@ def screen(net, outages, lam, opts: ScreenOptions = ScreenOptions()):
     return results, R
 
 
+CAUSE_PRUNED = 32
+
+
+def n3_prune(rows, sub_outages, sub_severe):
+    """Rows of three ids to solve (True) or to take as severe without solving
+    (False): a row is pruned when one of its single components or pairs is
+    severe in the screened N-1/N-2 list (sub_outages, sub_severe); reading:
+    more outaged elements never make a severe contingency secure.  Singles
+    and pairs absent from that list prune nothing; N-1 rows are never
+    pruned, N-2 rows only by their singles."""
+    severe_sets = set()
+    for row, s in zip(np.asarray(sub_outages), np.asarray(sub_severe)):
+        ids = frozenset(int(v) for v in row if v >= 0)
+        if s and ids:
+            severe_sets.add(ids)
+    keep = np.ones(len(rows), bool)
+    for r, row in enumerate(np.asarray(rows)):
+        ids = [int(v) for v in row if v >= 0]
+        subs = [frozenset([a]) for a in ids] if len(ids) >= 2 else []
+        if len(ids) == 3:
+            subs += [frozenset(p) for p in ((ids[0], ids[1]), (ids[0], ids[2]), (ids[1], ids[2]))]
+        keep[r] = not any(sb in severe_sets for sb in subs)
+    return keep
+
+
 RECORD_FIELDS = ("severe", "cause", "opf_status", "near", "n_islands",
                  "opf_iters", "n_states", "opf_cost", "max_real_eig",
                  "min_damping", "max_violation")

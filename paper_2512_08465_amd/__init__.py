@@ -18,6 +18,7 @@ CS_OK, CS_EINVAL, CS_ENOMEM, CS_EHBM, CS_EDEVICE, CS_EUNSUPPORTED = 0, -1, -2, -
 CS_EAGAIN, CS_ETIMEDOUT = -6, -7
 PREC_FP64, PREC_MIXED = 0, 1
 CAUSE_ISLAND, CAUSE_OPF, CAUSE_LIMIT, CAUSE_SSS, CAUSE_NUMERICAL = 1, 2, 4, 8, 16
+CAUSE_PRUNED = 32
 OPF_CONVERGED, OPF_MAXIT, OPF_NUMERICAL, OPF_NOT_RUN = 0, 1, 2, 3
 NEAR_SSS, NEAR_OPF, NEAR_LIMIT = 1, 2, 4
 N_DYN = 14
@@ -113,6 +114,11 @@ def library():
         "cs_screen_device_noalloc": (ctypes.c_int, [vp, vp, vp, i64, dp,
                                                     ctypes.POINTER(Options), vp, dp, vp]),
         "cs_risk_opts_default": (None, [ctypes.POINTER(RiskOptions)]),
+        "cs_screen3_device": (ctypes.c_int, [vp, vp, vp, i64, dp, ctypes.POINTER(Options),
+                                             vp, dp, vp]),
+        "cs_screen_n3_device": (ctypes.c_int, [vp, vp, vp, i64, vp, i64, vp, dp,
+                                               ctypes.POINTER(Options), vp, dp,
+                                               ctypes.POINTER(ctypes.c_int64), vp]),
         "cs_risk": (ctypes.c_int, [vp, vp, vp, i64, vp, dp, ctypes.POINTER(RiskOptions), dp,
                                    vp]),
         "cs_risk_mc": (ctypes.c_int, [vp, vp, vp, i64, vp, dp, i64, ctypes.POINTER(RiskOptions),
@@ -142,7 +148,7 @@ EXPORTED = ("cs_ctx_create", "cs_ctx_destroy", "cs_net_create", "cs_net_destroy"
             "cs_stats_reset", "cs_last_error", "cs_abi_version", "cs_server_create",
             "cs_server_destroy", "cs_submit", "cs_wait", "cs_req_free", "cs_screen_detail",
             "cs_dyn_at", "cs_screen_device_noalloc", "cs_risk_opts_default", "cs_risk",
-            "cs_risk_mc")
+            "cs_risk_mc", "cs_screen3_device", "cs_screen_n3_device")
 
 
 def _check(rc):
@@ -274,6 +280,24 @@ class Network:
         _check(library().cs_screen_device_noalloc(self.ctx.handle, self._h, d_outages, n,
                                                   d_lambda, ctypes.byref(o), d_results, d_risk,
                                                   stream))
+
+    def screen3_device(self, d_outages, n, d_lambda, d_results, d_risk,
+                       options: Options | None = None, stream=None):
+        """Rows of three component ids (N-3; -1 pads N-1/N-2 rows)."""
+        o = options or default_options()
+        _check(library().cs_screen3_device(self.ctx.handle, self._h, d_outages, n, d_lambda,
+                                           ctypes.byref(o), d_results, d_risk, stream))
+
+    def screen_n3_device(self, d_rows, n, d_sub, n_sub, d_sub_records, d_lambda, d_results,
+                         d_risk, options: Options | None = None, stream=None) -> int:
+        """N-3 rows with pruning by a screened N-1/N-2 list; returns the
+        number of rows actually solved."""
+        o = options or default_options()
+        solved = ctypes.c_int64(0)
+        _check(library().cs_screen_n3_device(self.ctx.handle, self._h, d_rows, n, d_sub, n_sub,
+                                             d_sub_records, d_lambda, ctypes.byref(o),
+                                             d_results, d_risk, ctypes.byref(solved), stream))
+        return int(solved.value)
 
     @staticmethod
     def _risk_opts(severity, zeta_ref, cc_pairs, cc_rate):

@@ -562,6 +562,7 @@ struct Engine {
   int* req_done = nullptr;
   TimedLaunches* T = nullptr;
   const DetailOut* detail = nullptr;   // per-scenario detail (parity entry point)
+  int width = 2;                 // ids per outage row (3 for N-3 lists)
   int cnt[PH_COUNT]{};
   long long assigned = 0;        // scenarios handed to slots so far
   bool dyn_busy = false;
@@ -603,8 +604,8 @@ struct Engine {
       const long long nnew = std::min<long long>(cnt[PH_EMPTY], N - assigned);
       rc = timed(CS_K_TOPOLOGY, st, nnew, -1, [&] {
         launch_refill(s, nslots, d_next, N, q_cap, st);
-        launch_islands(*D, s, d_list, nslots, st);
-        launch_setup_k(*D, s, nslots, d_list, st);
+        launch_islands(*D, s, d_list, nslots, st, width);
+        launch_setup_k(*D, s, nslots, d_list, st, width);
       });
       if (rc != CS_OK) return rc;
       work = true;
@@ -740,7 +741,8 @@ static int check_opts(const cs_opts& opts, const char* who) {
 static int run_screen(cs_ctx* c, cs_net* n, const int* d_out_list, long long N,
                       const double* d_lambda, const cs_opts* o, cs_result* d_res,
                       double* d_risk, hipStream_t st, Plan* keep,
-                      const DetailOut* detail = nullptr, bool in_scratch = false) {
+                      const DetailOut* detail = nullptr, bool in_scratch = false,
+                      int width = 2) {
   cs_opts opts;
   cs_opts_default(&opts);
   if (o) opts = *o;
@@ -800,6 +802,7 @@ static int run_screen(cs_ctx* c, cs_net* n, const int* d_out_list, long long N,
   e.q_cap = std::max<long long>(N, 1);
   e.T = tm ? &T : nullptr;
   e.detail = detail;
+  e.width = width;
   c->stats.kkt_order = p.s.nk;
   if ((rc = e.start()) != CS_OK) return rc;
   // every scenario needs at most max_it + 2 rounds in its slot, plus a few
@@ -818,7 +821,7 @@ static int run_screen(cs_ctx* c, cs_net* n, const int* d_out_list, long long N,
     const int n_comp = n->nl + n->ng + n->nd;
     rc = T.run(CS_K_RISK, st, n_comp, -1, [&] {
       launch_risk(d_out_list, N, reinterpret_cast<const uint8_t*>(d_res), (int)sizeof(cs_result),
-                  d_lambda, n_comp, d_risk, st);
+                  d_lambda, n_comp, d_risk, st, width);
     });
     if (rc != CS_OK) return rc;
   }
@@ -896,7 +899,8 @@ extern "C" int cs_screen(cs_ctx* c, cs_net* n, const int32_t* outages, int64_t N
 
 static int screen_device(const char* who, cs_ctx* c, cs_net* n, const int32_t* d_outages,
                          int64_t N, const double* d_lambda, const cs_opts* opts,
-                         cs_result* d_out, double* d_risk, void* stream, bool in_scratch) {
+                         cs_result* d_out, double* d_risk, void* stream, bool in_scratch,
+                         int width = 2) {
   if (!c || !n || N < 0 || (N > 0 && (!d_outages || !d_out)))
     return fail(CS_EINVAL, std::string(who) + ": NULL argument or negative n");
   if (d_risk && !d_lambda) return fail(CS_EINVAL, std::string(who) + ": risk requested without lambda");
@@ -907,7 +911,7 @@ static int screen_device(const char* who, cs_ctx* c, cs_net* n, const int32_t* d
   const int n_comp = n->nl + n->ng + n->nd;
   // validate the list (bit 1) and the rates (bit 2) on the device
   HIPCHK(hipMemsetAsync(c->d_counter, 0, sizeof(int), st));
-  launch_validate(d_outages, N, n_comp, c->d_counter, st);
+  launch_validate(d_outages, N, n_comp, c->d_counter, st, width);
   if (d_lambda) launch_validate_rates(d_lambda, n_comp, c->d_counter, st);
   HIPCHK(hipMemcpyAsync(c->h_counter, c->d_counter, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -920,7 +924,7 @@ static int screen_device(const char* who, cs_ctx* c, cs_net* n, const int32_t* d
     return CS_OK;
   }
   return run_screen(c, n, d_outages, N, d_lambda, opts, d_out, d_risk, st, nullptr, nullptr,
-                    in_scratch);
+                    in_scratch, width);
 }
 
 extern "C" int cs_screen_device(cs_ctx* c, cs_net* n, const int32_t* d_outages, int64_t N,
@@ -1723,6 +1727,80 @@ extern "C" int cs_risk_mc(cs_ctx* c, cs_net* n, const int32_t* d_outages, int64_
     launch_rank_hist(R, M, n_comp, hist, st);
   }
   if (d_moments || d_rank_q) launch_risk_summary(R, M, n_comp, hist, d_moments, d_rank_q, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return CS_OK;
+}
+
+// ---------------------------------------------------------------- N-3 lists
+extern "C" int cs_screen3_device(cs_ctx* c, cs_net* n, const int32_t* d_outages, int64_t N,
+                                 const double* d_lambda, const cs_opts* opts, cs_result* d_out,
+                                 double* d_risk, void* stream) {
+  return screen_device("cs_screen3_device", c, n, d_outages, N, d_lambda, opts, d_out, d_risk,
+                       stream, false, 3);
+}
+
+extern "C" int cs_screen_n3_device(cs_ctx* c, cs_net* n, const int32_t* d_rows, int64_t N,
+                                   const int32_t* d_sub, int64_t n_sub,
+                                   const cs_result* d_sub_rec, const double* d_lambda,
+                                   const cs_opts* opts, cs_result* d_out, double* d_risk,
+                                   int64_t* n_solved, void* stream) {
+  const char* who = "cs_screen_n3_device";
+  if (!c || !n || N < 0 || n_sub < 0 || (N > 0 && (!d_rows || !d_out)) ||
+      (n_sub > 0 && (!d_sub || !d_sub_rec)))
+    return fail(CS_EINVAL, std::string(who) + ": NULL argument or negative size");
+  if (d_risk && !d_lambda) return fail(CS_EINVAL, std::string(who) + ": risk requested without lambda");
+  if (N > 0x7fffffffll) return fail(CS_EINVAL, std::string(who) + ": more than 2^31 - 1 rows");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  const int n_comp = n->nl + n->ng + n->nd;
+  HIPCHK(hipMemsetAsync(c->d_counter, 0, sizeof(int), st));
+  launch_validate(d_rows, N, n_comp, c->d_counter, st, 3);
+  launch_validate(d_sub, n_sub, n_comp, c->d_counter, st, 2);
+  if (d_lambda) launch_validate_rates(d_lambda, n_comp, c->d_counter, st);
+  HIPCHK(hipMemcpyAsync(c->h_counter, c->d_counter, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (*c->h_counter & 1) return fail(CS_EINVAL, std::string(who) + ": invalid row in a list");
+  if (*c->h_counter & 2)
+    return fail(CS_EINVAL, std::string(who) + ": every failure rate must be finite and >= 0");
+  if (n_solved) *n_solved = 0;
+  if (N == 0) {
+    if (d_risk) HIPCHK(hipMemsetAsync(d_risk, 0, sizeof(double) * n_comp, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return CS_OK;
+  }
+  RiskTemps T;
+  uint8_t* single = T.take<uint8_t>(n_comp);
+  uint8_t* pair = T.take<uint8_t>((size_t)n_comp * n_comp);
+  uint8_t* keep = T.take<uint8_t>(N);
+  long long* idx = T.take<long long>(N);
+  long long* cnt = T.take<long long>(1);
+  const size_t sel_bytes = n3_select_bytes(N);
+  void* sel = T.take<unsigned char>(sel_bytes);
+  if (!single || !pair || !keep || !idx || !cnt || !sel || sel_bytes == 0)
+    return fail(CS_ENOMEM, std::string(who) + ": device allocation failed");
+  HIPCHK(hipMemsetAsync(single, 0, n_comp, st));
+  HIPCHK(hipMemsetAsync(pair, 0, (size_t)n_comp * n_comp, st));
+  launch_sub_severity(d_sub, n_sub, d_sub_rec, n_comp, single, pair, st);
+  launch_n3_prune(d_rows, N, n_comp, single, pair, keep, st);
+  if (n3_select(sel, sel_bytes, keep, N, idx, cnt, st) != 0)
+    return fail(CS_EDEVICE, std::string(who) + ": compaction failed");
+  long long k = 0;
+  HIPCHK(hipMemcpyAsync(&k, cnt, sizeof(long long), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (n_solved) *n_solved = k;
+  int* rows = T.take<int>(3 * (size_t)std::max<long long>(k, 1));
+  cs_result* rec = T.take<cs_result>((size_t)std::max<long long>(k, 1));
+  if (!rows || !rec) return fail(CS_ENOMEM, std::string(who) + ": device allocation failed");
+  if (k > 0) {
+    launch_gather_rows(d_rows, idx, k, rows, st);
+    int rc = run_screen(c, n, rows, k, nullptr, opts, rec, nullptr, st, nullptr, nullptr, false, 3);
+    if (rc != CS_OK) return rc;
+  }
+  launch_merge_n3(keep, N, rec, idx, k, d_out, st);
+  if (d_risk)
+    launch_risk(d_rows, N, reinterpret_cast<const uint8_t*>(d_out), (int)sizeof(cs_result),
+                d_lambda, n_comp, d_risk, st, 3);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   return CS_OK;

@@ -112,10 +112,11 @@ struct DetailOut {
 };
 
 // Launch wrappers (one per kernel file).
+// outage rows hold `width` ids each (2: N-1/N-2 lists, 3: N-3 lists), -1 pads
 void launch_islands(const DevNet& net, const Slots& s, const int* outages,
-                    int count, hipStream_t st);
+                    int count, hipStream_t st, int width = 2);
 void launch_setup_k(const DevNet& net, const Slots& s, int count, const int* outages,
-                    hipStream_t st);
+                    hipStream_t st, int width = 2);
 void launch_opf_eval(const DevNet& net, const Slots& s, int count, double tol,
                      int max_it, hipStream_t st);
 void launch_opf_update(const DevNet& net, const Slots& s, int count,
@@ -139,9 +140,9 @@ void launch_classify(const Slots& s, int count, double near_eps, int max_it,
                      const DetailOut* detail, int nb, int ng, hipStream_t st);
 void launch_risk(const int* outages, long long n, const uint8_t* severe_src,
                  int sev_stride, const double* lam, int n_comp, double* risk,
-                 hipStream_t st);
+                 hipStream_t st, int width = 2);
 void launch_validate(const int* outages, long long n, int n_comp, int* bad,
-                     hipStream_t st);
+                     hipStream_t st, int width = 2);
 // sets bit 2 of *bad when a failure rate is negative or not finite
 void launch_validate_rates(const double* lam, int n_comp, int* bad, hipStream_t st);
 // Risk Index extensions (k_risk.hip)
@@ -160,6 +161,19 @@ void launch_risk_summary(const double* R, long long M, int n, const int* hist, d
                          int* rank_q, hipStream_t st);
 // sets bit 2 of *bad when one of n values is negative or not finite
 void launch_validate_values(const double* v, long long n, int* bad, hipStream_t st);
+
+// N-3 pruning (k_prune.hip)
+void launch_sub_severity(const int* sub, long long n2, const void* rec, int n_comp,
+                         uint8_t* single, uint8_t* pair, hipStream_t st);
+void launch_n3_prune(const int* rows, long long n3, int n_comp, const uint8_t* single,
+                     const uint8_t* pair, uint8_t* keep, hipStream_t st);
+size_t n3_select_bytes(long long n3);
+int n3_select(void* tmp, size_t bytes, const uint8_t* keep, long long n3, long long* idx,
+              long long* count, hipStream_t st);
+void launch_gather_rows(const int* rows, const long long* idx, long long k, int* out,
+                        hipStream_t st);
+void launch_merge_n3(const uint8_t* keep, long long n3, const void* kept_rec, const long long* idx,
+                     long long k, void* out, hipStream_t st);
 
 // mixed-precision KKT solve
 void launch_kkt_to_f32(const Slots& s, int count, hipStream_t st);

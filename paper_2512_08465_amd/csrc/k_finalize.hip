@@ -138,15 +138,19 @@ void launch_classify(const Slots& s, int count, double near_eps, int max_it,
 __global__ __launch_bounds__(256) void k_risk(const int* __restrict__ outages, long long n,
                                               const uint8_t* __restrict__ sev, int sev_stride,
                                               const double* __restrict__ lam, int n_comp,
-                                              double* __restrict__ risk) {
+                                              double* __restrict__ risk, int width) {
   const int comp = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (comp >= n_comp) return;
   double acc = 0.0;
   for (long long c = lane; c < n; c += 64) {
-    const int a = outages[2 * c], b = outages[2 * c + 1];
-    if ((a == comp || b == comp) && sev[c * sev_stride]) {
-      acc += (b < 0) ? lam[a] : lam[a] * lam[b];
+    const int a = outages[width * c], b = outages[width * c + 1];
+    const int d = width > 2 ? outages[width * c + 2] : -1;
+    if ((a == comp || b == comp || d == comp) && sev[c * sev_stride]) {
+      // eq. (1)-(2): the product of the outaged components' rates
+      double f = (b < 0) ? lam[a] : lam[a] * lam[b];
+      if (d >= 0) f *= lam[d];
+      acc += f;
     }
   }
   for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
@@ -155,10 +159,10 @@ __global__ __launch_bounds__(256) void k_risk(const int* __restrict__ outages, l
 
 void launch_risk(const int* outages, long long n, const uint8_t* severe_src,
                  int sev_stride, const double* lam, int n_comp, double* risk,
-                 hipStream_t st) {
+                 hipStream_t st, int width) {
   if (n_comp <= 0) return;
   hipLaunchKernelGGL(k_risk, dim3((n_comp + 3) / 4), dim3(256), 0, st, outages, n,
-                     severe_src, sev_stride, lam, n_comp, risk);
+                     severe_src, sev_stride, lam, n_comp, risk, width);
 }
 
 // ------------------------------------------------------------- scheduling

@@ -108,7 +108,8 @@ __device__ inline int risum(int v, int* red) {
 
 // ---------------------------------------------------------------- setup
 __global__ __launch_bounds__(OPF_THREADS) void k_setup(DevNet net, Slots s,
-                                                       int count, const int* __restrict__ outages) {
+                                                       int count, const int* __restrict__ outages,
+                                                       int width) {
   const int slot = blockIdx.x;
   if (slot >= count) return;
   SlotState& S = s.st[slot];
@@ -118,7 +119,8 @@ __global__ __launch_bounds__(OPF_THREADS) void k_setup(DevNet net, Slots s,
   __shared__ double red[OPF_THREADS / 64];
   __shared__ int ired[OPF_THREADS / 64];
   const long long scen = S.scen;
-  const int o0 = outages[2 * scen], o1 = outages[2 * scen + 1];
+  const int o0 = outages[width * scen], o1 = outages[width * scen + 1];
+  const int o2 = width > 2 ? outages[width * scen + 2] : -1;
   const int main = S.main_label;
   const int* label = s.label + (size_t)slot * nb;
   Views v = views(s, slot, nb, nl, ng);
@@ -136,7 +138,7 @@ __global__ __launch_bounds__(OPF_THREADS) void k_setup(DevNet net, Slots s,
     if (on) {
       for (int e = net.bus_load_ptr[b]; e < net.bus_load_ptr[b + 1]; ++e) {
         const int d = net.bus_load[e];
-        if (load0 + d == o0 || load0 + d == o1) continue;
+        if (load0 + d == o0 || load0 + d == o1 || load0 + d == o2) continue;
         p += net.pd[d];
         q += net.qd[d];
       }
@@ -149,7 +151,8 @@ __global__ __launch_bounds__(OPF_THREADS) void k_setup(DevNet net, Slots s,
   }
   int ngon = 0;
   for (int g = tid; g < ng; g += OPF_THREADS) {
-    const bool on = (nl + g != o0) && (nl + g != o1) && (label[net.gen_bus[g]] == main);
+    const bool on = (nl + g != o0) && (nl + g != o1) && (nl + g != o2) &&
+                    (label[net.gen_bus[g]] == main);
     gen_on[g] = on;
     ngon += on;
     v.x[2 * nb + g] = on ? 0.5 * (net.pmin[g] + net.pmax[g]) : 0.0;
@@ -157,7 +160,7 @@ __global__ __launch_bounds__(OPF_THREADS) void k_setup(DevNet net, Slots s,
     cnt += on ? 4 : 0;
   }
   for (int l = tid; l < nl; l += OPF_THREADS) {
-    const bool on = (l != o0) && (l != o1) && (label[net.br_f[l]] == main);
+    const bool on = (l != o0) && (l != o1) && (l != o2) && (label[net.br_f[l]] == main);
     br_on[l] = on;
     if (on && net.rate[l] > 0.0) cnt += 2;
   }
@@ -707,10 +710,10 @@ void opf_set_attrs(size_t bytes) {
 }
 
 void launch_setup_k(const DevNet& net, const Slots& s, int count,
-                    const int* outages, hipStream_t st) {
+                    const int* outages, hipStream_t st, int width) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_setup, dim3(count), dim3(OPF_THREADS), 0, st, net, s,
-                     count, outages);
+                     count, outages, width);
 }
 
 void launch_opf_eval(const DevNet& net, const Slots& s, int count, double tol,

@@ -26,20 +26,22 @@ __device__ inline int uf_find(volatile int* parent, int x) {
 
 __global__ __launch_bounds__(64) void k_islands(DevNet net, Slots s,
                                                 const int* __restrict__ outages,
-                                                int count) {
+                                                int width, int count) {
   const int slot = blockIdx.x;
   if (slot >= count || s.st[slot].phase != PH_NEW) return;
   extern __shared__ int parent[];
   __shared__ int roots_count;
   const int lane = threadIdx.x;
   const long long scen = s.st[slot].scen;
-  const int o0 = outages[2 * scen], o1 = outages[2 * scen + 1];
+  // an outage row holds width ids (2: N-1/N-2 rows, 3: N-3 rows), -1 pads
+  const int o0 = outages[width * scen], o1 = outages[width * scen + 1];
+  const int o2 = width > 2 ? outages[width * scen + 2] : -1;
   const int nb = net.nb, nl = net.nl, ng = net.ng;
   const int gen0 = nl, load0 = nl + ng;
   for (int v = lane; v < nb; v += 64) parent[v] = v;
   __syncthreads();
   for (int l = lane; l < nl; l += 64) {
-    if (l == o0 || l == o1) continue;
+    if (l == o0 || l == o1 || l == o2) continue;
     int a = net.br_f[l], b = net.br_t[l];
     while (true) {
       a = uf_find(parent, a);
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(64) void k_islands(DevNet net, Slots s,
     if (parent[r] != r) continue;           // uniform across lanes
     double cap = 0.0;
     for (int g = lane; g < ng; g += 64) {
-      const bool on = (gen0 + g != o0) && (gen0 + g != o1);
+      const bool on = (gen0 + g != o0) && (gen0 + g != o1) && (gen0 + g != o2);
       if (on && parent[net.gen_bus[g]] == r) cap += net.pmax[g];
     }
     for (int off = 32; off > 0; off >>= 1) cap += __shfl_xor(cap, off, 64);
@@ -85,7 +87,7 @@ __global__ __launch_bounds__(64) void k_islands(DevNet net, Slots s,
   } else {
     int cand = 0x7fffffff;
     for (int g = lane; g < ng; g += 64) {
-      const bool on = (gen0 + g != o0) && (gen0 + g != o1);
+      const bool on = (gen0 + g != o0) && (gen0 + g != o1) && (gen0 + g != o2);
       if (on && parent[net.gen_bus[g]] == best) cand = min(cand, g);
     }
     for (int off = 32; off > 0; off >>= 1) cand = min(cand, __shfl_xor(cand, off, 64));
@@ -116,31 +118,40 @@ __global__ __launch_bounds__(64) void k_islands(DevNet net, Slots s,
 }
 
 void launch_islands(const DevNet& net, const Slots& s, const int* outages,
-                    int count, hipStream_t st) {
+                    int count, hipStream_t st, int width) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_islands, dim3(count), dim3(64), sizeof(int) * net.nb, st,
-                     net, s, outages, count);
+                     net, s, outages, width, count);
 }
 
-// outage list check: ids in range, j == -1 or a distinct id; (-1, -1) is
-// the base case (the kernels only compare ids, never index with them)
+// outage list check: a row of width ids holds distinct valid ids followed by
+// -1 padding (all -1 is the base case); the kernels only compare ids, never
+// index with them
 __global__ void k_validate(const int* __restrict__ outages, long long n,
-                           int n_comp, int* __restrict__ bad) {
+                           int n_comp, int width, int* __restrict__ bad) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int a = outages[2 * i], b = outages[2 * i + 1];
-  const bool ok = (a == -1 && b == -1) ||
-                  (a >= 0 && a < n_comp && (b == -1 || (b >= 0 && b < n_comp && b != a)));
+  bool ok = true, pad = false;
+  for (int t = 0; t < width; ++t) {
+    const int a = outages[width * i + t];
+    if (a == -1) {
+      pad = true;
+      continue;
+    }
+    if (pad || a < 0 || a >= n_comp) ok = false;
+    for (int u = 0; u < t; ++u)
+      if (outages[width * i + u] == a) ok = false;
+  }
   if (!ok) atomicOr(bad, 1);
 }
 
 void launch_validate(const int* outages, long long n, int n_comp, int* bad,
-                     hipStream_t st) {
+                     hipStream_t st, int width) {
   if (n <= 0) return;
   const int threads = 256;
   const long long blocks = (n + threads - 1) / threads;
   hipLaunchKernelGGL(k_validate, dim3((unsigned)blocks), dim3(threads), 0, st,
-                     outages, n, n_comp, bad);
+                     outages, n, n_comp, width, bad);
 }
 
 // failure-rate check: finite and >= 0 (eq. (1)-(2) take them as frequencies)

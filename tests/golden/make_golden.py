@@ -8,6 +8,9 @@ island labels and the Risk Index over that list.
   c2_118: every N-1 outage plus a seeded sample of N-2 outages of the
           118-bus-shaped case (a stratified sample; the full list has 57,630)
   c2_118_full: the whole 57,630-scenario list of the 118-bus-shaped case
+  c1_30_n3: every N-3 triple of the 30-bus case's 41 branches (10,660 rows),
+          all solved, with the pruning flags of screen.n3_prune (by c1_30's
+          records) and R_i with pruned rows counted as severe
 
 c1_30 and c2_118 also hold each scenario's operating point (vm, va over the
 buses, pg, qg over the generators; NaN outside the solved island or when the
@@ -39,9 +42,9 @@ from inputs import netgen, contingencies          # noqa: E402
 from oracle import screen, risk                    # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SAMPLES = {"c1_30": None, "c2_118": 600, "c2_118_full": None}
+SAMPLES = {"c1_30": None, "c2_118": 600, "c2_118_full": None, "c1_30_n3": None}
 WITH_DETAIL = {"c1_30", "c2_118"}
-CASE_OF = {"c2_118_full": "c2_118"}
+CASE_OF = {"c2_118_full": "c2_118", "c1_30_n3": "c1_30"}
 _NET = None
 
 
@@ -57,6 +60,8 @@ def _one(o):
 
 
 def case_list(net, name):
+    if name.endswith("_n3"):
+        return contingencies.n3(net["outage_set"])
     full = contingencies.n1_n2(net["outage_set"])
     n = SAMPLES[name]
     if n is None:
@@ -79,6 +84,13 @@ def make(name, procs=8):
     n_comp = int(net["n_branch"]) + int(net["n_gen"]) + int(net["n_load"])
     R = risk.risk_index(lst, tab["severe"], net["lam"], n_comp)
     extra = detail_arrays(net, res) if name in WITH_DETAIL else {}
+    if name.endswith("_n3"):
+        # pruning by the oracle's own N-1/N-2 records of the same case; R_i
+        # counts a pruned row as severe
+        with np.load(os.path.join(HERE, CASE_OF[name] + "_oracle.npz"), allow_pickle=False) as z:
+            keep = screen.n3_prune(lst, z["outages"], z["severe"])
+        extra["keep"] = keep
+        extra["risk_pruned"] = risk.risk_index(lst, tab["severe"] | ~keep, net["lam"], n_comp)
     out = os.path.join(HERE, name + "_oracle.npz")
     np.savez_compressed(out, outages=lst, labels=labels, risk=R, **tab, **extra)
     print(f"{name}: {len(lst)} scenarios, {int(tab['severe'].sum())} severe -> {out}")

@@ -146,3 +146,60 @@ def test_main_island_largest_capacity_and_tie_rule():
     # reference falls back to the lowest-index generator of the island
     assert islanding.island_reference(label, 3, 0, gen_bus, on) == 3
     assert islanding.island_reference(label, 0, 2, gen_bus, on) == 2
+
+
+# --- N-3 rows (three outaged branches) ---------------------------------------
+
+def _n3_islands(nb, edges, rows):
+    from oracle import islanding
+    br_f = np.array([e[0] for e in edges])
+    br_t = np.array([e[1] for e in edges])
+    out = []
+    for row in rows:
+        on = np.ones(len(edges), bool)
+        on[[k for k in row if k >= 0]] = False
+        out.append(islanding.components_bfs(nb, br_f, br_t, on)[1])
+    return np.array(out)
+
+
+def test_n3_closed_forms():
+    """Cycle C_n: any three branches out leave exactly 3 paths; a tree: 4
+    components; K_6 (edge connectivity 5) never islands under three
+    outages."""
+    from inputs import contingencies
+    n = 9
+    cyc = [(k, (k + 1) % n) for k in range(n)]
+    rows = contingencies.n3(np.arange(len(cyc)))
+    assert len(rows) == 84
+    assert np.all(_n3_islands(n, cyc, rows) == 3)
+    rng = np.random.default_rng(4)
+    tree = [(k, int(rng.integers(0, k))) for k in range(1, 10)]
+    assert np.all(_n3_islands(10, tree, contingencies.n3(np.arange(len(tree)))) == 4)
+    k6 = [(a, b) for a in range(6) for b in range(a + 1, 6)]
+    assert np.all(_n3_islands(6, k6, contingencies.n3(np.arange(len(k6)))) == 1)
+
+
+def test_n3_enumeration():
+    from inputs import contingencies
+    from math import comb
+    rows = contingencies.n3(np.arange(12))
+    assert len(rows) == comb(12, 3)
+    assert np.all(rows[:, 0] < rows[:, 1]) and np.all(rows[:, 1] < rows[:, 2])
+    assert len({tuple(r) for r in rows}) == len(rows)
+    # lexicographic order
+    assert [tuple(r) for r in rows] == sorted(tuple(r) for r in rows)
+
+
+def test_n3_pruning_rule():
+    """A triple is pruned exactly when a screened single or pair inside it is
+    severe; unscreened subsets prune nothing; N-1 rows are never pruned."""
+    from oracle import screen
+    sub = np.array([[0, -1], [1, -1], [2, -1], [0, 1], [0, 2], [1, 2], [3, 4]])
+    sev = np.array([0, 0, 0, 1, 0, 0, 0])
+    rows = np.array([[0, 1, 5], [0, 2, 5], [1, 2, 6], [3, 4, 5], [5, 6, 7], [0, 1, -1],
+                     [2, -1, -1], [0, 2, -1]])
+    assert screen.n3_prune(rows, sub, sev).tolist() == [False, True, True, True, True, True,
+                                                        True, True]
+    sev = np.array([0, 0, 1, 0, 0, 0, 1])       # single 2 and pair (3, 4) severe
+    assert screen.n3_prune(rows, sub, sev).tolist() == [True, False, False, False, True, True,
+                                                        True, False]

@@ -172,3 +172,20 @@ def test_rank_quantile_definition():
     _, _, _, hist, quant = risk.risk_monte_carlo(lst, np.ones(3), np.array(S), n)
     assert hist[0].tolist() == [1, 9, 10]
     assert quant[0].tolist() == [0, 1, 2]
+
+
+def test_n3_risk_closed_form():
+    """Every row of an N-1 + N-2 + N-3 list severe: R_k = lam_k (1 + e1 + e2)
+    with e1, e2 the first and second elementary symmetric sums of the other
+    components' rates."""
+    lam, _ = _all_severe(8, 2)
+    n = len(lam)
+    lst2 = contingencies.n1_n2(np.arange(n))
+    lst = np.concatenate([np.concatenate([lst2, np.full((len(lst2), 1), -1)], axis=1),
+                          contingencies.n3(np.arange(n))])
+    R = risk.risk_index(lst, np.ones(len(lst), bool), lam, n)
+    for k in range(n):
+        o = np.delete(lam, k)
+        e1 = o.sum()
+        e2 = (e1 * e1 - (o * o).sum()) / 2
+        assert abs(R[k] - lam[k] * (1 + e1 + e2)) < 1e-14
