@@ -61,7 +61,7 @@ def test_n3_with_pruning_matches_oracle(setup):
     assert solved == int(keep.sum())
     assert np.array_equal(pruned_dev, ~keep)
     assert np.all(res["severe"][~keep] == 1)
-    bad, flips, kind = outcome_mismatches({k: g3[k][keep] for k in g3.files if len(g3[k]) == n3},
+    bad, flips, kind = outcome_mismatches({k: g3[k][keep] for k in g3 if len(g3[k]) == n3},
                                           res[keep])
     print(f"N-3 solved rows: OPF converged on one side only {flips.tolist()}, both failed "
           f"with another kind {kind.tolist()}")
@@ -102,7 +102,7 @@ def test_width3_rows_match_width2_and_oracle(setup):
     ref2, _ = net.screen(rows2, case["lam"])
     a = res[:len(rows2)]
     assert np.array_equal(a.view(np.uint8), ref2.view(np.uint8))
-    sub = {k: g3[k][i3] for k in g3.files if len(g3[k]) == len(g3["outages"])}
+    sub = {k: g3[k][i3] for k in g3 if len(g3[k]) == len(g3["outages"])}
     bad, _, _ = outcome_mismatches(sub, res[len(rows2):-1])
     assert len(bad) == 0, bad[:10]
     # the base case row adds nothing; R_i is eq. (3) over the rows with the
