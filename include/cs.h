@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define CS_ABI_VERSION 5
+#define CS_ABI_VERSION 6
 
 enum {
   CS_OK = 0,
@@ -85,7 +85,12 @@ enum { CS_NEAR_SSS = 1   /* |max Re| <= near_eps                              */
        CS_NEAR_LIMIT = 4 /* 1e-7 < max violation <= 1e-5: a decade either side
                             of the 1e-6 p.u. limit test                      */ };
 
-#define CS_N_DYN 14  /* dyn row: H D Xd Xq Xd' Xq' Td0' Tq0' Rs KA TA R Tg Tt */
+/* dyn row of a synchronous generator (kind 0): H D Xd Xq Xd' Xq' Td0' Tq0' Rs
+ * KA TA R Tg Tt (two-axis machine, first-order AVR, governor and turbine);
+ * of a grid-following converter (kind 1): Kpp Kip Kpc Kic Lf Rf Cdc Kpdc Kidc
+ * Vdc0 and 4 unused entries (PLL PI, current PI with an L filter, DC link
+ * with a DC-voltage PI).  System base. */
+#define CS_N_DYN 14
 
 /* Network description, host structure-of-arrays (copied at cs_net_create). */
 typedef struct {
@@ -101,7 +106,8 @@ typedef struct {
   const double *br_tap;       /* off-nominal tap on the from side; 0 means 1   */
   const double *br_shift;     /* phase shift (rad)                             */
   const int32_t *gen_bus;     /* [n_gen]                                       */
-  const int32_t *gen_kind;    /* 0 = synchronous generator (only kind here)    */
+  const int32_t *gen_kind;    /* 0 synchronous generator, 1 grid-following
+                                 converter (NULL: all 0)                     */
   const double *pmin, *pmax, *qmin, *qmax;     /* [n_gen] limits (p.u.)       */
   const double *c2, *c1, *c0; /* cost c2 (Sb P)^2 + c1 (Sb P) + c0, $/h        */
   const double *dyn;          /* [n_gen][CS_N_DYN], system base                */
@@ -175,8 +181,11 @@ void cs_ctx_destroy(cs_ctx* ctx);
 
 /* Validate the network and copy it to the device (Section II.B.3 step 1: the
  * numerical model the outages are applied to).  Errors: CS_EINVAL (sizes,
- * bus ids, self-loops, non-finite values, a non-synchronous generator),
- * CS_ENOMEM, CS_EDEVICE. */
+ * bus ids, self-loops, non-finite values, non-positive time constants or
+ * divisor gains), CS_EUNSUPPORTED (another generator kind, more than 1024
+ * dynamic states or a network beyond the on-chip working set), CS_ENOMEM,
+ * CS_EDEVICE.  The largest state-matrix order of the network is
+ * n_a = 7 (machines) + 8 (converters) - 1. */
 int cs_net_create(cs_ctx* ctx, const cs_net_desc* desc, cs_net** out);
 void cs_net_destroy(cs_net* net);
 
@@ -218,7 +227,7 @@ int cs_screen_device_noalloc(cs_ctx* ctx, cs_net* net, const int32_t* d_outages,
 
 /* One scenario in full detail, for parity checks.  Host buffers:
  * vm, va [n_bus] (NaN outside the solved island), pg, qg [n_gen] (NaN when
- * out of service), eig_re, eig_im [7 n_gen] with *n_eig set to the number
+ * out of service), eig_re, eig_im [n_a] with *n_eig set to the number
  * written, label [n_bus] (island label = smallest bus id of the island).
  * Any pointer except rec may be NULL. */
 int cs_detail(cs_ctx* ctx, cs_net* net, const int32_t outage[2],
@@ -262,7 +271,7 @@ int cs_kkt_at(cs_ctx* ctx, cs_net* net, const int32_t outage[2], int32_t iters,
  * (Section II.B.1-II.B.2): vm, va [n][n_bus] and pg, qg [n][n_gen] (NaN
  * outside the solved island, for generators out of service, and for every
  * entry when the OPF did not run; the point reached is reported also when
- * the OPF did not converge), eig_re, eig_im [n][7 n_gen - 1] (NaN-padded)
+ * the OPF did not converge), eig_re, eig_im [n][n_a] (NaN-padded)
  * with n_eig [n] values each (0 unless the OPF converged and the state
  * matrix was formed).  Errors as cs_screen. */
 int cs_screen_detail(cs_ctx* ctx, cs_net* net, const int32_t* outages, int64_t n,
@@ -275,9 +284,11 @@ int cs_screen_detail(cs_ctx* ctx, cs_net* net, const int32_t* outages, int64_t n
  * [n_bus], pg, qg [n_gen] are host buffers over the whole network; only the
  * island's buses and its in-service generators are read (their values must
  * be finite, vm > 0).  A (may be NULL): [n][n] row-major, n = *n_states =
- * 7 (machines in the island) - 1, states per machine in ascending generator
- * order [delta, omega, Eq', Ed', Efd, Psv, Pm] with angles relative to the
- * first machine (its angle state removed).  eig_re, eig_im [n] (may be NULL:
+ * 7 (machines in the island) + 8 (converters) - 1, states per device in
+ * ascending generator order, [delta, omega, Eq', Ed', Efd, Psv, Pm] for a
+ * machine and [theta_p, x_pll, x_id, x_iq, i_d, i_q, v_dc, x_dc] for a
+ * converter, with angles (delta, theta_p) relative to the first device's
+ * (its angle state removed).  eig_re, eig_im [n] (may be NULL:
  * no eigenvalues computed).  Errors: CS_EINVAL (bad outage, no island with
  * a generator, non-finite point), CS_EDEVICE (singular algebraic system,
  * non-finite A, QR not converged; A is still written). */

@@ -157,6 +157,48 @@ def draw_network(shape: NetShape, attempt: int = 0, base_mva: float = 100.0,
     )
 
 
+# converter parameter row (system base); the remaining dyn columns are unused
+GFL_COLS = ("Kpp", "Kip", "Kpc", "Kic", "Lf", "Rf", "Cdc", "Kpdc", "Kidc", "Vdc0")
+
+
+def convert_to_gfl(net: dict, n_gfl: int, seed: int, attempt: int = 0) -> dict:
+    """Turn the n_gfl lowest-index synchronous generators that are not at the
+    reference bus into grid-following converters with seeded gains.
+
+    Gains are drawn on the converter base S_c = 1.2 Pmax and converted to
+    the system base (impedance-like gains divide by S_c, admittance-like and
+    energy-like ones multiply by it; the PLL gains are base-free):
+      PLL Kpp ~ U(0.05, 0.15), Kip ~ U(1, 3); current PI Kpc ~ U(0.3, 0.6),
+      Kic ~ U(5, 15); filter Lf ~ U(0.1, 0.2), Rf ~ U(0.005, 0.02); DC link
+      Cdc ~ U(0.05, 0.1) s, DC-voltage PI Kpdc ~ U(1, 3), Kidc ~ U(10, 30),
+      Vdc0 = 1."""
+    rng = np.random.Generator(np.random.PCG64([seed, attempt]))
+    net = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in net.items()}
+    ref = int(net["ref_bus"])
+    cand = [g for g in range(int(net["n_gen"])) if int(net["gen_bus"][g]) != ref][:n_gfl]
+    cand = np.array(cand, dtype=np.int64)
+    m = len(cand)
+    sc = 1.2 * net["pmax"][cand]
+    Kpp = rng.uniform(0.05, 0.15, m)
+    Kip = rng.uniform(1.0, 3.0, m)
+    Kpc = rng.uniform(0.3, 0.6, m)
+    Kic = rng.uniform(5.0, 15.0, m)
+    Lf = rng.uniform(0.1, 0.2, m)
+    Rf = rng.uniform(0.005, 0.02, m)
+    Cdc = rng.uniform(0.05, 0.1, m)
+    Kpdc = rng.uniform(1.0, 3.0, m)
+    Kidc = rng.uniform(10.0, 30.0, m)
+    rows = np.stack([Kpp, Kip, Kpc / sc, Kic / sc, Lf / sc, Rf / sc, Cdc * sc, Kpdc * sc,
+                     Kidc * sc, np.ones(m)], axis=1)
+    dyn = np.ones((m, N_DYN))
+    dyn[:, :len(GFL_COLS)] = rows
+    net["gen_kind"] = net["gen_kind"].astype(np.int32).copy()
+    net["gen_kind"][cand] = 1
+    net["dyn"][cand] = dyn
+    net["gfl_attempt"] = np.int32(attempt)
+    return net
+
+
 def outage_components(net: dict, classes) -> np.ndarray:
     """Component ids eligible for outage.
 

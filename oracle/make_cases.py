@@ -80,8 +80,38 @@ def build(shape_name, max_attempts=50):
     raise RuntimeError(f"no admissible draw for {shape_name}")
 
 
+# 118-bus shape with 16 machines replaced by grid-following converters: the
+# same network, loads, machines and ratings as c2_118 otherwise.
+C3 = dict(name="c3_118", base="c2_118", n_gfl=16, seed=1180)
+
+
+def build_c3(max_attempts=50):
+    base = netgen.load_case(os.path.join(CASE_DIR, C3["base"] + ".npz"))
+    for attempt in range(max_attempts):
+        net = netgen.convert_to_gfl(base, C3["n_gfl"], C3["seed"], attempt)
+        net["name"] = np.array(C3["name"])
+        sub = _full_subsystem(net)
+        o = opf.solve_opf(net, sub)
+        if o.status != opf.CONVERGED:
+            continue
+        A = dynamics.DynModel(net, sub, o.vm, o.va, o.pg, o.qg).state_matrix()
+        alpha, zeta = eigen.spectral_summary(eigen.eigvals(A))
+        if alpha < 0.0:
+            net["base_alpha"] = np.float64(alpha)
+            net["base_zeta"] = np.float64(zeta)
+            return net
+    raise RuntimeError("no admissible converter draw")
+
+
 def main(argv):
-    names = argv or list(netgen.SHAPES)
+    names = argv or list(netgen.SHAPES) + [C3["name"]]
+    if C3["name"] in names:
+        names = [n for n in names if n != C3["name"]]
+        net = build_c3()
+        path = os.path.join(CASE_DIR, C3["name"] + ".npz")
+        np.savez(path, **net)
+        print(f"{C3['name']}: converter attempt {int(net['gfl_attempt'])} alpha "
+              f"{float(net['base_alpha']):.6f} zeta {float(net['base_zeta']):.6f} -> {path}")
     os.makedirs(CASE_DIR, exist_ok=True)
     for name in names:
         net = build(name)

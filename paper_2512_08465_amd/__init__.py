@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -173,10 +174,17 @@ class Context:
 
     def __init__(self, device: int = 0, hbm_budget: int = 0):
         self._h = ctypes.c_void_p()
+        # networks and servers made on this context: closed before it, also
+        # when the garbage collector finalises them in another order
+        self._children = weakref.WeakSet()
         _check(library().cs_ctx_create(device, hbm_budget, ctypes.byref(self._h)))
 
     def close(self):
         if self._h:
+            kids = list(self._children)
+            for k in [k for k in kids if isinstance(k, Server)] + \
+                     [k for k in kids if not isinstance(k, Server)]:
+                k.close()
             library().cs_ctx_destroy(self._h)
             self._h = ctypes.c_void_p()
 
@@ -239,11 +247,19 @@ class Network:
         self.n_bus, self.n_branch = int(case["n_bus"]), int(case["n_branch"])
         self.n_gen, self.n_load = int(case["n_gen"]), int(case["n_load"])
         self.n_comp = self.n_branch + self.n_gen + self.n_load
+        self._servers = weakref.WeakSet()
+        kinds = np.asarray(case.get("gen_kind", np.zeros(self.n_gen)))
+        # largest state-matrix order: 7 per machine, 8 per converter, one
+        # angle removed
+        self.n_states_max = int(np.sum(np.where(kinds == 1, 8, 7))) - 1
         self._h = ctypes.c_void_p()
         _check(library().cs_net_create(ctx.handle, ctypes.byref(d), ctypes.byref(self._h)))
+        ctx._children.add(self)
 
     def close(self):
         if self._h:
+            for srv in list(self._servers):
+                srv.close()
             library().cs_net_destroy(self._h)
             self._h = ctypes.c_void_p()
 
@@ -359,8 +375,8 @@ class Network:
         va = np.zeros(self.n_bus)
         pg = np.zeros(self.n_gen)
         qg = np.zeros(self.n_gen)
-        er = np.zeros(7 * self.n_gen)
-        ei = np.zeros(7 * self.n_gen)
+        er = np.zeros(self.n_states_max)
+        ei = np.zeros(self.n_states_max)
         ne = np.zeros(1, dtype=np.int32)
         lab = np.zeros(self.n_bus, dtype=np.int32)
         o2 = np.ascontiguousarray(outage, dtype=np.int32).reshape(2)
@@ -379,7 +395,7 @@ class Network:
         out_list = np.ascontiguousarray(outages, dtype=np.int32).reshape(-1, 2)
         n = len(out_list)
         nb, ng = self.n_bus, self.n_gen
-        na = 7 * ng - 1
+        na = self.n_states_max
         res = np.zeros(n, dtype=RESULT_DTYPE)
         vm, va = np.zeros((n, nb)), np.zeros((n, nb))
         pg, qg = np.zeros((n, ng)), np.zeros((n, ng))
@@ -395,7 +411,7 @@ class Network:
     def dyn_at(self, outage, vm, va, pg, qg, eigenvalues: bool = True):
         """State matrix (row-major) and its eigenvalues at a given operating
         point over the whole network (only the island's entries are read)."""
-        na = 7 * self.n_gen - 1
+        na = self.n_states_max
         A = np.zeros(na * na)
         er, ei = np.zeros(na), np.zeros(na)
         ns = np.zeros(1, dtype=np.int32)
@@ -450,6 +466,8 @@ class Server:
         o = options or default_options()
         _check(library().cs_server_create(ctx.handle, net._h, ctypes.byref(o),
                                           int(queue_capacity), ctypes.byref(self._h)))
+        ctx._children.add(self)
+        net._servers.add(self)
 
     def submit(self, outages, lam=None) -> Request:
         out_list = np.ascontiguousarray(outages, dtype=np.int32).reshape(-1, 2)

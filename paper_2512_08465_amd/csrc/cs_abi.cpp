@@ -150,9 +150,11 @@ struct TimedLaunches {
 
 struct cs_net {
   cs_ctx* ctx = nullptr;
+  int device = 0;       // kept here so that destroying never reads the context
   DevNet d{};
   std::vector<void*> allocs;
   int nb = 0, nl = 0, ng = 0, nd = 0;
+  int na = 0;           // largest state-matrix order: 7 per machine + 8 per converter - 1
 };
 
 // Raise the dynamic LDS limit of the kernels that need more than the
@@ -280,7 +282,7 @@ static bool all_finite(const double* a, int n) {
 
 extern "C" void cs_net_destroy(cs_net* n) {
   if (!n) return;
-  if (n->ctx) hipSetDevice(n->ctx->device);
+  hipSetDevice(n->device);
   for (void* p : n->allocs) hipFree(p);
   delete n;
 }
@@ -291,8 +293,10 @@ extern "C" int cs_net_create(cs_ctx* ctx, const cs_net_desc* d, cs_net** out) {
   const int nb = d->n_bus, nl = d->n_branch, ng = d->n_gen, nd = d->n_load;
   if (nb <= 0 || nl < 0 || ng <= 0 || nd < 0)
     return fail(CS_EINVAL, "cs_net_create: sizes must be n_bus > 0, n_gen > 0, others >= 0");
-  if (nb > 4096 || ng > 1024 || 7 * ng - 1 > 1024)
-    return fail(CS_EUNSUPPORTED, "cs_net_create: at most 4096 buses and 146 generators' worth of states (1024)");
+  int n_states = 0;
+  for (int g = 0; g < ng; ++g) n_states += (d->gen_kind && d->gen_kind[g] == 1) ? 8 : 7;
+  if (nb > 4096 || ng > 1024 || n_states - 1 > 1024)
+    return fail(CS_EUNSUPPORTED, "cs_net_create: at most 4096 buses and 1024 dynamic states");
   if (d->ref_bus < 0 || d->ref_bus >= nb) return fail(CS_EINVAL, "cs_net_create: ref_bus out of range");
   if (!(d->base_mva > 0) || !(d->f_hz > 0)) return fail(CS_EINVAL, "cs_net_create: base_mva and f_hz must be > 0");
   const double* need[] = {d->vmin, d->vmax, d->gs, d->bs, d->br_r, d->br_x, d->br_b, d->br_rate,
@@ -322,16 +326,25 @@ extern "C" int cs_net_create(cs_ctx* ctx, const cs_net_desc* d, cs_net** out) {
   for (int g = 0; g < ng; ++g) {
     if (d->gen_bus[g] < 0 || d->gen_bus[g] >= nb)
       return fail(CS_EINVAL, "cs_net_create: generator " + std::to_string(g) + " bus out of range");
-    if (d->gen_kind && d->gen_kind[g] != 0)
-      return fail(CS_EUNSUPPORTED, "cs_net_create: only synchronous generators (kind 0)");
+    const int kind = d->gen_kind ? d->gen_kind[g] : 0;
+    if (kind != 0 && kind != 1)
+      return fail(CS_EUNSUPPORTED, "cs_net_create: generator kinds 0 (synchronous) and 1 "
+                                   "(grid-following converter) only");
     if (d->pmin[g] > d->pmax[g] || d->qmin[g] > d->qmax[g])
       return fail(CS_EINVAL, "cs_net_create: generator " + std::to_string(g) + " has min > max");
     const double* p = d->dyn + (size_t)g * CS_N_DYN;
-    // H, Td0', Tq0', TA, R, Tg, Tt appear as divisors
-    if (!(p[0] > 0) || !(p[6] > 0) || !(p[7] > 0) || !(p[10] > 0) || !(p[11] > 0) ||
-        !(p[12] > 0) || !(p[13] > 0))
-      return fail(CS_EINVAL, "cs_net_create: generator " + std::to_string(g) +
-                                 " needs positive H, Td0', Tq0', TA, R, Tg, Tt");
+    if (kind == 0) {
+      // H, Td0', Tq0', TA, R, Tg, Tt appear as divisors
+      if (!(p[0] > 0) || !(p[6] > 0) || !(p[7] > 0) || !(p[10] > 0) || !(p[11] > 0) ||
+          !(p[12] > 0) || !(p[13] > 0))
+        return fail(CS_EINVAL, "cs_net_create: generator " + std::to_string(g) +
+                                   " needs positive H, Td0', Tq0', TA, R, Tg, Tt");
+    } else {
+      // Kic, Lf, Cdc, Kidc, Vdc0 appear as divisors
+      if (!(p[3] > 0) || !(p[4] > 0) || !(p[6] > 0) || !(p[8] > 0) || !(p[9] > 0))
+        return fail(CS_EINVAL, "cs_net_create: converter " + std::to_string(g) +
+                                   " needs positive Kic, Lf, Cdc, Kidc, Vdc0");
+    }
   }
   for (int k = 0; k < nd; ++k)
     if (d->load_bus[k] < 0 || d->load_bus[k] >= nb)
@@ -352,7 +365,12 @@ extern "C" int cs_net_create(cs_ctx* ctx, const cs_net_desc* d, cs_net** out) {
   HIPCHK(hipSetDevice(ctx->device));
   cs_net* n = new cs_net();
   n->ctx = ctx;
+  n->device = ctx->device;
   n->nb = nb; n->nl = nl; n->ng = ng; n->nd = nd;
+  n->na = n_states - 1;
+  std::vector<int> kinds(ng, 0);
+  if (d->gen_kind)
+    for (int g = 0; g < ng; ++g) kinds[g] = d->gen_kind[g];
   // branch admittances (pi model, tap and shift on the from side)
   std::vector<double> yffr(nl), yffi(nl), yftr(nl), yfti(nl), ytfr(nl), ytfi(nl), yttr(nl), ytti(nl);
   for (int l = 0; l < nl; ++l) {
@@ -410,6 +428,7 @@ extern "C" int cs_net_create(cs_ctx* ctx, const cs_net_desc* d, cs_net** out) {
   UP(d->pmin, ng, D.pmin); UP(d->pmax, ng, D.pmax); UP(d->qmin, ng, D.qmin); UP(d->qmax, ng, D.qmax);
   UP(d->c2, ng, D.c2); UP(d->c1, ng, D.c1); UP(d->c0, ng, D.c0);
   UP(d->dyn, (size_t)ng * CS_N_DYN, D.dyn);
+  UP(kinds.data(), ng, D.gen_kind);
   UP(d->load_bus, nd, D.load_bus); UP(d->pd, nd, D.pd); UP(d->qd, nd, D.qd);
 #undef UP
   if (rc != CS_OK) {
@@ -440,7 +459,7 @@ static Plan plan_sizes(const cs_net* n, bool mixed) {
   s.ny = 2 * ng + 2 * nb;
   s.nyc = s.ny + 3 * ng;
   s.ldy = (int)round_up(s.nyc, 2);
-  s.na = 7 * ng - 1;
+  s.na = n->na;
   s.lda_a = (int)round_up(std::max(s.na, 1), 2);
   s.k_stride = round_up(std::max((size_t)s.nk * s.ldk, (size_t)s.ny * s.ldy), 64);
   s.a_stride = round_up((size_t)s.lda_a * s.na, 64);
@@ -749,6 +768,8 @@ static int run_screen(cs_ctx* c, cs_net* n, const int* d_out_list, long long N,
   int rc = check_opts(opts, "cs_screen");
   if (rc != CS_OK) return rc;
   HIPCHK(hipSetDevice(c->device));
+  // an error another runtime call left pending is not this call's
+  (void)hipGetLastError();
   Plan p = plan_sizes(n, opts.prec == CS_PREC_MIXED);
   const size_t budget = opts.hbm_budget ? opts.hbm_budget : c->hbm_budget;
   if (p.per_slot > budget)
@@ -961,6 +982,7 @@ struct cs_server {
   static constexpr int R = 1024;         // requests in flight at most
   cs_ctx* c = nullptr;
   cs_net* n = nullptr;
+  int device = 0;
   cs_opts opts{};
   Plan p;
   void* ws = nullptr;
@@ -1054,7 +1076,7 @@ static void server_fail_all(cs_server* S, int code, const std::string& msg) {
 }
 
 static void server_loop(cs_server* S) {
-  hipSetDevice(S->c->device);
+  hipSetDevice(S->device);
   int rc = S->e.start();
   if (rc != CS_OK) {
     server_fail_all(S, rc, g_err);
@@ -1093,6 +1115,7 @@ extern "C" int cs_server_create(cs_ctx* c, cs_net* n, const cs_opts* o,
   HIPCHK(hipSetDevice(c->device));
   cs_server* S = new cs_server();
   S->c = c;
+  S->device = c->device;
   S->n = n;
   S->opts = opts;
   S->q_cap = queue_capacity;
@@ -1169,7 +1192,7 @@ extern "C" void cs_server_destroy(cs_server* S) {
     S->cv_work.notify_all();
     S->th.join();
   }
-  hipSetDevice(S->c->device);
+  hipSetDevice(S->device);
   // requests the caller still holds outlive the server, detached from it
   for (cs_req* r : S->owned) {
     if (r->freed) {
@@ -1231,7 +1254,7 @@ extern "C" int cs_submit(cs_server* S, const int32_t* outages, int64_t n, const 
     *out = r;
     return CS_OK;
   }
-  hipSetDevice(S->c->device);
+  hipSetDevice(S->device);
   // copy into the ring (in two pieces when it wraps), tag the request
   const long long p0 = r->q0 % S->q_cap;
   const long long first = std::min<long long>(n, S->q_cap - p0);
@@ -1468,7 +1491,7 @@ extern "C" int cs_screen_detail(cs_ctx* c, cs_net* n, const int32_t* outages, in
   if (rc != CS_OK) return rc;
   if (N == 0) return CS_OK;
   HIPCHK(hipSetDevice(c->device));
-  const size_t nb = n->nb, ng = n->ng, na = 7 * (size_t)n->ng - 1;
+  const size_t nb = n->nb, ng = n->ng, na = (size_t)n->na;
   const size_t per = 2 * nb + 2 * ng + 2 * na;
   int* d_list = nullptr;
   cs_result* d_res = nullptr;

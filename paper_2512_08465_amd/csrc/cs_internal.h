@@ -26,6 +26,7 @@ namespace cs {
 
 constexpr int kDyn = 14;     // H D Xd Xq Xdp Xqp Td0p Tq0p Rs KA TA R Tg Tt
 constexpr int kNsSg = 7;     // delta omega Eq' Ed' Efd Psv Pm
+constexpr int kNsGfl = 8;    // theta_p x_pll x_id x_iq i_d i_q v_dc x_dc (converter)
 
 // Slot life cycle.  A free slot (EMPTY) is given the next scenario of the
 // list (NEW), islanded and set up (IPM), and leaves the interior-point loop
@@ -58,7 +59,10 @@ struct DevNet {
   const int* gen_bus;
   const double* pmin; const double* pmax; const double* qmin; const double* qmax;
   const double* c2; const double* c1; const double* c0;
-  const double* dyn;                               // [ng][kDyn]
+  const int* gen_kind;                             // 0 machine, 1 converter
+  const double* dyn;                               // [ng][kDyn]; a converter's row:
+                                                   // Kpp Kip Kpc Kic Lf Rf Cdc Kpdc
+                                                   // Kidc Vdc0
   const int* load_bus; const double* pd; const double* qd;
 };
 

@@ -8,6 +8,8 @@ island labels and the Risk Index over that list.
   c2_118: every N-1 outage plus a seeded sample of N-2 outages of the
           118-bus-shaped case (a stratified sample; the full list has 57,630)
   c2_118_full: the whole 57,630-scenario list of the 118-bus-shaped case
+  c3_118: the same stratified sample of the 118-bus shape with 16 machines
+          replaced by grid-following converters (c3_118 case)
   c1_30_n3: every N-3 triple of the 30-bus case's 41 branches (10,660 rows),
           all solved, with the pruning flags of screen.n3_prune (by c1_30's
           records) and R_i with pruned rows counted as severe
@@ -42,8 +44,9 @@ from inputs import netgen, contingencies          # noqa: E402
 from oracle import screen, risk                    # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SAMPLES = {"c1_30": None, "c2_118": 600, "c2_118_full": None, "c1_30_n3": None}
-WITH_DETAIL = {"c1_30", "c2_118"}
+SAMPLES = {"c1_30": None, "c2_118": 600, "c2_118_full": None, "c1_30_n3": None,
+           "c3_118": 600}
+WITH_DETAIL = {"c1_30", "c2_118", "c3_118"}
 CASE_OF = {"c2_118_full": "c2_118", "c1_30_n3": "c1_30"}
 _NET = None
 
@@ -98,7 +101,7 @@ def make(name, procs=8):
 
 def detail_arrays(net, res):
     nb, ng = int(net["n_bus"]), int(net["n_gen"])
-    na = 7 * ng - 1
+    na = int(np.sum(np.where(net["gen_kind"] == 1, 8, 7))) - 1
     n = len(res)
     d = {k: np.full((n, nb), np.nan) for k in ("vm", "va")}
     d.update({k: np.full((n, ng), np.nan) for k in ("pg", "qg")})

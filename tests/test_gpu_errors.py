@@ -124,3 +124,25 @@ def test_bad_options_rejected(c1, field, value):
     with pytest.raises(cs.CSError) as e:
         c1.screen(np.array([[0, -1]]), None, cs.default_options(**{field: value}))
     assert e.value.code == cs.CS_EINVAL
+
+
+def test_context_destroyed_before_its_network(c1):
+    """Destroying a context before its network (the C order, or a garbage
+    collector finalising both) leaves no error behind for later calls."""
+    import gc
+    import paper_2512_08465_amd as cs
+    case = load_case("c1_30")
+    ctx2 = cs.Context(0)
+    net2 = cs.Network(ctx2, case)
+    ctx2.close()                        # closes net2 first
+    assert not net2._h
+    ctx3 = cs.Context(0)
+    net3 = cs.Network(ctx3, case)
+    cs.library().cs_ctx_destroy(ctx3._h)  # the C order: context first
+    ctx3._h = type(ctx3._h)()
+    net3.close()
+    del net2, net3, ctx2, ctx3
+    gc.collect()
+    g = load_golden("c1_30")
+    res, _ = c1.screen(g["outages"][:5])
+    assert np.array_equal(res["n_islands"], g["n_islands"][:5])
