@@ -109,6 +109,9 @@ def main():
                     help="precisions to time: fp64 (the headline) and/or mixed")
     ap.add_argument("--overlap", type=int, default=0,
                     help="1: dynamic stage on a second stream beside the OPF iterations")
+    ap.add_argument("--c3-slice", type=int, default=14408,
+                    help="scenarios of the converter case (c3_118) screened in FP64 and "
+                         "mixed after the headline legs (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=12,
                     help="requests per arrival rate in the serving sweep (0: skip it)")
@@ -236,11 +239,73 @@ def main():
     }
     if "mixed" in results and legs[0] == "fp64":
         out["mixed"] = results["mixed"]
+    if args.c3_slice > 0:
+        out["c3"] = c3_legs(cs, ctx, torch, args, lst)
     if args.serve_requests > 0:
         out["serving"] = serve_sweep(cs, ctx, net, case, lst, args)
     if base is not None:
         out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
+
+
+def c3_legs(cs, ctx, torch, args, lst):
+    """The converter case (16 of the 54 machines replaced by grid-following
+    converters, 393 states): the first c3_slice scenarios of the same list,
+    FP64 and mixed, with the largest deviation of the mixed records from the
+    FP64 ones."""
+    import numpy as np
+    from inputs import netgen
+    case = netgen.load_case(os.path.join(ROOT, "inputs", "cases", "c3_118.npz"))
+    net = cs.Network(ctx, case)
+    n = min(args.c3_slice, len(lst))
+    dev = torch.device("cuda:0")
+    d_list = torch.from_numpy(np.ascontiguousarray(lst[:n])).to(dev)
+    d_lam = torch.from_numpy(case["lam"]).to(dev)
+    rec = cs.RESULT_DTYPE.itemsize
+    out, recs = {"scenarios": n, "state_order": net.n_states_max}, {}
+    for leg in ("fp64", "mixed"):
+        prec = cs.PREC_MIXED if leg == "mixed" else cs.PREC_FP64
+        d_res = torch.zeros(n * rec, dtype=torch.uint8, device=dev)
+        d_risk = torch.zeros(len(case["lam"]), dtype=torch.float64, device=dev)
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        net.screen_device(d_list.data_ptr(), min(n, args.warmup_size), d_lam.data_ptr(),
+                          d_res.data_ptr(), d_risk.data_ptr(),
+                          cs.default_options(batch=args.batch, prec=prec), stream=stream)
+        torch.cuda.synchronize()
+        ctx.reset_stats()
+        t0 = time.perf_counter()
+        net.screen_device(d_list.data_ptr(), n, d_lam.data_ptr(), d_res.data_ptr(),
+                          d_risk.data_ptr(), cs.default_options(batch=args.batch, prec=prec,
+                                                                timing=1), stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = ctx.stats()
+        lu = st["kkt_lu"]
+        nk = int(st["kkt_order"])
+        per = lu["units"] / max(lu["launches"], 1)
+        avg = lu["ms"] / max(lu["launches"], 1)
+        ach = per * kkt_lu_flops(nk) / (avg * 1e-3) / 1e12 if lu["ms"] else 0.0
+        peak = PEAK_FP32_TFLOPS if leg == "mixed" else PEAK_FP64_TFLOPS
+        out[leg] = {"value": round(n / dt, 3), "unit": "scenarios/s",
+                    "kkt_lu_tflops": round(ach, 4), "kkt_lu_frac": round(ach / peak, 5),
+                    "eig_share": round(st["eig"]["ms"] / max(sum(
+                        v["ms"] for v in st.values() if isinstance(v, dict)), 1e-9), 4)}
+        if leg == "mixed":
+            out[leg]["fp64_fallback_share"] = round(
+                st["kkt_lu64"]["units"] / max(lu["units"], 1), 4)
+        recs[leg] = d_res.cpu().numpy().view(cs.RESULT_DTYPE).copy()
+        log(f"c3 {leg}: {out[leg]['value']} scenarios/s")
+    a, b = recs["fp64"], recs["mixed"]
+    both = (a["opf_status"] == 0) & (b["opf_status"] == 0)
+    out["mixed_vs_fp64"] = {
+        "severity_differs": int((a["severe"] != b["severe"]).sum()),
+        "opf_cost_rel": float(np.max(np.abs(a["opf_cost"][both] - b["opf_cost"][both])
+                                     / np.abs(a["opf_cost"][both]))),
+        "max_real_eig": float(np.max(np.abs(a["max_real_eig"][both] - b["max_real_eig"][both])
+                                     / np.maximum(np.abs(a["max_real_eig"][both]), 1.0))),
+        "min_damping": float(np.max(np.abs(a["min_damping"][both] - b["min_damping"][both])))}
+    net.close()
+    return out
 
 
 def load_oracle_records():
