@@ -493,16 +493,19 @@ def serve(cs, ctx, net, case, lst, args, rate, prec):
     lens = np.floor(np.exp(rng.uniform(0, np.log(args.serve_max_len + 1), nreq)))
     lens = np.clip(lens.astype(int), 1, args.serve_max_len)
     lists = [lst[rng.choice(len(lst), k, replace=False)] for k in lens]
+    # each request screens its own snapshot: every load times N(1, 0.05)
+    from inputs.rate_samples import load_scales
+    scales = load_scales(int(case["n_load"]), nreq, seed=5000 + int(rate * 10))
     slots = 4096
     srv = cs.Server(ctx, net, cs.default_options(batch=slots, prec=prec),
                     queue_capacity=1 << 17)
     reqs = []
     t0 = time.perf_counter()
     due = t0
-    for g, l in zip(gaps, lists):
+    for g, l, sc in zip(gaps, lists, scales):
         due += g
         time.sleep(max(0.0, due - time.perf_counter()))
-        reqs.append(srv.submit(l, case["lam"]))
+        reqs.append(srv.submit(l, case["lam"], load_scale=sc))
     lat = []
     for r in reqs:
         _, _, l = r.wait(timeout_s=600)
@@ -513,6 +516,7 @@ def serve(cs, ctx, net, case, lst, args, rate, prec):
     lat = np.array(lat)
     return dict(requests=int(nreq), rate_per_s=rate,
                 length="log-uniform integer in [1, %d]" % args.serve_max_len,
+                snapshot="every load of a request times N(1, 0.05)",
                 scenarios=int(lens.sum()), slots=slots,
                 p50_latency_s=round(float(np.percentile(lat, 50)), 4),
                 p99_latency_s=round(float(np.percentile(lat, 99)), 4),

@@ -399,6 +399,15 @@ void cs_server_destroy(cs_server* srv);
 int cs_submit(cs_server* srv, const int32_t* outages, int64_t n, const double* lambda,
               cs_req** out);
 
+/* As cs_submit, for a snapshot of the network whose loads differ: every
+ * load d of the request's scenarios is load_scale[d] times the network's
+ * (host [n_load], finite and >= 0, copied before the call returns; NULL =
+ * the network's loads).  Records equal cs_screen's on a network created with
+ * the scaled loads.  The real-time data stage of the operator tool of
+ * Section V.E: each request screens the grid state it was taken at. */
+int cs_submit_snapshot(cs_server* srv, const int32_t* outages, int64_t n,
+                       const double* lambda, const double* load_scale, cs_req** out);
+
 /* Wait up to timeout_us microseconds (< 0: no limit) for a request; then
  * copy its records (out [n]) and R_i (risk [n_comp], if lambda was given;
  * either may be NULL) and its latency in seconds from admission to the last

@@ -132,6 +132,7 @@ def library():
                                             ctypes.POINTER(vp)]),
         "cs_server_destroy": (None, [vp]),
         "cs_submit": (ctypes.c_int, [vp, vp, i64, dp, ctypes.POINTER(vp)]),
+        "cs_submit_snapshot": (ctypes.c_int, [vp, vp, i64, dp, dp, ctypes.POINTER(vp)]),
         "cs_wait": (ctypes.c_int, [vp, i64, vp, dp, dp]),
         "cs_req_free": (None, [vp]),
     }
@@ -149,7 +150,7 @@ EXPORTED = ("cs_ctx_create", "cs_ctx_destroy", "cs_net_create", "cs_net_destroy"
             "cs_stats_reset", "cs_last_error", "cs_abi_version", "cs_server_create",
             "cs_server_destroy", "cs_submit", "cs_wait", "cs_req_free", "cs_screen_detail",
             "cs_dyn_at", "cs_screen_device_noalloc", "cs_risk_opts_default", "cs_risk",
-            "cs_risk_mc", "cs_screen3_device", "cs_screen_n3_device")
+            "cs_risk_mc", "cs_screen3_device", "cs_screen_n3_device", "cs_submit_snapshot")
 
 
 def _check(rc):
@@ -469,12 +470,19 @@ class Server:
         ctx._children.add(self)
         net._servers.add(self)
 
-    def submit(self, outages, lam=None) -> Request:
+    def submit(self, outages, lam=None, load_scale=None) -> Request:
+        """Admit a request; load_scale [n_load] screens it on a snapshot of
+        the network with every load scaled by its factor."""
         out_list = np.ascontiguousarray(outages, dtype=np.int32).reshape(-1, 2)
         lam_a = None if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
         h = ctypes.c_void_p()
-        _check(library().cs_submit(self._h, _ptr(out_list), len(out_list), _ptr(lam_a),
-                                   ctypes.byref(h)))
+        if load_scale is None:
+            _check(library().cs_submit(self._h, _ptr(out_list), len(out_list), _ptr(lam_a),
+                                       ctypes.byref(h)))
+        else:
+            sc = np.ascontiguousarray(load_scale, dtype=np.float64)
+            _check(library().cs_submit_snapshot(self._h, _ptr(out_list), len(out_list),
+                                                _ptr(lam_a), _ptr(sc), ctypes.byref(h)))
         return Request(self, h, len(out_list), lam is not None)
 
     def close(self):

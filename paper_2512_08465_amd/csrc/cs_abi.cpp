@@ -579,6 +579,7 @@ struct Engine {
   long long q_cap = 0;
   const int* item_req = nullptr;
   int* req_done = nullptr;
+  const double* load_scale = nullptr;  // serving: [request slot][n_load] factors
   TimedLaunches* T = nullptr;
   const DetailOut* detail = nullptr;   // per-scenario detail (parity entry point)
   int width = 2;                 // ids per outage row (3 for N-3 lists)
@@ -624,7 +625,7 @@ struct Engine {
       rc = timed(CS_K_TOPOLOGY, st, nnew, -1, [&] {
         launch_refill(s, nslots, d_next, N, q_cap, st);
         launch_islands(*D, s, d_list, nslots, st, width);
-        launch_setup_k(*D, s, nslots, d_list, st, width);
+        launch_setup_k(*D, s, nslots, d_list, st, width, load_scale, item_req);
       });
       if (rc != CS_OK) return rc;
       work = true;
@@ -993,6 +994,7 @@ struct cs_server {
   int* q_out = nullptr;                  // ring of outage pairs
   cs_result* q_res = nullptr;            // ring of records
   int* item_req = nullptr;               // ring: request table index per scenario
+  double* req_scale = nullptr;           // [R][n_load] each request's load factors
   int* req_done = nullptr;               // [R] records completed per request
   int* h_req_done = nullptr;             // pinned copy
   int* d_sched = nullptr;                // next (64-bit) + stage counts
@@ -1143,6 +1145,8 @@ extern "C" int cs_server_create(cs_ctx* c, cs_net* n, const cs_opts* o,
       hipMalloc(&S->q_out, sizeof(int) * 2 * queue_capacity) != hipSuccess ||
       hipMalloc(&S->q_res, sizeof(cs_result) * queue_capacity) != hipSuccess ||
       hipMalloc(&S->item_req, sizeof(int) * queue_capacity) != hipSuccess ||
+      hipMalloc(&S->req_scale, sizeof(double) * (size_t)cs_server::R *
+                                   std::max(n->nd, 1)) != hipSuccess ||
       hipMalloc(&S->req_done, sizeof(int) * cs_server::R) != hipSuccess ||
       hipHostMalloc(&S->h_req_done, sizeof(int) * cs_server::R, hipHostMallocDefault) != hipSuccess ||
       hipMalloc(&S->d_sched, sizeof(int) * (PH_COUNT + 2)) != hipSuccess ||
@@ -1175,6 +1179,7 @@ extern "C" int cs_server_create(cs_ctx* c, cs_net* n, const cs_opts* o,
   e.d_res = S->q_res;
   e.q_cap = queue_capacity;
   e.item_req = S->item_req;
+  e.load_scale = S->req_scale;
   e.req_done = S->req_done;
   e.T = nullptr;
   S->th = std::thread(server_loop, S);
@@ -1206,7 +1211,8 @@ extern "C" void cs_server_destroy(cs_server* S) {
     }
     r->srv = nullptr;
   }
-  for (void* q : {(void*)S->q_out, (void*)S->q_res, (void*)S->item_req, (void*)S->req_done,
+  for (void* q : {(void*)S->q_out, (void*)S->q_res, (void*)S->item_req, (void*)S->req_scale,
+                  (void*)S->req_done,
                   (void*)S->d_sched, (void*)S->g_out, (void*)S->g_res, (void*)S->g_lam,
                   (void*)S->g_risk, S->ws})
     if (q) hipFree(q);
@@ -1219,14 +1225,24 @@ extern "C" void cs_server_destroy(cs_server* S) {
   delete S;
 }
 
-extern "C" int cs_submit(cs_server* S, const int32_t* outages, int64_t n, const double* lambda,
-                         cs_req** out) {
+static int submit(cs_server* S, const int32_t* outages, int64_t n, const double* lambda,
+                  const double* load_scale, cs_req** out) {
   if (!S || !out || n < 0 || (n > 0 && !outages)) return fail(CS_EINVAL, "cs_submit: bad arguments");
   *out = nullptr;
   if (n > S->q_cap) return fail(CS_EINVAL, "cs_submit: request longer than the ring");
   int rc = validate_host(S->n, outages, n, lambda);
   if (rc != CS_OK) return rc;
   const int n_comp = S->n->nl + S->n->ng + S->n->nd;
+  const int nd = S->n->nd;
+  std::vector<double> scale(std::max(nd, 1), 1.0);
+  if (load_scale) {
+    for (int d = 0; d < nd; ++d) {
+      if (!(load_scale[d] >= 0) || !std::isfinite(load_scale[d]))
+        return fail(CS_EINVAL, "cs_submit_snapshot: load factor " + std::to_string(d) +
+                                   " must be finite and >= 0");
+      scale[d] = load_scale[d];
+    }
+  }
   std::unique_lock<std::mutex> lk(S->m);
   if (S->error != CS_OK) return fail(S->error, "cs_submit: server failed: " + S->error_msg);
   long long oldest = S->submitted;
@@ -1263,6 +1279,9 @@ extern "C" int cs_submit(cs_server* S, const int32_t* outages, int64_t n, const 
   if (ok && first < n)
     ok = hipMemcpyAsync(S->q_out, outages + 2 * first, sizeof(int) * 2 * (n - first),
                         hipMemcpyHostToDevice, S->scopy) == hipSuccess;
+  if (ok && nd > 0)
+    ok = hipMemcpyAsync(S->req_scale + (size_t)slot * nd, scale.data(), sizeof(double) * nd,
+                        hipMemcpyHostToDevice, S->scopy) == hipSuccess;
   if (ok) {
     launch_fill_req(S->item_req, r->q0, (int)n, S->q_cap, slot, S->scopy);
     ok = hipMemsetAsync(S->req_done + slot, 0, sizeof(int), S->scopy) == hipSuccess &&
@@ -1279,6 +1298,17 @@ extern "C" int cs_submit(cs_server* S, const int32_t* outages, int64_t n, const 
   S->cv_work.notify_all();
   *out = r;
   return CS_OK;
+}
+
+extern "C" int cs_submit(cs_server* S, const int32_t* outages, int64_t n, const double* lambda,
+                         cs_req** out) {
+  return submit(S, outages, n, lambda, nullptr, out);
+}
+
+extern "C" int cs_submit_snapshot(cs_server* S, const int32_t* outages, int64_t n,
+                                  const double* lambda, const double* load_scale,
+                                  cs_req** out) {
+  return submit(S, outages, n, lambda, load_scale, out);
 }
 
 extern "C" int cs_wait(cs_req* r, int64_t timeout_us, cs_result* out, double* risk,

@@ -119,8 +119,11 @@ struct DetailOut {
 // outage rows hold `width` ids each (2: N-1/N-2 lists, 3: N-3 lists), -1 pads
 void launch_islands(const DevNet& net, const Slots& s, const int* outages,
                     int count, hipStream_t st, int width = 2);
+// load_scale [requests][n_load] with item_req (ring position -> request):
+// per-request load factors of a server (nullptr: the network's loads)
 void launch_setup_k(const DevNet& net, const Slots& s, int count, const int* outages,
-                    hipStream_t st, int width = 2);
+                    hipStream_t st, int width = 2, const double* load_scale = nullptr,
+                    const int* item_req = nullptr);
 void launch_opf_eval(const DevNet& net, const Slots& s, int count, double tol,
                      int max_it, hipStream_t st);
 void launch_opf_update(const DevNet& net, const Slots& s, int count,

@@ -109,7 +109,9 @@ __device__ inline int risum(int v, int* red) {
 // ---------------------------------------------------------------- setup
 __global__ __launch_bounds__(OPF_THREADS) void k_setup(DevNet net, Slots s,
                                                        int count, const int* __restrict__ outages,
-                                                       int width) {
+                                                       int width,
+                                                       const double* __restrict__ load_scale,
+                                                       const int* __restrict__ item_req) {
   const int slot = blockIdx.x;
   if (slot >= count) return;
   SlotState& S = s.st[slot];
@@ -130,6 +132,10 @@ __global__ __launch_bounds__(OPF_THREADS) void k_setup(DevNet net, Slots s,
   double* pd = const_cast<double*>(v.pd);
   double* qd = const_cast<double*>(v.qd);
   const int load0 = nl + ng;
+  // a served request's own load snapshot: every load scaled by its factor
+  const double* scale = (load_scale != nullptr && item_req != nullptr)
+                            ? load_scale + (size_t)item_req[scen] * net.nd
+                            : nullptr;
   int cnt = 0;
   for (int b = tid; b < nb; b += OPF_THREADS) {
     const bool on = label[b] == main;
@@ -139,8 +145,13 @@ __global__ __launch_bounds__(OPF_THREADS) void k_setup(DevNet net, Slots s,
       for (int e = net.bus_load_ptr[b]; e < net.bus_load_ptr[b + 1]; ++e) {
         const int d = net.bus_load[e];
         if (load0 + d == o0 || load0 + d == o1 || load0 + d == o2) continue;
-        p += net.pd[d];
-        q += net.qd[d];
+        if (scale != nullptr) {
+          p += net.pd[d] * scale[d];
+          q += net.qd[d] * scale[d];
+        } else {
+          p += net.pd[d];
+          q += net.qd[d];
+        }
       }
       cnt += 2;
     }
@@ -710,10 +721,11 @@ void opf_set_attrs(size_t bytes) {
 }
 
 void launch_setup_k(const DevNet& net, const Slots& s, int count,
-                    const int* outages, hipStream_t st, int width) {
+                    const int* outages, hipStream_t st, int width, const double* load_scale,
+                    const int* item_req) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_setup, dim3(count), dim3(OPF_THREADS), 0, st, net, s,
-                     count, outages, width);
+                     count, outages, width, load_scale, item_req);
 }
 
 void launch_opf_eval(const DevNet& net, const Slots& s, int count, double tol,

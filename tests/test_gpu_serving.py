@@ -128,3 +128,60 @@ def test_overlapped_streams_and_refill_equal(nets):
     _same(a, b)
     _same(a, c)
     assert np.array_equal(Ra, Rb) and np.array_equal(Ra, Rc)
+
+
+def _scaled_case(case, scale):
+    c = dict(case)
+    c["pd"] = case["pd"] * scale
+    c["qd"] = case["qd"] * scale
+    return c
+
+
+def test_load_snapshots_equal_scaled_networks(nets):
+    """Requests carrying their own load snapshot (every load times an N(1,
+    0.05) factor), several in flight at once, give record for record what
+    cs_screen gives on a network created with those loads; and the scaled
+    network agrees with the oracle on the same snapshot."""
+    import paper_2512_08465_amd as cs
+    from inputs.rate_samples import load_scales
+    from oracle import screen
+    net, case = nets["c2_118"]
+    nd = int(case["n_load"])
+    scales = load_scales(nd, 3, seed=77)
+    lists = _lists("c2_118", [40, 15, 60], seed=9)
+    srv = cs.Server(net.ctx, net, cs.default_options(batch=48), queue_capacity=4096)
+    reqs = [srv.submit(l, case["lam"], load_scale=s) for l, s in zip(lists, scales)]
+    plain = srv.submit(lists[0], case["lam"])        # the network's own loads, in the mix
+    got = []
+    for l, s, r in zip(lists, scales, reqs):
+        res, risk, _ = r.wait(timeout_s=300)
+        got.append(res)
+        snap = cs.Network(net.ctx, _scaled_case(case, s))
+        ref, ref_risk = snap.screen(l, case["lam"])
+        _same(res, ref)
+        assert np.array_equal(risk, ref_risk)
+        snap.close()
+    res0, _, _ = plain.wait(timeout_s=300)
+    ref0, _ = net.screen(lists[0], case["lam"])
+    _same(res0, ref0)
+    srv.close()
+    # the snapshot itself against the oracle
+    sc = _scaled_case(case, scales[0])
+    for o, rec in zip(lists[0][:6], got[0][:6]):
+        ref = screen.evaluate(sc, o)
+        assert rec["n_islands"] == ref.n_islands
+        if ref.opf_status == 0 and rec["opf_status"] == 0:
+            assert abs(rec["opf_cost"] - ref.opf_cost) < 1e-6 * abs(ref.opf_cost)
+            assert abs(rec["max_real_eig"] - ref.max_real_eig) < 1e-6 * max(1.0, abs(ref.max_real_eig))
+
+
+def test_snapshot_factors_validated(nets):
+    import paper_2512_08465_amd as cs
+    net, case = nets["c1_30"]
+    srv = cs.Server(net.ctx, net, cs.default_options(batch=16), queue_capacity=256)
+    bad = np.ones(int(case["n_load"]))
+    bad[2] = np.nan
+    with pytest.raises(cs.CSError) as e:
+        srv.submit(_lists("c1_30", [3], 1)[0], case["lam"], load_scale=bad)
+    assert e.value.code == cs.CS_EINVAL
+    srv.close()
