@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcs.so")
 SOURCES = ["k_topology.hip", "k_opf.hip", "k_dense.hip", "k_mixed.hip", "k_dyn.hip",
-           "k_eig.hip", "k_finalize.hip", "k_risk.hip", "k_prune.hip", "cs_abi.cpp"]
+           "k_eig.hip", "k_finalize.hip", "k_risk.hip", "k_prune.hip", "k_lu_big.hip", "cs_abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall", "-pthread",
          # loadable by the HIP runtime that PyTorch ships (one runtime per process)

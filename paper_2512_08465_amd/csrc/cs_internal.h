@@ -134,6 +134,13 @@ enum LuRole : int { LU_KKT = 0, LU_DYN = 1, LU_KKT_FALLBACK = 2 };
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
                      int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
                      int count, int* info, hipStream_t stream, int role = LU_KKT);
+// orders above the register-resident kernel's limit (k_lu_big.hip)
+void launch_lu_big(double* A, size_t stride, int n, int ncols, int lda, int* piv,
+                   int piv_stride, SlotState* st, int want_phase, int want_job, int count,
+                   int* info, hipStream_t stream);
+void launch_lu_big_f32(float* A, size_t stride, int n, int ncols, int lda, int* piv,
+                       int piv_stride, SlotState* st, int want_phase, int want_job, int count,
+                       int* info, hipStream_t stream);
 void launch_lu_solve_f32(float* A, size_t stride, int n, int ncols, int lda,
                          int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
                          int count, int* info, hipStream_t stream);

@@ -814,18 +814,26 @@ static size_t lu_dynamic_lds(int n, int nrhs) {
 
 // total LDS one workgroup of the FP64 k_lu_solve needs for order n and nrhs
 // columns (the FP32 one needs less), with room for the compiler's padding of
-// the static part
+// the static part; orders above LU_MAX_N go to k_lu_big, whose LDS is static
+// and small
 size_t lu_lds_bytes(int n, int nrhs) {
+  if (n > LU_MAX_N) return 0;
   return lu_dynamic_lds<double>(n, nrhs) + lu_static_lds<double>() + 256;
 }
 
-// largest order k_lu_solve handles (panel rows are held in registers)
-int lu_max_order() { return LU_MAX_N; }
+// largest order the batched LU entry points take: k_lu_solve up to LU_MAX_N
+// (panel rows in registers), k_lu_big above
+int lu_max_order() { return 4096; }
 
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
                      int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
                      int count, int* info, hipStream_t stream, int role) {
   if (count <= 0) return;
+  if (n > LU_MAX_N) {
+    launch_lu_big(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, count,
+                  info, stream);
+    return;
+  }
   const size_t lds = lu_dynamic_lds<double>(n, ncols - n);
   auto k = role == LU_DYN ? k_lu_solve<double, LU_DYN>
            : role == LU_KKT_FALLBACK ? k_lu_solve<double, LU_KKT_FALLBACK>
@@ -838,6 +846,11 @@ void launch_lu_solve_f32(float* A, size_t stride, int n, int ncols, int lda,
                          int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
                          int count, int* info, hipStream_t stream) {
   if (count <= 0) return;
+  if (n > LU_MAX_N) {
+    launch_lu_big_f32(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, count,
+                      info, stream);
+    return;
+  }
   const size_t lds = lu_dynamic_lds<float>(n, ncols - n);
   hipLaunchKernelGGL((k_lu_solve<float, LU_KKT>), dim3(count), dim3(LU_THREADS), lds, stream,
                      A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, info);

@@ -1,0 +1,255 @@
+// Batched dense LU with partial pivoting and solve for orders above the
+// register-resident kernel's limit (k_dense.hip holds panels of up to 1,024
+// rows in registers): one workgroup per matrix, the matrix in global memory.
+//
+// Right-looking blocked LU, panel width 32, the same arithmetic contract as
+// LAPACK's getrf (largest |a| pivot, ties to the lowest row, rows swapped
+// across the whole augmented matrix, multipliers by division):
+//   panel   column by column over the rows below the diagonal: a workgroup
+//           argmax, the row interchange across every column, the scaling and
+//           the rank-1 update of the panel's remaining columns;
+//   U12     inv(L11) A12 for the panel's block row right of it (each thread
+//           owns columns, L11 staged in LDS);
+//   update  A22 -= L21 U12 on the matrix cores (v_mfma_f64_16x16x4f64, or
+//           the FP32 step for the mixed-precision factorisation), 32 x 32
+//           groups handed to the wavefronts in turn;
+//   solve   U x = y for the right-hand-side columns by 32-row blocks from the
+//           bottom (the forward substitution happened on the augmented
+//           columns during the elimination).
+// Its bound is the latency of the panel steps (four barriers per column);
+// it serves the KKT systems of networks whose order exceeds 1,024.
+#include "cs_internal.h"
+
+#include <climits>
+
+namespace cs {
+
+constexpr int BIG_T = 512, BIG_W = BIG_T / 64, BIG_NB = 32;
+
+template <class T> struct BigMfma;
+template <> struct BigMfma<double> {
+  typedef double acc __attribute__((ext_vector_type(4)));
+  static __device__ inline acc mac(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // accumulator q of lane (li, lk) holds row lk + 4 q, column li
+  static __device__ constexpr int row(int lk, int q) { return lk + 4 * q; }
+};
+template <> struct BigMfma<float> {
+  typedef float acc __attribute__((ext_vector_type(4)));
+  static __device__ inline acc mac(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // accumulator q of lane (li, lk) holds row 4 lk + q, column li
+  static __device__ constexpr int row(int lk, int q) { return 4 * lk + q; }
+};
+
+template <class T>
+__device__ inline bool big_better(T v, int i, T bv, int bi) {
+  return v > bv || (v == bv && i < bi);
+}
+
+// two workgroups per CU (register budget of 128), so that one's panel
+// latency overlaps the other's work
+template <class T>
+__global__ __launch_bounds__(BIG_T, 2) void k_lu_big(T* __restrict__ Abase, size_t stride, int n,
+                                                  int ncols, int lda, int* __restrict__ pivbase,
+                                                  int piv_stride, SlotState* __restrict__ st,
+                                                  int want_phase, int want_job,
+                                                  int* __restrict__ info) {
+  const int slot = blockIdx.x;
+  if (st != nullptr && (st[slot].job != want_job || st[slot].phase != want_phase)) return;
+  T* __restrict__ A = Abase + (size_t)slot * stride;
+  int* __restrict__ piv = pivbase + (size_t)slot * piv_stride;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  __shared__ T L11[BIG_NB][BIG_NB + 1];
+  __shared__ T red_v[BIG_W];
+  __shared__ int red_i[BIG_W];
+  __shared__ int s_p, s_sing;
+  __shared__ T s_d;
+  __shared__ T ublk[BIG_NB][BIG_NB + 1];
+  if (tid == 0) s_sing = 0;
+  __syncthreads();
+#define AA(r, c) A[(size_t)(r) * lda + (c)]
+  for (int k0 = 0; k0 < n; k0 += BIG_NB) {
+    const int kb = min(BIG_NB, n - k0);
+    const int k1 = k0 + kb;
+    // ---------------- panel
+    for (int j = k0; j < k1; ++j) {
+      T bv = T(-1);
+      int bi = INT_MAX;
+      for (int i = j + tid; i < n; i += BIG_T) {
+        const T x = AA(i, j);
+        // a NaN entry ranks above every number, so a row is always chosen
+        const T a = (x == x) ? fabs(x) : T(HUGE_VAL);
+        if (big_better(a, i, bv, bi)) {
+          bv = a;
+          bi = i;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const T v2 = __shfl_xor(bv, off, 64);
+        const int i2 = __shfl_xor(bi, off, 64);
+        if (big_better(v2, i2, bv, bi)) {
+          bv = v2;
+          bi = i2;
+        }
+      }
+      if (lane == 0) {
+        red_v[wave] = bv;
+        red_i[wave] = bi;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        T v = red_v[0];
+        int p = red_i[0];
+        for (int w = 1; w < BIG_W; ++w)
+          if (big_better(red_v[w], red_i[w], v, p)) {
+            v = red_v[w];
+            p = red_i[w];
+          }
+        s_p = p;
+        piv[j] = p;
+      }
+      __syncthreads();
+      const int p = s_p;
+      if (p != j)
+        for (int c = tid; c < ncols; c += BIG_T) {
+          const T a = AA(j, c), b = AA(p, c);
+          AA(j, c) = b;
+          AA(p, c) = a;
+        }
+      __syncthreads();
+      if (tid == 0) {
+        s_d = AA(j, j);
+        if (s_d == T(0)) s_sing = 1;
+      }
+      __syncthreads();
+      const T d = s_d;
+      if (d != T(0)) {
+        // multipliers, then the rank-1 update of the panel's other columns;
+        // each thread owns its rows
+        for (int i = j + 1 + tid; i < n; i += BIG_T) {
+          const T l = AA(i, j) / d;
+          AA(i, j) = l;
+          for (int c = j + 1; c < k1; ++c) AA(i, c) -= l * AA(j, c);
+        }
+      }
+      __syncthreads();
+    }
+    if (k1 >= ncols) continue;
+    // ---------------- U12 = inv(L11) A12 (L11 unit lower)
+    for (int e = tid; e < kb * kb; e += BIG_T) {
+      const int r = e / kb, c = e % kb;
+      L11[r][c] = AA(k0 + r, k0 + c);
+    }
+    __syncthreads();
+    // each thread owns columns; the column's values stay in the caches
+    for (int c = k1 + tid; c < ncols; c += BIG_T)
+      for (int r = 1; r < kb; ++r) {
+        T acc = AA(k0 + r, c);
+        for (int t = 0; t < r; ++t) acc -= L11[r][t] * AA(k0 + t, c);
+        AA(k0 + r, c) = acc;
+      }
+    __syncthreads();
+    // ---------------- A22 -= L21 U12 on the matrix cores, 32 x 32 groups
+    const int gr = (n - k1 + 31) / 32, gc = (ncols - k1 + 31) / 32;
+    for (int t = wave; t < gr * gc; t += BIG_W) {
+      const int i0 = k1 + 32 * (t / gc), j0 = k1 + 32 * (t % gc);
+      typename BigMfma<T>::acc acc[2][2];
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = i0 + 16 * ti + BigMfma<T>::row(lk, q), c = j0 + 16 * tj + li;
+            acc[ti][tj][q] = (r < n && c < ncols) ? AA(r, c) : T(0);
+          }
+#pragma unroll
+      for (int kk = 0; kk < BIG_NB; kk += 4) {
+        const int k = kk + lk;
+        T a[2], b[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int r = i0 + 16 * u + li, c = j0 + 16 * u + li;
+          a[u] = (k < kb && r < n) ? -AA(r, k0 + k) : T(0);
+          b[u] = (k < kb && c < ncols) ? AA(k0 + k, c) : T(0);
+        }
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = BigMfma<T>::mac(a[ti], b[tj], acc[ti][tj]);
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = i0 + 16 * ti + BigMfma<T>::row(lk, q), c = j0 + 16 * tj + li;
+            if (r < n && c < ncols) AA(r, c) = acc[ti][tj][q];
+          }
+    }
+    __syncthreads();
+  }
+  // ---------------- U x = y, 32-row blocks from the bottom
+  const int nrhs = ncols - n;
+  for (int r1 = n; r1 > 0; r1 -= BIG_NB) {
+    const int r0 = max(0, r1 - BIG_NB), bs = r1 - r0;
+    for (int e = tid; e < bs * bs; e += BIG_T) {
+      const int r = e / bs, c = e % bs;
+      ublk[r][c] = AA(r0 + r, r0 + c);
+    }
+    __syncthreads();
+    // the diagonal block: one thread per right-hand side
+    for (int c = n + tid; c < ncols; c += BIG_T) {
+      for (int r = bs - 1; r >= 0; --r) {
+        T acc = AA(r0 + r, c);
+        for (int t = r + 1; t < bs; ++t) acc -= ublk[r][t] * AA(r0 + t, c);
+        AA(r0 + r, c) = acc / ublk[r][r];
+      }
+    }
+    __syncthreads();
+    // the rows above take the block's solution
+    const long long work = (long long)r0 * nrhs;
+    for (long long e = tid; e < work; e += BIG_T) {
+      const int r = (int)(e / nrhs), c = n + (int)(e % nrhs);
+      T acc = AA(r, c);
+      for (int t = 0; t < bs; ++t) acc -= AA(r, r0 + t) * AA(r0 + t, c);
+      AA(r, c) = acc;
+    }
+    __syncthreads();
+  }
+#undef AA
+  if (tid == 0) {
+    if (st != nullptr) st[slot].singular = s_sing;
+    if (info != nullptr) info[slot] = s_sing;
+  }
+}
+
+template <class T>
+void launch_lu_big_t(T* A, size_t stride, int n, int ncols, int lda, int* piv, int piv_stride,
+                     SlotState* st, int want_phase, int want_job, int count, int* info,
+                     hipStream_t stream) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_lu_big<T>, dim3(count), dim3(BIG_T), 0, stream, A, stride, n, ncols, lda,
+                     piv, piv_stride, st, want_phase, want_job, info);
+}
+
+void launch_lu_big(double* A, size_t stride, int n, int ncols, int lda, int* piv,
+                   int piv_stride, SlotState* st, int want_phase, int want_job, int count,
+                   int* info, hipStream_t stream) {
+  launch_lu_big_t(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, count,
+                  info, stream);
+}
+
+void launch_lu_big_f32(float* A, size_t stride, int n, int ncols, int lda, int* piv,
+                       int piv_stride, SlotState* st, int want_phase, int want_job, int count,
+                       int* info, hipStream_t stream) {
+  launch_lu_big_t(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, count,
+                  info, stream);
+}
+
+}  // namespace cs

@@ -40,7 +40,9 @@ def _run_lu(ctx, mats, rhs):
 
 @pytest.mark.parametrize("n,k,B", [(1, 1, 3), (5, 2, 4), (16, 1, 2), (17, 3, 5), (32, 1, 2),
                                    (33, 1, 3), (64, 2, 2), (65, 1, 2), (131, 1, 4), (200, 7, 2),
-                                   (344, 162, 2), (513, 1, 2), (580, 1, 3), (1024, 1, 1)])
+                                   (344, 162, 2), (513, 1, 2), (580, 1, 3), (1024, 1, 1),
+                                   # above 1,024: the global-memory kernel (k_lu_big)
+                                   (1025, 1, 1), (1100, 5, 1), (1338, 1, 2), (1500, 2, 1)])
 def test_lu_solve_matches_scipy(ctx, n, k, B):
     rng = np.random.default_rng(n * 100 + k)
     A = rng.standard_normal((B, n, n))
@@ -90,11 +92,35 @@ def test_lu_saddle_point_needs_pivoting(ctx):
         assert np.allclose(sol[b], ref, rtol=1e-9, atol=1e-10)
 
 
-def test_lu_singular_flag(ctx):
-    A = np.ones((2, 8, 8))
-    A[1] = np.eye(8)
-    _, _, info = _run_lu(ctx, A, np.ones((2, 8, 1)))
+@pytest.mark.parametrize("n", [8, 1100])
+def test_lu_singular_flag(ctx, n):
+    A = np.ones((2, n, n))
+    A[1] = np.eye(n)
+    _, _, info = _run_lu(ctx, A, np.ones((2, n, 1)))
     assert info[0] == 1 and info[1] == 0
+
+
+def test_lu_big_pivot_ties_and_saddle_point(ctx):
+    """Above 1,024: ties go to the first row as in LAPACK, and a saddle-point
+    system (the KKT structure) needs and gets the interchanges."""
+    rng = np.random.default_rng(5)
+    n = 1200
+    A = rng.standard_normal((1, n, n))
+    A[0, :, 0] = rng.choice([-1.0, 1.0, 0.5], size=n)
+    fac, _, info = _run_lu(ctx, A, A @ rng.standard_normal((1, n, 1)))
+    lu, _ = sla.lu_factor(A[0])
+    assert info[0] == 0
+    assert np.allclose(fac[0], lu, rtol=1e-9, atol=1e-9 * np.abs(lu).max())
+    nx, ne = 800, 500
+    M = rng.standard_normal((nx, nx))
+    M = M @ M.T + np.eye(nx)
+    J = rng.standard_normal((ne, nx))
+    K = np.block([[M, J.T], [J, np.zeros((ne, ne))]])[None]
+    r = rng.standard_normal((1, nx + ne, 1))
+    _, sol, info = _run_lu(ctx, K, r)
+    assert info[0] == 0
+    ref = np.linalg.solve(K[0], r[0])
+    assert np.max(np.abs(sol[0] - ref)) <= 1e-12 * np.linalg.cond(K[0]) * np.abs(ref).max()
 
 
 def _run_eig(ctx, mats):
