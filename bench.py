@@ -112,6 +112,9 @@ def main():
     ap.add_argument("--c3-slice", type=int, default=14408,
                     help="scenarios of the converter case (c3_118) screened in FP64 and "
                          "mixed after the headline legs (0: skip)")
+    ap.add_argument("--c4-slice", type=int, default=1024,
+                    help="scenarios of the 300-bus-shaped case (random branch/generator "
+                         "pairs) screened in the mixed form and in FP64 (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=12,
                     help="requests per arrival rate in the serving sweep (0: skip it)")
@@ -241,6 +244,8 @@ def main():
         out["mixed"] = results["mixed"]
     if args.c3_slice > 0:
         out["c3"] = c3_legs(cs, ctx, torch, args, lst)
+    if args.c4_slice > 0:
+        out["c4"] = c4_legs(cs, ctx, torch, args)
     if args.serve_requests > 0:
         out["serving"] = serve_sweep(cs, ctx, net, case, lst, args)
     if base is not None:
@@ -304,6 +309,56 @@ def c3_legs(cs, ctx, torch, args, lst):
         "max_real_eig": float(np.max(np.abs(a["max_real_eig"][both] - b["max_real_eig"][both])
                                      / np.maximum(np.abs(a["max_real_eig"][both]), 1.0))),
         "min_damping": float(np.max(np.abs(a["min_damping"][both] - b["min_damping"][both])))}
+    net.close()
+    return out
+
+
+def c4_legs(cs, ctx, torch, args):
+    """The 300-bus-shaped case (411 branches, 69 machines, 200 loads; KKT
+    order 1,338, 482 states): the head of its list of random branch/generator
+    pairs in the mixed form (FP32 KKT factorisation with FP64 refinement, the
+    form this workload is specified in) and in FP64."""
+    import numpy as np
+    from inputs import netgen, contingencies
+    case = netgen.load_case(os.path.join(ROOT, "inputs", "cases", "c4_300.npz"))
+    lst = contingencies.c4_list(case["outage_set"])
+    net = cs.Network(ctx, case)
+    n = min(args.c4_slice, len(lst))
+    dev = torch.device("cuda:0")
+    d_list = torch.from_numpy(np.ascontiguousarray(lst[:n])).to(dev)
+    d_lam = torch.from_numpy(case["lam"]).to(dev)
+    rec = cs.RESULT_DTYPE.itemsize
+    out = {"scenarios": n, "list": "20,000 seeded random branch/generator pairs",
+           "kkt_order": 4 * int(case["n_bus"]) + 2 * int(case["n_gen"]),
+           "state_order": net.n_states_max}
+    for leg in ("mixed", "fp64"):
+        prec = cs.PREC_MIXED if leg == "mixed" else cs.PREC_FP64
+        d_res = torch.zeros(n * rec, dtype=torch.uint8, device=dev)
+        d_risk = torch.zeros(len(case["lam"]), dtype=torch.float64, device=dev)
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        ctx.reset_stats()
+        t0 = time.perf_counter()
+        net.screen_device(d_list.data_ptr(), n, d_lam.data_ptr(), d_res.data_ptr(),
+                          d_risk.data_ptr(), cs.default_options(prec=prec, timing=1),
+                          stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = ctx.stats()
+        lu = st["kkt_lu"]
+        nk = int(st["kkt_order"])
+        per = lu["units"] / max(lu["launches"], 1)
+        avg = lu["ms"] / max(lu["launches"], 1)
+        ach = per * kkt_lu_flops(nk) / (avg * 1e-3) / 1e12 if lu["ms"] else 0.0
+        peak = PEAK_FP32_TFLOPS if leg == "mixed" else PEAK_FP64_TFLOPS
+        res = d_res.cpu().numpy().view(cs.RESULT_DTYPE)
+        out[leg] = {"value": round(n / dt, 3), "unit": "scenarios/s",
+                    "kkt_lu_tflops": round(ach, 4), "kkt_lu_frac": round(ach / peak, 5),
+                    "islanded_fraction": round(float(np.mean(res["n_islands"] > 1)), 4),
+                    "severe_fraction": round(float(np.mean(res["severe"])), 4)}
+        if leg == "mixed":
+            out[leg]["fp64_fallback_share"] = round(
+                st["kkt_lu64"]["units"] / max(lu["units"], 1), 4)
+        log(f"c4 {leg}: {out[leg]['value']} scenarios/s")
     net.close()
     return out
 

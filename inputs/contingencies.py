@@ -60,6 +60,12 @@ def random_list(components, n: int, seed: int, p_n1: float = 0.1) -> np.ndarray:
     return out
 
 
+def c4_list(outage_set, n: int = 20000, seed: int = 300) -> np.ndarray:
+    """The 300-bus-shaped workload: n seeded random distinct pairs of the
+    outage set (branches and generators)."""
+    return random_list(outage_set, n, seed, p_n1=0.0)
+
+
 def stratified_sample(lst: np.ndarray, n: int, seed: int) -> np.ndarray:
     """Indices of a seeded sample: every N-1 row plus random N-2 rows."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -37,6 +37,7 @@ class NetShape:
     seed: int
     n_pendant: int          # pendant (degree-1) buses left uncovered
     outage_classes: tuple   # which component classes are outaged
+    load_scale: float = 1.0  # factor on the drawn loads (P and Q)
 
 
 SHAPES = {
@@ -45,6 +46,12 @@ SHAPES = {
     # 118-bus-shaped network: every branch, generator and load outaged
     "c2_118": NetShape("c2_118", 118, 186, 54, 99, 118, 6,
                        ("branch", "gen", "load")),
+    # 300-bus-shaped network: random N-2 outages of branches and generators;
+    # 18 pendant buses make about 8% of random branch/generator pairs island
+    # (loads drawn at half the 30- and 118-bus range: with the full range the
+    # longer electrical distances of a 300-bus random tree leave the base
+    # case infeasible)
+    "c4_300": NetShape("c4_300", 300, 411, 69, 200, 300, 18, ("branch", "gen"), 0.5),
 }
 
 
@@ -105,7 +112,7 @@ def draw_network(shape: NetShape, attempt: int = 0, base_mva: float = 100.0,
     br_b = rng.uniform(0.0, 0.05, nl)
 
     load_bus = np.sort(rng.choice(nb, nd, replace=False)).astype(np.int32)
-    pd = rng.uniform(0.1, 1.0, nd)
+    pd = rng.uniform(0.1, 1.0, nd) * shape.load_scale
     pf = rng.uniform(0.9, 0.98, nd)
     qd = pd * np.tan(np.arccos(pf))
 

@@ -10,6 +10,8 @@ island labels and the Risk Index over that list.
   c2_118_full: the whole 57,630-scenario list of the 118-bus-shaped case
   c3_118: the same stratified sample of the 118-bus shape with 16 machines
           replaced by grid-following converters (c3_118 case)
+  c4_300: the first 200 of the 20,000 random branch/generator pairs of the
+          300-bus-shaped case
   c1_30_n3: every N-3 triple of the 30-bus case's 41 branches (10,660 rows),
           all solved, with the pruning flags of screen.n3_prune (by c1_30's
           records) and R_i with pruned rows counted as severe
@@ -45,8 +47,8 @@ from oracle import screen, risk                    # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SAMPLES = {"c1_30": None, "c2_118": 600, "c2_118_full": None, "c1_30_n3": None,
-           "c3_118": 600}
-WITH_DETAIL = {"c1_30", "c2_118", "c3_118"}
+           "c3_118": 600, "c4_300": 200}
+WITH_DETAIL = {"c1_30", "c2_118", "c3_118", "c4_300"}
 CASE_OF = {"c2_118_full": "c2_118", "c1_30_n3": "c1_30"}
 _NET = None
 
@@ -65,6 +67,9 @@ def _one(o):
 def case_list(net, name):
     if name.endswith("_n3"):
         return contingencies.n3(net["outage_set"])
+    if name == "c4_300":
+        # the head of the 300-bus workload (random branch/generator pairs)
+        return contingencies.c4_list(net["outage_set"])[:SAMPLES[name]]
     full = contingencies.n1_n2(net["outage_set"])
     n = SAMPLES[name]
     if n is None:
