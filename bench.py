@@ -112,7 +112,7 @@ def main():
     ap.add_argument("--c3-slice", type=int, default=14408,
                     help="scenarios of the converter case (c3_118) screened in FP64 and "
                          "mixed after the headline legs (0: skip)")
-    ap.add_argument("--c4-slice", type=int, default=1024,
+    ap.add_argument("--c4-slice", type=int, default=512,
                     help="scenarios of the 300-bus-shaped case (random branch/generator "
                          "pairs) screened in the mixed form and in FP64 (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
