@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define CS_ABI_VERSION 6
+#define CS_ABI_VERSION 7
 
 enum {
   CS_OK = 0,
@@ -374,7 +374,7 @@ int cs_risk_mc(cs_ctx* ctx, cs_net* net, const int32_t* d_outages, int64_t n,
                int64_t n_samples, const cs_risk_opts* ropts, double* d_risk,
                double* d_moments, int32_t* d_rank_q, void* stream);
 
-/* Serving (continuous batching).  A server owns B scenario slots of one
+/* Serving (continuous batching).  A server owns B scenario slots of a
  * network and a host thread that runs them; requests (each an outage list
  * with its own failure rates) are admitted into a device ring of
  * queue_capacity scenarios and their scenarios join the slots as slots free
@@ -390,6 +390,26 @@ typedef struct cs_req cs_req;
 int cs_server_create(cs_ctx* ctx, cs_net* net, const cs_opts* opts,
                      int64_t queue_capacity, cs_server** out);
 void cs_server_destroy(cs_server* srv);
+
+/* A server for several networks (for instance a 118-bus and a 300-bus grid)
+ * under one HBM budget: network i gets the part shares[i] / sum(shares) of
+ * the budget (shares NULL = equal parts; each > 0 and finite) as its own
+ * scenario slots (capped by opts->batch), its own ring of queue_capacity
+ * scenarios and its own streams, fixed for the server's lifetime.  One host
+ * thread steps every network's slots in turn, so that their kernels overlap
+ * on the device.  Requests name their network (cs_submit_net) and share the
+ * table of requests in flight; each record is cs_screen's on that network.
+ * n_nets is 1 .. CS_SERVER_MAX_NETS, every network made on ctx's device.
+ * Errors: CS_EINVAL, CS_EHBM (a network's part holds no scenario),
+ * CS_ENOMEM, CS_EDEVICE.  cs_server_create is this call with one network. */
+#define CS_SERVER_MAX_NETS 16
+int cs_server_create_multi(cs_ctx* ctx, cs_net* const* nets, int n_nets,
+                           const double* shares, const cs_opts* opts,
+                           int64_t queue_capacity, cs_server** out);
+
+/* Scenario slots of network net (index into the creation list) in the
+ * server, or a negative error code. */
+int cs_server_slots(const cs_server* srv, int net);
 
 /* Admit a request: outages [n][2] and lambda [n_comp] (may be NULL: no risk)
  * are host buffers, copied before the call returns.  Returns CS_EAGAIN when
@@ -407,6 +427,13 @@ int cs_submit(cs_server* srv, const int32_t* outages, int64_t n, const double* l
  * Section V.E: each request screens the grid state it was taken at. */
 int cs_submit_snapshot(cs_server* srv, const int32_t* outages, int64_t n,
                        const double* lambda, const double* load_scale, cs_req** out);
+
+/* As cs_submit_snapshot for network net of the server (index into the list
+ * given to cs_server_create_multi; component ids, n_comp and n_load are that
+ * network's).  CS_EINVAL when net is out of range.  cs_submit and
+ * cs_submit_snapshot are this call with net = 0. */
+int cs_submit_net(cs_server* srv, int net, const int32_t* outages, int64_t n,
+                  const double* lambda, const double* load_scale, cs_req** out);
 
 /* Wait up to timeout_us microseconds (< 0: no limit) for a request; then
  * copy its records (out [n]) and R_i (risk [n_comp], if lambda was given;

@@ -133,6 +133,11 @@ def library():
         "cs_server_destroy": (None, [vp]),
         "cs_submit": (ctypes.c_int, [vp, vp, i64, dp, ctypes.POINTER(vp)]),
         "cs_submit_snapshot": (ctypes.c_int, [vp, vp, i64, dp, dp, ctypes.POINTER(vp)]),
+        "cs_server_create_multi": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.c_int, dp,
+                                                  ctypes.POINTER(Options), i64,
+                                                  ctypes.POINTER(vp)]),
+        "cs_server_slots": (ctypes.c_int, [vp, ctypes.c_int]),
+        "cs_submit_net": (ctypes.c_int, [vp, ctypes.c_int, vp, i64, dp, dp, ctypes.POINTER(vp)]),
         "cs_wait": (ctypes.c_int, [vp, i64, vp, dp, dp]),
         "cs_req_free": (None, [vp]),
     }
@@ -150,7 +155,8 @@ EXPORTED = ("cs_ctx_create", "cs_ctx_destroy", "cs_net_create", "cs_net_destroy"
             "cs_stats_reset", "cs_last_error", "cs_abi_version", "cs_server_create",
             "cs_server_destroy", "cs_submit", "cs_wait", "cs_req_free", "cs_screen_detail",
             "cs_dyn_at", "cs_screen_device_noalloc", "cs_risk_opts_default", "cs_risk",
-            "cs_risk_mc", "cs_screen3_device", "cs_screen_n3_device", "cs_submit_snapshot")
+            "cs_risk_mc", "cs_screen3_device", "cs_screen_n3_device", "cs_submit_snapshot",
+            "cs_server_create_multi", "cs_server_slots", "cs_submit_net")
 
 
 def _check(rc):
@@ -428,16 +434,17 @@ class Network:
 class Request:
     """One submitted screening request (cs_req)."""
 
-    def __init__(self, server: "Server", handle, n: int, has_lam: bool):
+    def __init__(self, server: "Server", handle, n: int, has_lam: bool, n_comp: int):
         self.server = server
         self._h = handle
         self.n = n
         self.has_lam = has_lam
+        self.n_comp = n_comp
 
     def wait(self, timeout_s: float | None = None):
         """(records, risk or None, latency_s); raises CSError(CS_ETIMEDOUT)."""
         res = np.zeros(self.n, dtype=RESULT_DTYPE)
-        risk = np.zeros(self.server.net.n_comp) if self.has_lam else None
+        risk = np.zeros(self.n_comp) if self.has_lam else None
         lat = np.zeros(1)
         us = -1 if timeout_s is None else int(timeout_s * 1e6)
         _check(library().cs_wait(self._h, us, _ptr(res), _ptr(risk), _ptr(lat)))
@@ -456,34 +463,45 @@ class Request:
 
 
 class Server:
-    """A serving engine for one network (cs_server): requests are admitted
-    as slots free up and run beside each other on the device."""
+    """A serving engine (cs_server) for one network, or for several under
+    one HBM budget (``net`` a list; ``shares`` their parts of the budget):
+    requests are admitted as slots free up and run beside each other on the
+    device."""
 
-    def __init__(self, ctx: Context, net: Network, options: Options | None = None,
-                 queue_capacity: int = 1 << 18):
+    def __init__(self, ctx: Context, net, options: Options | None = None,
+                 queue_capacity: int = 1 << 18, shares=None):
         self.ctx = ctx
-        self.net = net
+        self.nets = list(net) if isinstance(net, (list, tuple)) else [net]
+        self.net = self.nets[0]
         self._h = ctypes.c_void_p()
         o = options or default_options()
-        _check(library().cs_server_create(ctx.handle, net._h, ctypes.byref(o),
-                                          int(queue_capacity), ctypes.byref(self._h)))
+        handles = (ctypes.c_void_p * len(self.nets))(*[n._h for n in self.nets])
+        sh = None if shares is None else np.ascontiguousarray(shares, dtype=np.float64)
+        if sh is not None and len(sh) != len(self.nets):
+            raise ValueError("one share per network")
+        _check(library().cs_server_create_multi(ctx.handle, handles, len(self.nets), _ptr(sh),
+                                                ctypes.byref(o), int(queue_capacity),
+                                                ctypes.byref(self._h)))
         ctx._children.add(self)
-        net._servers.add(self)
+        for n in self.nets:
+            n._servers.add(self)
 
-    def submit(self, outages, lam=None, load_scale=None) -> Request:
-        """Admit a request; load_scale [n_load] screens it on a snapshot of
-        the network with every load scaled by its factor."""
+    def slots(self, net: int = 0) -> int:
+        rc = library().cs_server_slots(self._h, int(net))
+        _check(rc if rc < 0 else CS_OK)
+        return rc
+
+    def submit(self, outages, lam=None, load_scale=None, net: int = 0) -> Request:
+        """Admit a request for network ``net``; load_scale [n_load] screens it
+        on a snapshot of the network with every load scaled by its factor."""
         out_list = np.ascontiguousarray(outages, dtype=np.int32).reshape(-1, 2)
         lam_a = None if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
+        sc = None if load_scale is None else np.ascontiguousarray(load_scale, dtype=np.float64)
         h = ctypes.c_void_p()
-        if load_scale is None:
-            _check(library().cs_submit(self._h, _ptr(out_list), len(out_list), _ptr(lam_a),
-                                       ctypes.byref(h)))
-        else:
-            sc = np.ascontiguousarray(load_scale, dtype=np.float64)
-            _check(library().cs_submit_snapshot(self._h, _ptr(out_list), len(out_list),
-                                                _ptr(lam_a), _ptr(sc), ctypes.byref(h)))
-        return Request(self, h, len(out_list), lam is not None)
+        _check(library().cs_submit_net(self._h, int(net), _ptr(out_list), len(out_list),
+                                       _ptr(lam_a), _ptr(sc), ctypes.byref(h)))
+        n_comp = self.nets[net].n_comp if 0 <= net < len(self.nets) else 0
+        return Request(self, h, len(out_list), lam is not None, n_comp)
 
     def close(self):
         if self._h:

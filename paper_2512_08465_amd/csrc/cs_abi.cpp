@@ -586,6 +586,7 @@ struct Engine {
   int cnt[PH_COUNT]{};
   long long assigned = 0;        // scenarios handed to slots so far
   bool dyn_busy = false;
+  bool dyn_finished = false;     // the dynamic stage was seen complete in issue()
 
   int timed(int kind, hipStream_t stream, int64_t units, int uidx, const std::function<void()>& f) {
     if (T) return T->run(kind, stream, units, uidx, f);
@@ -617,7 +618,14 @@ struct Engine {
   // One round with N scenarios available so far (absolute count).  idle is
   // set when every available scenario has been recorded and no slot is busy.
   int round(long long N, bool& idle) {
-    idle = false;
+    int rc = issue(N);
+    if (rc != CS_OK) return rc;
+    return settle(N, idle, true, nullptr);
+  }
+
+  // First half of a round, asynchronous: refill, one Newton step, and the
+  // stage counts on their way to the host.
+  int issue(long long N) {
     bool work = false;
     int rc;
     if (assigned < N && cnt[PH_EMPTY] > 0) {
@@ -669,13 +677,27 @@ struct Engine {
     // Ask whether the dynamic stage has finished before the slot counts are
     // taken: if it finished between the two, its slots would be counted as
     // still busy while it is marked idle, and nothing would free them.
-    bool dyn_finished = false;
+    dyn_finished = false;
     if (dyn_busy) {
       const hipError_t q = hipEventQuery(ev_dyn);
       if (q == hipSuccess) dyn_finished = true;
       else if (q != hipErrorNotReady) return fail(CS_EDEVICE, "dynamic stage failed");
     }
-    if ((rc = count()) != CS_OK) return rc;
+    launch_phase_counts(s, nslots, d_counts, st);
+    HIPCHK(hipMemcpyAsync(h_counts, d_counts, sizeof(int) * PH_COUNT, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_next, d_next, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    return CS_OK;
+  }
+
+  // Second half: wait for the counts, then hand finished slots to the
+  // dynamic stage.  When the only thing left is to wait for the dynamic
+  // stage, a caller that may not block gets *waiting = true instead.
+  int settle(long long N, bool& idle, bool may_block, bool* waiting) {
+    idle = false;
+    if (waiting) *waiting = false;
+    int rc;
+    HIPCHK(hipStreamSynchronize(st));
+    for (int k = 0; k < PH_COUNT; ++k) cnt[k] = h_counts[k];
     if (dyn_finished) dyn_busy = false;
     assigned = std::min<long long>((long long)*h_next, N);
     const int ready = cnt[PH_DYN] + cnt[PH_DONE];
@@ -724,6 +746,10 @@ struct Engine {
     if (ipm_left == 0 && !can_refill) {
       if (dyn_busy) {
         // nothing to iterate: wait for the dynamic stage to free its slots
+        if (!may_block) {
+          *waiting = true;
+          return CS_OK;
+        }
         HIPCHK(hipEventSynchronize(ev_dyn));
         dyn_busy = false;
         return count();
@@ -964,11 +990,19 @@ extern "C" int cs_screen_device_noalloc(cs_ctx* c, cs_net* n, const int32_t* d_o
 }
 
 // ------------------------------------------------------------------ serving
+// A server runs one lane per network: the lane's scenario slots (its part of
+// the HBM budget), its device ring of outage pairs and records, its streams
+// and its engine.  One host thread drives every lane: it issues a round on
+// each lane that has work (their launches overlap on the device, each lane
+// on its own streams), then settles them in turn, then finishes the requests
+// whose records are all in.
 struct cs_req {
   cs_server* srv = nullptr;
+  int lane = 0;                          // network index
   int slot = -1;                         // request table index
   long long q0 = 0;                      // first ring position (absolute)
   int64_t n = 0;
+  int n_comp = 0;
   bool has_lam = false;
   std::vector<double> lam;
   std::vector<cs_result> res;
@@ -979,44 +1013,53 @@ struct cs_req {
   std::chrono::steady_clock::time_point t0, t1;
 };
 
-struct cs_server {
-  static constexpr int R = 1024;         // requests in flight at most
-  cs_ctx* c = nullptr;
+struct ServerLane {
   cs_net* n = nullptr;
-  int device = 0;
-  cs_opts opts{};
   Plan p;
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  hipStream_t st = nullptr, sd = nullptr, scopy = nullptr;
+  hipStream_t st = nullptr, sd = nullptr;
   hipEvent_t ev_ipm = nullptr, ev_dyn = nullptr;
-  long long q_cap = 0;
   int* q_out = nullptr;                  // ring of outage pairs
   cs_result* q_res = nullptr;            // ring of records
   int* item_req = nullptr;               // ring: request table index per scenario
   double* req_scale = nullptr;           // [R][n_load] each request's load factors
-  int* req_done = nullptr;               // [R] records completed per request
-  int* h_req_done = nullptr;             // pinned copy
   int* d_sched = nullptr;                // next (64-bit) + stage counts
   int* h_sched = nullptr;
   int* g_out = nullptr;                  // one request's list, contiguous
   cs_result* g_res = nullptr;
   double* g_lam = nullptr;
   double* g_risk = nullptr;
+  long long submitted = 0;               // scenarios admitted (absolute)
+  long long seen = 0;                    // scenarios the engine has been told about
+  bool idle = false;                     // every admitted scenario recorded
+  bool waiting = false;                  // only the dynamic stage is left to wait for
+  Engine e;
+};
+
+struct cs_server {
+  static constexpr int R = 1024;         // requests in flight at most
+  cs_ctx* c = nullptr;
+  int device = 0;
+  cs_opts opts{};
+  long long q_cap = 0;                   // ring capacity per lane
+  std::vector<ServerLane*> lanes;
+  int* req_done = nullptr;               // [R] records completed per request
+  int* h_req_done = nullptr;             // pinned copy
+  hipStream_t scopy = nullptr;
   std::vector<cs_req*> table;            // requests in flight
   std::set<cs_req*> owned;               // every request not yet freed by the caller
-  long long submitted = 0;               // scenarios admitted (absolute)
   std::mutex m;
   std::condition_variable cv_work, cv_done;
   bool stop = false;
   int error = CS_OK;
   std::string error_msg;
   std::thread th;
-  Engine e;
 };
 
-// Finish every request whose records are all in: gather its slice of the
-// ring, reduce its R_i, copy to the host.  Called by the server thread.
+// Finish every request whose records are all in: gather its slice of its
+// lane's ring, reduce its R_i, copy to the host.  The gather runs on the
+// stream of the lane's dynamic stage (e.sd), after the records it reads.
 static int server_complete(cs_server* S) {
   std::vector<cs_req*> live;
   {
@@ -1026,25 +1069,25 @@ static int server_complete(cs_server* S) {
   }
   if (live.empty()) return CS_OK;
   HIPCHK(hipMemcpyAsync(S->h_req_done, S->req_done, sizeof(int) * cs_server::R,
-                        hipMemcpyDeviceToHost, S->st));
-  HIPCHK(hipStreamSynchronize(S->st));
-  const int n_comp = S->n->nl + S->n->ng + S->n->nd;
+                        hipMemcpyDeviceToHost, S->scopy));
+  HIPCHK(hipStreamSynchronize(S->scopy));
   for (cs_req* r : live) {
     if (S->h_req_done[r->slot] < r->n) continue;
-    launch_gather_request(S->q_out, S->q_res, r->q0, (int)r->n, S->q_cap, S->g_out, S->g_res, S->st);
+    ServerLane& L = *S->lanes[r->lane];
+    launch_gather_request(L.q_out, L.q_res, r->q0, (int)r->n, S->q_cap, L.g_out, L.g_res, L.e.sd);
     if (r->has_lam) {
-      HIPCHK(hipMemcpyAsync(S->g_lam, r->lam.data(), sizeof(double) * n_comp,
-                            hipMemcpyHostToDevice, S->st));
-      launch_risk(S->g_out, r->n, reinterpret_cast<const uint8_t*>(S->g_res),
-                  (int)sizeof(cs_result), S->g_lam, n_comp, S->g_risk, S->st);
-      r->risk.resize(n_comp);
-      HIPCHK(hipMemcpyAsync(r->risk.data(), S->g_risk, sizeof(double) * n_comp,
-                            hipMemcpyDeviceToHost, S->st));
+      HIPCHK(hipMemcpyAsync(L.g_lam, r->lam.data(), sizeof(double) * r->n_comp,
+                            hipMemcpyHostToDevice, L.e.sd));
+      launch_risk(L.g_out, r->n, reinterpret_cast<const uint8_t*>(L.g_res),
+                  (int)sizeof(cs_result), L.g_lam, r->n_comp, L.g_risk, L.e.sd);
+      r->risk.resize(r->n_comp);
+      HIPCHK(hipMemcpyAsync(r->risk.data(), L.g_risk, sizeof(double) * r->n_comp,
+                            hipMemcpyDeviceToHost, L.e.sd));
     }
     r->res.resize(r->n);
-    HIPCHK(hipMemcpyAsync(r->res.data(), S->g_res, sizeof(cs_result) * r->n,
-                          hipMemcpyDeviceToHost, S->st));
-    HIPCHK(hipStreamSynchronize(S->st));
+    HIPCHK(hipMemcpyAsync(r->res.data(), L.g_res, sizeof(cs_result) * r->n,
+                          hipMemcpyDeviceToHost, L.e.sd));
+    HIPCHK(hipStreamSynchronize(L.e.sd));
     std::lock_guard<std::mutex> lk(S->m);
     r->t1 = std::chrono::steady_clock::now();
     r->done = true;
@@ -1079,35 +1122,163 @@ static void server_fail_all(cs_server* S, int code, const std::string& msg) {
 
 static void server_loop(cs_server* S) {
   hipSetDevice(S->device);
-  int rc = S->e.start();
-  if (rc != CS_OK) {
-    server_fail_all(S, rc, g_err);
-    return;
-  }
-  for (;;) {
-    long long N;
-    {
-      std::lock_guard<std::mutex> lk(S->m);
-      N = S->submitted;
-    }
-    bool idle = false;
-    if ((rc = S->e.round(N, idle)) != CS_OK || (rc = server_complete(S)) != CS_OK) {
+  const size_t nl = S->lanes.size();
+  int rc = CS_OK;
+  for (ServerLane* L : S->lanes)
+    if ((rc = L->e.start()) != CS_OK) {
       server_fail_all(S, rc, g_err);
       return;
     }
-    if (idle) {
+  // one lane: the engine may block on its own dynamic stage; several: a
+  // lane never blocks while another could be stepped
+  const bool may_block = nl == 1;
+  std::vector<long long> N(nl);
+  std::vector<char> issued(nl);
+  for (;;) {
+    {
+      std::lock_guard<std::mutex> lk(S->m);
+      for (size_t i = 0; i < nl; ++i) N[i] = S->lanes[i]->submitted;
+    }
+    for (size_t i = 0; i < nl; ++i) {
+      ServerLane& L = *S->lanes[i];
+      issued[i] = !L.idle || N[i] > L.seen;
+      if (issued[i] && (rc = L.e.issue(N[i])) != CS_OK) break;
+    }
+    for (size_t i = 0; rc == CS_OK && i < nl; ++i) {
+      ServerLane& L = *S->lanes[i];
+      if (!issued[i]) continue;
+      bool idle = false, waiting = false;
+      rc = L.e.settle(N[i], idle, may_block, &waiting);
+      L.idle = idle;
+      L.waiting = waiting;
+      L.seen = N[i];
+    }
+    if (rc != CS_OK || (rc = server_complete(S)) != CS_OK) {
+      server_fail_all(S, rc, g_err);
+      return;
+    }
+    bool all_idle = true, all_wait = true;
+    for (ServerLane* L : S->lanes) {
+      all_idle = all_idle && L->idle;
+      all_wait = all_wait && (L->idle || L->waiting);
+    }
+    if (all_idle) {
       std::unique_lock<std::mutex> lk(S->m);
-      S->cv_work.wait(lk, [&] { return S->stop || S->submitted > N; });
-      if (S->stop && S->submitted == N) return;
+      S->cv_work.wait(lk, [&] {
+        if (S->stop) return true;
+        for (size_t i = 0; i < nl; ++i)
+          if (S->lanes[i]->submitted > N[i]) return true;
+        return false;
+      });
+      if (S->stop) {
+        bool more = false;
+        for (size_t i = 0; i < nl; ++i) more = more || S->lanes[i]->submitted > N[i];
+        if (!more) return;
+      }
+    } else if (all_wait) {
+      // nothing to step anywhere: wait for the first lane's dynamic stage
+      for (ServerLane* L : S->lanes)
+        if (L->waiting) {
+          if (hipEventSynchronize(L->e.ev_dyn) != hipSuccess) {
+            server_fail_all(S, CS_EDEVICE, "dynamic stage failed");
+            return;
+          }
+          break;
+        }
     }
   }
 }
 
-extern "C" int cs_server_create(cs_ctx* c, cs_net* n, const cs_opts* o,
-                                int64_t queue_capacity, cs_server** out) {
-  if (!c || !n || !out || queue_capacity <= 0 || queue_capacity > (1ll << 30))
+static void lane_free(ServerLane* L) {
+  for (void* q : {(void*)L->q_out, (void*)L->q_res, (void*)L->item_req, (void*)L->req_scale,
+                  (void*)L->d_sched, (void*)L->g_out, (void*)L->g_res, (void*)L->g_lam,
+                  (void*)L->g_risk, L->ws})
+    if (q) hipFree(q);
+  if (L->h_sched) hipHostFree(L->h_sched);
+  for (hipStream_t q : {L->st, L->sd})
+    if (q) hipStreamDestroy(q);
+  for (hipEvent_t q : {L->ev_ipm, L->ev_dyn})
+    if (q) hipEventDestroy(q);
+  delete L;
+}
+
+// Slots, ring and engine of one lane; bytes is the lane's part of the budget.
+static int lane_create(cs_server* S, cs_net* n, size_t bytes, int index, ServerLane** out) {
+  const cs_opts& opts = S->opts;
+  ServerLane* L = new ServerLane();
+  *out = L;
+  L->n = n;
+  L->p = plan_sizes(n, opts.prec == CS_PREC_MIXED);
+  if (L->p.per_slot > bytes)
+    return fail(CS_EHBM, "cs_server_create: network " + std::to_string(index) +
+                             ": one scenario needs " + std::to_string(L->p.per_slot) +
+                             " bytes, over its part of the budget, " + std::to_string(bytes));
+  long long B = (long long)(bytes / L->p.per_slot);
+  if (opts.batch > 0) B = std::min<long long>(B, opts.batch);
+  B = std::max<long long>(1, std::min<long long>(B, 1 << 20));
+  int rc = bind_workspace(&L->ws, &L->ws_bytes, n, L->p, (int)B);
+  if (rc != CS_OK) return rc;
+  const long long qc = S->q_cap;
+  const int n_comp = n->nl + n->ng + n->nd;
+  if (hipStreamCreateWithFlags(&L->st, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&L->sd, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&L->ev_ipm, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&L->ev_dyn, hipEventDisableTiming) != hipSuccess ||
+      hipMalloc(&L->q_out, sizeof(int) * 2 * qc) != hipSuccess ||
+      hipMalloc(&L->q_res, sizeof(cs_result) * qc) != hipSuccess ||
+      hipMalloc(&L->item_req, sizeof(int) * qc) != hipSuccess ||
+      hipMalloc(&L->req_scale, sizeof(double) * (size_t)cs_server::R * std::max(n->nd, 1)) != hipSuccess ||
+      hipMalloc(&L->d_sched, sizeof(int) * (PH_COUNT + 2)) != hipSuccess ||
+      hipHostMalloc(&L->h_sched, sizeof(int) * (PH_COUNT + 2), hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&L->g_out, sizeof(int) * 2 * qc) != hipSuccess ||
+      hipMalloc(&L->g_res, sizeof(cs_result) * qc) != hipSuccess ||
+      hipMalloc(&L->g_lam, sizeof(double) * std::max(n_comp, 1)) != hipSuccess ||
+      hipMalloc(&L->g_risk, sizeof(double) * std::max(n_comp, 1)) != hipSuccess)
+    return fail(CS_ENOMEM, "cs_server_create: allocation failed");
+  Engine& e = L->e;
+  e.c = S->c;
+  e.D = &n->d;
+  e.s = L->p.s;
+  e.opts = opts;
+  e.nslots = (int)B;
+  e.pstride = std::max(L->p.s.nk, L->p.s.ny);
+  e.dyn_min = std::max(1, std::min((int)B, 1024));
+  e.eager = true;
+  e.st = L->st;
+  // the records a request gathers are written on e.sd (== st without overlap)
+  e.sd = opts.overlap ? L->sd : L->st;
+  e.ev_ipm = L->ev_ipm;
+  e.ev_dyn = L->ev_dyn;
+  e.d_next = reinterpret_cast<unsigned long long*>(L->d_sched);
+  e.d_counts = L->d_sched + 2;
+  e.h_counts = L->h_sched + 2;
+  e.h_next = reinterpret_cast<unsigned long long*>(L->h_sched);
+  e.d_list = L->q_out;
+  e.d_res = L->q_res;
+  e.q_cap = qc;
+  e.item_req = L->item_req;
+  e.load_scale = L->req_scale;
+  e.req_done = S->req_done;
+  e.T = nullptr;
+  return CS_OK;
+}
+
+extern "C" int cs_server_create_multi(cs_ctx* c, cs_net* const* nets, int n_nets,
+                                      const double* shares, const cs_opts* o,
+                                      int64_t queue_capacity, cs_server** out) {
+  if (!c || !nets || !out || n_nets < 1 || n_nets > CS_SERVER_MAX_NETS || queue_capacity <= 0 ||
+      queue_capacity > (1ll << 30))
     return fail(CS_EINVAL, "cs_server_create: bad arguments");
   *out = nullptr;
+  double share_sum = 0.0;
+  for (int i = 0; i < n_nets; ++i) {
+    if (!nets[i]) return fail(CS_EINVAL, "cs_server_create: NULL network");
+    if (nets[i]->device != c->device)
+      return fail(CS_EINVAL, "cs_server_create: network made on another device");
+    if (shares && !(shares[i] > 0 && std::isfinite(shares[i])))
+      return fail(CS_EINVAL, "cs_server_create: shares must be finite and > 0");
+    share_sum += shares ? shares[i] : 1.0;
+  }
   cs_opts opts;
   cs_opts_default(&opts);
   if (o) opts = *o;
@@ -1118,73 +1289,47 @@ extern "C" int cs_server_create(cs_ctx* c, cs_net* n, const cs_opts* o,
   cs_server* S = new cs_server();
   S->c = c;
   S->device = c->device;
-  S->n = n;
   S->opts = opts;
   S->q_cap = queue_capacity;
   S->table.assign(cs_server::R, nullptr);
-  S->p = plan_sizes(n, opts.prec == CS_PREC_MIXED);
   const size_t budget = opts.hbm_budget ? opts.hbm_budget : c->hbm_budget;
-  auto bail = [&](int code, const std::string& msg) {
+  auto bail = [&](int code) {
+    const std::string msg = g_err;
     cs_server_destroy(S);
     return fail(code, msg);
   };
-  if (S->p.per_slot > budget)
-    return bail(CS_EHBM, "cs_server_create: one scenario needs " + std::to_string(S->p.per_slot) +
-                             " bytes, over the budget of " + std::to_string(budget));
-  long long B = (long long)(budget / S->p.per_slot);
-  if (opts.batch > 0) B = std::min<long long>(B, opts.batch);
-  B = std::max<long long>(1, std::min<long long>(B, 1 << 20));
-  rc = bind_workspace(&S->ws, &S->ws_bytes, n, S->p, (int)B);
-  if (rc != CS_OK) return bail(rc, g_err);
-  const int n_comp = n->nl + n->ng + n->nd;
-  if (hipStreamCreateWithFlags(&S->st, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&S->sd, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&S->scopy, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&S->ev_ipm, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&S->ev_dyn, hipEventDisableTiming) != hipSuccess ||
-      hipMalloc(&S->q_out, sizeof(int) * 2 * queue_capacity) != hipSuccess ||
-      hipMalloc(&S->q_res, sizeof(cs_result) * queue_capacity) != hipSuccess ||
-      hipMalloc(&S->item_req, sizeof(int) * queue_capacity) != hipSuccess ||
-      hipMalloc(&S->req_scale, sizeof(double) * (size_t)cs_server::R *
-                                   std::max(n->nd, 1)) != hipSuccess ||
+  if (hipStreamCreateWithFlags(&S->scopy, hipStreamNonBlocking) != hipSuccess ||
       hipMalloc(&S->req_done, sizeof(int) * cs_server::R) != hipSuccess ||
-      hipHostMalloc(&S->h_req_done, sizeof(int) * cs_server::R, hipHostMallocDefault) != hipSuccess ||
-      hipMalloc(&S->d_sched, sizeof(int) * (PH_COUNT + 2)) != hipSuccess ||
-      hipHostMalloc(&S->h_sched, sizeof(int) * (PH_COUNT + 2), hipHostMallocDefault) != hipSuccess ||
-      hipMalloc(&S->g_out, sizeof(int) * 2 * queue_capacity) != hipSuccess ||
-      hipMalloc(&S->g_res, sizeof(cs_result) * queue_capacity) != hipSuccess ||
-      hipMalloc(&S->g_lam, sizeof(double) * std::max(n_comp, 1)) != hipSuccess ||
-      hipMalloc(&S->g_risk, sizeof(double) * std::max(n_comp, 1)) != hipSuccess)
-    return bail(CS_ENOMEM, "cs_server_create: allocation failed");
-  if (hipMemset(S->req_done, 0, sizeof(int) * cs_server::R) != hipSuccess)
-    return bail(CS_EDEVICE, "cs_server_create: device error");
-  Engine& e = S->e;
-  e.c = c;
-  e.D = &n->d;
-  e.s = S->p.s;
-  e.opts = opts;
-  e.nslots = (int)B;
-  e.pstride = std::max(S->p.s.nk, S->p.s.ny);
-  e.dyn_min = std::max(1, std::min((int)B, 1024));
-  e.eager = true;
-  e.st = S->st;
-  e.sd = opts.overlap ? S->sd : S->st;
-  e.ev_ipm = S->ev_ipm;
-  e.ev_dyn = S->ev_dyn;
-  e.d_next = reinterpret_cast<unsigned long long*>(S->d_sched);
-  e.d_counts = S->d_sched + 2;
-  e.h_counts = S->h_sched + 2;
-  e.h_next = reinterpret_cast<unsigned long long*>(S->h_sched);
-  e.d_list = S->q_out;
-  e.d_res = S->q_res;
-  e.q_cap = queue_capacity;
-  e.item_req = S->item_req;
-  e.load_scale = S->req_scale;
-  e.req_done = S->req_done;
-  e.T = nullptr;
+      hipHostMalloc(&S->h_req_done, sizeof(int) * cs_server::R, hipHostMallocDefault) != hipSuccess) {
+    fail(CS_ENOMEM, "cs_server_create: allocation failed");
+    return bail(CS_ENOMEM);
+  }
+  if (hipMemset(S->req_done, 0, sizeof(int) * cs_server::R) != hipSuccess) {
+    fail(CS_EDEVICE, "cs_server_create: device error");
+    return bail(CS_EDEVICE);
+  }
+  for (int i = 0; i < n_nets; ++i) {
+    const double f = (shares ? shares[i] : 1.0) / share_sum;
+    ServerLane* L = nullptr;
+    rc = lane_create(S, nets[i], (size_t)((double)budget * f), i, &L);
+    S->lanes.push_back(L);
+    if (rc != CS_OK) return bail(rc);
+  }
   S->th = std::thread(server_loop, S);
   *out = S;
   return CS_OK;
+}
+
+extern "C" int cs_server_create(cs_ctx* c, cs_net* n, const cs_opts* o,
+                                int64_t queue_capacity, cs_server** out) {
+  if (!n) return fail(CS_EINVAL, "cs_server_create: bad arguments");
+  return cs_server_create_multi(c, &n, 1, nullptr, o, queue_capacity, out);
+}
+
+extern "C" int cs_server_slots(const cs_server* S, int net) {
+  if (!S || net < 0 || net >= (int)S->lanes.size())
+    return fail(CS_EINVAL, "cs_server_slots: bad arguments");
+  return S->lanes[net]->e.nslots;
 }
 
 extern "C" void cs_server_destroy(cs_server* S) {
@@ -1211,29 +1356,26 @@ extern "C" void cs_server_destroy(cs_server* S) {
     }
     r->srv = nullptr;
   }
-  for (void* q : {(void*)S->q_out, (void*)S->q_res, (void*)S->item_req, (void*)S->req_scale,
-                  (void*)S->req_done,
-                  (void*)S->d_sched, (void*)S->g_out, (void*)S->g_res, (void*)S->g_lam,
-                  (void*)S->g_risk, S->ws})
-    if (q) hipFree(q);
+  for (ServerLane* L : S->lanes)
+    if (L) lane_free(L);
+  if (S->req_done) hipFree(S->req_done);
   if (S->h_req_done) hipHostFree(S->h_req_done);
-  if (S->h_sched) hipHostFree(S->h_sched);
-  for (hipStream_t q : {S->st, S->sd, S->scopy})
-    if (q) hipStreamDestroy(q);
-  for (hipEvent_t q : {S->ev_ipm, S->ev_dyn})
-    if (q) hipEventDestroy(q);
+  if (S->scopy) hipStreamDestroy(S->scopy);
   delete S;
 }
 
-static int submit(cs_server* S, const int32_t* outages, int64_t n, const double* lambda,
-                  const double* load_scale, cs_req** out) {
+extern "C" int cs_submit_net(cs_server* S, int net, const int32_t* outages, int64_t n,
+                             const double* lambda, const double* load_scale, cs_req** out) {
   if (!S || !out || n < 0 || (n > 0 && !outages)) return fail(CS_EINVAL, "cs_submit: bad arguments");
   *out = nullptr;
+  if (net < 0 || net >= (int)S->lanes.size())
+    return fail(CS_EINVAL, "cs_submit: network index " + std::to_string(net) + " out of range");
   if (n > S->q_cap) return fail(CS_EINVAL, "cs_submit: request longer than the ring");
-  int rc = validate_host(S->n, outages, n, lambda);
+  ServerLane& L = *S->lanes[net];
+  int rc = validate_host(L.n, outages, n, lambda);
   if (rc != CS_OK) return rc;
-  const int n_comp = S->n->nl + S->n->ng + S->n->nd;
-  const int nd = S->n->nd;
+  const int n_comp = L.n->nl + L.n->ng + L.n->nd;
+  const int nd = L.n->nd;
   std::vector<double> scale(std::max(nd, 1), 1.0);
   if (load_scale) {
     for (int d = 0; d < nd; ++d) {
@@ -1245,20 +1387,22 @@ static int submit(cs_server* S, const int32_t* outages, int64_t n, const double*
   }
   std::unique_lock<std::mutex> lk(S->m);
   if (S->error != CS_OK) return fail(S->error, "cs_submit: server failed: " + S->error_msg);
-  long long oldest = S->submitted;
+  long long oldest = L.submitted;
   int slot = -1;
   for (int i = 0; i < cs_server::R; ++i) {
     const cs_req* r = S->table[i];
-    if (r) oldest = std::min(oldest, r->q0);
-    else if (slot < 0) slot = i;
+    if (r && r->lane == net) oldest = std::min(oldest, r->q0);
+    else if (!r && slot < 0) slot = i;
   }
-  if (slot < 0 || S->submitted + n - oldest > S->q_cap)
+  if (slot < 0 || L.submitted + n - oldest > S->q_cap)
     return fail(CS_EAGAIN, "cs_submit: no room for the request right now");
   cs_req* r = new cs_req();
   r->srv = S;
+  r->lane = net;
   r->slot = slot;
-  r->q0 = S->submitted;
+  r->q0 = L.submitted;
   r->n = n;
+  r->n_comp = n_comp;
   r->has_lam = lambda != nullptr;
   if (lambda) r->lam.assign(lambda, lambda + n_comp);
   r->t0 = std::chrono::steady_clock::now();
@@ -1274,16 +1418,16 @@ static int submit(cs_server* S, const int32_t* outages, int64_t n, const double*
   // copy into the ring (in two pieces when it wraps), tag the request
   const long long p0 = r->q0 % S->q_cap;
   const long long first = std::min<long long>(n, S->q_cap - p0);
-  bool ok = hipMemcpyAsync(S->q_out + 2 * p0, outages, sizeof(int) * 2 * first,
+  bool ok = hipMemcpyAsync(L.q_out + 2 * p0, outages, sizeof(int) * 2 * first,
                            hipMemcpyHostToDevice, S->scopy) == hipSuccess;
   if (ok && first < n)
-    ok = hipMemcpyAsync(S->q_out, outages + 2 * first, sizeof(int) * 2 * (n - first),
+    ok = hipMemcpyAsync(L.q_out, outages + 2 * first, sizeof(int) * 2 * (n - first),
                         hipMemcpyHostToDevice, S->scopy) == hipSuccess;
   if (ok && nd > 0)
-    ok = hipMemcpyAsync(S->req_scale + (size_t)slot * nd, scale.data(), sizeof(double) * nd,
+    ok = hipMemcpyAsync(L.req_scale + (size_t)slot * nd, scale.data(), sizeof(double) * nd,
                         hipMemcpyHostToDevice, S->scopy) == hipSuccess;
   if (ok) {
-    launch_fill_req(S->item_req, r->q0, (int)n, S->q_cap, slot, S->scopy);
+    launch_fill_req(L.item_req, r->q0, (int)n, S->q_cap, slot, S->scopy);
     ok = hipMemsetAsync(S->req_done + slot, 0, sizeof(int), S->scopy) == hipSuccess &&
          hipStreamSynchronize(S->scopy) == hipSuccess;
   }
@@ -1293,7 +1437,7 @@ static int submit(cs_server* S, const int32_t* outages, int64_t n, const double*
     return fail(CS_EDEVICE, "cs_submit: copy to the device failed");
   }
   S->table[slot] = r;
-  S->submitted += n;
+  L.submitted += n;
   lk.unlock();
   S->cv_work.notify_all();
   *out = r;
@@ -1302,13 +1446,13 @@ static int submit(cs_server* S, const int32_t* outages, int64_t n, const double*
 
 extern "C" int cs_submit(cs_server* S, const int32_t* outages, int64_t n, const double* lambda,
                          cs_req** out) {
-  return submit(S, outages, n, lambda, nullptr, out);
+  return cs_submit_net(S, 0, outages, n, lambda, nullptr, out);
 }
 
 extern "C" int cs_submit_snapshot(cs_server* S, const int32_t* outages, int64_t n,
                                   const double* lambda, const double* load_scale,
                                   cs_req** out) {
-  return submit(S, outages, n, lambda, load_scale, out);
+  return cs_submit_net(S, 0, outages, n, lambda, load_scale, out);
 }
 
 extern "C" int cs_wait(cs_req* r, int64_t timeout_us, cs_result* out, double* risk,

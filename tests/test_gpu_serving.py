@@ -185,3 +185,57 @@ def test_snapshot_factors_validated(nets):
         srv.submit(_lists("c1_30", [3], 1)[0], case["lam"], load_scale=bad)
     assert e.value.code == cs.CS_EINVAL
     srv.close()
+
+
+def test_several_networks_one_budget(nets):
+    """One server for the 30-, 118- and 300-bus networks under one HBM
+    budget split by shares: requests for all three, interleaved and several
+    in flight, give record for record what cs_screen gives for the same list
+    on its network alone (a load snapshot included)."""
+    import paper_2512_08465_amd as cs
+    from inputs.rate_samples import load_scales
+    net1, case1 = nets["c1_30"]
+    net2, case2 = nets["c2_118"]
+    case4 = load_case("c4_300")
+    net4 = cs.Network(net2.ctx, case4)
+    g4 = load_golden("c4_300")
+    quick = np.flatnonzero(g4["opf_iters"] < 40)
+    l4 = [g4["outages"][quick[:6]], g4["outages"][quick[6:16]]]
+    l2 = _lists("c2_118", [70, 25], seed=21)
+    l1 = _lists("c1_30", [90], seed=22)
+    snap = load_scales(int(case2["n_load"]), 1, seed=23)[0]
+    budget = 3 << 30
+    srv = cs.Server(net2.ctx, [net1, net2, net4],
+                    cs.default_options(batch=0, hbm_budget=budget), queue_capacity=2048,
+                    shares=[1.0, 2.0, 4.0])
+    s1, s2, s4 = srv.slots(0), srv.slots(1), srv.slots(2)
+    print(f"slots under {budget >> 20} MiB split 1:2:4: 30-bus {s1}, 118-bus {s2}, 300-bus {s4}")
+    assert 0 < s4 < s2
+    reqs = [(4, l4[0], None, srv.submit(l4[0], case4["lam"], net=2)),
+            (2, l2[0], None, srv.submit(l2[0], case2["lam"], net=1)),
+            (1, l1[0], None, srv.submit(l1[0], case1["lam"], net=0)),
+            (4, l4[1], None, srv.submit(l4[1], case4["lam"], net=2)),
+            (2, l2[1], snap, srv.submit(l2[1], case2["lam"], load_scale=snap, net=1))]
+    for kind, lst, sc, r in reqs:
+        res, risk, lat = r.wait(timeout_s=600)
+        if kind == 4:
+            ref, ref_risk = net4.screen(lst, case4["lam"])
+        elif kind == 1:
+            ref, ref_risk = net1.screen(lst, case1["lam"])
+        elif sc is None:
+            ref, ref_risk = net2.screen(lst, case2["lam"])
+        else:
+            snap_net = cs.Network(net2.ctx, _scaled_case(case2, sc))
+            ref, ref_risk = snap_net.screen(lst, case2["lam"])
+            snap_net.close()
+        print(f"{kind}: {len(lst)} scenarios, latency {lat:.2f} s")
+        _same(res, ref)
+        assert np.array_equal(risk, ref_risk)
+    with pytest.raises(cs.CSError) as e:
+        srv.submit(l1[0], case1["lam"], net=3)
+    assert e.value.code == cs.CS_EINVAL
+    srv.close()
+    with pytest.raises(cs.CSError) as e:
+        cs.Server(net2.ctx, [net1, net2], shares=[1.0, 0.0])
+    assert e.value.code == cs.CS_EINVAL
+    net4.close()
