@@ -4,16 +4,16 @@
 // matrix is reduced to upper Hessenberg form by Householder reflections, one
 // read-write pass over the trailing columns per reflector (the two-sided
 // update of one step fused with the products the next step needs), then
-// Francis implicit double-shift QR sweeps run on the active window [lo, hi]
-// until every 1x1 or 2x2 diagonal block has split off (eigenvalues only, so
-// updates stay inside the window).  A sweep chases its bulge in blocks of 16
-// steps through a small diagonal block held in LDS and applies the
-// accumulated reflectors to the rest of the window once per block.
+// implicit QR sweeps run on the active window [lo, hi] until every 1x1 or
+// 2x2 diagonal block has split off (eigenvalues only, so updates stay inside
+// the window).  A sweep chases a chain of up to four double-shift bulges in
+// blocks of 16 steps through a small diagonal block held in LDS and applies
+// the accumulated reflectors to the rest of the window once per block.
 // Deflation: a subdiagonal entry is negligible when |h(k,k-1)| <= eps
 // (|h(k-1,k-1)| + |h(k,k)|).  Every tenth sweep without deflation uses an
 // exceptional shift.  The matrix lives in global memory (column-major, lda);
-// the reflector vectors, the reduction's partial sums and the chased block
-// live in LDS.
+// the reflector vectors, the reduction's partial sums, the chased block and
+// the shift computation live in LDS.
 #include "cs_internal.h"
 #include <float.h>
 
@@ -84,7 +84,7 @@ __device__ inline void eig2x2(double a, double b, double c, double d,
 constexpr int EIG_NW = EIG_THREADS / 64;
 constexpr int EIG_CG = 8;                   // row chunks of 64 loaded together
 
-size_t eig_hess_lds(int nmax) { return sizeof(double) * 9 * (size_t)nmax; }
+size_t eig_hess_lds(int nmax);
 
 __device__ void hessenberg(double* __restrict__ H, int n, int lda, double* __restrict__ lds,
                            double* red) {
@@ -213,28 +213,293 @@ __device__ void hessenberg(double* __restrict__ H, int n, int lda, double* __res
   }
 }
 
-// Bulge chasing in blocks.  A block covers QR_NB consecutive bulge steps
-// k0 .. kend-1; every row and column those steps touch inside the window
-// lies in the index range [c0, c1] (plus the row c1 + 1, which the last
-// step's right-hand update reaches).  That diagonal block is chased in LDS by
-// one wavefront while the reflectors are accumulated into U (P_k0 ... P_kend-1);
-// afterwards the rest of the window gets them in one pass each:
+// Francis QR in blocks, with a chain of up to QR_KMAX double-shift bulges
+// per sweep (small-bulge multishift: Braman, Byers and Mathias, SIMAX 2002).
+//
+// Bulge b of the chain is introduced at the top of the window [lo, hi] three
+// positions behind bulge b-1 and chased to the bottom; at chain step t it
+// sits at position p_b = lo + t - 3 b.  One wavefront owns each bulge and the
+// wavefronts move in lockstep: at every chain step all of them first form
+// their reflectors and apply them from the left (their rows are disjoint),
+// then, after a barrier, from the right (their columns are disjoint).  This
+// keeps the order of the sequential chase for every entry except the 3 x 3
+// corners a trailing bulge's left and a leading bulge's right reflector both
+// touch, where the two commute.
+//
+// A block covers QR_NB chain steps; everything those steps touch inside the
+// window lies in the index range [c0, c1] (plus row c1 + 1, which the
+// leading bulge's right-hand update reaches).  That diagonal block is held in
+// LDS while the reflectors are accumulated into U; afterwards the rest of
+// the window gets them in one pass each:
 //   rows c0..c1, columns c1+1..hi:  H <- U^T H
 //   rows lo..c0-1, columns c0..c1:  H <- H U
+// Shifts: the eigenvalues of the window's trailing 2 QR_KMAX square block
+// (one wavefront runs a plain double-shift QR on it in LDS), complex pairs as
+// (2 Re, |.|^2), real ones sorted and paired in order; the two eigenvalues of
+// the trailing 2 x 2 block (one bulge) for windows below QR_MS_MIN, when the
+// small QR fails, and on every tenth sweep without deflation, which uses an
+// exceptional shift instead.
 constexpr int QR_NB = 16;
-constexpr int QR_D = QR_NB + 3;      // block order
-constexpr int QR_LD = QR_D + 1;      // LDS row stride of the block and of U
+constexpr int QR_KMAX = 4;                       // bulges per chain (<= wavefronts)
+constexpr int QR_MS_MIN = 4 * QR_KMAX;           // smallest window for a chain
+constexpr int QR_D = QR_NB + 3 * QR_KMAX;        // largest block order
+constexpr int QR_LD = QR_D + 1;                  // LDS row stride of the block and of U
+constexpr int QR_NS = 2 * QR_KMAX;               // order of the shift block
+constexpr int QR_SLD = QR_NS + 1;
+// LDS of the QR phase (doubles): block (QR_D + 1 rows), U, shift block, its
+// eigenvalues, the shift pairs
+constexpr int QR_LDS = (QR_D + 1) * QR_LD + QR_D * QR_LD + QR_NS * QR_SLD + 2 * QR_NS + 2 * QR_KMAX;
+static_assert(QR_KMAX <= EIG_NW, "one wavefront per bulge");
+static_assert(QR_D + 1 <= 64, "block rows fit a wavefront");
 
-// one Francis double-shift sweep over the window [lo, hi] (hi - lo >= 2)
-__device__ void francis_sweep(double* __restrict__ H, int lda, int lo, int hi,
-                              double x, double y, double z,
-                              double* __restrict__ D, double* __restrict__ U) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Double-shift QR on a small Hessenberg matrix S (m <= QR_NS, row stride
+// QR_SLD) by one wavefront: lanes run over the columns of a left update and
+// the rows of a right update; every lane takes the same control decisions
+// from the shared values.  Returns 0 on success.
+__device__ int small_francis(double* S, int m, double* wr, double* wi) {
+  const int lane = threadIdx.x & 63;
+  const double eps = DBL_EPSILON;
+#define SS(i, j) S[(i) * QR_SLD + (j)]
+  int hi = m - 1, its = 0, total = 0;
+  while (hi >= 0) {
+    if (hi == 0) {
+      if (lane == 0) { wr[0] = SS(0, 0); wi[0] = 0.0; }
+      break;
+    }
+    int lo = 0;
+    for (int k = hi; k >= 1; --k) {
+      const double s = fabs(SS(k - 1, k - 1)) + fabs(SS(k, k));
+      const double sub = fabs(SS(k, k - 1));
+      if (sub <= eps * s || sub == 0.0) { lo = k; break; }
+    }
+    if (lo == hi) {
+      if (lane == 0) { wr[hi] = SS(hi, hi); wi[hi] = 0.0; }
+      hi -= 1;
+      its = 0;
+      continue;
+    }
+    if (lo == hi - 1) {
+      if (lane == 0) {
+        double r1, i1, r2, i2;
+        eig2x2(SS(hi - 1, hi - 1), SS(hi - 1, hi), SS(hi, hi - 1), SS(hi, hi), r1, i1, r2, i2);
+        wr[hi - 1] = r1; wi[hi - 1] = i1;
+        wr[hi] = r2; wi[hi] = i2;
+      }
+      hi -= 2;
+      its = 0;
+      continue;
+    }
+    ++its;
+    if (++total > 30 * m) return 1;
+    double s_sum, s_prod;
+    if (its % 10 == 0) {
+      const double w = fabs(SS(hi, hi - 1)) + fabs(SS(hi - 1, hi - 2));
+      s_sum = 1.5 * w;
+      s_prod = w * w;
+    } else {
+      s_sum = SS(hi - 1, hi - 1) + SS(hi, hi);
+      s_prod = SS(hi - 1, hi - 1) * SS(hi, hi) - SS(hi - 1, hi) * SS(hi, hi - 1);
+    }
+    double x = SS(lo, lo) * SS(lo, lo) + SS(lo, lo + 1) * SS(lo + 1, lo) - s_sum * SS(lo, lo) + s_prod;
+    double y = SS(lo + 1, lo) * (SS(lo, lo) + SS(lo + 1, lo + 1) - s_sum);
+    double z = SS(lo + 1, lo) * SS(lo + 2, lo + 1);
+    for (int k = lo; k <= hi - 1; ++k) {
+      const bool three = k < hi - 1;
+      if (k > lo) {
+        x = SS(k, k - 1);
+        y = SS(k + 1, k - 1);
+        z = three ? SS(k + 2, k - 1) : 0.0;
+      }
+      const double nv = three ? sqrt(x * x + y * y + z * z) : sqrt(x * x + y * y);
+      wave_sync();
+      if (nv != 0.0) {
+        const double v0 = x + copysign(nv, x), v1 = y, v2 = three ? z : 0.0;
+        const double t = 2.0 / (v0 * v0 + v1 * v1 + v2 * v2);
+        const int c = max(lo, k - 1) + lane;
+        if (c <= hi) {
+          const double a0 = SS(k, c), a1 = SS(k + 1, c), a2 = three ? SS(k + 2, c) : 0.0;
+          const double sv = t * (v0 * a0 + v1 * a1 + v2 * a2);
+          double b0 = a0 - sv * v0, b1 = a1 - sv * v1, b2 = a2 - sv * v2;
+          if (k > lo && c == k - 1) { b0 = -copysign(nv, x); b1 = 0.0; b2 = 0.0; }
+          SS(k, c) = b0;
+          SS(k + 1, c) = b1;
+          if (three) SS(k + 2, c) = b2;
+        }
+        wave_sync();
+        const int r = lo + lane;
+        if (r <= min(k + 3, hi)) {
+          const double a0 = SS(r, k), a1 = SS(r, k + 1), a2 = three ? SS(r, k + 2) : 0.0;
+          const double sv = t * (a0 * v0 + a1 * v1 + a2 * v2);
+          SS(r, k) = a0 - sv * v0;
+          SS(r, k + 1) = a1 - sv * v1;
+          if (three) SS(r, k + 2) = a2 - sv * v2;
+        }
+        wave_sync();
+      }
+    }
+  }
+#undef SS
+  return 0;
+}
+
+// The shift pairs of one sweep into pairs[0 .. 2k); returns k (1 .. QR_KMAX).
+// All threads of the workgroup call it.
+__device__ int sweep_shifts(const double* __restrict__ H, int lda, int lo, int hi, int its,
+                            double* S, double* swr, double* swi, double* pairs, int* ired) {
+  const int tid = threadIdx.x, wave = tid >> 6;
 #define HH(i, j) H[(size_t)(j) * lda + (i)]
-  for (int k0 = lo; k0 <= hi - 1; k0 += QR_NB) {
-    const int kend = min(k0 + QR_NB, hi);        // steps k0 .. kend-1
-    const int c0 = max(lo, k0 - 1);
-    const int c1 = min(kend + 1, hi);
+  const int m = hi - lo + 1;
+  if (its % 10 != 0 && m >= QR_MS_MIN) {
+    const int b0 = hi - QR_NS + 1;
+    for (int e = tid; e < QR_NS * QR_NS; e += EIG_THREADS) {
+      const int r = e / QR_NS, c = e - r * QR_NS;
+      S[r * QR_SLD + c] = (r <= c + 1) ? HH(b0 + r, b0 + c) : 0.0;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      const int fail = small_francis(S, QR_NS, swr, swi);
+      if ((tid & 63) == 0) ired[0] = fail;
+    }
+    __syncthreads();
+    const int fail = ired[0];
+    __syncthreads();
+    if (!fail) {
+      if (tid == 0) {
+        // complex pairs first; the real shifts, sorted in place at the front
+        // of swr, then paired in order
+        int k = 0, nre = 0;
+        for (int i = 0; i < QR_NS; ++i) {
+          const double re = swr[i], im = swi[i];
+          if (im > 0.0) {
+            pairs[2 * k] = 2.0 * re;
+            pairs[2 * k + 1] = re * re + im * im;
+            ++k;
+          } else if (im == 0.0) {
+            int j = nre++;
+            for (; j > 0 && swr[j - 1] > re; --j) swr[j] = swr[j - 1];
+            swr[j] = re;
+          }
+        }
+        for (int i = 0; i + 1 < nre; i += 2) {
+          pairs[2 * k] = swr[i] + swr[i + 1];
+          pairs[2 * k + 1] = swr[i] * swr[i + 1];
+          ++k;
+        }
+        ired[1] = k;
+      }
+      __syncthreads();
+      const int k = ired[1];
+      __syncthreads();
+      if (k >= 1) return k;
+    }
+  }
+  if (tid == 0) {
+    if (its % 10 == 0) {
+      const double w = fabs(HH(hi, hi - 1)) + fabs(HH(hi - 1, hi - 2));
+      pairs[0] = 1.5 * w;
+      pairs[1] = w * w;
+    } else {
+      const double a = HH(hi - 1, hi - 1), b = HH(hi - 1, hi);
+      const double c = HH(hi, hi - 1), d = HH(hi, hi);
+      pairs[0] = a + d;
+      pairs[1] = a * d - b * c;
+    }
+  }
+  __syncthreads();
+#undef HH
+  return 1;
+}
+
+// One chain step of bulge (wavefront) at position p, left half: form the
+// reflector (introducing the bulge from its shift pair at p == lo) and apply
+// it to rows p..p+2 of the block; the bulge column becomes exactly
+// (-sign(x) |(x,y,z)|, 0, 0).  Returns false when the reflector is trivial.
+__device__ inline bool chase_left(double* D, int c0, int d, int lo, int hi, int p,
+                                  double s_sum, double s_prod, double& v0, double& v1,
+                                  double& v2, double& t, bool& three) {
+  const int lane = threadIdx.x & 63;
+  const int j = p - c0;
+  three = p < hi - 1;
+  double x, y, z;
+  if (p == lo) {
+    const double h00 = D[j * QR_LD + j], h01 = D[j * QR_LD + j + 1];
+    const double h10 = D[(j + 1) * QR_LD + j], h11 = D[(j + 1) * QR_LD + j + 1];
+    x = h00 * h00 + h01 * h10 - s_sum * h00 + s_prod;
+    y = h10 * (h00 + h11 - s_sum);
+    z = three ? h10 * D[(j + 2) * QR_LD + j + 1] : 0.0;
+  } else {
+    x = D[j * QR_LD + j - 1];
+    y = D[(j + 1) * QR_LD + j - 1];
+    z = three ? D[(j + 2) * QR_LD + j - 1] : 0.0;
+  }
+  const double nv = three ? sqrt(x * x + y * y + z * z) : sqrt(x * x + y * y);
+  if (nv == 0.0) return false;
+  v0 = x + copysign(nv, x);
+  v1 = y;
+  v2 = three ? z : 0.0;
+  t = 2.0 / (v0 * v0 + v1 * v1 + v2 * v2);
+  const int q = max(lo, p - 1) - c0;
+  if (lane >= q && lane < d) {
+    double* pp = D + j * QR_LD + lane;
+    const double a0 = pp[0], a1 = pp[QR_LD], a2 = three ? pp[2 * QR_LD] : 0.0;
+    const double sv = t * (v0 * a0 + v1 * a1 + v2 * a2);
+    double b0 = a0 - sv * v0, b1 = a1 - sv * v1, b2 = a2 - sv * v2;
+    if (p > lo && lane == j - 1) {
+      b0 = -copysign(nv, x);
+      b1 = 0.0;
+      b2 = 0.0;
+    }
+    pp[0] = b0;
+    pp[QR_LD] = b1;
+    if (three) pp[2 * QR_LD] = b2;
+  }
+  return true;
+}
+
+// Right half: columns p..p+2 of the block rows c0..min(p+3, hi), and of U.
+__device__ inline void chase_right(double* D, double* U, int c0, int d, int hi, int p,
+                                   double v0, double v1, double v2, double t, bool three) {
+  const int lane = threadIdx.x & 63;
+  const int j = p - c0;
+  const int rl = min(p + 3, hi) - c0;
+  if (lane <= rl) {
+    double* pp = D + lane * QR_LD + j;
+    const double a0 = pp[0], a1 = pp[1], a2 = three ? pp[2] : 0.0;
+    const double sv = t * (a0 * v0 + a1 * v1 + a2 * v2);
+    pp[0] = a0 - sv * v0;
+    pp[1] = a1 - sv * v1;
+    if (three) pp[2] = a2 - sv * v2;
+  }
+  if (lane < d) {
+    double* pp = U + lane * QR_LD + j;
+    const double a0 = pp[0], a1 = pp[1], a2 = three ? pp[2] : 0.0;
+    const double sv = t * (a0 * v0 + a1 * v1 + a2 * v2);
+    pp[0] = a0 - sv * v0;
+    pp[1] = a1 - sv * v1;
+    if (three) pp[2] = a2 - sv * v2;
+  }
+}
+
+// one sweep with k bulges over the window [lo, hi] (hi - lo >= 2)
+__device__ void francis_sweep(double* __restrict__ H, int lda, int lo, int hi, int k,
+                              const double* __restrict__ pairs, double* __restrict__ D,
+                              double* __restrict__ U) {
+  const int tid = threadIdx.x, wave = tid >> 6;
+#define HH(i, j) H[(size_t)(j) * lda + (i)]
+  const int T = (hi - 1 - lo) + 3 * (k - 1) + 1;       // chain steps
+  const double s_sum = wave < k ? pairs[2 * wave] : 0.0;
+  const double s_prod = wave < k ? pairs[2 * wave + 1] : 0.0;
+  for (int t0 = 0; t0 < T; t0 += QR_NB) {
+    const int t1 = min(t0 + QR_NB, T);
+    const int pmin = max(lo, lo + t0 - 3 * (k - 1));
+    const int pmax = min(hi - 1, lo + t1 - 1);
+    const int c0 = max(lo, pmin - 1);
+    const int c1 = min(hi, pmax + 2);
     const int d = c1 - c0 + 1;
     const int dr = d + (c1 < hi ? 1 : 0);
     for (int e = tid; e < dr * d; e += EIG_THREADS) {
@@ -247,59 +512,28 @@ __device__ void francis_sweep(double* __restrict__ H, int lda, int lo, int hi,
       U[r * QR_LD + c] = (r == c && r < d) ? 1.0 : 0.0;
     }
     __syncthreads();
-    if (wave == 0) {
-      for (int k = k0; k < kend; ++k) {
-        const int j = k - c0;
-        const bool three = k < hi - 1;
-        if (k > lo) {
-          x = D[j * QR_LD + j - 1];
-          y = D[(j + 1) * QR_LD + j - 1];
-          z = three ? D[(j + 2) * QR_LD + j - 1] : 0.0;
+    if (k == 1) {
+      // one bulge: wavefront 0 alone, wavefront-level synchronisation
+      if (wave == 0)
+        for (int t = t0; t < t1; ++t) {
+          const int p = lo + t;
+          double v0, v1, v2, tt;
+          bool three;
+          const bool app = chase_left(D, c0, d, lo, hi, p, s_sum, s_prod, v0, v1, v2, tt, three);
+          wave_sync();
+          if (app) chase_right(D, U, c0, d, hi, p, v0, v1, v2, tt, three);
+          wave_sync();
         }
-        const double nv = three ? sqrt(x * x + y * y + z * z) : sqrt(x * x + y * y);
-        if (nv != 0.0) {
-          const double v0 = x + copysign(nv, x), v1 = y, v2 = three ? z : 0.0;
-          const double t = 2.0 / (v0 * v0 + v1 * v1 + v2 * v2);
-          // from the left: rows j..j+2, columns max(lo, k-1) .. c1; the
-          // bulge column k-1 becomes exactly (-sign(x) |(x,y,z)|, 0, 0)
-          const int q = max(lo, k - 1) - c0;
-          if (lane >= q && lane < d) {
-            double* p = D + j * QR_LD + lane;
-            const double a0 = p[0], a1 = p[QR_LD], a2 = three ? p[2 * QR_LD] : 0.0;
-            const double sv = t * (v0 * a0 + v1 * a1 + v2 * a2);
-            double b0 = a0 - sv * v0, b1 = a1 - sv * v1, b2 = a2 - sv * v2;
-            if (k > lo && lane == j - 1) {
-              b0 = -copysign(nv, x);
-              b1 = 0.0;
-              b2 = 0.0;
-            }
-            p[0] = b0;
-            p[QR_LD] = b1;
-            if (three) p[2 * QR_LD] = b2;
-          }
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          // from the right: columns j..j+2, rows c0 .. min(k+3, hi); and U
-          const int rl = min(k + 3, hi) - c0;
-          if (lane <= rl) {
-            double* p = D + lane * QR_LD + j;
-            const double a0 = p[0], a1 = p[1], a2 = three ? p[2] : 0.0;
-            const double sv = t * (a0 * v0 + a1 * v1 + a2 * v2);
-            p[0] = a0 - sv * v0;
-            p[1] = a1 - sv * v1;
-            if (three) p[2] = a2 - sv * v2;
-          }
-          if (lane < d) {
-            double* p = U + lane * QR_LD + j;
-            const double a0 = p[0], a1 = p[1], a2 = three ? p[2] : 0.0;
-            const double sv = t * (a0 * v0 + a1 * v1 + a2 * v2);
-            p[0] = a0 - sv * v0;
-            p[1] = a1 - sv * v1;
-            if (three) p[2] = a2 - sv * v2;
-          }
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-        }
+    } else {
+      for (int t = t0; t < t1; ++t) {
+        const int p = lo + t - 3 * wave;
+        const bool act = wave < k && p >= lo && p <= hi - 1;
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0, tt = 0.0;
+        bool three = false, app = false;
+        if (act) app = chase_left(D, c0, d, lo, hi, p, s_sum, s_prod, v0, v1, v2, tt, three);
+        __syncthreads();
+        if (app) chase_right(D, U, c0, d, hi, p, v0, v1, v2, tt, three);
+        __syncthreads();
       }
     }
     __syncthreads();
@@ -340,12 +574,19 @@ __device__ void francis_sweep(double* __restrict__ H, int lda, int lo, int hi,
 #undef HH
 }
 
-// Francis double-shift QR on Hessenberg H; returns 0 on success.
+// Francis QR on Hessenberg H; returns 0 on success.  lds holds QR_LDS
+// doubles.
 __device__ int francis(double* __restrict__ H, int n, int lda,
                        double* __restrict__ wr, double* __restrict__ wi,
-                       int* ired, double* D, double* U) {
+                       int* ired, double* lds) {
   const int tid = threadIdx.x;
   const double eps = DBL_EPSILON;
+  double* D = lds;
+  double* U = D + (QR_D + 1) * QR_LD;
+  double* S = U + QR_D * QR_LD;
+  double* swr = S + QR_NS * QR_SLD;
+  double* swi = swr + QR_NS;
+  double* pairs = swi + QR_NS;
   int hi = n - 1;
   int its = 0;
   int total = 0;
@@ -389,28 +630,15 @@ __device__ int francis(double* __restrict__ H, int n, int lda,
     ++its;
     ++total;
     if (total > max_total) return 1;
-    double s_sum, s_prod;
-    if (its % 10 == 0) {
-      const double w = fabs(HH(hi, hi - 1)) + fabs(HH(hi - 1, hi - 2));
-      s_sum = 1.5 * w;
-      s_prod = w * w;
-    } else {
-      const double a = HH(hi - 1, hi - 1), b = HH(hi - 1, hi);
-      const double c = HH(hi, hi - 1), d = HH(hi, hi);
-      s_sum = a + d;
-      s_prod = a * d - b * c;
-    }
-    const double x = HH(lo, lo) * HH(lo, lo) + HH(lo, lo + 1) * HH(lo + 1, lo) - s_sum * HH(lo, lo) + s_prod;
-    const double y = HH(lo + 1, lo) * (HH(lo, lo) + HH(lo + 1, lo + 1) - s_sum);
-    const double z = HH(lo + 1, lo) * HH(lo + 2, lo + 1);
-    __syncthreads();
-    francis_sweep(H, lda, lo, hi, x, y, z, D, U);
+    const int k = sweep_shifts(H, lda, lo, hi, its, S, swr, swi, pairs, ired);
+    francis_sweep(H, lda, lo, hi, k, pairs, D, U);
   }
 #undef HH
   return 0;
 }
 
-__global__ __launch_bounds__(EIG_THREADS) void k_eig(
+// four waves per SIMD: the register budget (128) admits four workgroups per CU
+__global__ __launch_bounds__(EIG_THREADS, 4) void k_eig(
     double* __restrict__ Abase, size_t stride, int lda,
     const SlotState* __restrict__ st, int n_uniform, int nmax, double* __restrict__ wrb,
     double* __restrict__ wib, int w_stride, int* __restrict__ info) {
@@ -424,16 +652,19 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(
   extern __shared__ double eig_lds[];
   __shared__ double red[EIG_THREADS / 64];
   __shared__ int ired[EIG_THREADS / 64];
-  __shared__ double qd[(QR_D + 1) * QR_LD];
-  __shared__ double qu[QR_D * QR_LD];
   double* H = Abase + (size_t)slot * stride;
   double* wr = wrb + (size_t)slot * w_stride;
   double* wi = wib + (size_t)slot * w_stride;
   hessenberg(H, n, lda, eig_lds, red);
-  // zero below the subdiagonal (the reduction leaves exact zeros already)
-  const int fail = francis(H, n, lda, wr, wi, ired, qd, qu);
+  __syncthreads();
+  // the QR phase reuses the reduction's LDS
+  const int fail = francis(H, n, lda, wr, wi, ired, eig_lds);
   if (threadIdx.x == 0 && info != nullptr) info[slot] = fail;
   if (threadIdx.x == 0 && st != nullptr) const_cast<SlotState*>(st)[slot].qr_fail = fail;
+}
+
+size_t eig_hess_lds(int nmax) {
+  return sizeof(double) * std::max<size_t>(9 * (size_t)nmax, QR_LDS);
 }
 
 void launch_eig(double* A, size_t stride, int lda, const int* /*n_per*/,
