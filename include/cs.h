@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define CS_ABI_VERSION 7
+#define CS_ABI_VERSION 8
 
 enum {
   CS_OK = 0,
@@ -134,6 +134,17 @@ typedef struct {
                           solve before that system is factorised in FP64
                           instead (default 4, 0..100; 0: the FP32 solution is
                           tested as it is)                                   */
+  int32_t graph;       /* 0: every Newton step's kernels are launched from the
+                          host (default); k = 1..64: the step's kernels
+                          (KKT assembly, factorisation and solve, update) are
+                          captured once per call into a HIP graph and the
+                          graph is replayed k times per scheduling round,
+                          between two host synchronisations.  Records are
+                          identical either way.  Ignored when timing = 1.    */
+  int32_t autotune;    /* 1: launch variants of the large-order LU are chosen
+                          by timing them on the device at first use
+                          (cs_autotune) and cached per (device, order,
+                          precision) for the process; 0: defaults (default) */
 } cs_opts;
 
 /* Per-kernel accumulated device time of the calls made with opts.timing = 1
@@ -445,6 +456,27 @@ int cs_wait(cs_req* req, int64_t timeout_us, cs_result* out, double* risk,
 /* Release a request (at any time; an unfinished one is dropped when it
  * completes). */
 void cs_req_free(cs_req* req);
+
+/* Autotuning of launch variants.  For a KKT order n above the
+ * register-resident LU's limit (1,024), times the large-order LU with panel
+ * widths 16, 32 and 64 (one untimed, one timed launch each) on
+ * min(batch, 512) synthetic systems of order n (diagonally dominant,
+ * entries from a counter hash) in the precision prec names (FP64, or FP32
+ * for CS_PREC_MIXED, the mixed form's main factorisation), keeps the fastest
+ * for (ctx's device, n, precision) for the rest of the process and returns
+ * it in *choice (may be NULL), with the milliseconds of each timed launch in
+ * ms[CS_TUNE_VARIANTS] (may be NULL).  For n <= 1,024 there is nothing to
+ * tune: *choice = 0, ms NaN.  opts.autotune = 1 runs it at first use.
+ * Allocates temporary device memory (at most half the context's budget).
+ * Errors: CS_EINVAL, CS_EUNSUPPORTED (n > 4,096), CS_ENOMEM, CS_EDEVICE. */
+#define CS_TUNE_VARIANTS 3
+int cs_autotune(cs_ctx* ctx, int32_t n, int32_t prec, int32_t batch, int32_t* choice,
+                double* ms);
+
+/* Install a choice measured earlier (for instance in another process) for
+ * (ctx's device, n, prec): a panel width of 16, 32 or 64, or 0 to return to
+ * the default (32).  CS_EINVAL for any other value. */
+int cs_autotune_set(cs_ctx* ctx, int32_t n, int32_t prec, int32_t choice);
 
 /* Copy / clear the context's kernel timing counters. */
 int cs_stats_get(const cs_ctx* ctx, cs_stats* out);

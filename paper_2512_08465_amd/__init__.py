@@ -64,7 +64,8 @@ class Options(ctypes.Structure):
                 ("tol", ctypes.c_double), ("near_eps", ctypes.c_double),
                 ("hbm_budget", ctypes.c_size_t), ("batch", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("overlap", ctypes.c_int32),
-                ("refine_steps", ctypes.c_int32)]
+                ("refine_steps", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("autotune", ctypes.c_int32)]
 
 
 KERNELS = ("topology", "kkt_assemble", "kkt_lu", "ipm_update", "dyn_assemble", "dyn_lu",
@@ -138,6 +139,8 @@ def library():
                                                   ctypes.POINTER(vp)]),
         "cs_server_slots": (ctypes.c_int, [vp, ctypes.c_int]),
         "cs_submit_net": (ctypes.c_int, [vp, ctypes.c_int, vp, i64, dp, dp, ctypes.POINTER(vp)]),
+        "cs_autotune": (ctypes.c_int, [vp, i32, i32, i32, ctypes.POINTER(i32), dp]),
+        "cs_autotune_set": (ctypes.c_int, [vp, i32, i32, i32]),
         "cs_wait": (ctypes.c_int, [vp, i64, vp, dp, dp]),
         "cs_req_free": (None, [vp]),
     }
@@ -156,7 +159,8 @@ EXPORTED = ("cs_ctx_create", "cs_ctx_destroy", "cs_net_create", "cs_net_destroy"
             "cs_server_destroy", "cs_submit", "cs_wait", "cs_req_free", "cs_screen_detail",
             "cs_dyn_at", "cs_screen_device_noalloc", "cs_risk_opts_default", "cs_risk",
             "cs_risk_mc", "cs_screen3_device", "cs_screen_n3_device", "cs_submit_snapshot",
-            "cs_server_create_multi", "cs_server_slots", "cs_submit_net")
+            "cs_server_create_multi", "cs_server_slots", "cs_submit_net", "cs_autotune",
+            "cs_autotune_set")
 
 
 def _check(rc):
@@ -216,6 +220,19 @@ class Context:
 
     def reset_stats(self):
         _check(library().cs_stats_reset(self._h))
+
+    def autotune(self, n: int, prec: int = 0, batch: int = 512):
+        """Time the large-order LU's panel widths for KKT order n (cs_autotune):
+        (chosen width or 0 when order n has nothing to tune, ms per variant)."""
+        choice = ctypes.c_int32(0)
+        ms = np.zeros(3)
+        _check(library().cs_autotune(self.handle, int(n), int(prec), int(batch),
+                                     ctypes.byref(choice), _ptr(ms)))
+        return int(choice.value), ms
+
+    def autotune_set(self, n: int, prec: int, choice: int):
+        """Install a panel width (16, 32, 64; 0 = default) for KKT order n."""
+        _check(library().cs_autotune_set(self.handle, int(n), int(prec), int(choice)))
 
     # kernel-level entry points (device pointers, e.g. torch tensors' data_ptr)
     def dense_solve_batched(self, a_ptr, n, nrhs, lda, batch, info_ptr=None, stream=None):

@@ -34,6 +34,7 @@
 namespace cs {
 size_t lu_lds_bytes(int n, int nrhs);
 int lu_max_order();
+int lu_reg_order();
 size_t opf_eval_lds(int nb, int nl, int ng);
 size_t form_state_lds(int ng);
 void lu_set_attrs(size_t bytes);
@@ -192,6 +193,8 @@ void cs_opts_default(cs_opts* o) {
   o->timing = 0;
   o->overlap = 0;
   o->refine_steps = kRefineMax;
+  o->graph = 0;
+  o->autotune = 0;
 }
 
 int cs_ctx_create(int device, size_t hbm_budget, cs_ctx** out) {
@@ -587,6 +590,53 @@ struct Engine {
   long long assigned = 0;        // scenarios handed to slots so far
   bool dyn_busy = false;
   bool dyn_finished = false;     // the dynamic stage was seen complete in issue()
+  hipGraphExec_t newton = nullptr;  // captured Newton step (opts.graph > 0)
+
+  Engine() = default;
+  Engine(const Engine&) = delete;
+  Engine& operator=(const Engine&) = delete;
+  ~Engine() {
+    if (newton) hipGraphExecDestroy(newton);
+  }
+
+  // One Newton step for every slot in the OPF loop, launches only (what the
+  // graph captures): KKT assembly, factorisation and solve, update.
+  void newton_launches(hipStream_t q) {
+    launch_opf_eval(*D, s, nslots, opts.tol, opts.max_it, q);
+    if (opts.prec == CS_PREC_MIXED) {
+      launch_kkt_to_f32(s, nslots, q);
+      launch_lu_solve_f32(s.K32, s.k32_stride, s.nk, s.nk + 1, s.ld32, s.piv, pstride, s.st,
+                          PH_IPM, 1, nslots, nullptr, q);
+      launch_kkt_refine(s, nslots, pstride, opts.refine_steps, q);
+      launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv, pstride, s.st, PH_IPM, 3,
+                      nslots, nullptr, q, LU_KKT_FALLBACK);
+    } else {
+      launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv, pstride, s.st, PH_IPM, 1,
+                      nslots, nullptr, q);
+    }
+    launch_opf_update(*D, s, nslots, 1e10, q);
+  }
+
+  // opts.graph Newton steps replayed from the captured graph (captured on
+  // first use; the kernels read every slot's stage from device memory, so
+  // one capture serves every round)
+  int newton_graph() {
+    if (!newton) {
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      newton_launches(st);
+      const hipError_t ec = hipStreamEndCapture(st, &g);
+      if (ec != hipSuccess) return fail(CS_EDEVICE, std::string("Newton step capture: ") + hipGetErrorString(ec));
+      const hipError_t ei = hipGraphInstantiate(&newton, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        newton = nullptr;
+        return fail(CS_EDEVICE, std::string("Newton step graph: ") + hipGetErrorString(ei));
+      }
+    }
+    for (int r = 0; r < opts.graph; ++r) HIPCHK(hipGraphLaunch(newton, st));
+    return CS_OK;
+  }
 
   int timed(int kind, hipStream_t stream, int64_t units, int uidx, const std::function<void()>& f) {
     if (T) return T->run(kind, stream, units, uidx, f);
@@ -638,7 +688,9 @@ struct Engine {
       if (rc != CS_OK) return rc;
       work = true;
     }
-    if (work || cnt[PH_IPM] > 0) {
+    if ((work || cnt[PH_IPM] > 0) && opts.graph > 0 && !T) {
+      if ((rc = newton_graph()) != CS_OK) return rc;
+    } else if (work || cnt[PH_IPM] > 0) {
       rc = timed(CS_K_KKT_ASSEMBLE, st, cnt[PH_IPM], -1,
                  [&] { launch_opf_eval(*D, s, nslots, opts.tol, opts.max_it, st); });
       if (rc != CS_OK) return rc;
@@ -781,6 +833,111 @@ static int check_opts(const cs_opts& opts, const char* who) {
   if (!(opts.tol > 0)) return fail(CS_EINVAL, std::string(who) + ": tol must be > 0");
   if (opts.refine_steps < 0 || opts.refine_steps > 100)
     return fail(CS_EINVAL, std::string(who) + ": refine_steps must be in 0..100");
+  if (opts.graph < 0 || opts.graph > 64)
+    return fail(CS_EINVAL, std::string(who) + ": graph must be in 0..64");
+  if (opts.autotune != 0 && opts.autotune != 1)
+    return fail(CS_EINVAL, std::string(who) + ": autotune must be 0 or 1");
+  return CS_OK;
+}
+
+// ------------------------------------------------------------------ autotuning
+// Panel width of the large-order LU: every candidate times one launch over
+// min(batch, 512) synthetic systems of order n (after one untimed launch),
+// the fastest is kept for (device, n, precision).
+static const int kTunePanels[CS_TUNE_VARIANTS] = {16, 32, 64};
+
+static int tune_lu_big(cs_ctx* c, int n, bool f32, int batch, int* choice, double* ms) {
+  const size_t es = f32 ? sizeof(float) : sizeof(double);
+  const int ncols = n + 1;
+  const int lda = (int)round_up(ncols, 2);
+  const size_t stride = (size_t)n * lda;
+  long long count = std::max(1, std::min(batch, 512));
+  const size_t cap = std::max<size_t>(c->hbm_budget / 2, stride * es);
+  count = std::max<long long>(1, std::min<long long>(count, (long long)(cap / (stride * es))));
+  void* A = nullptr;
+  int* piv = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&] {
+    if (A) hipFree(A);
+    if (piv) hipFree(piv);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  };
+  if (hipMalloc(&A, stride * es * count) != hipSuccess ||
+      hipMalloc(&piv, sizeof(int) * (size_t)n * count) != hipSuccess) {
+    cleanup();
+    return fail(CS_ENOMEM, "cs_autotune: allocation failed");
+  }
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(CS_EDEVICE, "cs_autotune: event creation failed");
+  }
+  hipStream_t st = c->stream;
+  int best = 32;
+  float best_ms = 0.0f;
+  for (int v = 0; v < CS_TUNE_VARIANTS; ++v) {
+    const int nb = kTunePanels[v];
+    float t = 0.0f;
+    for (int rep = 0; rep < 2; ++rep) {
+      launch_tune_fill(A, f32, stride, n, ncols, lda, (int)count, 12345u + rep, st);
+      hipEventRecord(e0, st);
+      if (f32)
+        launch_lu_big_f32(static_cast<float*>(A), stride, n, ncols, lda, piv, n, nullptr, 0, 0,
+                          (int)count, nullptr, st, nb);
+      else
+        launch_lu_big(static_cast<double*>(A), stride, n, ncols, lda, piv, n, nullptr, 0, 0,
+                      (int)count, nullptr, st, nb);
+      hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+        cleanup();
+        return fail(CS_EDEVICE, "cs_autotune: timing launch failed");
+      }
+    }
+    if (ms) ms[v] = t;
+    if (v == 0 || t < best_ms) {
+      best_ms = t;
+      best = nb;
+    }
+  }
+  cleanup();
+  HIPCHK(hipGetLastError());
+  lu_big_set_panel(c->device, n, f32, best);
+  if (choice) *choice = best;
+  return CS_OK;
+}
+
+extern "C" int cs_autotune(cs_ctx* c, int32_t n, int32_t prec, int32_t batch, int32_t* choice,
+                           double* ms) {
+  if (!c || n <= 0 || batch <= 0 || (prec != CS_PREC_FP64 && prec != CS_PREC_MIXED))
+    return fail(CS_EINVAL, "cs_autotune: bad arguments");
+  if (n > lu_max_order())
+    return fail(CS_EUNSUPPORTED, "cs_autotune: order above " + std::to_string(lu_max_order()));
+  if (choice) *choice = 0;
+  if (ms)
+    for (int v = 0; v < CS_TUNE_VARIANTS; ++v) ms[v] = std::nan("");
+  if (n <= lu_reg_order()) return CS_OK;   // the register-resident kernel has one shape
+  HIPCHK(hipSetDevice(c->device));
+  return tune_lu_big(c, n, prec == CS_PREC_MIXED, batch, choice, ms);
+}
+
+extern "C" int cs_autotune_set(cs_ctx* c, int32_t n, int32_t prec, int32_t choice) {
+  if (!c || n <= 0 || (prec != CS_PREC_FP64 && prec != CS_PREC_MIXED) ||
+      (choice != 0 && choice != 16 && choice != 32 && choice != 64))
+    return fail(CS_EINVAL, "cs_autotune_set: bad arguments");
+  lu_big_set_panel(c->device, n, prec == CS_PREC_MIXED, choice);
+  return CS_OK;
+}
+
+// opts.autotune: tune the large-order LU of the KKT order once per process
+static int autotune_for(cs_ctx* c, const Plan& p, const cs_opts& opts, int B) {
+  if (!opts.autotune || p.s.nk <= lu_reg_order()) return CS_OK;
+  for (int f = 0; f < 2; ++f) {
+    const bool f32 = f == 1;
+    if (f32 && opts.prec != CS_PREC_MIXED) continue;
+    if (lu_big_panel(c->device, p.s.nk, f32) != 0) continue;
+    const int rc = tune_lu_big(c, p.s.nk, f32, B, nullptr, nullptr);
+    if (rc != CS_OK) return rc;
+  }
   return CS_OK;
 }
 
@@ -828,6 +985,7 @@ static int run_screen(cs_ctx* c, cs_net* n, const int* d_out_list, long long N,
     HIPCHK(hipMalloc(&c->d_units, sizeof(int) * cap));
     c->units_cap = cap;
   }
+  if ((rc = autotune_for(c, p, opts, (int)B)) != CS_OK) return rc;
   TimedLaunches T(c, tm);
   Engine e;
   e.c = c;
@@ -954,6 +1112,8 @@ static int screen_device(const char* who, cs_ctx* c, cs_net* n, const int32_t* d
   if (d_risk && !d_lambda) return fail(CS_EINVAL, std::string(who) + ": risk requested without lambda");
   if (in_scratch && opts && opts->timing)
     return fail(CS_EINVAL, std::string(who) + ": kernel timing is not available (it allocates)");
+  if (in_scratch && opts && (opts->graph || opts->autotune))
+    return fail(CS_EINVAL, std::string(who) + ": graphs and autotuning are not available (they allocate)");
   HIPCHK(hipSetDevice(c->device));
   hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
   const int n_comp = n->nl + n->ng + n->nd;
@@ -1218,6 +1378,7 @@ static int lane_create(cs_server* S, cs_net* n, size_t bytes, int index, ServerL
   B = std::max<long long>(1, std::min<long long>(B, 1 << 20));
   int rc = bind_workspace(&L->ws, &L->ws_bytes, n, L->p, (int)B);
   if (rc != CS_OK) return rc;
+  if ((rc = autotune_for(S->c, L->p, opts, (int)B)) != CS_OK) return rc;
   const long long qc = S->q_cap;
   const int n_comp = n->nl + n->ng + n->nd;
   if (hipStreamCreateWithFlags(&L->st, hipStreamNonBlocking) != hipSuccess ||

@@ -135,12 +135,18 @@ void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
                      int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
                      int count, int* info, hipStream_t stream, int role = LU_KKT);
 // orders above the register-resident kernel's limit (k_lu_big.hip)
+// nb: panel width 16, 32 or 64; 0 = the autotuner's choice for (current
+// device, n, precision), else 32
 void launch_lu_big(double* A, size_t stride, int n, int ncols, int lda, int* piv,
                    int piv_stride, SlotState* st, int want_phase, int want_job, int count,
-                   int* info, hipStream_t stream);
+                   int* info, hipStream_t stream, int nb = 0);
 void launch_lu_big_f32(float* A, size_t stride, int n, int ncols, int lda, int* piv,
                        int piv_stride, SlotState* st, int want_phase, int want_job, int count,
-                       int* info, hipStream_t stream);
+                       int* info, hipStream_t stream, int nb = 0);
+void lu_big_set_panel(int device, int n, bool f32, int nb);
+int lu_big_panel(int device, int n, bool f32);   // 0 when not tuned
+void launch_tune_fill(void* A, bool f32, size_t stride, int n, int ncols, int lda, int count,
+                      unsigned seed, hipStream_t stream);
 void launch_lu_solve_f32(float* A, size_t stride, int n, int ncols, int lda,
                          int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
                          int count, int* info, hipStream_t stream);

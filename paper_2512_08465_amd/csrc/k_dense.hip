@@ -825,6 +825,9 @@ size_t lu_lds_bytes(int n, int nrhs) {
 // (panel rows in registers), k_lu_big above
 int lu_max_order() { return 4096; }
 
+// largest order the register-resident kernel takes
+int lu_reg_order() { return LU_MAX_N; }
+
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
                      int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
                      int count, int* info, hipStream_t stream, int role) {

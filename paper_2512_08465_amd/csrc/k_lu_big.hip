@@ -2,7 +2,8 @@
 // register-resident kernel's limit (k_dense.hip holds panels of up to 1,024
 // rows in registers): one workgroup per matrix, the matrix in global memory.
 //
-// Right-looking blocked LU, panel width 32, the same arithmetic contract as
+// Right-looking blocked LU, panel width NB (16, 32 or 64: the autotuner's
+// choice per order and precision, 32 by default), the same arithmetic contract as
 // LAPACK's getrf (largest |a| pivot, ties to the lowest row, rows swapped
 // across the whole augmented matrix, multipliers by division):
 //   panel   column by column over the rows below the diagonal: a workgroup
@@ -13,7 +14,7 @@
 //   update  A22 -= L21 U12 on the matrix cores (v_mfma_f64_16x16x4f64, or
 //           the FP32 step for the mixed-precision factorisation), 32 x 32
 //           groups handed to the wavefronts in turn;
-//   solve   U x = y for the right-hand-side columns by 32-row blocks from the
+//   solve   U x = y for the right-hand-side columns by NB-row blocks from the
 //           bottom (the forward substitution happened on the augmented
 //           columns during the elimination).
 // Its bound is the latency of the panel steps (four barriers per column);
@@ -21,10 +22,13 @@
 #include "cs_internal.h"
 
 #include <climits>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace cs {
 
-constexpr int BIG_T = 512, BIG_W = BIG_T / 64, BIG_NB = 32;
+constexpr int BIG_T = 512, BIG_W = BIG_T / 64;
 
 template <class T> struct BigMfma;
 template <> struct BigMfma<double> {
@@ -51,7 +55,7 @@ __device__ inline bool big_better(T v, int i, T bv, int bi) {
 
 // two workgroups per CU (register budget of 128), so that one's panel
 // latency overlaps the other's work
-template <class T>
+template <class T, int BIG_NB>
 __global__ __launch_bounds__(BIG_T, 2) void k_lu_big(T* __restrict__ Abase, size_t stride, int n,
                                                   int ncols, int lda, int* __restrict__ pivbase,
                                                   int piv_stride, SlotState* __restrict__ st,
@@ -229,27 +233,79 @@ __global__ __launch_bounds__(BIG_T, 2) void k_lu_big(T* __restrict__ Abase, size
   }
 }
 
+// panel width per (device, order, precision), set by the autotuner
+static std::mutex g_nb_m;
+static std::map<std::tuple<int, int, int>, int> g_nb;
+
+void lu_big_set_panel(int device, int n, bool f32, int nb) {
+  std::lock_guard<std::mutex> lk(g_nb_m);
+  g_nb[std::make_tuple(device, n, f32 ? 1 : 0)] = nb;
+}
+
+int lu_big_panel(int device, int n, bool f32) {
+  std::lock_guard<std::mutex> lk(g_nb_m);
+  auto it = g_nb.find(std::make_tuple(device, n, f32 ? 1 : 0));
+  return it == g_nb.end() ? 0 : it->second;
+}
+
 template <class T>
 void launch_lu_big_t(T* A, size_t stride, int n, int ncols, int lda, int* piv, int piv_stride,
                      SlotState* st, int want_phase, int want_job, int count, int* info,
-                     hipStream_t stream) {
+                     hipStream_t stream, int nb) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_lu_big<T>, dim3(count), dim3(BIG_T), 0, stream, A, stride, n, ncols, lda,
-                     piv, piv_stride, st, want_phase, want_job, info);
+  if (nb == 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    nb = lu_big_panel(dev, n, sizeof(T) == 4);
+  }
+  auto k = nb == 16 ? k_lu_big<T, 16> : nb == 64 ? k_lu_big<T, 64> : k_lu_big<T, 32>;
+  hipLaunchKernelGGL(k, dim3(count), dim3(BIG_T), 0, stream, A, stride, n, ncols, lda, piv,
+                     piv_stride, st, want_phase, want_job, info);
 }
 
 void launch_lu_big(double* A, size_t stride, int n, int ncols, int lda, int* piv,
                    int piv_stride, SlotState* st, int want_phase, int want_job, int count,
-                   int* info, hipStream_t stream) {
+                   int* info, hipStream_t stream, int nb) {
   launch_lu_big_t(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, count,
-                  info, stream);
+                  info, stream, nb);
 }
 
 void launch_lu_big_f32(float* A, size_t stride, int n, int ncols, int lda, int* piv,
                        int piv_stride, SlotState* st, int want_phase, int want_job, int count,
-                       int* info, hipStream_t stream) {
+                       int* info, hipStream_t stream, int nb) {
   launch_lu_big_t(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, count,
-                  info, stream);
+                  info, stream, nb);
+}
+
+// Synthetic systems for timing: entries from a counter hash in [-1, 1), the
+// diagonal raised by n (no pivot is ever zero).
+template <class T>
+__global__ void k_tune_fill(T* __restrict__ A, size_t stride, int n, int ncols, int lda,
+                            unsigned seed) {
+  const int slot = blockIdx.x;
+  T* a = A + (size_t)slot * stride;
+  for (long long e = threadIdx.x; e < (long long)n * ncols; e += blockDim.x) {
+    const int r = (int)(e / ncols), c = (int)(e % ncols);
+    unsigned h = (unsigned)e * 2654435761u ^ (unsigned)slot * 40503u ^ seed;
+    h ^= h >> 16;
+    h *= 0x7feb352du;
+    h ^= h >> 15;
+    h *= 0x846ca68bu;
+    h ^= h >> 16;
+    T v = T((double)h * (2.0 / 4294967296.0) - 1.0);
+    if (r == c) v += T(n);
+    a[(size_t)r * lda + c] = v;
+  }
+}
+
+void launch_tune_fill(void* A, bool f32, size_t stride, int n, int ncols, int lda, int count,
+                      unsigned seed, hipStream_t stream) {
+  if (f32)
+    hipLaunchKernelGGL(k_tune_fill<float>, dim3(count), dim3(256), 0, stream,
+                       static_cast<float*>(A), stride, n, ncols, lda, seed);
+  else
+    hipLaunchKernelGGL(k_tune_fill<double>, dim3(count), dim3(256), 0, stream,
+                       static_cast<double*>(A), stride, n, ncols, lda, seed);
 }
 
 }  // namespace cs

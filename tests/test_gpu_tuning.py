@@ -1,0 +1,167 @@
+"""Launch-shape machinery through the C-ABI: the Newton step replayed from a
+captured HIP graph (opts.graph) and the large-order LU's panel widths with
+the autotuner that chooses among them (cs_autotune, opts.autotune).
+
+* Graph replays: every scheduling round replays the captured Newton step k
+  times between the engine's own eager kernels (refill, stage counts, the
+  dynamic stage) and host synchronisations; the records and R_i of a whole
+  list are bit-identical to the eager launches', FP64 and mixed, in a batch
+  call and in a server.
+* Panel widths 16, 32 and 64 each give factors and solutions equal to
+  SciPy's (LAPACK's pivoting) at orders 1,100 and 1,338; the autotuner
+  returns the fastest of its own timings and leaves orders up to 1,024 alone.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from helpers import load_case, load_golden
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("severe", "cause", "opf_status", "near", "n_islands", "opf_iters", "n_states",
+          "opf_cost", "max_real_eig", "min_damping", "max_violation")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2512_08465_amd as cs
+    return cs.Context(0)
+
+
+@pytest.fixture(scope="module")
+def nets(ctx):
+    import paper_2512_08465_amd as cs
+    return {k: (cs.Network(ctx, load_case(k)), load_case(k)) for k in ("c1_30", "c2_118")}
+
+
+def _same(a, b):
+    assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), \
+        [k for k in FIELDS if not np.array_equal(a[k], b[k], equal_nan=True)]
+
+
+@pytest.mark.parametrize("prec,steps", [(0, 1), (0, 3), (1, 2)])
+def test_graph_replays_equal_eager_c1(nets, prec, steps):
+    import paper_2512_08465_amd as cs
+    net, case = nets["c1_30"]
+    lst = load_golden("c1_30")["outages"]
+    print(f"c1_30: {len(lst)} scenarios, prec {prec}, {steps} replays per round", flush=True)
+    ref, ref_r = net.screen(lst, case["lam"], cs.default_options(prec=prec, batch=200))
+    got, got_r = net.screen(lst, case["lam"], cs.default_options(prec=prec, batch=200, graph=steps))
+    _same(got, ref)
+    assert np.array_equal(got_r, ref_r)
+
+
+def test_graph_replays_equal_eager_c2(nets):
+    import paper_2512_08465_amd as cs
+    net, case = nets["c2_118"]
+    lst = load_golden("c2_118")["outages"][:300]
+    print(f"c2_118: {len(lst)} scenarios", flush=True)
+    ref, ref_r = net.screen(lst, case["lam"], cs.default_options(batch=128))
+    got, got_r = net.screen(lst, case["lam"], cs.default_options(batch=128, graph=1))
+    _same(got, ref)
+    assert np.array_equal(got_r, ref_r)
+
+
+def test_graph_in_a_server(nets):
+    import paper_2512_08465_amd as cs
+    net, case = nets["c1_30"]
+    g = load_golden("c1_30")["outages"]
+    lists = [g[:150], g[400:470], g[700:861]]
+    srv = cs.Server(net.ctx, net, cs.default_options(batch=64, graph=2), queue_capacity=2048)
+    reqs = [srv.submit(l, case["lam"]) for l in lists]
+    for l, r in zip(lists, reqs):
+        res, risk, _ = r.wait(timeout_s=300)
+        ref, ref_r = net.screen(l, case["lam"])
+        _same(res, ref)
+        assert np.array_equal(risk, ref_r)
+    srv.close()
+
+
+def test_noalloc_refuses_graph_and_autotune(nets):
+    import torch
+    import paper_2512_08465_amd as cs
+    net, case = nets["c1_30"]
+    d_rows = torch.tensor([[0, -1]], dtype=torch.int32, device="cuda")
+    d_out = torch.zeros(cs.RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    for kw in (dict(graph=1), dict(autotune=1)):
+        with pytest.raises(cs.CSError) as e:
+            net.screen_device_noalloc(d_rows.data_ptr(), 1, None, d_out.data_ptr(), None,
+                                      cs.default_options(**kw))
+        assert e.value.code == cs.CS_EINVAL
+
+
+def _run_lu(ctx, A, rhs):
+    import torch
+    B, n, _ = A.shape
+    k = rhs.shape[2]
+    lda = n + k + ((n + k) % 2)
+    buf = np.zeros((B, n, lda))
+    buf[:, :, :n] = A
+    buf[:, :, n:n + k] = rhs
+    d = torch.from_numpy(buf).cuda()
+    info = torch.zeros(B, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    ctx.dense_solve_batched(d.data_ptr(), n, k, lda, B, info.data_ptr())
+    out = d.cpu().numpy()
+    return out[:, :, :n], out[:, :, n:], info.cpu().numpy()
+
+
+@pytest.mark.parametrize("n", [1100, 1338])
+@pytest.mark.parametrize("nb", [16, 32, 64])
+def test_panel_widths_match_scipy(ctx, n, nb):
+    rng = np.random.default_rng(n + nb)
+    A = rng.standard_normal((2, n, n))
+    X = rng.standard_normal((2, n, 2))
+    ctx.autotune_set(n, 0, nb)
+    try:
+        fac, sol, info = _run_lu(ctx, A, A @ X)
+    finally:
+        ctx.autotune_set(n, 0, 0)
+    assert np.all(info == 0)
+    for b in range(2):
+        lu, piv = sla.lu_factor(A[b])
+        assert np.allclose(fac[b], lu, rtol=1e-9, atol=1e-9 * np.abs(lu).max())
+        ref = sla.lu_solve((lu, piv), (A @ X)[b])
+        assert np.max(np.abs(sol[b] - ref)) <= 1e-13 * np.linalg.cond(A[b]) * max(1, np.abs(ref).max())
+
+
+def test_autotune_picks_its_fastest(ctx):
+    import paper_2512_08465_amd as cs
+    choice, ms = ctx.autotune(1338, cs.PREC_FP64, 256)
+    print(f"order 1338 FP64: panel widths 16/32/64 take {ms} ms; chose {choice}")
+    assert choice in (16, 32, 64)
+    assert np.all(np.isfinite(ms)) and np.all(ms > 0)
+    assert choice == (16, 32, 64)[int(np.argmin(ms))]
+    choice32, ms32 = ctx.autotune(1338, cs.PREC_MIXED, 256)
+    print(f"order 1338 FP32: {ms32} ms; chose {choice32}")
+    assert choice32 == (16, 32, 64)[int(np.argmin(ms32))]
+    none, ms0 = ctx.autotune(580, cs.PREC_FP64, 256)
+    assert none == 0 and np.all(np.isnan(ms0))
+    ctx.autotune_set(1338, cs.PREC_FP64, 0)
+    ctx.autotune_set(1338, cs.PREC_MIXED, 0)
+    with pytest.raises(cs.CSError) as e:
+        ctx.autotune_set(1338, cs.PREC_FP64, 48)
+    assert e.value.code == cs.CS_EINVAL
+
+
+def test_autotuned_c4_records_match_oracle(ctx):
+    """opts.autotune on the 300-bus case (KKT order 1,338): the tuned run's
+    records agree with the oracle's to the usual bars, FP64 and mixed."""
+    import paper_2512_08465_amd as cs
+    from helpers import outcome_mismatches
+    case = load_case("c4_300")
+    net = cs.Network(ctx, case)
+    g = load_golden("c4_300")
+    idx = np.flatnonzero(g["opf_iters"] < 40)[:12]
+    for prec in (cs.PREC_FP64, cs.PREC_MIXED):
+        res, _ = net.screen(g["outages"][idx], None, cs.default_options(prec=prec, autotune=1))
+        sub = {k: g[k][idx] for k in g if len(g[k]) == len(g["outages"])}
+        bad, _, _ = outcome_mismatches(sub, res)
+        assert len(bad) == 0, bad
+        both = (sub["opf_status"] == 0) & (res["opf_status"] == 0)
+        rel = np.abs(res["opf_cost"][both] - sub["opf_cost"][both]) / np.abs(sub["opf_cost"][both])
+        assert rel.max() < 1e-6
+    net.close()
+    ctx.autotune_set(1338, cs.PREC_FP64, 0)
+    ctx.autotune_set(1338, cs.PREC_MIXED, 0)
