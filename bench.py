@@ -107,6 +107,8 @@ def main():
                     help="scenario slots resident at once (refilled as scenarios finish)")
     ap.add_argument("--legs", default="fp64,mixed",
                     help="precisions to time: fp64 (the headline) and/or mixed")
+    ap.add_argument("--graph", type=int, default=0,
+                    help="Newton steps replayed from a captured HIP graph per round (0: eager)")
     ap.add_argument("--overlap", type=int, default=0,
                     help="1: dynamic stage on a second stream beside the OPF iterations")
     ap.add_argument("--c3-slice", type=int, default=14408,
@@ -115,6 +117,8 @@ def main():
     ap.add_argument("--c4-slice", type=int, default=512,
                     help="scenarios of the 300-bus-shaped case (random branch/generator "
                          "pairs) screened in the mixed form and in FP64 (0: skip)")
+    ap.add_argument("--c4-panel", type=int, default=0,
+                    help="panel width of the large-order LU (16, 32, 64); 0 = autotuned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=12,
                     help="requests per arrival rate in the serving sweep (0: skip it)")
@@ -188,8 +192,12 @@ def main():
     results = {}
     for leg in legs:
         prec = cs.PREC_MIXED if leg == "mixed" else cs.PREC_FP64
-        plain = cs.default_options(batch=args.batch, overlap=args.overlap, prec=prec)
-        timed = cs.default_options(batch=args.batch, overlap=args.overlap, prec=prec, timing=1)
+        plain = cs.default_options(batch=args.batch, overlap=args.overlap, prec=prec,
+                                   graph=args.graph)
+        # (kernel timing launches every kernel itself: the timed steps run
+        # eagerly, with the graph only when --graph is given and timing off)
+        timed = cs.default_options(batch=args.batch, overlap=args.overlap, prec=prec,
+                                   timing=0 if args.graph else 1, graph=args.graph)
         for w in range(args.warmup):
             run(0, min(args.warmup_size, n_all), plain)
             log(f"{leg}: warmup step {w + 1}/{args.warmup} done")
@@ -231,6 +239,7 @@ def main():
             "scenarios_per_step": step,
             "slots": args.batch,
             "overlap": args.overlap,
+            "graph_steps": args.graph,
             "kkt_order": head["kkt_order"],
             "state_order": 7 * int(case["n_gen"]) - 1,
         },
@@ -291,8 +300,12 @@ def c3_legs(cs, ctx, torch, args, lst):
         avg = lu["ms"] / max(lu["launches"], 1)
         ach = per * kkt_lu_flops(nk) / (avg * 1e-3) / 1e12 if lu["ms"] else 0.0
         peak = PEAK_FP32_TFLOPS if leg == "mixed" else PEAK_FP64_TFLOPS
+        total_ms = sum(v["ms"] for v in st.values() if isinstance(v, dict))
         out[leg] = {"value": round(n / dt, 3), "unit": "scenarios/s",
                     "kkt_lu_tflops": round(ach, 4), "kkt_lu_frac": round(ach / peak, 5),
+                    "kernel_time_share": {k: round(v["ms"] / max(total_ms, 1e-9), 4)
+                                          for k, v in st.items()
+                                          if isinstance(v, dict) and v["ms"] > 0},
                     "eig_share": round(st["eig"]["ms"] / max(sum(
                         v["ms"] for v in st.values() if isinstance(v, dict)), 1e-9), 4)}
         if leg == "mixed":
@@ -328,9 +341,20 @@ def c4_legs(cs, ctx, torch, args):
     d_list = torch.from_numpy(np.ascontiguousarray(lst[:n])).to(dev)
     d_lam = torch.from_numpy(case["lam"]).to(dev)
     rec = cs.RESULT_DTYPE.itemsize
+    nk = 4 * int(case["n_bus"]) + 2 * int(case["n_gen"])
     out = {"scenarios": n, "list": "20,000 seeded random branch/generator pairs",
-           "kkt_order": 4 * int(case["n_bus"]) + 2 * int(case["n_gen"]),
-           "state_order": net.n_states_max}
+           "kkt_order": nk, "state_order": net.n_states_max}
+    # the large-order LU's panel width, tuned for this order and slot count
+    # before the timed legs (cs_autotune)
+    tune = {}
+    for leg, prec in (("fp64", cs.PREC_FP64), ("mixed", cs.PREC_MIXED)):
+        if args.c4_panel:
+            ctx.autotune_set(nk, prec, args.c4_panel)
+            tune[leg] = {"panel_width": args.c4_panel, "ms_16_32_64": None}
+            continue
+        choice, ms = ctx.autotune(nk, prec, n)
+        tune[leg] = {"panel_width": choice, "ms_16_32_64": [round(float(v), 2) for v in ms]}
+    out["autotune"] = tune
     for leg in ("mixed", "fp64"):
         prec = cs.PREC_MIXED if leg == "mixed" else cs.PREC_FP64
         d_res = torch.zeros(n * rec, dtype=torch.uint8, device=dev)
@@ -351,8 +375,12 @@ def c4_legs(cs, ctx, torch, args):
         ach = per * kkt_lu_flops(nk) / (avg * 1e-3) / 1e12 if lu["ms"] else 0.0
         peak = PEAK_FP32_TFLOPS if leg == "mixed" else PEAK_FP64_TFLOPS
         res = d_res.cpu().numpy().view(cs.RESULT_DTYPE)
+        total_ms = sum(v["ms"] for v in st.values() if isinstance(v, dict))
         out[leg] = {"value": round(n / dt, 3), "unit": "scenarios/s",
                     "kkt_lu_tflops": round(ach, 4), "kkt_lu_frac": round(ach / peak, 5),
+                    "kernel_time_share": {k: round(v["ms"] / max(total_ms, 1e-9), 4)
+                                          for k, v in st.items()
+                                          if isinstance(v, dict) and v["ms"] > 0},
                     "islanded_fraction": round(float(np.mean(res["n_islands"] > 1)), 4),
                     "severe_fraction": round(float(np.mean(res["severe"])), 4)}
         if leg == "mixed":

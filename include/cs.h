@@ -460,8 +460,8 @@ void cs_req_free(cs_req* req);
 /* Autotuning of launch variants.  For a KKT order n above the
  * register-resident LU's limit (1,024), times the large-order LU with panel
  * widths 16, 32 and 64 (one untimed, one timed launch each) on
- * min(batch, 512) synthetic systems of order n (diagonally dominant,
- * entries from a counter hash) in the precision prec names (FP64, or FP32
+ * min(batch, 512) synthetic systems of order n (dense, entries from a
+ * counter hash, so that pivoting interchanges rows as on KKT systems) in the precision prec names (FP64, or FP32
  * for CS_PREC_MIXED, the mixed form's main factorisation), keeps the fastest
  * for (ctx's device, n, precision) for the rest of the process and returns
  * it in *choice (may be NULL), with the milliseconds of each timed launch in

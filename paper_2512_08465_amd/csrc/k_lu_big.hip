@@ -277,8 +277,9 @@ void launch_lu_big_f32(float* A, size_t stride, int n, int ncols, int lda, int* 
                   info, stream, nb);
 }
 
-// Synthetic systems for timing: entries from a counter hash in [-1, 1), the
-// diagonal raised by n (no pivot is ever zero).
+// Synthetic systems for timing: entries from a counter hash in [-1, 1)
+// (dense random matrices, so that partial pivoting interchanges rows at
+// almost every column, as it does on the KKT systems).
 template <class T>
 __global__ void k_tune_fill(T* __restrict__ A, size_t stride, int n, int ncols, int lda,
                             unsigned seed) {
@@ -292,9 +293,7 @@ __global__ void k_tune_fill(T* __restrict__ A, size_t stride, int n, int ncols, 
     h ^= h >> 15;
     h *= 0x846ca68bu;
     h ^= h >> 16;
-    T v = T((double)h * (2.0 / 4294967296.0) - 1.0);
-    if (r == c) v += T(n);
-    a[(size_t)r * lda + c] = v;
+    a[(size_t)r * lda + c] = T((double)h * (2.0 / 4294967296.0) - 1.0);
   }
 }
 
