@@ -184,7 +184,11 @@ __device__ inline void choose_step(T& bv, int& bp, int& bw) {
 template <class T, int J>
 __device__ __attribute__((always_inline)) inline void panel_column(
     PanelRows<T>& R, int m, int r0, int* __restrict__ piv, LuShared<T>& S, int tid) {
-  const int lane = tid & 63, wave = tid >> 6;
+  // FP32: the wavefront index as a scalar, so that the candidate's LDS
+  // address is formed on the scalar unit instead of occupying a vector
+  // register
+  const int lane = tid & 63;
+  const int wave = sizeof(T) == 4 ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> 6;
   constexpr int BUF = J & 1;
   // --- candidates: largest |a| in column J among rows not yet pivoted
   T bv = T(-1);
@@ -221,21 +225,47 @@ __device__ __attribute__((always_inline)) inline void panel_column(
     }
   }
   __syncthreads();
-  // --- the winner (ties to the lower position, as LAPACK): lanes 0..7 of
-  // every wavefront take the eight candidates and reduce them on DPP
-  T cv = T(-1);
-  int cp = INT_MAX, cw = 0;
-  if (lane < LU_WAVES) {
-    cv = S.cand_v[BUF][lane];
-    cp = S.cand_pos[BUF][lane];
-    cw = lane;
+  // --- the winner (ties to the lower position, as LAPACK).  The order is
+  // total, so the winner does not depend on the order of the reduction.
+  int bw;
+  if constexpr (sizeof(T) == 4) {
+    // every lane reads the eight candidates (the same LDS words for all
+    // lanes, at fixed addresses) and reduces them in wavefront order: no
+    // per-lane address stays live across the columns (in the FP32 kernel,
+    // whose register budget is 128, such an address was spilled and
+    // reloaded in every column)
+    T cv = S.cand_v[BUF][0];
+    int cp = S.cand_pos[BUF][0], cw = 0;
+#pragma unroll
+    for (int w = 1; w < LU_WAVES; ++w) {
+      const T v2 = S.cand_v[BUF][w];
+      const int p2 = S.cand_pos[BUF][w];
+      if (better(v2, p2, cv, cp)) {
+        cv = v2;
+        cp = p2;
+        cw = w;
+      }
+    }
+    bv = read_lane(cv, 0);
+    bp = read_lane(cp, 0);
+    bw = read_lane(cw, 0);
+  } else {
+    // lanes 0..7 of every wavefront take the eight candidates and reduce
+    // them on DPP (measured faster in FP64 than the form above)
+    T cv = T(-1);
+    int cp = INT_MAX, cw = 0;
+    if (lane < LU_WAVES) {
+      cv = S.cand_v[BUF][lane];
+      cp = S.cand_pos[BUF][lane];
+      cw = lane;
+    }
+    choose_step<T, DPP_XOR1>(cv, cp, cw);
+    choose_step<T, DPP_XOR2>(cv, cp, cw);
+    choose_step<T, DPP_HALF_MIRROR>(cv, cp, cw);
+    bv = read_lane(cv, 0);
+    bp = read_lane(cp, 0);
+    bw = read_lane(cw, 0);
   }
-  choose_step<T, DPP_XOR1>(cv, cp, cw);
-  choose_step<T, DPP_XOR2>(cv, cp, cw);
-  choose_step<T, DPP_HALF_MIRROR>(cv, cp, cw);
-  bv = read_lane(cv, 0);
-  bp = read_lane(cp, 0);
-  const int bw = read_lane(cw, 0);
   const T* prow = S.slot[BUF][bw];
   // LAPACK interchanges positions J and bp
 #pragma unroll
@@ -474,9 +504,11 @@ __device__ inline void update_group(T* __restrict__ A, int lda, int n, int ncols
 // Back substitution U x = y for the right-hand-side columns n..ncols-1 (the
 // forward substitution was done on them during the elimination), by 32-row
 // blocks from the bottom.  A wavefront solves a diagonal block for one
-// right-hand side at a time (lane i holds row i; x_i is broadcast and
-// eliminated from the rows above), the block solution is kept in LDS (xs,
-// 32 x nrhs; ub, 32 x 32), then every row above is updated.
+// right-hand side at a time (lane i holds row i; x_i is broadcast by a
+// scalar read of lane i and eliminated from the rows above), the block
+// solution is kept in LDS (xs, 32 x nrhs; ub, 32 x 32 with row i's column j
+// at i * 32 + (j ^ i), so that the 32 lanes' reads of one column fall in
+// different banks), then every row above is updated.
 constexpr int LU_BS = 32;
 template <class T>
 __device__ void back_substitute(T* __restrict__ A, int lda, int n, int ncols, T* xs, T* ub,
@@ -490,15 +522,15 @@ __device__ void back_substitute(T* __restrict__ A, int lda, int n, int ncols, T*
     const int bs = min(LU_BS, n - b0);
     for (int e = tid; e < LU_BS * LU_BS; e += LU_THREADS) {
       const int i = e / LU_BS, j = e % LU_BS;
-      ub[e] = (i < bs && j < bs) ? A[(size_t)(b0 + i) * lda + b0 + j] : T(0);
+      ub[i * LU_BS + (j ^ i)] = (i < bs && j < bs) ? A[(size_t)(b0 + i) * lda + b0 + j] : T(0);
     }
     __syncthreads();
     for (int rc = wave; rc < nrhs; rc += LU_WAVES) {
       T y = (lane < bs) ? A[(size_t)(b0 + lane) * lda + n + rc] : T(0);
       for (int i = bs - 1; i >= 0; --i) {
-        const T xi = __shfl(y, i, 64) / ub[i * LU_BS + i];
+        const T xi = read_lane(y, i) / ub[i * LU_BS];      // the diagonal: (i ^ i) = 0
         if (lane == i) y = xi;
-        if (lane < i) y -= ub[lane * LU_BS + i] * xi;
+        if (lane < i) y -= ub[lane * LU_BS + (i ^ lane)] * xi;
       }
       if (lane < bs) {
         xs[lane * nrhs + rc] = y;
