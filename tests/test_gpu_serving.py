@@ -239,3 +239,29 @@ def test_several_networks_one_budget(nets):
         cs.Server(net2.ctx, [net1, net2], shares=[1.0, 0.0])
     assert e.value.code == cs.CS_EINVAL
     net4.close()
+
+
+def test_overlap_with_islanding_only_lists(nets):
+    """Two streams with a batch of at most 1,024 slots claim every slot for
+    the dynamic stage at once; when the claimed scenarios need little
+    dynamic work (islanded, most with a failed OPF) the stage can finish
+    between the engine's query and its stage counts.  The engine asks first,
+    so the call finishes; records equal the one-stream run's, in a batch call
+    and in a server."""
+    import paper_2512_08465_amd as cs
+    net, case = nets["c1_30"]
+    g = load_golden("c1_30")
+    isl = g["outages"][g["n_islands"] > 1]
+    assert len(isl) >= 20
+    lst = np.concatenate([isl] * 4)
+    print(f"{len(lst)} islanding scenarios, batch 16, two streams", flush=True)
+    ref, ref_r = net.screen(lst, case["lam"], cs.default_options(batch=16))
+    got, got_r = net.screen(lst, case["lam"], cs.default_options(batch=16, overlap=1))
+    _same(got, ref)
+    assert np.array_equal(got_r, ref_r)
+    srv = cs.Server(net.ctx, net, cs.default_options(batch=16, overlap=1), queue_capacity=1024)
+    reqs = [srv.submit(lst[i::3], case["lam"]) for i in range(3)]
+    for i, r in enumerate(reqs):
+        res, risk, _ = r.wait(timeout_s=300)
+        _same(res, ref[i::3])
+    srv.close()
