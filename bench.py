@@ -103,7 +103,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1,
                     help="untimed steps, each over the first --warmup-size scenarios")
     ap.add_argument("--warmup-size", type=int, default=4096)
-    ap.add_argument("--batch", type=int, default=4096,
+    ap.add_argument("--batch", type=int, default=8192,
                     help="scenario slots resident at once (refilled as scenarios finish)")
     ap.add_argument("--legs", default="fp64,mixed",
                     help="precisions to time: fp64 (the headline) and/or mixed")
