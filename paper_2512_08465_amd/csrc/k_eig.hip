@@ -8,7 +8,8 @@
 // 2x2 diagonal block has split off (eigenvalues only, so updates stay inside
 // the window).  A sweep chases a chain of up to four double-shift bulges in
 // blocks of 16 steps through a small diagonal block held in LDS and applies
-// the accumulated reflectors to the rest of the window once per block.
+// the accumulated reflectors to the rest of the window once per block, as
+// small products on the FP64 matrix cores.
 // Deflation: a subdiagonal entry is negligible when |h(k,k-1)| <= eps
 // (|h(k-1,k-1)| + |h(k,k)|).  Every tenth sweep without deflation uses an
 // exceptional shift.  The matrix lives in global memory (column-major, lda);
@@ -251,6 +252,9 @@ constexpr int QR_SLD = QR_NS + 1;
 constexpr int QR_LDS = (QR_D + 1) * QR_LD + QR_D * QR_LD + QR_NS * QR_SLD + 2 * QR_NS + 2 * QR_KMAX;
 static_assert(QR_KMAX <= EIG_NW, "one wavefront per bulge");
 static_assert(QR_D + 1 <= 64, "block rows fit a wavefront");
+static_assert(QR_D <= 32, "the off-block products take K = 32");
+
+typedef double EigMfma __attribute__((ext_vector_type(4)));
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -489,7 +493,7 @@ __device__ inline void chase_right(double* D, double* U, int c0, int d, int hi, 
 __device__ void francis_sweep(double* __restrict__ H, int lda, int lo, int hi, int k,
                               const double* __restrict__ pairs, double* __restrict__ D,
                               double* __restrict__ U) {
-  const int tid = threadIdx.x, wave = tid >> 6;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 #define HH(i, j) H[(size_t)(j) * lda + (i)]
   const int T = (hi - 1 - lo) + 3 * (k - 1) + 1;       // chain steps
   const double s_sum = wave < k ? pairs[2 * wave] : 0.0;
@@ -541,32 +545,88 @@ __device__ void francis_sweep(double* __restrict__ H, int lda, int lo, int hi, i
       const int r = e / d, c = e - r * d;
       HH(c0 + r, c0 + c) = D[r * QR_LD + c];
     }
-    // rows c0..c1 right of the block: H <- U^T H, one thread per column
-    for (int cc = c1 + 1 + tid; cc <= hi; cc += EIG_THREADS) {
-      double* col = H + (size_t)cc * lda + c0;
-      double a[QR_D];
+    // The off-block products on the matrix cores (v_mfma_f64_16x16x4f64;
+    // lane (li, lk) supplies A[li][lk] and B[lk][li], and accumulator q holds
+    // row lk + 4 q, column li of the 16 x 16 tile).  The block's order is at
+    // most QR_D = 28 <= 32, so the products have K = 32 with U zero beyond d.
+    //   rows c0..c1, columns c1+1..hi:  H <- U^T H  (16-column tiles)
+    //   rows lo..c0-1, columns c0..c1:  H <- H U    (16-row tiles)
+    {
+      const int li = lane & 15, lk = lane >> 4;
+      const int nct = c1 < hi ? (hi - c1 + 15) / 16 : 0;      // U^T H tiles
+      const int nrt = (c0 - lo + 15) / 16;                     // H U tiles
+      if (nct > 0 && wave < nct) {
+        // U^T fragments: A[16 ti + li][4 kk + lk] = U[4 kk + lk][16 ti + li]
+        double ua[2][8];
 #pragma unroll
-      for (int i = 0; i < QR_D; ++i) a[i] = (i < d) ? col[i] : 0.0;
-#pragma nounroll
-      for (int i = 0; i < d; ++i) {
-        double sv = 0.0;
+        for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-        for (int r = 0; r < QR_D; ++r) sv += U[r * QR_LD + i] * a[r];
-        col[i] = sv;
+          for (int kk = 0; kk < 8; ++kk) {
+            const int r = 4 * kk + lk, c = 16 * ti + li;
+            ua[ti][kk] = (r < QR_D && c < QR_D) ? U[r * QR_LD + c] : 0.0;
+          }
+        for (int t = wave; t < nct; t += EIG_NW) {
+          const int col = c1 + 1 + 16 * t + li;
+          const bool cok = col <= hi;
+          double bv[8];
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk) {
+            const int r = 4 * kk + lk;
+            bv[kk] = (cok && r < d) ? HH(c0 + r, col) : 0.0;
+          }
+          EigMfma acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk) {
+            acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[0][kk], bv[kk], acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[1][kk], bv[kk], acc[1], 0, 0, 0);
+          }
+#pragma unroll
+          for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int r = 16 * ti + lk + 4 * q;
+              if (cok && r < d) HH(c0 + r, col) = acc[ti][q];
+            }
+        }
       }
-    }
-    // rows lo..c0-1 of the block's columns: H <- H U, one thread per row
-    for (int rr = lo + tid; rr < c0; rr += EIG_THREADS) {
-      double* row = H + (size_t)c0 * lda + rr;
-      double a[QR_D];
+      if (nrt > 0) {
+        // U fragments: B[4 kk + lk][16 tj + li] = U[4 kk + lk][16 tj + li]
+        const int w0 = nct % EIG_NW;                 // continue the waves' turns
+        const int wv = (wave - w0 + EIG_NW) % EIG_NW;
+        if (wv < nrt) {
+          double ub[2][8];
 #pragma unroll
-      for (int i = 0; i < QR_D; ++i) a[i] = (i < d) ? row[(size_t)i * lda] : 0.0;
-#pragma nounroll
-      for (int jj = 0; jj < d; ++jj) {
-        double sv = 0.0;
+          for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
-        for (int i = 0; i < QR_D; ++i) sv += a[i] * U[i * QR_LD + jj];
-        row[(size_t)jj * lda] = sv;
+            for (int kk = 0; kk < 8; ++kk) {
+              const int r = 4 * kk + lk, c = 16 * tj + li;
+              ub[tj][kk] = (r < QR_D && c < QR_D) ? U[r * QR_LD + c] : 0.0;
+            }
+          for (int t = wv; t < nrt; t += EIG_NW) {
+            const int row = lo + 16 * t + li;
+            const bool rok = row < c0;
+            double av[8];
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+              const int c = 4 * kk + lk;
+              av[kk] = (rok && c < d) ? HH(row, c0 + c) : 0.0;
+            }
+            EigMfma acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+              acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], ub[0][kk], acc[0], 0, 0, 0);
+              acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], ub[1][kk], acc[1], 0, 0, 0);
+            }
+            const int rbase = lo + 16 * t;
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int r = rbase + lk + 4 * q, c = 16 * tj + li;
+                if (r < c0 && c < d) HH(r, c0 + c) = acc[tj][q];
+              }
+          }
+        }
       }
     }
     __syncthreads();
