@@ -464,7 +464,9 @@ static Plan plan_sizes(const cs_net* n, bool mixed) {
   s.ldy = (int)round_up(s.nyc, 2);
   s.na = n->na;
   s.lda_a = (int)round_up(std::max(s.na, 1), 2);
-  s.k_stride = round_up(std::max((size_t)s.nk * s.ldk, (size_t)s.ny * s.ldy), 64);
+  // the KKT array also serves as the eigenvalue kernel's scratch
+  s.k_stride = round_up(std::max({(size_t)s.nk * s.ldk, (size_t)s.ny * s.ldy,
+                                  eig_scratch_doubles(s.na)}), 64);
   s.a_stride = round_up((size_t)s.lda_a * s.na, 64);
   const size_t piv = std::max(s.nk, s.ny);
   p.per_slot = 8 * (s.k_stride + s.a_stride + s.nx + s.neq + 3 * (size_t)s.ni + 8 * (size_t)nl +
@@ -781,7 +783,7 @@ struct Engine {
       if (rc != CS_OK) return rc;
       rc = timed(CS_K_EIG, sd, ndyn, -1, [&] {
         launch_eig(s.A, s.a_stride, s.lda_a, nullptr, 0, s.wr, s.wi, s.na, s.st, nslots,
-                   nullptr, sd);
+                   nullptr, s.K, s.k_stride, sd);
       });
       if (rc != CS_OK) return rc;
       rc = timed(CS_K_CLASSIFY, sd, ready, -1, [&] {
@@ -1752,9 +1754,19 @@ extern "C" int cs_eigvals_batched(const cs_ctx* c, double* d_A, int32_t n, int32
   if (batch == 0) return CS_OK;
   HIPCHK(hipSetDevice(c->device));
   hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
-  launch_eig(d_A, (size_t)lda * n, lda, nullptr, n, d_wr, d_wi, n, nullptr, batch, d_info, st);
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(st));
+  // the reduction's panel products: a temporary scratch of 64 n doubles per matrix
+  double* scr = nullptr;
+  const size_t scr_stride = eig_scratch_doubles(n);
+  if (hipMalloc(&scr, sizeof(double) * scr_stride * (size_t)batch) != hipSuccess)
+    return fail(CS_ENOMEM, "cs_eigvals_batched: scratch allocation failed");
+  launch_eig(d_A, (size_t)lda * n, lda, nullptr, n, d_wr, d_wi, n, nullptr, batch, d_info, scr,
+             scr_stride, st);
+  const hipError_t e1 = hipGetLastError();
+  const hipError_t e2 = hipStreamSynchronize(st);
+  hipFree(scr);
+  if (e1 != hipSuccess || e2 != hipSuccess)
+    return fail(CS_EDEVICE, std::string("cs_eigvals_batched: ") +
+                                hipGetErrorString(e1 != hipSuccess ? e1 : e2));
   return CS_OK;
 }
 
@@ -1948,7 +1960,8 @@ extern "C" int cs_dyn_at(cs_ctx* c, cs_net* n, const int32_t outage[2], const do
   if (S.phase != PH_EIG)
     return fail(CS_EDEVICE, "cs_dyn_at: the algebraic system is singular or the state matrix is not finite");
   if (eig_re || eig_im) {
-    launch_eig(s.A, s.a_stride, s.lda_a, nullptr, 0, s.wr, s.wi, s.na, s.st, 1, nullptr, st);
+    launch_eig(s.A, s.a_stride, s.lda_a, nullptr, 0, s.wr, s.wi, s.na, s.st, 1, nullptr, s.K,
+               s.k_stride, st);
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipMemcpy(&S, s.st, sizeof(SlotState), hipMemcpyDeviceToHost));
     if (S.qr_fail) return fail(CS_EDEVICE, "cs_dyn_at: QR iteration did not converge");

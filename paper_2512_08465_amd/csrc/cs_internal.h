@@ -152,9 +152,12 @@ void launch_lu_solve_f32(float* A, size_t stride, int n, int ncols, int lda,
                          int count, int* info, hipStream_t stream);
 void launch_dyn_assemble(const DevNet& net, const Slots& s, int count, hipStream_t st);
 void launch_form_state(const DevNet& net, const Slots& s, int count, hipStream_t st);
+// scr: scratch of eig_scratch_doubles(order) doubles per matrix, scr_stride
+// doubles apart (the slot's KKT array in the engine)
 void launch_eig(double* A, size_t stride, int lda, const int* n_per, int n_uniform,
                 double* wr, double* wi, int w_stride, SlotState* st, int count,
-                int* info, hipStream_t stream);
+                int* info, double* scr, size_t scr_stride, hipStream_t stream);
+size_t eig_scratch_doubles(int n);
 void launch_classify(const Slots& s, int count, double near_eps, int max_it,
                      void* results, const int* item_req, int* req_done,
                      const DetailOut* detail, int nb, int ng, hipStream_t st);

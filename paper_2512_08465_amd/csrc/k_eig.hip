@@ -1,9 +1,9 @@
 // Batched nonsymmetric eigenvalues (one workgroup per matrix).
 //
 // The small-signal test needs every eigenvalue of the state matrix.  Each
-// matrix is reduced to upper Hessenberg form by Householder reflections, one
-// read-write pass over the trailing columns per reflector (the two-sided
-// update of one step fused with the products the next step needs), then
+// matrix is reduced to upper Hessenberg form by Householder reflections in
+// panels of 16 (one read-only pass over the trailing columns per reflector,
+// one read-write update per panel on the matrix cores), then
 // implicit QR sweeps run on the active window [lo, hi] until every 1x1 or
 // 2x2 diagonal block has split off (eigenvalues only, so updates stay inside
 // the window).  A sweep chases a chain of up to four double-shift bulges in
@@ -12,9 +12,10 @@
 // small products on the FP64 matrix cores.
 // Deflation: a subdiagonal entry is negligible when |h(k,k-1)| <= eps
 // (|h(k-1,k-1)| + |h(k,k)|).  Every tenth sweep without deflation uses an
-// exceptional shift.  The matrix lives in global memory (column-major, lda);
-// the reflector vectors, the reduction's partial sums, the chased block and
-// the shift computation live in LDS.
+// exceptional shift.  The matrix lives in global memory (column-major, lda),
+// with 64 n doubles of global scratch per matrix for the reduction's panel
+// products; the reflector vectors, the reduction's partial sums, the chased
+// block and the shift computation live in LDS.
 #include "cs_internal.h"
 #include <float.h>
 
@@ -68,150 +69,314 @@ __device__ inline void eig2x2(double a, double b, double c, double d,
   }
 }
 
-// Householder reduction to upper Hessenberg form with one read-write pass
-// over the matrix per reflector.  Step k uses P_k = I - tau u u^T on indices
-// k+1..n-1 (u from column k below the diagonal).  With B = H[:, k+1:],
-// p = B u and s = tau B[k+1:, :]^T u, both taken from H before the step, the
-// two-sided update P_k H P_k is the rank-2 change
-//   H[i][k+1+j] -= a_i s_j + w_i u_j,   a_i = u_{i-k-1} (i > k, else 0),
-//   w_i = tau (p_i - a_i (s . u)),
-// so one pass can apply step k and, on the values it has just written,
-// gather p and s for step k+1 (whose reflector comes from column k+1, which
-// is brought up to date first).  Columns are shared out to the wavefronts,
-// lanes run over the rows: s of a column is a wavefront sum, p a per-lane
-// partial per wavefront (kept in LDS), added in a fixed order.
-// LDS (dynamic, 9 n doubles): u, s, w of the current step, un, sn of the
-// next, and the NW partials of the next p.
 constexpr int EIG_NW = EIG_THREADS / 64;
 constexpr int EIG_CG = 8;                   // row chunks of 64 loaded together
 
-size_t eig_hess_lds(int nmax);
+// Blocked Householder reduction to upper Hessenberg form (compact WY:
+// Dongarra, Hammarling and Sorensen; the panel recurrences as in LAPACK's
+// gehrd).  Reflector j of the panel starting at column k0 (column c = k0 + j)
+// is H_j = I - tau_j v_j v_j^T with v_j = 1 at row c + 1, zero above; the
+// panel's product is Q = I - V T V^T.  Per reflector:
+//   1. column c is brought up to date: the right-hand part of the panel's
+//      earlier reflectors, h -= Y V[c, :]^T (Y = A V T, all rows), then the
+//      left-hand part on rows k0+1.., h -= V (T^T (V^T h));
+//   2. the reflector is formed from rows c+1.. of h (v stored below the
+//      subdiagonal of column c until the panel ends);
+//   3. one read-only pass over the columns right of c of the panel-start
+//      matrix A gives y = A v (all rows) and z[col] = v^T A[:, col] for the
+//      columns right of the panel;
+//   4. Y[:, j] = tau (y - Y (V^T v)), and column j of T.
+// After the panel, with M = V^T Y, every column right of the panel takes
+//   A[:, col] -= Y a + V w,  a = V[col, :]^T,  w = T^T (z[col] - M a)
+// in one read-write pass, a K = 32 product on the FP64 matrix cores.  The
+// trailing columns are thus read once per reflector and read and written once
+// per panel of HB_NB reflectors, instead of read and written once per
+// reflector.  Scratch (global, per matrix, 4 HB_NB n doubles): Y, z and the
+// right-hand operand [a; w] of the panel's update.  LDS: the column or the
+// reflector (n), the wavefronts' partial products (EIG_NW n), T, M and small
+// vectors.
+constexpr int HB_NB = 16;
+static_assert(HB_NB == 16 && EIG_THREADS == 256, "16 x 16 panel products, one entry per thread");
+typedef double EigMfma __attribute__((ext_vector_type(4)));
+
+size_t eig_scratch_doubles(int n) { return 4 * (size_t)HB_NB * (size_t)n; }
+
+// entry (row i, reflector l) of the panel's V: 1 at row k0 + l + 1, the
+// stored vector below it, 0 above
+__device__ inline double vget(const double* __restrict__ H, int lda, int k0, int l, int i) {
+  const int c = k0 + l;
+  return i == c + 1 ? 1.0 : (i > c + 1 ? H[(size_t)c * lda + i] : 0.0);
+}
+
+// out[l] = sum_i V[i][l] x[i] for l < j: 16 row groups of threads per l,
+// partials in part[16][16] added in a fixed order
+__device__ inline void panel_dots(const double* __restrict__ H, int lda, int k0, int j,
+                                  const double* __restrict__ x, int n, double* part,
+                                  double* out) {
+  const int tid = threadIdx.x, l = tid & 15, g = tid >> 4;
+  double acc = 0.0;
+  if (l < j) {
+#pragma unroll 4
+    for (int i = k0 + l + 1 + g; i < n; i += 16) acc += vget(H, lda, k0, l, i) * x[i];
+  }
+  part[g * 16 + l] = acc;
+  __syncthreads();
+  if (tid < j) {
+    double s = 0.0;
+#pragma unroll
+    for (int gg = 0; gg < 16; ++gg) s += part[gg * 16 + tid];
+    out[tid] = s;
+  }
+  __syncthreads();
+}
+
+size_t eig_hess_lds_doubles(int n) {
+  return (size_t)(1 + EIG_NW) * n + 2 * HB_NB * HB_NB + EIG_NW * 256 + 2 * HB_NB;
+}
 
 __device__ void hessenberg(double* __restrict__ H, int n, int lda, double* __restrict__ lds,
-                           double* red) {
+                           double* red, double* __restrict__ scr) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* u = lds;
-  double* sv = u + n;
-  double* w = sv + n;
-  double* un = w + n;
-  double* sn = un + n;
-  double* pn = sn + n;            // [EIG_NW][n]
-  double tau = 0.0;
-  __shared__ double s_x0;
-  for (int k = -1; k <= n - 3; ++k) {
-    const bool upd = k >= 0 && tau != 0.0;   // step k changes H
-    const bool nxt = k + 1 <= n - 3;         // a reflector for column k+1
-    // ---- column k+1: step k's update, then the next reflector from it
-    double* c1 = H + (size_t)(k + 1) * lda;
-    double part = 0.0;
-    for (int i = tid; i < n; i += EIG_THREADS) {
-      double h = c1[i];
-      if (upd) h -= ((i > k) ? u[i - k - 1] * sv[0] : 0.0) + w[i] * u[0];
-      if (i >= k + 2 && nxt) {
-        un[i - k - 2] = h;
-        part += h * h;
-      } else {
-        c1[i] = h;
+#define HH(i, j) H[(size_t)(j) * lda + (i)]
+  double* hc = lds;                          // [n] column c, then v_j by row
+  double* pn = hc + n;                       // [EIG_NW][n] partial y per wavefront
+  double* Tm = pn + EIG_NW * n;              // [HB_NB][HB_NB] T, row-major
+  double* Mm = Tm + HB_NB * HB_NB;           // [HB_NB][HB_NB] M = V^T Y
+  double* part = Mm + HB_NB * HB_NB;         // [EIG_NW][16][16] partial sums
+  double* sv1 = part + EIG_NW * 16 * 16;     // [HB_NB]
+  double* sv2 = sv1 + HB_NB;                 // [HB_NB]
+  double* Ys = scr;                          // [HB_NB][n], column l at l * n
+  double* Zs = Ys + HB_NB * (size_t)n;       // [HB_NB][n]
+  double* Bs = Zs + HB_NB * (size_t)n;       // [2 HB_NB][n]: a (rows 0..15), w (16..31)
+  __shared__ double s_tau, s_beta, s_scale;
+  for (int k0 = 0; k0 < n - 2; k0 += HB_NB) {
+    const int kb = min(HB_NB, n - 2 - k0);
+    const int cfirst = k0 + kb;              // first column right of the panel
+    for (int e = tid; e < HB_NB * HB_NB; e += EIG_THREADS) Tm[e] = 0.0;
+    for (int j = 0; j < kb; ++j) {
+      const int c = k0 + j;
+      // ---- 1. column c up to date
+      for (int i = tid; i < n; i += EIG_THREADS) hc[i] = HH(i, c);
+      if (j > 0) {
+        if (tid < j) sv1[tid] = vget(H, lda, k0, tid, c);   // row c of V
+        __syncthreads();
+        for (int i = tid; i < n; i += EIG_THREADS) {
+          double acc = hc[i];
+          for (int l = 0; l < j; ++l) acc -= Ys[(size_t)l * n + i] * sv1[l];
+          hc[i] = acc;
+        }
+        __syncthreads();
+        panel_dots(H, lda, k0, j, hc, n, part, sv2);          // V^T h
+        if (tid < j) {
+          double a = 0.0;
+          for (int m = 0; m <= tid; ++m) a += Tm[m * HB_NB + tid] * sv2[m];
+          sv1[tid] = a;                                       // T^T (V^T h)
+        }
+        __syncthreads();
+        for (int i = k0 + 1 + tid; i < n; i += EIG_THREADS) {
+          double acc = hc[i];
+          for (int l = 0; l < j; ++l) acc -= vget(H, lda, k0, l, i) * sv1[l];
+          hc[i] = acc;
+        }
       }
-    }
-    double taun = 0.0, alpha = 0.0;
-    if (nxt) {
-      const double sig2 = block_sum(part, red);   // barriers: un[] complete
-      if (tid == 0) s_x0 = un[0];
       __syncthreads();
-      const double x0 = s_x0;
-      if (sig2 != 0.0) {
-        const double sig = sqrt(sig2);
-        alpha = -copysign(sig, x0);
-        taun = 1.0 / (sig * (sig + fabs(x0)));
-        if (tid == 0) un[0] = x0 - alpha;
+      // ---- 2. the reflector from rows c+1.. (LAPACK's convention: v = 1
+      // at row c + 1, beta = -sign(alpha) ||x||, tau = (beta - alpha) / beta)
+      double p2 = 0.0;
+      for (int i = c + 2 + tid; i < n; i += EIG_THREADS) p2 += hc[i] * hc[i];
+      const double sig2 = block_sum(p2, red);
+      if (tid == 0) {
+        const double alpha = hc[c + 1];
+        if (sig2 == 0.0) {
+          s_tau = 0.0;
+          s_beta = alpha;
+          s_scale = 0.0;
+        } else {
+          const double beta = -copysign(sqrt(alpha * alpha + sig2), alpha);
+          s_tau = (beta - alpha) / beta;
+          s_beta = beta;
+          s_scale = 1.0 / (alpha - beta);
+        }
       }
-      for (int i = k + 2 + tid; i < n; i += EIG_THREADS) c1[i] = (i == k + 2) ? alpha : 0.0;
-    }
-    __syncthreads();
-    // ---- one pass over columns k+2..n-1: apply step k, gather p and s of
-    // step k+1 from the updated values
-    if (upd || nxt) {
-      double* pw = pn + wave * n;   // this wavefront's partial p (lane-owned rows)
-      if (nxt)
+      __syncthreads();
+      const double tau = s_tau, beta = s_beta, scale = s_scale;
+      // column c is final above row c + 2; v is kept below the subdiagonal
+      // until the panel ends, and in hc (by row) for the pass
+      for (int i = tid; i < n; i += EIG_THREADS) {
+        const double hv = hc[i];
+        const double v = (i <= c) ? 0.0 : (i == c + 1 ? 1.0 : hv * scale);
+        HH(i, c) = (i <= c) ? hv : (i == c + 1 ? beta : v);
+        hc[i] = v;
+      }
+      __syncthreads();
+      // ---- 3. one read-only pass over columns c+1..n-1: y = A v, and
+      // z[col] = v^T A[:, col] right of the panel.  Columns go to the
+      // wavefronts (two per pass), lanes run over the rows.
+      {
+        double* pw = pn + wave * n;
         for (int i = lane; i < n; i += 64) pw[i] = 0.0;
-      // two columns per pass of a wavefront (j and j + EIG_NW), all their
-      // loads in flight together
-      for (int j0 = k + 2 + wave; j0 < n; j0 += 2 * EIG_NW) {
-        double* cj[2];
-        double sj[2], uj[2], unj[2], t[2];
-        bool jok[2];
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-          const int j = j0 + p * EIG_NW;
-          jok[p] = j < n;
-          cj[p] = H + (size_t)(jok[p] ? j : j0) * lda;
-          sj[p] = (upd && jok[p]) ? sv[j - k - 1] : 0.0;
-          uj[p] = (upd && jok[p]) ? u[j - k - 1] : 0.0;
-          unj[p] = (nxt && jok[p]) ? un[j - k - 2] : 0.0;
-          t[p] = 0.0;
-        }
-        for (int i0 = 0; i0 < n; i0 += 64 * EIG_CG) {
-          double hv[2][EIG_CG];
-#pragma unroll
-          for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int c = 0; c < EIG_CG; ++c) {
-              const int i = i0 + 64 * c + lane;
-              hv[p][c] = (jok[p] && i < n) ? cj[p][i] : 0.0;
-            }
-#pragma unroll
-          for (int c = 0; c < EIG_CG; ++c) {
-            const int i = i0 + 64 * c + lane;
-            if (i < n) {
-              const double ai = (upd && i > k) ? u[i - k - 1] : 0.0;
-              const double wi = upd ? w[i] : 0.0;
-              const double uni = (nxt && i >= k + 2) ? un[i - k - 2] : 0.0;
-              double pacc = 0.0;
-#pragma unroll
-              for (int p = 0; p < 2; ++p) {
-                if (jok[p]) {
-                  double h = hv[p][c];
-                  if (upd) {
-                    h -= ai * sj[p] + wi * uj[p];
-                    cj[p][i] = h;
-                  }
-                  pacc += h * unj[p];
-                  t[p] += uni * h;
-                }
-              }
-              if (nxt) pw[i] += pacc;
-            }
-          }
-        }
-        if (nxt) {
+        for (int j0 = c + 1 + wave; j0 < n; j0 += 2 * EIG_NW) {
+          const double* cj[2];
+          double vj[2], t[2];
+          bool jok[2];
 #pragma unroll
           for (int p = 0; p < 2; ++p) {
+            const int jj = j0 + p * EIG_NW;
+            jok[p] = jj < n;
+            cj[p] = H + (size_t)(jok[p] ? jj : j0) * lda;
+            vj[p] = jok[p] ? hc[jj] : 0.0;
+            t[p] = 0.0;
+          }
+          for (int i0 = 0; i0 < n; i0 += 64 * EIG_CG) {
+            double hv[2][EIG_CG];
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+              for (int q = 0; q < EIG_CG; ++q) {
+                const int i = i0 + 64 * q + lane;
+                hv[p][q] = (jok[p] && i < n) ? cj[p][i] : 0.0;
+              }
+#pragma unroll
+            for (int q = 0; q < EIG_CG; ++q) {
+              const int i = i0 + 64 * q + lane;
+              if (i < n) {
+                const double vi = hc[i];
+                double pacc = 0.0;
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                  pacc += hv[p][q] * vj[p];
+                  t[p] += vi * hv[p][q];
+                }
+                pw[i] += pacc;
+              }
+            }
+          }
+#pragma unroll
+          for (int p = 0; p < 2; ++p) {
+            const int jj = j0 + p * EIG_NW;
             double tp = t[p];
             for (int off = 32; off > 0; off >>= 1) tp += __shfl_xor(tp, off, 64);
-            if (lane == 0 && jok[p]) sn[j0 + p * EIG_NW - k - 2] = taun * tp;
+            if (lane == 0 && jok[p] && jj >= cfirst) Zs[(size_t)j * n + jj] = tp;
+          }
+        }
+      }
+      __syncthreads();
+      // ---- 4. Y[:, j] = tau (y - Y (V^T v)); column j of T
+      panel_dots(H, lda, k0, j, hc, n, part, sv2);            // t = V^T v
+      for (int i = tid; i < n; i += EIG_THREADS) {
+        double y = 0.0;
+#pragma unroll
+        for (int w = 0; w < EIG_NW; ++w) y += pn[w * n + i];
+        for (int l = 0; l < j; ++l) y -= Ys[(size_t)l * n + i] * sv2[l];
+        Ys[(size_t)j * n + i] = tau * y;
+      }
+      if (tid < j) {
+        double a = 0.0;
+        for (int m = tid; m < j; ++m) a += Tm[tid * HB_NB + m] * sv2[m];
+        Tm[tid * HB_NB + j] = -tau * a;
+      }
+      if (tid == 0) Tm[j * HB_NB + j] = tau;
+      __syncthreads();
+    }
+    // ---- M = V^T Y (kb x kb) on the matrix cores: each wavefront takes every
+    // fourth group of four rows (A[li][lk] = V[i][li], B[lk][li] = Y[i][li],
+    // i = k0 + 1 + 4 s + lk); the four partial products are added in order
+    {
+      const int li = lane & 15, lk = lane >> 4;
+      EigMfma acc = {0.0, 0.0, 0.0, 0.0};
+      const int nsteps = (n - k0 - 1 + 3) / 4;
+      for (int st = wave; st < nsteps; st += EIG_NW) {
+        const int i = k0 + 1 + 4 * st + lk;
+        const bool ok = i < n && li < kb;
+        const double av = ok ? vget(H, lda, k0, li, i) : 0.0;
+        const double bv = ok ? Ys[(size_t)li * n + i] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) part[wave * 256 + (lk + 4 * q) * 16 + li] = acc[q];
+      __syncthreads();
+      double m = 0.0;
+#pragma unroll
+      for (int w = 0; w < EIG_NW; ++w) m += part[w * 256 + tid];
+      Mm[tid] = m;                              // tid = l * 16 + m
+    }
+    __syncthreads();
+    // ---- the right-hand operand of the panel's update, per column right of
+    // the panel: a = V[col, :]^T, w = T^T (z - M a)
+    // (a goes to Bs, r = z - M a replaces z in Zs, then w = T^T r: the
+    // thread's own global words, no private arrays)
+    for (int col = cfirst + tid; col < n; col += EIG_THREADS) {
+      for (int m = 0; m < HB_NB; ++m)
+        Bs[(size_t)m * n + col] = (m < kb) ? vget(H, lda, k0, m, col) : 0.0;
+      for (int l = 0; l < kb; ++l) {
+        double r = Zs[(size_t)l * n + col];
+        for (int m = 0; m < kb; ++m) r -= Mm[l * HB_NB + m] * Bs[(size_t)m * n + col];
+        Zs[(size_t)l * n + col] = r;
+      }
+      for (int l = 0; l < HB_NB; ++l) {
+        double w = 0.0;
+        if (l < kb)
+          for (int m = 0; m <= l; ++m) w += Tm[m * HB_NB + l] * Zs[(size_t)m * n + col];
+        Bs[(size_t)(HB_NB + l) * n + col] = w;
+      }
+    }
+    __syncthreads();
+    // ---- A[:, col] -= [Y | V] [a; w] for every column right of the panel,
+    // on the matrix cores in transposed form (out^T = [a; w]^T [Y | V]^T) so
+    // that a lane's accumulators are 16 consecutive rows of 4 columns: lane
+    // (li, lk) supplies A'[li][lk] = B[k][col0 + li] and B'[lk][li] =
+    // [Y | V][row0 + li][k], k = 4 kk + lk; accumulator q is row row0 + li of
+    // column col0 + lk + 4 q.
+    {
+      const int li = lane & 15, lk = lane >> 4;
+      const int nrt = (n + 15) / 16, nct = (n - cfirst + 15) / 16;
+      for (int rt = wave; rt < nrt; rt += EIG_NW) {
+        const int row = 16 * rt + li;
+        const bool rok = row < n;
+        double bf[8];
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+          const int k = 4 * kk + lk;
+          double v = 0.0;
+          if (rok) {
+            if (k < HB_NB) v = (k < kb) ? Ys[(size_t)k * n + row] : 0.0;
+            else v = (k - HB_NB < kb) ? vget(H, lda, k0, k - HB_NB, row) : 0.0;
+          }
+          bf[kk] = v;
+        }
+        for (int ct = 0; ct < nct; ++ct) {
+          const int colb = cfirst + 16 * ct;
+          double af[8];
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk) {
+            const int k = 4 * kk + lk, col = colb + li;
+            const bool kok = (k < HB_NB) ? (k < kb) : (k - HB_NB < kb);
+            af[kk] = (kok && col < n) ? -Bs[(size_t)k * n + col] : 0.0;
+          }
+          EigMfma acc;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int col = colb + lk + 4 * q;
+            acc[q] = (rok && col < n) ? HH(row, col) : 0.0;
+          }
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af[kk], bf[kk], acc, 0, 0, 0);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int col = colb + lk + 4 * q;
+            if (rok && col < n) HH(row, col) = acc[q];
           }
         }
       }
     }
     __syncthreads();
-    if (!nxt) break;
-    // ---- step k+1's w from p (the partials in a fixed order) and s . u
-    double dot = 0.0;
-    for (int j = tid; j < n - k - 2; j += EIG_THREADS) dot += sn[j] * un[j];
-    const double cdot = block_sum(dot, red);
-    for (int i = tid; i < n; i += EIG_THREADS) {
-      double pi = 0.0;
-#pragma unroll
-      for (int v = 0; v < EIG_NW; ++v) pi += pn[v * n + i];
-      const double ai = (i > k + 1) ? un[i - k - 2] : 0.0;
-      w[i] = taun * (pi - ai * cdot);
-    }
-    double* t1 = u; u = un; un = t1;
-    double* t2 = sv; sv = sn; sn = t2;
-    tau = taun;
+    // ---- the panel's columns: zero below the subdiagonal (v no longer needed)
+    for (int l = 0; l < kb; ++l)
+      for (int i = k0 + l + 2 + tid; i < n; i += EIG_THREADS) HH(i, k0 + l) = 0.0;
     __syncthreads();
   }
+#undef HH
 }
 
 // Francis QR in blocks, with a chain of up to QR_KMAX double-shift bulges
@@ -253,8 +418,6 @@ constexpr int QR_LDS = (QR_D + 1) * QR_LD + QR_D * QR_LD + QR_NS * QR_SLD + 2 * 
 static_assert(QR_KMAX <= EIG_NW, "one wavefront per bulge");
 static_assert(QR_D + 1 <= 64, "block rows fit a wavefront");
 static_assert(QR_D <= 32, "the off-block products take K = 32");
-
-typedef double EigMfma __attribute__((ext_vector_type(4)));
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -701,7 +864,8 @@ __device__ int francis(double* __restrict__ H, int n, int lda,
 __global__ __launch_bounds__(EIG_THREADS, 4) void k_eig(
     double* __restrict__ Abase, size_t stride, int lda,
     const SlotState* __restrict__ st, int n_uniform, int nmax, double* __restrict__ wrb,
-    double* __restrict__ wib, int w_stride, int* __restrict__ info) {
+    double* __restrict__ wib, int w_stride, int* __restrict__ info,
+    double* __restrict__ scrbase, size_t scr_stride) {
   const int slot = blockIdx.x;
   int n = n_uniform;
   if (st != nullptr) {
@@ -715,7 +879,7 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_eig(
   double* H = Abase + (size_t)slot * stride;
   double* wr = wrb + (size_t)slot * w_stride;
   double* wi = wib + (size_t)slot * w_stride;
-  hessenberg(H, n, lda, eig_lds, red);
+  hessenberg(H, n, lda, eig_lds, red, scrbase + (size_t)slot * scr_stride);
   __syncthreads();
   // the QR phase reuses the reduction's LDS
   const int fail = francis(H, n, lda, wr, wi, ired, eig_lds);
@@ -724,18 +888,19 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_eig(
 }
 
 size_t eig_hess_lds(int nmax) {
-  return sizeof(double) * std::max<size_t>(9 * (size_t)nmax, QR_LDS);
+  return sizeof(double) * std::max<size_t>(eig_hess_lds_doubles(nmax), QR_LDS);
 }
 
 void launch_eig(double* A, size_t stride, int lda, const int* /*n_per*/,
                 int n_uniform, double* wr, double* wi, int w_stride,
-                SlotState* st, int count, int* info, hipStream_t stream) {
+                SlotState* st, int count, int* info, double* scr, size_t scr_stride,
+                hipStream_t stream) {
   if (count <= 0) return;
   // the dynamic LDS is sized for the largest order a slot can have (the
   // eigenvalue arrays have that many entries per slot)
   const int nmax = n_uniform > 0 ? n_uniform : w_stride;
   hipLaunchKernelGGL(k_eig, dim3(count), dim3(EIG_THREADS), eig_hess_lds(nmax), stream, A,
-                     stride, lda, st, n_uniform, nmax, wr, wi, w_stride, info);
+                     stride, lda, st, n_uniform, nmax, wr, wi, w_stride, info, scr, scr_stride);
 }
 
 void eig_set_attrs(size_t bytes) {
