@@ -258,7 +258,9 @@ int cs_dense_solve_batched(const cs_ctx* ctx, double* d_A, int32_t n,
 
 /* Eigenvalues of `batch` column-major n x n matrices (lda), overwritten by
  * their Hessenberg/Schur work; wr, wi: [batch][n].  info[b] = 1 if QR did
- * not converge. */
+ * not converge.  Allocates a temporary device scratch of 512 n bytes per
+ * matrix (the reduction's panel products); CS_ENOMEM if that fails.
+ * Section II.B.2: the full eigenspectrum of the state matrix. */
 int cs_eigvals_batched(const cs_ctx* ctx, double* d_A, int32_t n, int32_t lda,
                        int32_t batch, double* d_wr, double* d_wi,
                        int32_t* d_info, void* stream);
