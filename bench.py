@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--serve-max-len", type=int, default=5000,
                     help="request lengths are log-uniform integers in [1, this]")
     ap.add_argument("--serve-legs", default="fp64,mixed")
+    ap.add_argument("--serve-mixed-sizes", type=int, default=1,
+                    help="1: also serve 118- and 300-bus requests from one server")
     ap.add_argument("--pmc-copy", action="store_true",
                     help="begin with a device copy of known size (the scale of the HBM "
                          "counters in a counter pass over this run)")
@@ -571,7 +573,67 @@ def serve_sweep(cs, ctx, net, case, lst, args):
             out.append(r)
             log(f"serving {leg} at {rate}/s: p50 {r['p50_latency_s']} s, "
                 f"p99 {r['p99_latency_s']} s, {r['scenarios_per_s']} scenarios/s")
+    if args.serve_mixed_sizes:
+        r = serve_two_sizes(cs, ctx, net, case, lst, args)
+        out.append(r)
+        log(f"serving 118- and 300-bus requests: p99 {r['p99_latency_s']} s, "
+            f"{r['scenarios_per_s']} scenarios/s")
     return out
+
+
+def serve_two_sizes(cs, ctx, net, case, lst, args):
+    """One server for the 118- and the 300-bus networks under one HBM
+    budget (cs_server_create_multi): 12 requests at 20 per second, every
+    fourth a 300-bus snapshot with 1-200 random pairs of its list, the others
+    118-bus snapshots with 1-5,000 scenarios; p50/p99 latency per network."""
+    import numpy as np
+    from inputs import netgen, contingencies
+    from inputs.rate_samples import load_scales
+    c4 = netgen.load_case(os.path.join(ROOT, "inputs", "cases", "c4_300.npz"))
+    lst4 = contingencies.c4_list(c4["outage_set"])
+    net4 = cs.Network(ctx, c4)
+    rng = np.random.default_rng(7300)
+    nreq, rate = 12, 20.0
+    gaps = rng.exponential(1.0 / rate, nreq)
+    kinds = [1 if i % 4 == 3 else 0 for i in range(nreq)]
+    reqs_in = []
+    for i, k in enumerate(kinds):
+        top = 200 if k else args.serve_max_len
+        m = int(np.clip(np.floor(np.exp(rng.uniform(0, np.log(top + 1)))), 1, top))
+        src, cc = (lst4, c4) if k else (lst, case)
+        sc = load_scales(int(cc["n_load"]), 1, seed=7300 + i)[0]
+        reqs_in.append((k, src[rng.choice(len(src), m, replace=False)], cc, sc))
+    budget = 48 << 30
+    srv = cs.Server(ctx, [net, net4], cs.default_options(hbm_budget=budget, batch=4096),
+                    queue_capacity=1 << 16, shares=[1.0, 1.0])
+    slots = [srv.slots(0), srv.slots(1)]
+    t0 = time.perf_counter()
+    due = t0
+    reqs = []
+    for g, (k, l, cc, sc) in zip(gaps, reqs_in):
+        due += g
+        time.sleep(max(0.0, due - time.perf_counter()))
+        reqs.append((k, len(l), srv.submit(l, cc["lam"], load_scale=sc, net=k)))
+    lat = {0: [], 1: []}
+    for k, m, r in reqs:
+        _, _, t = r.wait(timeout_s=900)
+        lat[k].append(t)
+        r.close()
+    dt = time.perf_counter() - t0
+    srv.close()
+    net4.close()
+    total = sum(m for _, m, _ in reqs)
+    allat = np.array(lat[0] + lat[1])
+    return dict(requests=nreq, rate_per_s=rate, networks="118-bus and 300-bus in one server",
+                hbm_budget_gib=budget >> 30, slots_118_300=slots,
+                length="118-bus: log-uniform [1, %d]; 300-bus: log-uniform [1, 200]"
+                % args.serve_max_len,
+                scenarios=int(total), prec="fp64",
+                p50_latency_s=round(float(np.percentile(allat, 50)), 4),
+                p99_latency_s=round(float(np.percentile(allat, 99)), 4),
+                p99_latency_118_s=round(float(np.percentile(lat[0], 99)), 4),
+                p99_latency_300_s=round(float(np.percentile(lat[1], 99)), 4),
+                scenarios_per_s=round(total / dt, 2), wall_s=round(dt, 2))
 
 
 def serve(cs, ctx, net, case, lst, args, rate, prec):

@@ -1196,6 +1196,9 @@ struct ServerLane {
   long long seen = 0;                    // scenarios the engine has been told about
   bool idle = false;                     // every admitted scenario recorded
   bool waiting = false;                  // only the dynamic stage is left to wait for
+  bool pending = false;                  // a round issued and not yet settled
+  long long n_issued = 0;                // scenarios available when it was issued
+  hipEvent_t ev_round = nullptr;         // recorded after the round's stage counts
   Engine e;
 };
 
@@ -1282,48 +1285,88 @@ static void server_fail_all(cs_server* S, int code, const std::string& msg) {
   S->cv_done.notify_all();
 }
 
-static void server_loop(cs_server* S) {
-  hipSetDevice(S->device);
-  const size_t nl = S->lanes.size();
+// One network: each round is issued and settled in turn, and the engine may
+// block on its own dynamic stage.
+static void server_loop_one(cs_server* S) {
+  ServerLane& L = *S->lanes[0];
   int rc = CS_OK;
-  for (ServerLane* L : S->lanes)
-    if ((rc = L->e.start()) != CS_OK) {
+  for (;;) {
+    long long N;
+    {
+      std::lock_guard<std::mutex> lk(S->m);
+      N = L.submitted;
+    }
+    bool idle = false;
+    if ((rc = L.e.round(N, idle)) != CS_OK || (rc = server_complete(S)) != CS_OK) {
       server_fail_all(S, rc, g_err);
       return;
     }
-  // one lane: the engine may block on its own dynamic stage; several: a
-  // lane never blocks while another could be stepped
-  const bool may_block = nl == 1;
+    if (idle) {
+      std::unique_lock<std::mutex> lk(S->m);
+      S->cv_work.wait(lk, [&] { return S->stop || L.submitted > N; });
+      if (S->stop && L.submitted == N) return;
+    }
+  }
+}
+
+// Several networks: every lane advances at its own pace.  A lane's round is
+// issued, an event marks the end of its stage counts, and the round is
+// settled when that event has completed, so that a lane with short rounds
+// (a small network) is never held to the pace of one with long rounds.
+// With nothing to settle or issue the thread sleeps for a few microseconds.
+static void server_loop_many(cs_server* S) {
+  const size_t nl = S->lanes.size();
+  int rc = CS_OK;
   std::vector<long long> N(nl);
-  std::vector<char> issued(nl);
   for (;;) {
     {
       std::lock_guard<std::mutex> lk(S->m);
       for (size_t i = 0; i < nl; ++i) N[i] = S->lanes[i]->submitted;
     }
-    for (size_t i = 0; i < nl; ++i) {
+    bool progress = false;
+    for (size_t i = 0; i < nl && rc == CS_OK; ++i) {
       ServerLane& L = *S->lanes[i];
-      issued[i] = !L.idle || N[i] > L.seen;
-      if (issued[i] && (rc = L.e.issue(N[i])) != CS_OK) break;
-    }
-    for (size_t i = 0; rc == CS_OK && i < nl; ++i) {
-      ServerLane& L = *S->lanes[i];
-      if (!issued[i]) continue;
-      bool idle = false, waiting = false;
-      rc = L.e.settle(N[i], idle, may_block, &waiting);
-      L.idle = idle;
-      L.waiting = waiting;
-      L.seen = N[i];
+      if (!L.pending) {
+        if (L.idle && N[i] <= L.seen) continue;
+        if (L.waiting && !L.idle) {
+          // only the dynamic stage is left: issue again once it has ended
+          const hipError_t q = hipEventQuery(L.e.ev_dyn);
+          if (q == hipErrorNotReady) continue;
+          if (q != hipSuccess) {
+            rc = fail(CS_EDEVICE, "dynamic stage failed");
+            break;
+          }
+        }
+        if ((rc = L.e.issue(N[i])) != CS_OK) break;
+        if (hipEventRecord(L.ev_round, L.st) != hipSuccess) {
+          rc = fail(CS_EDEVICE, "server: event record failed");
+          break;
+        }
+        L.n_issued = N[i];
+        L.pending = true;
+        progress = true;
+      } else {
+        const hipError_t q = hipEventQuery(L.ev_round);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) {
+          rc = fail(CS_EDEVICE, "server: round failed");
+          break;
+        }
+        bool idle = false, waiting = false;
+        if ((rc = L.e.settle(L.n_issued, idle, false, &waiting)) != CS_OK) break;
+        L.idle = idle;
+        L.waiting = waiting;
+        L.seen = L.n_issued;
+        L.pending = false;
+        progress = true;
+      }
     }
     if (rc != CS_OK || (rc = server_complete(S)) != CS_OK) {
       server_fail_all(S, rc, g_err);
       return;
     }
-    bool all_idle = true, all_wait = true;
-    for (ServerLane* L : S->lanes) {
-      all_idle = all_idle && L->idle;
-      all_wait = all_wait && (L->idle || L->waiting);
-    }
+    bool all_idle = true;
+    for (ServerLane* L : S->lanes) all_idle = all_idle && L->idle && !L->pending;
     if (all_idle) {
       std::unique_lock<std::mutex> lk(S->m);
       S->cv_work.wait(lk, [&] {
@@ -1337,18 +1380,23 @@ static void server_loop(cs_server* S) {
         for (size_t i = 0; i < nl; ++i) more = more || S->lanes[i]->submitted > N[i];
         if (!more) return;
       }
-    } else if (all_wait) {
-      // nothing to step anywhere: wait for the first lane's dynamic stage
-      for (ServerLane* L : S->lanes)
-        if (L->waiting) {
-          if (hipEventSynchronize(L->e.ev_dyn) != hipSuccess) {
-            server_fail_all(S, CS_EDEVICE, "dynamic stage failed");
-            return;
-          }
-          break;
-        }
+    } else if (!progress) {
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
   }
+}
+
+static void server_loop(cs_server* S) {
+  hipSetDevice(S->device);
+  for (ServerLane* L : S->lanes) {
+    const int rc = L->e.start();
+    if (rc != CS_OK) {
+      server_fail_all(S, rc, g_err);
+      return;
+    }
+  }
+  if (S->lanes.size() == 1) server_loop_one(S);
+  else server_loop_many(S);
 }
 
 static void lane_free(ServerLane* L) {
@@ -1359,7 +1407,7 @@ static void lane_free(ServerLane* L) {
   if (L->h_sched) hipHostFree(L->h_sched);
   for (hipStream_t q : {L->st, L->sd})
     if (q) hipStreamDestroy(q);
-  for (hipEvent_t q : {L->ev_ipm, L->ev_dyn})
+  for (hipEvent_t q : {L->ev_ipm, L->ev_dyn, L->ev_round})
     if (q) hipEventDestroy(q);
   delete L;
 }
@@ -1387,6 +1435,7 @@ static int lane_create(cs_server* S, cs_net* n, size_t bytes, int index, ServerL
       hipStreamCreateWithFlags(&L->sd, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&L->ev_ipm, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&L->ev_dyn, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&L->ev_round, hipEventDisableTiming) != hipSuccess ||
       hipMalloc(&L->q_out, sizeof(int) * 2 * qc) != hipSuccess ||
       hipMalloc(&L->q_res, sizeof(cs_result) * qc) != hipSuccess ||
       hipMalloc(&L->item_req, sizeof(int) * qc) != hipSuccess ||
