@@ -497,8 +497,8 @@ def deviation(res, g):
 # factorisations those dispatches performed.  Valid only for the kernel source
 # it was measured on (hash below); otherwise traffic is null.
 LU_TRAFFIC = dict(source_sha256_16="6d7e8309d2fa6e75", factorisations=2217483,
-                  fetch_kib=27300771244.0625, write_kib=24553935062.34375,
-                  copy_fetch_kib=524307.875, copy_write_kib=1048576.0,
+                  fetch_kib=27252471652.375, write_kib=24531202196.03125,
+                  copy_fetch_kib=524308.0625, copy_write_kib=1048576.0,
                   copy_bytes=1 << 30)
 
 
