@@ -118,7 +118,7 @@ def main():
                     help="scenarios of the 300-bus-shaped case (random branch/generator "
                          "pairs) screened in the mixed form and in FP64 (0: skip)")
     ap.add_argument("--c4-panel", type=int, default=0,
-                    help="panel width of the large-order LU (16, 32, 64); 0 = autotuned")
+                    help="launch variant of the large-order LU (16, 32, 64, 1664, 3264); 0 = autotuned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=12,
                     help="requests per arrival rate in the serving sweep (0: skip it)")
@@ -354,10 +354,11 @@ def c4_legs(cs, ctx, torch, args):
     for leg, prec in (("fp64", cs.PREC_FP64), ("mixed", cs.PREC_MIXED)):
         if args.c4_panel:
             ctx.autotune_set(nk, prec, args.c4_panel)
-            tune[leg] = {"panel_width": args.c4_panel, "ms_16_32_64": None}
+            tune[leg] = {"variant": args.c4_panel, "variants": list(cs.TUNE_VARIANTS), "ms": None}
             continue
         choice, ms = ctx.autotune(nk, prec, n)
-        tune[leg] = {"panel_width": choice, "ms_16_32_64": [round(float(v), 2) for v in ms]}
+        tune[leg] = {"variant": choice, "variants": list(cs.TUNE_VARIANTS),
+                     "ms": [round(float(v), 2) for v in ms]}
     out["autotune"] = tune
     for leg in ("mixed", "fp64"):
         prec = cs.PREC_MIXED if leg == "mixed" else cs.PREC_FP64

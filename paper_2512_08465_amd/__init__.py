@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libcs.so")
 CS_OK, CS_EINVAL, CS_ENOMEM, CS_EHBM, CS_EDEVICE, CS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 CS_EAGAIN, CS_ETIMEDOUT = -6, -7
 PREC_FP64, PREC_MIXED = 0, 1
+# launch variants of the large-order LU, in the autotuner's order: panel
+# widths 16, 32, 64 (right-looking), panels of 16 / 32 in groups of 64
+TUNE_VARIANTS = (16, 32, 64, 1664, 3264)
 CAUSE_ISLAND, CAUSE_OPF, CAUSE_LIMIT, CAUSE_SSS, CAUSE_NUMERICAL = 1, 2, 4, 8, 16
 CAUSE_PRUNED = 32
 OPF_CONVERGED, OPF_MAXIT, OPF_NUMERICAL, OPF_NOT_RUN = 0, 1, 2, 3
@@ -222,16 +225,17 @@ class Context:
         _check(library().cs_stats_reset(self._h))
 
     def autotune(self, n: int, prec: int = 0, batch: int = 512):
-        """Time the large-order LU's panel widths for KKT order n (cs_autotune):
-        (chosen width or 0 when order n has nothing to tune, ms per variant)."""
+        """Time the large-order LU's launch variants (TUNE_VARIANTS) for KKT
+        order n (cs_autotune): (chosen variant or 0 when order n has nothing
+        to tune, ms per variant)."""
         choice = ctypes.c_int32(0)
-        ms = np.zeros(3)
+        ms = np.zeros(len(TUNE_VARIANTS))
         _check(library().cs_autotune(self.handle, int(n), int(prec), int(batch),
                                      ctypes.byref(choice), _ptr(ms)))
         return int(choice.value), ms
 
     def autotune_set(self, n: int, prec: int, choice: int):
-        """Install a panel width (16, 32, 64; 0 = default) for KKT order n."""
+        """Install a launch variant (one of TUNE_VARIANTS; 0 = default) for KKT order n."""
         _check(library().cs_autotune_set(self.handle, int(n), int(prec), int(choice)))
 
     # kernel-level entry points (device pointers, e.g. torch tensors' data_ptr)

@@ -843,10 +843,10 @@ static int check_opts(const cs_opts& opts, const char* who) {
 }
 
 // ------------------------------------------------------------------ autotuning
-// Panel width of the large-order LU: every candidate times one launch over
+// Launch variant of the large-order LU: every candidate times one launch over
 // min(batch, 512) synthetic systems of order n (after one untimed launch),
 // the fastest is kept for (device, n, precision).
-static const int kTunePanels[CS_TUNE_VARIANTS] = {16, 32, 64};
+static const int kTunePanels[CS_TUNE_VARIANTS] = {16, 32, 64, 1664, 3264};
 
 static int tune_lu_big(cs_ctx* c, int n, bool f32, int batch, int* choice, double* ms) {
   const size_t es = f32 ? sizeof(float) : sizeof(double);
@@ -924,7 +924,8 @@ extern "C" int cs_autotune(cs_ctx* c, int32_t n, int32_t prec, int32_t batch, in
 
 extern "C" int cs_autotune_set(cs_ctx* c, int32_t n, int32_t prec, int32_t choice) {
   if (!c || n <= 0 || (prec != CS_PREC_FP64 && prec != CS_PREC_MIXED) ||
-      (choice != 0 && choice != 16 && choice != 32 && choice != 64))
+      (choice != 0 && choice != 16 && choice != 32 && choice != 64 && choice != 1664 &&
+       choice != 3264))
     return fail(CS_EINVAL, "cs_autotune_set: bad arguments");
   lu_big_set_panel(c->device, n, prec == CS_PREC_MIXED, choice);
   return CS_OK;

@@ -135,8 +135,9 @@ void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
                      int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
                      int count, int* info, hipStream_t stream, int role = LU_KKT);
 // orders above the register-resident kernel's limit (k_lu_big.hip)
-// nb: panel width 16, 32 or 64; 0 = the autotuner's choice for (current
-// device, n, precision), else 32
+// nb: launch variant, the panel width 16, 32 or 64, or 1664 / 3264 (panels of
+// 16 / 32 in groups of 64); 0 = the autotuner's choice for (current device,
+// n, precision), else 32
 void launch_lu_big(double* A, size_t stride, int n, int ncols, int lda, int* piv,
                    int piv_stride, SlotState* st, int want_phase, int want_job, int count,
                    int* info, hipStream_t stream, int nb = 0);

@@ -7,8 +7,9 @@ the autotuner that chooses among them (cs_autotune, opts.autotune).
   dynamic stage) and host synchronisations; the records and R_i of a whole
   list are bit-identical to the eager launches', FP64 and mixed, in a batch
   call and in a server.
-* Panel widths 16, 32 and 64 each give factors and solutions equal to
-  SciPy's (LAPACK's pivoting) at orders 1,100 and 1,338; the autotuner
+* Every launch variant of the large-order LU (panel widths 16, 32 and 64,
+  and panels of 16 or 32 in groups of 64) gives factors and solutions equal
+  to SciPy's (LAPACK's pivoting) at orders 1,100 and 1,338; the autotuner
   returns the fastest of its own timings and leaves orders up to 1,024 alone.
 """
 import numpy as np
@@ -108,7 +109,7 @@ def _run_lu(ctx, A, rhs):
 
 
 @pytest.mark.parametrize("n", [1100, 1338])
-@pytest.mark.parametrize("nb", [16, 32, 64])
+@pytest.mark.parametrize("nb", [16, 32, 64, 1664, 3264])
 def test_panel_widths_match_scipy(ctx, n, nb):
     rng = np.random.default_rng(n + nb)
     A = rng.standard_normal((2, n, n))
@@ -129,13 +130,13 @@ def test_panel_widths_match_scipy(ctx, n, nb):
 def test_autotune_picks_its_fastest(ctx):
     import paper_2512_08465_amd as cs
     choice, ms = ctx.autotune(1338, cs.PREC_FP64, 256)
-    print(f"order 1338 FP64: panel widths 16/32/64 take {ms} ms; chose {choice}")
-    assert choice in (16, 32, 64)
+    print(f"order 1338 FP64: variants {cs.TUNE_VARIANTS} take {ms} ms; chose {choice}")
+    assert choice in cs.TUNE_VARIANTS
     assert np.all(np.isfinite(ms)) and np.all(ms > 0)
-    assert choice == (16, 32, 64)[int(np.argmin(ms))]
+    assert choice == cs.TUNE_VARIANTS[int(np.argmin(ms))]
     choice32, ms32 = ctx.autotune(1338, cs.PREC_MIXED, 256)
     print(f"order 1338 FP32: {ms32} ms; chose {choice32}")
-    assert choice32 == (16, 32, 64)[int(np.argmin(ms32))]
+    assert choice32 == cs.TUNE_VARIANTS[int(np.argmin(ms32))]
     none, ms0 = ctx.autotune(580, cs.PREC_FP64, 256)
     assert none == 0 and np.all(np.isnan(ms0))
     ctx.autotune_set(1338, cs.PREC_FP64, 0)
