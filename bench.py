@@ -430,7 +430,9 @@ def leg_summary(leg, st, done, dt, steps, res, golden):
         "ms_per_step": round(1e3 * dt / steps, 3),
         "kkt_order": nk,
         "roofline": {
-            "kernel": "k_lu_solve<%s, LU_KKT> (KKT LU + solve)" % ("float" if mixed else "double"),
+            # four wavefronts per matrix by default in FP64 (orders up to 768), eight in FP32
+            "kernel": "k_lu_solve<%s, LU_KKT, %d> (KKT LU + solve)" % (
+                ("float", 8) if mixed else ("double", 4 if nk <= 768 else 8)),
             "bound": "mfma",
             "achieved": round(achieved, 4),
             "peak": peak,

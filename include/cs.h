@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define CS_ABI_VERSION 9
+#define CS_ABI_VERSION 10
 
 enum {
   CS_OK = 0,
@@ -459,30 +459,35 @@ int cs_wait(cs_req* req, int64_t timeout_us, cs_result* out, double* risk,
  * completes). */
 void cs_req_free(cs_req* req);
 
-/* Autotuning of launch variants.  For a KKT order n above the
- * register-resident LU's limit (1,024), times the large-order LU's variants
- * (one untimed, one timed launch each) on min(batch, 512) synthetic systems
- * of order n (dense, entries from a counter hash, so that pivoting
- * interchanges rows as on KKT systems) in the precision prec names (FP64,
- * or FP32 for CS_PREC_MIXED, the mixed form's main factorisation), keeps the
- * fastest for (ctx's device, n, precision) for the rest of the process and
- * returns it in *choice (may be NULL), with the milliseconds of each timed
- * launch in ms[CS_TUNE_VARIANTS] (may be NULL), in this order of variants:
+/* Autotuning of launch variants.  Times the batched LU's launch variants
+ * for order n (one untimed, one timed launch each) on synthetic systems of
+ * order n (dense, entries from a counter hash, so that pivoting interchanges
+ * rows as on KKT systems; min(batch, 2048) of them up to order 1,024,
+ * min(batch, 512) above) in the precision prec names (FP64, or FP32 for
+ * CS_PREC_MIXED, the mixed form's main factorisation), keeps the fastest for
+ * (ctx's device, n, precision) for the rest of the process and returns it in
+ * *choice (may be NULL), with the milliseconds of each timed launch in
+ * ms[CS_TUNE_VARIANTS] (may be NULL; entries without a variant NaN).
+ * Orders up to 1,024 (the register-resident LU), ms[0..1]:
+ *   4, 8          wavefronts per matrix: 256 threads with up to three panel
+ *                 rows each (orders up to 768; two matrices per CU in FP64),
+ *                 or 512 threads with two.  The factors are the same bits.
+ * Orders above 1,024 (the large-order LU), ms[0..4]:
  *   16, 32, 64    right-looking with panels of that width (the trailing
  *                 matrix updated after every panel);
  *   1664, 3264    panels of 16 or 32 columns, left-looking inside groups of
  *                 64 (the trailing matrix updated once per group).
- * For n <= 1,024 there is nothing to tune: *choice = 0, ms NaN.
- * opts.autotune = 1 runs it at first use.  Allocates temporary device
- * memory (at most half the context's budget).  Errors: CS_EINVAL,
- * CS_EUNSUPPORTED (n > 4,096), CS_ENOMEM, CS_EDEVICE. */
+ * opts.autotune = 1 runs it for the KKT order at first use.  Allocates
+ * temporary device memory (at most half the context's budget).  Errors:
+ * CS_EINVAL, CS_EUNSUPPORTED (n > 4,096), CS_ENOMEM, CS_EDEVICE. */
 #define CS_TUNE_VARIANTS 5
 int cs_autotune(cs_ctx* ctx, int32_t n, int32_t prec, int32_t batch, int32_t* choice,
                 double* ms);
 
 /* Install a choice measured earlier (for instance in another process) for
- * (ctx's device, n, prec): one of the variants above (16, 32, 64, 1664,
- * 3264), or 0 to return to the default (32).  CS_EINVAL for any other
+ * (ctx's device, n, prec): one of the variants above for that order (4 only
+ * up to order 768), or 0 to return to the default (up to order 768: 4 in
+ * FP64, 8 in FP32; 769 to 1,024: 8; above: 32).  CS_EINVAL for any other
  * value. */
 int cs_autotune_set(cs_ctx* ctx, int32_t n, int32_t prec, int32_t choice);
 

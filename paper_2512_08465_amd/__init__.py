@@ -20,7 +20,9 @@ CS_EAGAIN, CS_ETIMEDOUT = -6, -7
 PREC_FP64, PREC_MIXED = 0, 1
 # launch variants of the large-order LU, in the autotuner's order: panel
 # widths 16, 32, 64 (right-looking), panels of 16 / 32 in groups of 64
-TUNE_VARIANTS = (16, 32, 64, 1664, 3264)
+TUNE_VARIANTS = (16, 32, 64, 1664, 3264)   # large-order LU (order > REG_ORDER)
+REG_TUNE_VARIANTS = (4, 8)                  # wavefronts per matrix (order <= REG_ORDER)
+REG_ORDER, REG_ORDER_W4 = 1024, 768
 CAUSE_ISLAND, CAUSE_OPF, CAUSE_LIMIT, CAUSE_SSS, CAUSE_NUMERICAL = 1, 2, 4, 8, 16
 CAUSE_PRUNED = 32
 OPF_CONVERGED, OPF_MAXIT, OPF_NUMERICAL, OPF_NOT_RUN = 0, 1, 2, 3
@@ -225,9 +227,10 @@ class Context:
         _check(library().cs_stats_reset(self._h))
 
     def autotune(self, n: int, prec: int = 0, batch: int = 512):
-        """Time the large-order LU's launch variants (TUNE_VARIANTS) for KKT
-        order n (cs_autotune): (chosen variant or 0 when order n has nothing
-        to tune, ms per variant)."""
+        """Time the batched LU's launch variants for order n (cs_autotune):
+        (chosen variant, ms).  Orders up to REG_ORDER: REG_TUNE_VARIANTS in
+        ms[0:2] (4 only up to REG_ORDER_W4; NaN where not timed); above:
+        TUNE_VARIANTS in ms[0:5]."""
         choice = ctypes.c_int32(0)
         ms = np.zeros(len(TUNE_VARIANTS))
         _check(library().cs_autotune(self.handle, int(n), int(prec), int(batch),
@@ -235,7 +238,8 @@ class Context:
         return int(choice.value), ms
 
     def autotune_set(self, n: int, prec: int, choice: int):
-        """Install a launch variant (one of TUNE_VARIANTS; 0 = default) for KKT order n."""
+        """Install a launch variant for order n (REG_TUNE_VARIANTS up to
+        REG_ORDER, TUNE_VARIANTS above; 0 = default)."""
         _check(library().cs_autotune_set(self.handle, int(n), int(prec), int(choice)))
 
     # kernel-level entry points (device pointers, e.g. torch tensors' data_ptr)

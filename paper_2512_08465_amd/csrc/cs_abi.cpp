@@ -35,6 +35,8 @@ namespace cs {
 size_t lu_lds_bytes(int n, int nrhs);
 int lu_max_order();
 int lu_reg_order();
+int lu_reg_order_w4();
+int lu_reg_waves(int n, bool f32);
 size_t opf_eval_lds(int nb, int nl, int ng);
 size_t form_state_lds(int ng);
 void lu_set_attrs(size_t bytes);
@@ -843,17 +845,22 @@ static int check_opts(const cs_opts& opts, const char* who) {
 }
 
 // ------------------------------------------------------------------ autotuning
-// Launch variant of the large-order LU: every candidate times one launch over
-// min(batch, 512) synthetic systems of order n (after one untimed launch),
-// the fastest is kept for (device, n, precision).
+// Launch variant of the batched LU for order n: every candidate times one
+// launch over min(batch, 512) (large orders) or min(batch, 2048) (orders the
+// register-resident kernel takes) synthetic systems of order n, after one
+// untimed launch; the fastest is kept for (device, n, precision).
+// Large orders: the panel code of k_lu_big.  Up to lu_reg_order(): the
+// wavefronts per matrix of k_lu_solve (four only up to lu_reg_order_w4()).
 static const int kTunePanels[CS_TUNE_VARIANTS] = {16, 32, 64, 1664, 3264};
+static const int kTuneWaves[2] = {4, 8};
 
-static int tune_lu_big(cs_ctx* c, int n, bool f32, int batch, int* choice, double* ms) {
+static int tune_lu(cs_ctx* c, int n, bool f32, int batch, int* choice, double* ms) {
+  const bool reg = n <= lu_reg_order();
   const size_t es = f32 ? sizeof(float) : sizeof(double);
   const int ncols = n + 1;
   const int lda = (int)round_up(ncols, 2);
   const size_t stride = (size_t)n * lda;
-  long long count = std::max(1, std::min(batch, 512));
+  long long count = std::max(1, std::min(batch, reg ? 2048 : 512));
   const size_t cap = std::max<size_t>(c->hbm_budget / 2, stride * es);
   count = std::max<long long>(1, std::min<long long>(count, (long long)(cap / (stride * es))));
   void* A = nullptr;
@@ -875,15 +882,24 @@ static int tune_lu_big(cs_ctx* c, int n, bool f32, int batch, int* choice, doubl
     return fail(CS_EDEVICE, "cs_autotune: event creation failed");
   }
   hipStream_t st = c->stream;
-  int best = 32;
+  const int nvar = reg ? (n <= lu_reg_order_w4() ? 2 : 1) : CS_TUNE_VARIANTS;
+  int best = 0;
   float best_ms = 0.0f;
-  for (int v = 0; v < CS_TUNE_VARIANTS; ++v) {
-    const int nb = kTunePanels[v];
+  for (int v = 0; v < nvar; ++v) {
+    // a register-resident order with only eight wavefronts possible times that one
+    const int nb = reg ? (nvar == 1 ? 8 : kTuneWaves[v]) : kTunePanels[v];
+    if (reg) lu_set_variant(c->device, n, f32, nb);
     float t = 0.0f;
     for (int rep = 0; rep < 2; ++rep) {
       launch_tune_fill(A, f32, stride, n, ncols, lda, (int)count, 12345u + rep, st);
       hipEventRecord(e0, st);
-      if (f32)
+      if (reg && f32)
+        launch_lu_solve_f32(static_cast<float*>(A), stride, n, ncols, lda, piv, n, nullptr, 0,
+                            0, (int)count, nullptr, st);
+      else if (reg)
+        launch_lu_solve(static_cast<double*>(A), stride, n, ncols, lda, piv, n, nullptr, 0, 0,
+                        (int)count, nullptr, st);
+      else if (f32)
         launch_lu_big_f32(static_cast<float*>(A), stride, n, ncols, lda, piv, n, nullptr, 0, 0,
                           (int)count, nullptr, st, nb);
       else
@@ -891,11 +907,12 @@ static int tune_lu_big(cs_ctx* c, int n, bool f32, int batch, int* choice, doubl
                       (int)count, nullptr, st, nb);
       hipEventRecord(e1, st);
       if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+        if (reg) lu_set_variant(c->device, n, f32, 0);
         cleanup();
         return fail(CS_EDEVICE, "cs_autotune: timing launch failed");
       }
     }
-    if (ms) ms[v] = t;
+    if (ms) ms[reg && nvar == 1 ? 1 : v] = t;
     if (v == 0 || t < best_ms) {
       best_ms = t;
       best = nb;
@@ -903,7 +920,7 @@ static int tune_lu_big(cs_ctx* c, int n, bool f32, int batch, int* choice, doubl
   }
   cleanup();
   HIPCHK(hipGetLastError());
-  lu_big_set_panel(c->device, n, f32, best);
+  lu_set_variant(c->device, n, f32, best);
   if (choice) *choice = best;
   return CS_OK;
 }
@@ -917,28 +934,30 @@ extern "C" int cs_autotune(cs_ctx* c, int32_t n, int32_t prec, int32_t batch, in
   if (choice) *choice = 0;
   if (ms)
     for (int v = 0; v < CS_TUNE_VARIANTS; ++v) ms[v] = std::nan("");
-  if (n <= lu_reg_order()) return CS_OK;   // the register-resident kernel has one shape
   HIPCHK(hipSetDevice(c->device));
-  return tune_lu_big(c, n, prec == CS_PREC_MIXED, batch, choice, ms);
+  return tune_lu(c, n, prec == CS_PREC_MIXED, batch, choice, ms);
 }
 
 extern "C" int cs_autotune_set(cs_ctx* c, int32_t n, int32_t prec, int32_t choice) {
-  if (!c || n <= 0 || (prec != CS_PREC_FP64 && prec != CS_PREC_MIXED) ||
-      (choice != 0 && choice != 16 && choice != 32 && choice != 64 && choice != 1664 &&
-       choice != 3264))
+  bool ok = choice == 0;
+  if (n <= lu_reg_order())
+    ok = ok || choice == 8 || (choice == 4 && n <= lu_reg_order_w4());
+  else
+    ok = ok || choice == 16 || choice == 32 || choice == 64 || choice == 1664 || choice == 3264;
+  if (!c || n <= 0 || (prec != CS_PREC_FP64 && prec != CS_PREC_MIXED) || !ok)
     return fail(CS_EINVAL, "cs_autotune_set: bad arguments");
-  lu_big_set_panel(c->device, n, prec == CS_PREC_MIXED, choice);
+  lu_set_variant(c->device, n, prec == CS_PREC_MIXED, choice);
   return CS_OK;
 }
 
-// opts.autotune: tune the large-order LU of the KKT order once per process
+// opts.autotune: tune the LU of the KKT order once per process
 static int autotune_for(cs_ctx* c, const Plan& p, const cs_opts& opts, int B) {
-  if (!opts.autotune || p.s.nk <= lu_reg_order()) return CS_OK;
+  if (!opts.autotune) return CS_OK;
   for (int f = 0; f < 2; ++f) {
     const bool f32 = f == 1;
     if (f32 && opts.prec != CS_PREC_MIXED) continue;
-    if (lu_big_panel(c->device, p.s.nk, f32) != 0) continue;
-    const int rc = tune_lu_big(c, p.s.nk, f32, B, nullptr, nullptr);
+    if (lu_variant(c->device, p.s.nk, f32) != 0) continue;
+    const int rc = tune_lu(c, p.s.nk, f32, B, nullptr, nullptr);
     if (rc != CS_OK) return rc;
   }
   return CS_OK;

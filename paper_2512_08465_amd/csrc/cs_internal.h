@@ -144,8 +144,11 @@ void launch_lu_big(double* A, size_t stride, int n, int ncols, int lda, int* piv
 void launch_lu_big_f32(float* A, size_t stride, int n, int ncols, int lda, int* piv,
                        int piv_stride, SlotState* st, int want_phase, int want_job, int count,
                        int* info, hipStream_t stream, int nb = 0);
-void lu_big_set_panel(int device, int n, bool f32, int nb);
-int lu_big_panel(int device, int n, bool f32);   // 0 when not tuned
+// launch variant per (device, order, precision), 0 when not set: for orders
+// up to lu_reg_order() the wavefronts per matrix of k_lu_solve (4 or 8), above
+// it the panel code of k_lu_big
+void lu_set_variant(int device, int n, bool f32, int v);
+int lu_variant(int device, int n, bool f32);
 void launch_tune_fill(void* A, bool f32, size_t stride, int n, int ncols, int lda, int count,
                       unsigned seed, hipStream_t stream);
 void launch_lu_solve_f32(float* A, size_t stride, int n, int ncols, int lda,

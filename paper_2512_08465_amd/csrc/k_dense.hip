@@ -6,12 +6,13 @@
 // n..ncols-1 (an augmented matrix): the forward substitution falls out of the
 // elimination and only the back substitution with U remains.
 //
-// Right-looking blocked LU, panel width NB = 32, eight wavefronts per matrix,
-// panels taken in pairs so that the trailing matrix is updated once per pair
-// with rank 64.  Per pair (panels [k0, k1) and [k1, k2)):
+// Right-looking blocked LU, panel width NB = 32, four or eight wavefronts per
+// matrix (LuGeo), panels taken in pairs so that the trailing matrix is updated
+// once per pair with rank 64.  Per pair (panels [k0, k1) and [k1, k2)):
 //   B1. the first panel's columns are brought up to date by the previous
 //       pair (A -= L21 U12 on MFMA), passed through LDS in 16-column chunks
-//       and loaded into registers: thread t holds panel rows t and t + 512;
+//       and loaded into registers: thread t holds panel rows t, t + THREADS
+//       (and t + 2 THREADS with four wavefronts, while the panel needs it);
 //   P1. that panel is factorised in registers by all threads.  Rows are never
 //       moved while it runs: each keeps its LAPACK position (the position it
 //       would occupy after the interchanges so far) and a "pivoted" flag.  Per
@@ -36,6 +37,9 @@
 
 #include <algorithm>
 #include <climits>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace cs {
 
@@ -63,41 +67,64 @@ template <> struct Mfma<float> {
 
 constexpr int LU_NB = 32;             // panel width
 constexpr int LU_CW = 16;             // columns per LDS transposition chunk
-constexpr int LU_THREADS = 512;
-constexpr int LU_WAVES = LU_THREADS / 64;
-constexpr int LU_R = 2;               // panel rows per thread: n <= LU_R * LU_THREADS
 // LDS chunk layout: row r, column c (< 16) at r * 17 + c (the padding
 // spreads a column over the banks for the row-wise reads)
 constexpr int PLD = LU_CW + 1;
 __device__ inline int chunk_at(int r, int c) { return r * PLD + c; }
 constexpr int LU_KK = LU_NB / 4;      // k-steps of the 16x16x4 MFMA per panel
-constexpr int LU_MAX_N = LU_R * LU_THREADS;
 constexpr int LU_KU = 2 * LU_NB;     // rank of the trailing update (a panel pair)
-// elements of the chunk area of the dynamic LDS: a 16-column chunk of the
-// panel rows below the first panel; at least 64 staged U12 rows of 33
-// columns for the trailing
-// update, and two 32 x 32 blocks for the pair's coupling term
+
+// Launch geometry: W wavefronts per matrix.  Every element goes through the
+// same operations in the same order whatever W is (pivot ties go to the lower
+// position, each MFMA tile and group covers the same rows and columns), so the
+// factors do not depend on it.
+//   W = 8: 512 threads, panel rows tid and tid + 512 (orders up to 1,024); the
+//          16-column chunk of the panel update holds every row below the
+//          first panel.
+//   W = 4: 256 threads, three panel rows per thread (orders up to 768); the
+//          chunk holds 256 rows at a time.  In FP64 two workgroups fit a CU
+//          (registers and LDS), so that one matrix's latency-bound panel runs
+//          beside another matrix's trailing update.
+template <int W>
+struct LuGeo {
+  static constexpr int WAVES = W;
+  static constexpr int THREADS = 64 * W;
+  static constexpr int R = W == 8 ? 2 : 3;            // panel rows per thread
+  static constexpr int MAX_N = R * THREADS;
+  static constexpr int PASS_ROWS = W == 8 ? MAX_N : THREADS;   // chunk rows per pass
+  // smallest chunk area: the pair's coupling term (two 32 x 32 blocks) and
+  // staged U12 rows (64 rows of 33 columns; W = 4: of 97, three groups of 32
+  // columns per staging pass)
+  static constexpr int MIN_CHUNK = W == 8 ? (LU_NB + 1) * LU_KU : (3 * 32 + 1) * LU_KU;
+};
+constexpr int LU_MAX_N = LuGeo<8>::MAX_N;
+// elements of the chunk area of the dynamic LDS: a 16-column chunk of (a pass
+// of) the panel rows below the first panel, or the staged U12 rows of the
+// trailing update, or the two 32 x 32 blocks of the pair's coupling term
+template <int W>
 __host__ __device__ inline int chunk_elems(int n) {
-  // the chunk holds the rows below the first panel (at most n - 32)
-  const int c = PLD * (n - LU_NB);
-  return c > (LU_NB + 1) * LU_KU ? c : (LU_NB + 1) * LU_KU;
+  // the chunk holds rows below the first panel (at most n - 32)
+  const int rows = n - LU_NB < LuGeo<W>::PASS_ROWS ? n - LU_NB : LuGeo<W>::PASS_ROWS;
+  const int c = PLD * rows;
+  return c > LuGeo<W>::MIN_CHUNK ? c : LuGeo<W>::MIN_CHUNK;
 }
 // columns of U12 staged per pass of the trailing update (a multiple of 32;
 // the staged rows have a stride of cols + 1 elements)
+template <int W>
 __device__ inline int u_stage_cols(int n) {
-  return ((chunk_elems(n) / LU_KU - 1) / 32) * 32;
+  return ((chunk_elems<W>(n) / LU_KU - 1) / 32) * 32;
 }
 
 // static LDS of the kernel
-template <class T>
+template <class T, int W>
 struct LuShared {
   T rows[LU_NB * LU_NB];        // pivot rows of the panel: [L11 | U11]; U block in the solve
   T linv[LU_NB * LU_NB];        // inv(L11), row-major
   // per panel column (two buffers, alternating): each wavefront's pivot
   // candidate, |value| and LAPACK position, and the candidate's whole row
-  T slot[2][LU_WAVES][LU_NB];
-  T cand_v[2][LU_WAVES];
-  int cand_pos[2][LU_WAVES];
+  T slot[2][W][LU_NB];
+  T cand_v[2][W];
+  int cand_pos[2][W];
   int piv[LU_NB];               // relative pivot positions of the panel
   int bq[LU_NB];                // interchanged rows below the panel's top: position, -1 unused
   int bs[LU_NB];                //   and the position its new content comes from
@@ -110,11 +137,12 @@ __device__ inline bool better(T v, int pos, T bv, int bpos) {
 }
 
 // Per-thread state of the panel factorisation.
-template <class T>
+template <class T, int W>
 struct PanelRows {
-  T v[LU_R][LU_NB];        // panel row tid + LU_THREADS s, columns of the panel
-  int pos[LU_R];           // its LAPACK position within the panel
-  bool live[LU_R];         // not yet chosen as a pivot
+  static constexpr int R = LuGeo<W>::R;
+  T v[R][LU_NB];           // panel row tid + THREADS s, columns of the panel
+  int pos[R];              // its LAPACK position within the panel
+  bool live[R];            // not yet chosen as a pivot
 };
 
 // Cross-lane moves within a 16-lane row of the wavefront (DPP), for 32-bit
@@ -181,9 +209,9 @@ __device__ inline void choose_step(T& bv, int& bp, int& bw) {
 // own rows (the winner takes position J, the row at position J takes the
 // winner's) and eliminates with the winner's row.  The two buffers alternate
 // between columns, so a buffer is rewritten only after the next barrier.
-template <class T, int J>
+template <class T, int W, int NR, int J>
 __device__ __attribute__((always_inline)) inline void panel_column(
-    PanelRows<T>& R, int m, int r0, int* __restrict__ piv, LuShared<T>& S, int tid) {
+    PanelRows<T, W>& R, int m, int r0, int* __restrict__ piv, LuShared<T, W>& S, int tid) {
   // FP32: the wavefront index as a scalar, so that the candidate's LDS
   // address is formed on the scalar unit instead of occupying a vector
   // register
@@ -194,7 +222,7 @@ __device__ __attribute__((always_inline)) inline void panel_column(
   T bv = T(-1);
   int bp = INT_MAX;
 #pragma unroll
-  for (int s = 0; s < LU_R; ++s) {
+  for (int s = 0; s < NR; ++s) {
     // a NaN entry ranks above every number, so a row is always chosen
     const T x = R.v[s][J];
     const T a = (x == x) ? fabs(x) : T(HUGE_VAL);
@@ -218,7 +246,7 @@ __device__ __attribute__((always_inline)) inline void panel_column(
   // (only columns J.. are needed by the elimination; the whole pivot rows
   // go to S.rows at the end of the panel)
 #pragma unroll
-  for (int s = 0; s < LU_R; ++s) {
+  for (int s = 0; s < NR; ++s) {
     if (R.live[s] && R.pos[s] == bp) {
 #pragma unroll
       for (int c = J; c < LU_NB; ++c) S.slot[BUF][wave][c] = R.v[s][c];
@@ -229,7 +257,7 @@ __device__ __attribute__((always_inline)) inline void panel_column(
   // total, so the winner does not depend on the order of the reduction.
   int bw;
   if constexpr (sizeof(T) == 4) {
-    // every lane reads the eight candidates (the same LDS words for all
+    // every lane reads the W candidates (the same LDS words for all
     // lanes, at fixed addresses) and reduces them in wavefront order: no
     // per-lane address stays live across the columns (in the FP32 kernel,
     // whose register budget is 128, such an address was spilled and
@@ -237,7 +265,7 @@ __device__ __attribute__((always_inline)) inline void panel_column(
     T cv = S.cand_v[BUF][0];
     int cp = S.cand_pos[BUF][0], cw = 0;
 #pragma unroll
-    for (int w = 1; w < LU_WAVES; ++w) {
+    for (int w = 1; w < W; ++w) {
       const T v2 = S.cand_v[BUF][w];
       const int p2 = S.cand_pos[BUF][w];
       if (better(v2, p2, cv, cp)) {
@@ -250,18 +278,18 @@ __device__ __attribute__((always_inline)) inline void panel_column(
     bp = read_lane(cp, 0);
     bw = read_lane(cw, 0);
   } else {
-    // lanes 0..7 of every wavefront take the eight candidates and reduce
+    // lanes 0..W-1 of every wavefront take the W candidates and reduce
     // them on DPP (measured faster in FP64 than the form above)
     T cv = T(-1);
     int cp = INT_MAX, cw = 0;
-    if (lane < LU_WAVES) {
+    if (lane < W) {
       cv = S.cand_v[BUF][lane];
       cp = S.cand_pos[BUF][lane];
       cw = lane;
     }
     choose_step<T, DPP_XOR1>(cv, cp, cw);
     choose_step<T, DPP_XOR2>(cv, cp, cw);
-    choose_step<T, DPP_HALF_MIRROR>(cv, cp, cw);
+    if constexpr (W > 4) choose_step<T, DPP_HALF_MIRROR>(cv, cp, cw);
     bv = read_lane(cv, 0);
     bp = read_lane(cp, 0);
     bw = read_lane(cw, 0);
@@ -269,7 +297,7 @@ __device__ __attribute__((always_inline)) inline void panel_column(
   const T* prow = S.slot[BUF][bw];
   // LAPACK interchanges positions J and bp
 #pragma unroll
-  for (int s = 0; s < LU_R; ++s) {
+  for (int s = 0; s < NR; ++s) {
     if (R.live[s]) {
       if (R.pos[s] == bp) {
         R.live[s] = false;
@@ -289,7 +317,7 @@ __device__ __attribute__((always_inline)) inline void panel_column(
   if (pv != T(0)) {
     const T inv = T(1) / pv;
 #pragma unroll
-    for (int s = 0; s < LU_R; ++s) {
+    for (int s = 0; s < NR; ++s) {
       if (R.live[s]) {
         const T l = R.v[s][J] * inv;
         R.v[s][J] = l;
@@ -300,24 +328,25 @@ __device__ __attribute__((always_inline)) inline void panel_column(
   }
 }
 
-template <class T, int J>
+template <class T, int W, int NR, int J>
 struct PanelColumns {
   static __device__ __attribute__((always_inline)) inline void run(
-      PanelRows<T>& R, int m, int r0, int kb, int* piv, LuShared<T>& S, int tid) {
+      PanelRows<T, W>& R, int m, int r0, int kb, int* piv, LuShared<T, W>& S, int tid) {
     if (J < kb) {
-      panel_column<T, J>(R, m, r0, piv, S, tid);
-      PanelColumns<T, J + 1>::run(R, m, r0, kb, piv, S, tid);
+      panel_column<T, W, NR, J>(R, m, r0, piv, S, tid);
+      PanelColumns<T, W, NR, J + 1>::run(R, m, r0, kb, piv, S, tid);
     }
   }
 };
-template <class T>
-struct PanelColumns<T, LU_NB> {
+template <class T, int W, int NR>
+struct PanelColumns<T, W, NR, LU_NB> {
   static __device__ __attribute__((always_inline)) inline void run(
-      PanelRows<T>&, int, int, int, int*, LuShared<T>&, int) {}
+      PanelRows<T, W>&, int, int, int, int*, LuShared<T, W>&, int) {}
 };
 
-// Factorise the m x kb panel whose rows sit in R.v (row tid + LU_THREADS s of the
-// panel, relative to its first row r0) with all threads of the workgroup.
+// Factorise the m x kb panel whose rows sit in R.v (row tid + THREADS s of the
+// panel, relative to its first row r0, s < NR: m <= NR * THREADS) with all
+// threads of the workgroup.
 // Rows are never moved while it runs: each keeps its LAPACK position (the
 // position it would occupy after the interchanges so far) and a "pivoted"
 // flag.  Writes the factored rows to A at their pivoted positions, the
@@ -325,23 +354,24 @@ struct PanelColumns<T, LU_NB> {
 // inv(L11) to S.linv and the rows interchanged below the panel's top to
 // S.bq / S.bs, and in ridx[t] (LDS, m ints) the row, relative to r0, that
 // ends up at position t.
-template <class T>
+template <class T, int W, int NR>
 __device__ __attribute__((always_inline)) inline void factor_panel(
-    PanelRows<T>& R, int m, int r0, int kb, T* __restrict__ A, int lda,
-    int* __restrict__ piv, int* __restrict__ ridx, LuShared<T>& S, int tid) {
+    PanelRows<T, W>& R, int m, int r0, int kb, T* __restrict__ A, int lda,
+    int* __restrict__ piv, int* __restrict__ ridx, LuShared<T, W>& S, int tid) {
+  constexpr int NT = LuGeo<W>::THREADS;
 #pragma unroll
-  for (int s = 0; s < LU_R; ++s) {
-    R.pos[s] = tid + LU_THREADS * s;
+  for (int s = 0; s < NR; ++s) {
+    R.pos[s] = tid + NT * s;
     R.live[s] = R.pos[s] < m;
   }
   __syncthreads();
-  PanelColumns<T, 0>::run(R, m, r0, kb, piv, S, tid);
+  PanelColumns<T, W, NR, 0>::run(R, m, r0, kb, piv, S, tid);
   // every row to its pivoted position (columns r0 .. r0+kb); ridx[t] = the
   // row (relative to r0) that ends up at position t; the pivot rows also to
   // S.rows ([L11 | U11])
 #pragma unroll
-  for (int s = 0; s < LU_R; ++s) {
-    const int r = tid + LU_THREADS * s;
+  for (int s = 0; s < NR; ++s) {
+    const int r = tid + NT * s;
     if (r < m) {
       ridx[R.pos[s]] = r;
       if (R.pos[s] < kb) {
@@ -510,9 +540,10 @@ __device__ inline void update_group(T* __restrict__ A, int lda, int n, int ncols
 // at i * 32 + (j ^ i), so that the 32 lanes' reads of one column fall in
 // different banks), then every row above is updated.
 constexpr int LU_BS = 32;
-template <class T>
+template <class T, int W>
 __device__ void back_substitute(T* __restrict__ A, int lda, int n, int ncols, T* xs, T* ub,
                                 int tid) {
+  constexpr int NT = LuGeo<W>::THREADS;
   const int lane = tid & 63, wave = tid >> 6;
   const int nrhs = ncols - n;
   if (nrhs <= 0) return;
@@ -520,12 +551,12 @@ __device__ void back_substitute(T* __restrict__ A, int lda, int n, int ncols, T*
   for (int b = nblk - 1; b >= 0; --b) {
     const int b0 = b * LU_BS;
     const int bs = min(LU_BS, n - b0);
-    for (int e = tid; e < LU_BS * LU_BS; e += LU_THREADS) {
+    for (int e = tid; e < LU_BS * LU_BS; e += NT) {
       const int i = e / LU_BS, j = e % LU_BS;
       ub[i * LU_BS + (j ^ i)] = (i < bs && j < bs) ? A[(size_t)(b0 + i) * lda + b0 + j] : T(0);
     }
     __syncthreads();
-    for (int rc = wave; rc < nrhs; rc += LU_WAVES) {
+    for (int rc = wave; rc < nrhs; rc += W) {
       T y = (lane < bs) ? A[(size_t)(b0 + lane) * lda + n + rc] : T(0);
       for (int i = bs - 1; i >= 0; --i) {
         const T xi = read_lane(y, i) / ub[i * LU_BS];      // the diagonal: (i ^ i) = 0
@@ -540,7 +571,7 @@ __device__ void back_substitute(T* __restrict__ A, int lda, int n, int ncols, T*
     __syncthreads();
     // y[0:b0] -= U[0:b0, b0:b0+bs] x[b0:b0+bs]
     const int work = b0 * nrhs;
-    for (int e = tid; e < work; e += LU_THREADS) {
+    for (int e = tid; e < work; e += NT) {
       const int i = e / nrhs, rc = e - i * nrhs;
       const T* urow = A + (size_t)i * lda + b0;
       // the block's U entries all in flight before the first is used
@@ -560,41 +591,60 @@ __device__ void back_substitute(T* __restrict__ A, int lda, int n, int ncols, T*
 // Panel columns [k0, k0 + kb) of rows k0.. into the registers R: straight
 // from memory when no update is pending (kbp = 0), else after the update by
 // L21 / U12 of columns [kp, kp + kbp) (MFMA), passed through the LDS chunk
-// buffer P in 16-column chunks.
-template <class T>
-__device__ inline void load_panel(PanelRows<T>& R, const T* __restrict__ A, int lda, int n,
+// buffer P in 16-column chunks, PASS_ROWS rows at a time.  Rows tid + THREADS s
+// for s < NR (n - k0 <= NR * THREADS).
+template <class T, int W, int NR>
+__device__ inline void load_panel(PanelRows<T, W>& R, const T* __restrict__ A, int lda, int n,
                                   int k0, int kb, int kp, int kbp, T* __restrict__ P, int tid) {
+  constexpr int NT = LuGeo<W>::THREADS, PR = LuGeo<W>::PASS_ROWS;
+  constexpr int NPASS = (NR * NT + PR - 1) / PR;
   const int lane = tid & 63, wave = tid >> 6;
   const int m = n - k0;
   if (kbp == 0) {
 #pragma unroll
-    for (int s = 0; s < LU_R; ++s) {
-      const int r = tid + LU_THREADS * s;
+    for (int s = 0; s < NR; ++s) {
+      const int r = tid + NT * s;
 #pragma unroll
       for (int c = 0; c < LU_NB; ++c)
         R.v[s][c] = (r < m && c < kb) ? A[(size_t)(k0 + r) * lda + k0 + c] : T(0);
     }
     return;
   }
-  const int tr = (m + 15) >> 4;
 #pragma unroll
   for (int ch = 0; ch < LU_NB; ch += LU_CW) {
     if (ch < kb) {
       const int cend = k0 + min(kb, ch + LU_CW);
-      for (int t = wave; t < tr; t += LU_WAVES)
-        update_tile_to_lds(A, lda, n, cend, kp, kbp, k0 + 16 * t, k0 + ch, k0, P, lane);
-      __syncthreads();
 #pragma unroll
-      for (int s = 0; s < LU_R; ++s) {
-        const int r = tid + LU_THREADS * s;
+      for (int p = 0; p < NPASS; ++p) {
+        // rows [p0, p0 + PR) of the panel (a multiple of 16 apart); the
+        // condition is the same for the whole workgroup
+        const int p0 = p * PR;
+        if (p0 < m) {
+          const int t0 = p0 >> 4, t1 = (min(m, p0 + PR) + 15) >> 4;
+          for (int t = t0 + wave; t < t1; t += W)
+            update_tile_to_lds(A, lda, n, cend, kp, kbp, k0 + 16 * t, k0 + ch, k0 + p0, P, lane);
+          __syncthreads();
 #pragma unroll
-        for (int c = 0; c < LU_CW; ++c)
-          R.v[s][ch + c] = (r < m && ch + c < kb) ? P[chunk_at(r, c)] : T(0);
+          for (int s = 0; s < NR; ++s) {
+            if (s * NT >= p0 && s * NT < p0 + PR) {
+              const int r = tid + NT * s;
+#pragma unroll
+              for (int c = 0; c < LU_CW; ++c)
+                R.v[s][ch + c] = (r < m && ch + c < kb) ? P[chunk_at(r - p0, c)] : T(0);
+            }
+          }
+          __syncthreads();
+        } else {
+#pragma unroll
+          for (int s = 0; s < NR; ++s)
+            if (s * NT >= p0 && s * NT < p0 + PR)
+#pragma unroll
+              for (int c = 0; c < LU_CW; ++c) R.v[s][ch + c] = T(0);
+        }
       }
-      __syncthreads();
     } else {
 #pragma unroll
-      for (int s = 0; s < LU_R; ++s)
+      for (int s = 0; s < NR; ++s)
 #pragma unroll
         for (int c = 0; c < LU_CW; ++c) R.v[s][ch + c] = T(0);
     }
@@ -606,30 +656,31 @@ __device__ inline void load_panel(PanelRows<T>& R, const T* __restrict__ A, int 
 // chunk area P, a block of columns per pass, so that every 32 x 32 group
 // reads them from there and its L21 operands go from memory straight into
 // the MFMAs; groups are handed out by an LDS ticket counter.
-template <class T>
+template <class T, int W>
 __device__ inline void trailing_update(T* __restrict__ A, int lda, int n, int ncols, int kp,
                                        int kbp, int i0, int c1, T* __restrict__ P,
-                                       LuShared<T>& S, int tid) {
+                                       LuShared<T, W>& S, int tid) {
+  constexpr int NT = LuGeo<W>::THREADS;
   const int lane = tid & 63;
   const int gr = (n - i0 + 31) >> 5;
-  const int cap = u_stage_cols(n);
+  const int cap = u_stage_cols<W>(n);
   for (int c0 = c1; c0 < ncols; c0 += cap) {
     const int w = min(cap, ncols - c0);
     const int ldu = w + 1;
     if (tid == 0) S.tile = 0;
     // eight loads in flight per thread before any of them is used
     const int tot = kbp * w;
-    for (int e0 = 0; e0 < tot; e0 += 8 * LU_THREADS) {
+    for (int e0 = 0; e0 < tot; e0 += 8 * NT) {
       T v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * LU_THREADS + tid;
+        const int e = e0 + u * NT + tid;
         const int r = e / w, c = e - r * w;
         v[u] = (e < tot) ? A[(size_t)(kp + r) * lda + c0 + c] : T(0);
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * LU_THREADS + tid;
+        const int e = e0 + u * NT + tid;
         const int r = e / w, c = e - r * w;
         if (e < tot) P[r * ldu + c] = -v[u];
       }
@@ -658,9 +709,9 @@ __device__ inline void trailing_update(T* __restrict__ A, int lda, int n, int nc
 // the former either as they are (columns left of the panel) or multiplied by
 // inv(L11) (to the right).  With Mneg (LDS, 32 x 32, row-major), the right
 // side also takes + Mneg U[kc .. kc + kbc) (rows of an earlier panel's U12).
-template <class T>
+template <class T, int W>
 __device__ inline void interchange_trsm(T* __restrict__ A, int lda, int ncols, int k0, int kb,
-                                        const int* __restrict__ ridx, const LuShared<T>& S,
+                                        const int* __restrict__ ridx, const LuShared<T, W>& S,
                                         const T* __restrict__ Mneg, int kc, int kbc, int tid) {
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -675,7 +726,7 @@ __device__ inline void interchange_trsm(T* __restrict__ A, int lda, int ncols, i
     bq[kk] = S.bq[k];
     bsrc[kk] = S.bs[k];
   }
-  for (int t = wave; t < ntl + ntr; t += LU_WAVES) {
+  for (int t = wave; t < ntl + ntr; t += W) {
     const bool right = t >= ntl;
     const int col = right ? r0 + 16 * (t - ntl) + li : 16 * t + li;
     const bool cok = col < ncols;
@@ -727,10 +778,34 @@ __device__ inline void interchange_trsm(T* __restrict__ A, int lda, int ncols, i
   }
 }
 
-// Wavefronts per SIMD the register budget is cut for.  FP64: two (one
-// workgroup per CU; the panel rows fill the registers).  FP32: four (two
-// workgroups per CU), so that one workgroup's latency-bound panel steps
-// overlap the other's work.
+// Load (B) and factorise (P) the panel [k0, k0 + kb) after the pending update
+// by columns [kp, kp + kbp).  Four wavefronts: the panel's height picks two or
+// three rows per thread.
+template <class T, int W>
+__device__ __attribute__((always_inline)) inline void panel_step(
+    PanelRows<T, W>& R, T* __restrict__ A, int lda, int n, int k0, int kb, int kp,
+    int kbp, T* __restrict__ P, int* __restrict__ piv, int* __restrict__ ridx,
+    LuShared<T, W>& S, int tid) {
+  constexpr int NR = LuGeo<W>::R, NT = LuGeo<W>::THREADS;
+  if constexpr (NR == 3) {
+    if (n - k0 > 2 * NT) {
+      load_panel<T, W, 3>(R, A, lda, n, k0, kb, kp, kbp, P, tid);
+      factor_panel<T, W, 3>(R, n - k0, k0, kb, A, lda, piv, ridx, S, tid);
+      return;
+    }
+    load_panel<T, W, 2>(R, A, lda, n, k0, kb, kp, kbp, P, tid);
+    factor_panel<T, W, 2>(R, n - k0, k0, kb, A, lda, piv, ridx, S, tid);
+  } else {
+    load_panel<T, W, NR>(R, A, lda, n, k0, kb, kp, kbp, P, tid);
+    factor_panel<T, W, NR>(R, n - k0, k0, kb, A, lda, piv, ridx, S, tid);
+  }
+}
+
+// Wavefronts per SIMD the register budget is cut for.  FP64: two (eight
+// wavefronts: one workgroup of 512 threads or two of 256 per CU; the panel
+// rows fill the registers).  FP32: four (two workgroups of 512 threads or four
+// of 256 per CU), so that one workgroup's latency-bound panel steps overlap
+// another's work.
 template <class T>
 struct LuWavesPerEu { static constexpr int value = sizeof(T) == 4 ? 4 : 2; };
 
@@ -738,8 +813,8 @@ struct LuWavesPerEu { static constexpr int value = sizeof(T) == 4 ? 4 : 2; };
 // algebraic systems and the FP64 fallback of the mixed-precision solve run
 // the same code under their own kernel symbols, so that a profiler's
 // per-kernel statistics separate them.
-template <class T, int ROLE>
-__global__ __launch_bounds__(LU_THREADS, LuWavesPerEu<T>::value) void k_lu_solve(
+template <class T, int ROLE, int W>
+__global__ __launch_bounds__(64 * W, LuWavesPerEu<T>::value) void k_lu_solve(
     T* __restrict__ Abase, size_t stride, int n, int ncols, int lda,
     int* __restrict__ pivbase, int piv_stride, SlotState* __restrict__ st,
     int want_phase, int want_job, int* __restrict__ info) {
@@ -754,14 +829,15 @@ __global__ __launch_bounds__(LU_THREADS, LuWavesPerEu<T>::value) void k_lu_solve
 
   extern __shared__ __attribute__((aligned(16))) unsigned char lu_lds[];
   T* P = reinterpret_cast<T*>(lu_lds);   // a 16-column chunk (chunk_at); then ridx
-  int* ridx = reinterpret_cast<int*>(P + chunk_elems(n));
-  __shared__ LuShared<T> S;
+  int* ridx = reinterpret_cast<int*>(P + chunk_elems<W>(n));
+  __shared__ LuShared<T, W> S;
   if (tid == 0) {
     S.sing = 0;
     S.tile = 0;
   }
   __syncthreads();
-  PanelRows<T> R;
+  PanelRows<T, W> R;
+  constexpr int NT = LuGeo<W>::THREADS;
   // Panels are taken in pairs: the trailing update is applied once per pair
   // with rank 64, which halves the passes over the trailing matrix.
   int kp = 0, kbp = 0;                   // previous pair: columns [kp, kp + kbp)
@@ -772,9 +848,10 @@ __global__ __launch_bounds__(LU_THREADS, LuWavesPerEu<T>::value) void k_lu_solve
     const int k2 = k1 + kb2;
     // ---- B1: first panel's columns into registers, after the previous
     // pair's update
-    load_panel(R, A, lda, n, k0, kb1, kp, kbp, P, tid);
-    // ---- P1
-    factor_panel(R, n - k0, k0, kb1, A, lda, piv, ridx, S, tid);
+    // ---- P1 (with four wavefronts, the third row of each thread only while
+    // the panel is taller than 512 rows: the registers of the shorter panels'
+    // columns then need no spill slots)
+    panel_step(R, A, lda, n, k0, kb1, kp, kbp, P, piv, ridx, S, tid);
     // ---- C: the rest of the previous pair's update (rows from k0, columns
     // right of the first panel), independent of the first panel's factors
     if (kbp > 0 && k1 < ncols) trailing_update(A, lda, n, ncols, kp, kbp, k0, k1, P, S, tid);
@@ -784,8 +861,7 @@ __global__ __launch_bounds__(LU_THREADS, LuWavesPerEu<T>::value) void k_lu_solve
     __syncthreads();
     if (kb2 > 0) {
       // ---- B2, P2: the second panel after the first panel's update
-      load_panel(R, A, lda, n, k1, kb2, k0, kb1, P, tid);
-      factor_panel(R, n - k1, k1, kb2, A, lda, piv, ridx, S, tid);
+      panel_step(R, A, lda, n, k1, kb2, k0, kb1, P, piv, ridx, S, tid);
       __syncthreads();
       // ---- A2: the second panel's interchanges; the U12 rows of its top
       // rows right of the pair still lack the first panel's update, so
@@ -797,18 +873,18 @@ __global__ __launch_bounds__(LU_THREADS, LuWavesPerEu<T>::value) void k_lu_solve
       if (k2 < ncols) {
         {
           // both elements of a thread in flight together
-          T v[LU_NB * LU_NB / LU_THREADS];
+          T v[LU_NB * LU_NB / NT];
 #pragma unroll
-          for (int u = 0; u < LU_NB * LU_NB / LU_THREADS; ++u) {
-            const int e = u * LU_THREADS + tid;
+          for (int u = 0; u < LU_NB * LU_NB / NT; ++u) {
+            const int e = u * NT + tid;
             const int t = e / LU_NB, c = e - t * LU_NB;
             v[u] = (t < kb2 && c < kb1) ? A[(size_t)(k1 + ridx[t]) * lda + k0 + c] : T(0);
           }
 #pragma unroll
-          for (int u = 0; u < LU_NB * LU_NB / LU_THREADS; ++u) P[u * LU_THREADS + tid] = v[u];
+          for (int u = 0; u < LU_NB * LU_NB / NT; ++u) P[u * NT + tid] = v[u];
         }
         __syncthreads();
-        for (int e = tid; e < LU_NB * LU_NB; e += LU_THREADS) {
+        for (int e = tid; e < LU_NB * LU_NB; e += NT) {
           const int i = e / LU_NB, c = e - i * LU_NB;
           T acc = T(0);
 #pragma unroll 8
@@ -824,7 +900,7 @@ __global__ __launch_bounds__(LU_THREADS, LuWavesPerEu<T>::value) void k_lu_solve
     kbp = kb1 + kb2;
   }
 
-  back_substitute(A, lda, n, ncols, P, S.rows, tid);
+  back_substitute<T, W>(A, lda, n, ncols, P, S.rows, tid);
   if (tid == 0) {
     if (st != nullptr) st[slot].singular = S.sing;
     if (info != nullptr) info[slot] = S.sing;
@@ -832,25 +908,28 @@ __global__ __launch_bounds__(LU_THREADS, LuWavesPerEu<T>::value) void k_lu_solve
 }
 
 // static LDS of k_lu_solve
-template <class T>
-constexpr size_t lu_static_lds() { return sizeof(LuShared<T>); }
+template <class T, int W>
+constexpr size_t lu_static_lds() { return sizeof(LuShared<T, W>); }
 
 // dynamic LDS: the chunk area (a 16-column chunk of panel rows, or staged
 // U12 rows) and the panel's row-index scratch during the factorisation; a
 // 32 x nrhs block during the solve
-template <class T>
+template <class T, int W>
 static size_t lu_dynamic_lds(int n, int nrhs) {
-  return std::max(sizeof(T) * (size_t)chunk_elems(n) + sizeof(int) * (size_t)n,
+  return std::max(sizeof(T) * (size_t)chunk_elems<W>(n) + sizeof(int) * (size_t)n,
                   sizeof(T) * (size_t)LU_BS * (size_t)nrhs);
 }
 
 // total LDS one workgroup of the FP64 k_lu_solve needs for order n and nrhs
-// columns (the FP32 one needs less), with room for the compiler's padding of
-// the static part; orders above LU_MAX_N go to k_lu_big, whose LDS is static
-// and small
+// columns, whichever geometry runs it (the FP32 one needs less), with room
+// for the compiler's padding of the static part; orders above LU_MAX_N go to
+// k_lu_big, whose LDS is static and small
 size_t lu_lds_bytes(int n, int nrhs) {
   if (n > LU_MAX_N) return 0;
-  return lu_dynamic_lds<double>(n, nrhs) + lu_static_lds<double>() + 256;
+  size_t b = lu_dynamic_lds<double, 8>(n, nrhs) + lu_static_lds<double, 8>();
+  if (n <= LuGeo<4>::MAX_N)
+    b = std::max(b, lu_dynamic_lds<double, 4>(n, nrhs) + lu_static_lds<double, 4>());
+  return b + 256;
 }
 
 // largest order the batched LU entry points take: k_lu_solve up to LU_MAX_N
@@ -859,6 +938,64 @@ int lu_max_order() { return 4096; }
 
 // largest order the register-resident kernel takes
 int lu_reg_order() { return LU_MAX_N; }
+
+// largest order its four-wavefront geometry takes
+int lu_reg_order_w4() { return LuGeo<4>::MAX_N; }
+
+// launch variant per (device, order, precision), set by the autotuner or by
+// hand: for k_lu_solve the wavefronts per matrix (4 or 8), for k_lu_big its
+// panel code; 0 = not set
+static std::mutex g_var_m;
+static std::map<std::tuple<int, int, int>, int> g_var;
+
+void lu_set_variant(int device, int n, bool f32, int v) {
+  std::lock_guard<std::mutex> lk(g_var_m);
+  g_var[std::make_tuple(device, n, f32 ? 1 : 0)] = v;
+}
+
+int lu_variant(int device, int n, bool f32) {
+  std::lock_guard<std::mutex> lk(g_var_m);
+  auto it = g_var.find(std::make_tuple(device, n, f32 ? 1 : 0));
+  return it == g_var.end() ? 0 : it->second;
+}
+
+// wavefronts per matrix for order n: the variant table, else four in FP64
+// where the order allows (measured 4-5% faster on the order-580 KKT systems,
+// 7% on the order-344 algebraic ones) and eight in FP32 (where four, with its
+// four workgroups per CU, spilled and ran a third slower)
+static int lu_waves_for(int n, bool f32) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const int v = lu_variant(dev, n, f32);
+  if (v == 8 || n > LuGeo<4>::MAX_N) return 8;
+  if (v == 4) return 4;
+  return f32 ? 8 : 4;
+}
+
+// launch variant that lu_waves_for picks for order n
+int lu_reg_waves(int n, bool f32) { return lu_waves_for(n, f32); }
+
+template <class T, int ROLE, int W>
+static void lu_launch_w(T* A, size_t stride, int n, int ncols, int lda, int* piv,
+                        int piv_stride, SlotState* st, int want_phase, int want_job, int count,
+                        int* info, hipStream_t stream) {
+  const size_t lds = lu_dynamic_lds<T, W>(n, ncols - n);
+  hipLaunchKernelGGL((k_lu_solve<T, ROLE, W>), dim3(count), dim3(LuGeo<W>::THREADS), lds,
+                     stream, A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job,
+                     info);
+}
+
+template <class T, int ROLE>
+static void lu_launch(T* A, size_t stride, int n, int ncols, int lda, int* piv, int piv_stride,
+                      SlotState* st, int want_phase, int want_job, int count, int* info,
+                      hipStream_t stream) {
+  if (lu_waves_for(n, sizeof(T) == 4) == 4)
+    lu_launch_w<T, ROLE, 4>(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job,
+                            count, info, stream);
+  else
+    lu_launch_w<T, ROLE, 8>(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job,
+                            count, info, stream);
+}
 
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
                      int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
@@ -869,12 +1006,15 @@ void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
                   info, stream);
     return;
   }
-  const size_t lds = lu_dynamic_lds<double>(n, ncols - n);
-  auto k = role == LU_DYN ? k_lu_solve<double, LU_DYN>
-           : role == LU_KKT_FALLBACK ? k_lu_solve<double, LU_KKT_FALLBACK>
-                                     : k_lu_solve<double, LU_KKT>;
-  hipLaunchKernelGGL(k, dim3(count), dim3(LU_THREADS), lds, stream,
-                     A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, info);
+  if (role == LU_DYN)
+    lu_launch<double, LU_DYN>(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase,
+                              want_job, count, info, stream);
+  else if (role == LU_KKT_FALLBACK)
+    lu_launch<double, LU_KKT_FALLBACK>(A, stride, n, ncols, lda, piv, piv_stride, st,
+                                       want_phase, want_job, count, info, stream);
+  else
+    lu_launch<double, LU_KKT>(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase,
+                              want_job, count, info, stream);
 }
 
 void launch_lu_solve_f32(float* A, size_t stride, int n, int ncols, int lda,
@@ -886,27 +1026,30 @@ void launch_lu_solve_f32(float* A, size_t stride, int n, int ncols, int lda,
                       info, stream);
     return;
   }
-  const size_t lds = lu_dynamic_lds<float>(n, ncols - n);
-  hipLaunchKernelGGL((k_lu_solve<float, LU_KKT>), dim3(count), dim3(LU_THREADS), lds, stream,
-                     A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, info);
+  lu_launch<float, LU_KKT>(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job,
+                           count, info, stream);
 }
 
 // the dynamic LDS limit of a kernel: what is left of `bytes` beside its
 // static LDS as the compiler laid it out (which may pad the struct)
-template <class T, int ROLE>
+template <class T, int ROLE, int W>
 static void lu_set_attr(size_t bytes) {
-  const void* f = reinterpret_cast<const void*>(k_lu_solve<T, ROLE>);
+  const void* f = reinterpret_cast<const void*>(k_lu_solve<T, ROLE, W>);
   hipFuncAttributes fa;
-  size_t fixed = lu_static_lds<T>();
+  size_t fixed = lu_static_lds<T, W>();
   if (hipFuncGetAttributes(&fa, f) == hipSuccess) fixed = std::max(fixed, fa.sharedSizeBytes);
   hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(bytes - fixed));
 }
 
 void lu_set_attrs(size_t bytes) {
-  lu_set_attr<double, LU_KKT>(bytes);
-  lu_set_attr<double, LU_DYN>(bytes);
-  lu_set_attr<double, LU_KKT_FALLBACK>(bytes);
-  lu_set_attr<float, LU_KKT>(bytes);
+  lu_set_attr<double, LU_KKT, 8>(bytes);
+  lu_set_attr<double, LU_DYN, 8>(bytes);
+  lu_set_attr<double, LU_KKT_FALLBACK, 8>(bytes);
+  lu_set_attr<float, LU_KKT, 8>(bytes);
+  lu_set_attr<double, LU_KKT, 4>(bytes);
+  lu_set_attr<double, LU_DYN, 4>(bytes);
+  lu_set_attr<double, LU_KKT_FALLBACK, 4>(bytes);
+  lu_set_attr<float, LU_KKT, 4>(bytes);
 }
 
 }  // namespace cs

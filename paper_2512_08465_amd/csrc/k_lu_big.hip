@@ -23,9 +23,6 @@
 #include "cs_internal.h"
 
 #include <climits>
-#include <map>
-#include <mutex>
-#include <tuple>
 
 namespace cs {
 
@@ -274,23 +271,6 @@ __global__ __launch_bounds__(BIG_T, 2) void k_lu_big(T* __restrict__ Abase, size
 }
 #undef AA
 
-// launch variant per (device, order, precision), set by the autotuner: the
-// panel width (16, 32, 64: plain right-looking), or width * 100 + group
-// (1664, 3264: panels of 16 or 32 columns in groups of 64)
-static std::mutex g_nb_m;
-static std::map<std::tuple<int, int, int>, int> g_nb;
-
-void lu_big_set_panel(int device, int n, bool f32, int nb) {
-  std::lock_guard<std::mutex> lk(g_nb_m);
-  g_nb[std::make_tuple(device, n, f32 ? 1 : 0)] = nb;
-}
-
-int lu_big_panel(int device, int n, bool f32) {
-  std::lock_guard<std::mutex> lk(g_nb_m);
-  auto it = g_nb.find(std::make_tuple(device, n, f32 ? 1 : 0));
-  return it == g_nb.end() ? 0 : it->second;
-}
-
 template <class T>
 void launch_lu_big_t(T* A, size_t stride, int n, int ncols, int lda, int* piv, int piv_stride,
                      SlotState* st, int want_phase, int want_job, int count, int* info,
@@ -299,7 +279,7 @@ void launch_lu_big_t(T* A, size_t stride, int n, int ncols, int lda, int* piv, i
   if (nb == 0) {
     int dev = 0;
     (void)hipGetDevice(&dev);
-    nb = lu_big_panel(dev, n, sizeof(T) == 4);
+    nb = lu_variant(dev, n, sizeof(T) == 4);
   }
   auto k = nb == 16     ? k_lu_big<T, 16, 16>
            : nb == 64   ? k_lu_big<T, 64, 64>

@@ -10,7 +10,12 @@ the autotuner that chooses among them (cs_autotune, opts.autotune).
 * Every launch variant of the large-order LU (panel widths 16, 32 and 64,
   and panels of 16 or 32 in groups of 64) gives factors and solutions equal
   to SciPy's (LAPACK's pivoting) at orders 1,100 and 1,338; the autotuner
-  returns the fastest of its own timings and leaves orders up to 1,024 alone.
+  returns the fastest of its own timings.
+* The register-resident LU at four and at eight wavefronts per matrix gives
+  the same bits (factors, pivots' effect, solutions) at orders that span one,
+  two and three panel rows per thread, and the same screening records, FP64
+  and mixed; the autotuner picks between the two up to order 768 and keeps
+  eight above.
 """
 import numpy as np
 import pytest
@@ -137,8 +142,6 @@ def test_autotune_picks_its_fastest(ctx):
     choice32, ms32 = ctx.autotune(1338, cs.PREC_MIXED, 256)
     print(f"order 1338 FP32: {ms32} ms; chose {choice32}")
     assert choice32 == cs.TUNE_VARIANTS[int(np.argmin(ms32))]
-    none, ms0 = ctx.autotune(580, cs.PREC_FP64, 256)
-    assert none == 0 and np.all(np.isnan(ms0))
     ctx.autotune_set(1338, cs.PREC_FP64, 0)
     ctx.autotune_set(1338, cs.PREC_MIXED, 0)
     with pytest.raises(cs.CSError) as e:
@@ -166,3 +169,82 @@ def test_autotuned_c4_records_match_oracle(ctx):
     net.close()
     ctx.autotune_set(1338, cs.PREC_FP64, 0)
     ctx.autotune_set(1338, cs.PREC_MIXED, 0)
+
+
+@pytest.mark.parametrize("n,k", [(1, 1), (33, 2), (200, 3), (344, 162), (513, 1), (580, 1),
+                                 (768, 2)])
+def test_wave_counts_give_the_same_bits(ctx, n, k):
+    """Four and eight wavefronts per matrix run the same operations on every
+    element: factors and solutions are equal bit for bit (and equal SciPy's
+    to rounding)."""
+    rng = np.random.default_rng(7 * n + k)
+    A = rng.standard_normal((3, n, n))
+    rhs = A @ rng.standard_normal((3, n, k))
+    out = {}
+    try:
+        for w in (8, 4):
+            ctx.autotune_set(n, 0, w)
+            out[w] = _run_lu(ctx, A, rhs)
+    finally:
+        ctx.autotune_set(n, 0, 0)
+    for a, b in zip(out[8], out[4]):
+        assert np.array_equal(a, b)
+    fac, sol, info = out[4]
+    assert np.all(info == 0)
+    for b in range(3):
+        lu, piv = sla.lu_factor(A[b])
+        assert np.allclose(fac[b], lu, rtol=1e-9, atol=1e-9 * np.abs(lu).max())
+
+
+def test_wave_counts_give_the_same_records(ctx):
+    """A slice of the 118-bus-shaped list screened with the KKT LU (order 580)
+    and the algebraic-system LU (order 344) at four and at eight wavefronts:
+    identical records and R_i, FP64 and mixed (FP32 factorisation and FP64
+    fallback)."""
+    import paper_2512_08465_amd as cs
+    case = load_case("c2_118")
+    net = cs.Network(ctx, case)
+    g = load_golden("c2_118")
+    lst = g["outages"][:96]
+    recs = {}
+    try:
+        for prec in (cs.PREC_FP64, cs.PREC_MIXED):
+            for w in (8, 4):
+                for order in (580, 344):
+                    ctx.autotune_set(order, cs.PREC_FP64, w)
+                    ctx.autotune_set(order, cs.PREC_MIXED, w)
+                recs[prec, w] = net.screen(lst, case["lam"], cs.default_options(prec=prec))
+    finally:
+        for order in (580, 344):
+            ctx.autotune_set(order, cs.PREC_FP64, 0)
+            ctx.autotune_set(order, cs.PREC_MIXED, 0)
+        net.close()
+    for prec in (cs.PREC_FP64, cs.PREC_MIXED):
+        (r8, R8), (r4, R4) = recs[prec, 8], recs[prec, 4]
+        assert r8.tobytes() == r4.tobytes()
+        assert np.array_equal(R8, R4)
+
+
+def test_autotune_register_resident_orders(ctx):
+    import paper_2512_08465_amd as cs
+    try:
+        for prec in (cs.PREC_FP64, cs.PREC_MIXED):
+            choice, ms = ctx.autotune(580, prec, 512)
+            print(f"order 580 prec {prec}: waves {cs.REG_TUNE_VARIANTS} take {ms[:2]} ms; "
+                  f"chose {choice}")
+            assert np.all(np.isfinite(ms[:2])) and np.all(ms[:2] > 0)
+            assert np.all(np.isnan(ms[2:]))
+            assert choice == cs.REG_TUNE_VARIANTS[int(np.argmin(ms[:2]))]
+        # above order 768 only eight wavefronts fit
+        choice, ms = ctx.autotune(900, cs.PREC_FP64, 64)
+        assert choice == 8 and np.isnan(ms[0]) and np.isfinite(ms[1])
+        with pytest.raises(cs.CSError) as e:
+            ctx.autotune_set(900, cs.PREC_FP64, 4)
+        assert e.value.code == cs.CS_EINVAL
+        with pytest.raises(cs.CSError) as e:
+            ctx.autotune_set(580, cs.PREC_FP64, 32)
+        assert e.value.code == cs.CS_EINVAL
+    finally:
+        for n in (580, 900):
+            ctx.autotune_set(n, cs.PREC_FP64, 0)
+            ctx.autotune_set(n, cs.PREC_MIXED, 0)
