@@ -499,9 +499,9 @@ def deviation(res, g):
 # same counter reads for the run's 1 GiB device copy, divided by the
 # factorisations those dispatches performed.  Valid only for the kernel source
 # it was measured on (hash below); otherwise traffic is null.
-LU_TRAFFIC = dict(source_sha256_16="6d7e8309d2fa6e75", factorisations=2217483,
-                  fetch_kib=27252471652.375, write_kib=24531202196.03125,
-                  copy_fetch_kib=524308.0625, copy_write_kib=1048576.0,
+LU_TRAFFIC = dict(source_sha256_16="d6de9049a6b4a955", factorisations=2217483,
+                  fetch_kib=33083204901.75, write_kib=25158311940.28125,
+                  copy_fetch_kib=524308.125, copy_write_kib=1048576.0,
                   copy_bytes=1 << 30)
 
 
