@@ -430,9 +430,10 @@ def leg_summary(leg, st, done, dt, steps, res, golden):
         "ms_per_step": round(1e3 * dt / steps, 3),
         "kkt_order": nk,
         "roofline": {
-            # four wavefronts per matrix by default in FP64 (orders up to 768), eight in FP32
-            "kernel": "k_lu_solve<%s, LU_KKT, %d> (KKT LU + solve)" % (
-                ("float", 8) if mixed else ("double", 4 if nk <= 768 else 8)),
+            # four wavefronts per matrix by default in FP64 (orders up to 768), eight
+            # in FP32 and for FP64 launches with at most one system per compute unit
+            "kernel": "k_lu_solve<%s, LU_KKT, %s> (KKT LU + solve)" % (
+                ("float", "8") if mixed else ("double", "4 or 8" if nk <= 768 else "8")),
             "bound": "mfma",
             "achieved": round(achieved, 4),
             "peak": peak,
@@ -493,15 +494,16 @@ def deviation(res, g):
 
 
 # HBM traffic of the FP64 KKT LU from two rocprofv3 counter passes over
-# `python bench.py --warmup 0 --no-cpu-baseline --serve-requests 0 --c3-slice 0
-# --c4-slice 0 --pmc-copy --legs fp64` (profiles/k_lu_solve_hbm_traffic_c2_118.md): FETCH_SIZE and
-# WRITE_SIZE summed over the run's KKT LU dispatches, each scaled by what the
-# same counter reads for the run's 1 GiB device copy, divided by the
+# `python bench.py --steps 20 --warmup 0 --legs fp64 --no-cpu-baseline
+# --serve-requests 0 --c3-slice 0 --c4-slice 0 --pmc-copy`
+# (profiles/k_lu_solve_hbm_traffic_c2_118.md): FETCH_SIZE and WRITE_SIZE summed
+# over the run's KKT LU dispatches (both launch geometries), each scaled by
+# what the same counter reads for the run's 1 GiB device copy, divided by the
 # factorisations those dispatches performed.  Valid only for the kernel source
 # it was measured on (hash below); otherwise traffic is null.
-LU_TRAFFIC = dict(source_sha256_16="d6de9049a6b4a955", factorisations=2217483,
-                  fetch_kib=33083204901.75, write_kib=25158311940.28125,
-                  copy_fetch_kib=524308.125, copy_write_kib=1048576.0,
+LU_TRAFFIC = dict(source_sha256_16="7ddd4a60bcbe1ff1", factorisations=2217483,
+                  fetch_kib=31730681076.5625, write_kib=25081074168.09375,
+                  copy_fetch_kib=524307.3125, copy_write_kib=1048576.0,
                   copy_bytes=1 << 30)
 
 

@@ -128,7 +128,12 @@ typedef struct {
                           stream and accumulate cs_stats when the call ends  */
   int32_t overlap;     /* 1: the dynamic stage (state matrix, eigenvalues,
                           records) runs on a second stream beside the OPF
-                          iterations of other slots; 0: one stream (default 0) */
+                          iterations of other slots, started as soon as the
+                          list's OPF tail is smaller than what waits; 2: the
+                          same, started at the end of a list only once the
+                          OPF tail holds at most two systems per compute
+                          unit; 0: one stream (default 0).  Other values:
+                          CS_EINVAL.  Records are identical either way.     */
   int32_t refine_steps; /* CS_PREC_MIXED: FP64 refinement steps a Newton solve
                           may take to reach the backward error of an FP64
                           solve before that system is factorised in FP64

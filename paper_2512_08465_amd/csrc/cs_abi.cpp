@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstring>
 #include <chrono>
+#include <climits>
 #include <condition_variable>
 #include <functional>
 #include <mutex>
@@ -89,6 +90,7 @@ struct cs_ctx {
   // kernel timing
   cs_stats stats{};
   size_t lds_max = 64 * 1024;   // dynamic LDS per workgroup this device allows
+  int n_cu = 0;                 // compute units of the device
   void* scratch = nullptr;      // this device's copy of the static scratch array
 };
 
@@ -225,6 +227,8 @@ int cs_ctx_create(int device, size_t hbm_budget, cs_ctx** out) {
   }
   // kernels whose LDS may exceed the default dynamic limit
   c->lds_max = set_kernel_attrs(device);
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    c->n_cu = 0;
   // the device address of the static scratch array on this device
   const hipError_t se = hipGetSymbolAddress(&c->scratch, HIP_SYMBOL(scratch));
   if (se != hipSuccess || c->scratch == nullptr) {
@@ -699,6 +703,10 @@ struct Engine {
                  [&] { launch_opf_eval(*D, s, nslots, opts.tol, opts.max_it, st); });
       if (rc != CS_OK) return rc;
       const int u = T ? T->unit_slot() : -1;
+      // at most this many slots have a system this step (the LU's launch
+      // geometry depends on it): those in the OPF loop at the last count and
+      // whatever the refill could have added since
+      const long long jobs = (long long)cnt[PH_IPM] + cnt[PH_NEW] + (assigned < N ? N - assigned : 0);
       if (opts.prec == CS_PREC_MIXED) {
         // (scenarios already on FP64 factorisations are switched to job 3 here)
         rc = timed(CS_K_KKT_REFINE, st, 0, -1, [&] { launch_kkt_to_f32(s, nslots, st); });
@@ -716,13 +724,14 @@ struct Engine {
         if (u3 >= 0) launch_count_jobs(s, nslots, 3, c->d_units + u3, st);
         rc = timed(CS_K_KKT_LU64, st, 0, u3, [&] {
           launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv, pstride, s.st, PH_IPM, 3,
-                          nslots, nullptr, st, LU_KKT_FALLBACK);
+                          nslots, nullptr, st, LU_KKT_FALLBACK,
+                          (int)std::min<long long>(jobs, INT_MAX));
         });
       } else {
         if (u >= 0) launch_count_jobs(s, nslots, 1, c->d_units + u, st);
         rc = timed(CS_K_KKT_LU, st, 0, u, [&] {
           launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv, pstride, s.st, PH_IPM, 1,
-                          nslots, nullptr, st);
+                          nslots, nullptr, st, LU_KKT, (int)std::min<long long>(jobs, INT_MAX));
         });
       }
       if (rc != CS_OK) return rc;
@@ -761,12 +770,16 @@ struct Engine {
     // While more scenarios wait, the dynamic stage takes the ready slots in
     // groups of dyn_min so that they can be refilled.  At the end of a list,
     // one stream waits for the last OPF to finish (one large eigenvalue
-    // launch); two streams, or a server, start as soon as the OPF tail is
-    // smaller than what waits.
+    // launch); two streams (overlap 1), or a server, start as soon as the OPF
+    // tail is smaller than what waits; overlap 2 starts once the OPF tail
+    // holds at most two systems per compute unit, so that the eigenvalue
+    // workgroups fill the CUs that the tail's factorisations leave idle
+    // without slowing the full-width launches before it.
     bool go = false;
     if (!dyn_busy && ready > 0) {
       if (ipm_left == 0) go = true;
-      else if (eager || (opts.overlap && assigned >= N)) go = ready >= dyn_min || ipm_left < ready;
+      else if (eager || (opts.overlap == 1 && assigned >= N)) go = ready >= dyn_min || ipm_left < ready;
+      else if (opts.overlap == 2 && assigned >= N) go = ipm_left <= 2 * std::max(c->n_cu, 1);
       else if (assigned < N) go = ready >= dyn_min;
     }
     if (go) {
@@ -778,7 +791,7 @@ struct Engine {
       if (rc != CS_OK) return rc;
       rc = timed(CS_K_DYN_LU, sd, ndyn, -1, [&] {
         launch_lu_solve(s.K, s.k_stride, s.ny, s.nyc, s.ldy, s.piv, pstride, s.st, PH_DYNB, 1,
-                        nslots, nullptr, sd, LU_DYN);
+                        nslots, nullptr, sd, LU_DYN, ndyn);
       });
       if (rc != CS_OK) return rc;
       rc = timed(CS_K_STATE_MATRIX, sd, ndyn, -1, [&] { launch_form_state(*D, s, nslots, sd); });
@@ -841,6 +854,8 @@ static int check_opts(const cs_opts& opts, const char* who) {
     return fail(CS_EINVAL, std::string(who) + ": graph must be in 0..64");
   if (opts.autotune != 0 && opts.autotune != 1)
     return fail(CS_EINVAL, std::string(who) + ": autotune must be 0 or 1");
+  if (opts.overlap < 0 || opts.overlap > 2)
+    return fail(CS_EINVAL, std::string(who) + ": overlap must be 0, 1 or 2");
   return CS_OK;
 }
 
@@ -1804,7 +1819,8 @@ extern "C" int cs_dense_solve_batched(const cs_ctx* c, double* d_A, int32_t n, i
   hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
   int* piv = nullptr;
   HIPCHK(hipMalloc(&piv, sizeof(int) * (size_t)n * batch));
-  launch_lu_solve(d_A, (size_t)lda * n, n, n + nrhs, lda, piv, n, nullptr, 0, 0, batch, d_info, st);
+  launch_lu_solve(d_A, (size_t)lda * n, n, n + nrhs, lda, piv, n, nullptr, 0, 0, batch, d_info, st,
+                  LU_KKT, batch);
   hipError_t e = hipGetLastError();
   hipError_t e2 = hipStreamSynchronize(st);
   hipFree(piv);

@@ -133,7 +133,8 @@ void launch_opf_update(const DevNet& net, const Slots& s, int count,
 enum LuRole : int { LU_KKT = 0, LU_DYN = 1, LU_KKT_FALLBACK = 2 };
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
                      int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
-                     int count, int* info, hipStream_t stream, int role = LU_KKT);
+                     int count, int* info, hipStream_t stream, int role = LU_KKT,
+                     int max_jobs = -1);
 // orders above the register-resident kernel's limit (k_lu_big.hip)
 // nb: launch variant, the panel width 16, 32 or 64, or 1664 / 3264 (panels of
 // 16 / 32 in groups of 64); 0 = the autotuner's choice for (current device,

@@ -959,17 +959,37 @@ int lu_variant(int device, int n, bool f32) {
   return it == g_var.end() ? 0 : it->second;
 }
 
+// compute units of a device (cached per device)
+static int device_cus(int dev) {
+  static std::mutex m;
+  static std::map<int, int> cus;
+  std::lock_guard<std::mutex> lk(m);
+  auto it = cus.find(dev);
+  if (it != cus.end()) return it->second;
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n = 0;
+  cus[dev] = n;
+  return n;
+}
+
 // wavefronts per matrix for order n: the variant table, else four in FP64
 // where the order allows (measured 4-5% faster on the order-580 KKT systems,
 // 7% on the order-344 algebraic ones) and eight in FP32 (where four, with its
-// four workgroups per CU, spilled and ran a third slower)
-static int lu_waves_for(int n, bool f32) {
+// four workgroups per CU, spilled and ran a third slower).  max_jobs, when
+// known (>= 0), bounds the matrices that have work in the launch: with at most
+// one per compute unit no second matrix shares a CU to overlap the panel's
+// latency, and eight wavefronts take one matrix 20-25% faster (measured at
+// orders 580 and 344 with 16 to 256 systems per launch; 4 is ahead from 320).
+// Both geometries give the same bits.
+static int lu_waves_for(int n, bool f32, int max_jobs = -1) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   const int v = lu_variant(dev, n, f32);
   if (v == 8 || n > LuGeo<4>::MAX_N) return 8;
   if (v == 4) return 4;
-  return f32 ? 8 : 4;
+  if (f32) return 8;
+  if (max_jobs >= 0 && max_jobs <= device_cus(dev)) return 8;
+  return 4;
 }
 
 // launch variant that lu_waves_for picks for order n
@@ -988,8 +1008,8 @@ static void lu_launch_w(T* A, size_t stride, int n, int ncols, int lda, int* piv
 template <class T, int ROLE>
 static void lu_launch(T* A, size_t stride, int n, int ncols, int lda, int* piv, int piv_stride,
                       SlotState* st, int want_phase, int want_job, int count, int* info,
-                      hipStream_t stream) {
-  if (lu_waves_for(n, sizeof(T) == 4) == 4)
+                      hipStream_t stream, int max_jobs = -1) {
+  if (lu_waves_for(n, sizeof(T) == 4, max_jobs) == 4)
     lu_launch_w<T, ROLE, 4>(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job,
                             count, info, stream);
   else
@@ -999,7 +1019,7 @@ static void lu_launch(T* A, size_t stride, int n, int ncols, int lda, int* piv, 
 
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
                      int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
-                     int count, int* info, hipStream_t stream, int role) {
+                     int count, int* info, hipStream_t stream, int role, int max_jobs) {
   if (count <= 0) return;
   if (n > LU_MAX_N) {
     launch_lu_big(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, count,
@@ -1008,13 +1028,13 @@ void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
   }
   if (role == LU_DYN)
     lu_launch<double, LU_DYN>(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase,
-                              want_job, count, info, stream);
+                              want_job, count, info, stream, max_jobs);
   else if (role == LU_KKT_FALLBACK)
     lu_launch<double, LU_KKT_FALLBACK>(A, stride, n, ncols, lda, piv, piv_stride, st,
-                                       want_phase, want_job, count, info, stream);
+                                       want_phase, want_job, count, info, stream, max_jobs);
   else
     lu_launch<double, LU_KKT>(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase,
-                              want_job, count, info, stream);
+                              want_job, count, info, stream, max_jobs);
 }
 
 void launch_lu_solve_f32(float* A, size_t stride, int n, int ncols, int lda,

@@ -119,7 +119,8 @@ def test_mixed_without_refinement_falls_back_to_fp64(ctx, c1):
 
 @pytest.mark.parametrize("field,value", [("prec", 7), ("max_it", 0), ("tol", 0.0),
                                          ("refine_steps", -1), ("refine_steps", 101),
-                                         ("graph", -1), ("graph", 65), ("autotune", 2)])
+                                         ("graph", -1), ("graph", 65), ("autotune", 2),
+                                         ("overlap", -1), ("overlap", 3)])
 def test_bad_options_rejected(c1, field, value):
     import paper_2512_08465_amd as cs
     with pytest.raises(cs.CSError) as e:

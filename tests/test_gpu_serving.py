@@ -125,9 +125,15 @@ def test_overlapped_streams_and_refill_equal(nets):
     a, Ra = net.screen(lst, case["lam"])
     b, Rb = net.screen(lst, case["lam"], cs.default_options(batch=48, overlap=1))
     c, Rc = net.screen(lst, case["lam"], cs.default_options(batch=100, overlap=0))
+    # the second stream started only in the OPF tail, all slots resident and refilled
+    d, Rd = net.screen(lst, case["lam"], cs.default_options(batch=300, overlap=2))
+    f, Rf = net.screen(lst, case["lam"], cs.default_options(batch=64, overlap=2))
     _same(a, b)
     _same(a, c)
+    _same(a, d)
+    _same(a, f)
     assert np.array_equal(Ra, Rb) and np.array_equal(Ra, Rc)
+    assert np.array_equal(Ra, Rd) and np.array_equal(Ra, Rf)
 
 
 def _scaled_case(case, scale):
@@ -257,6 +263,9 @@ def test_overlap_with_islanding_only_lists(nets):
     print(f"{len(lst)} islanding scenarios, batch 16, two streams", flush=True)
     ref, ref_r = net.screen(lst, case["lam"], cs.default_options(batch=16))
     got, got_r = net.screen(lst, case["lam"], cs.default_options(batch=16, overlap=1))
+    _same(got, ref)
+    assert np.array_equal(got_r, ref_r)
+    got, got_r = net.screen(lst, case["lam"], cs.default_options(batch=16, overlap=2))
     _same(got, ref)
     assert np.array_equal(got_r, ref_r)
     srv = cs.Server(net.ctx, net, cs.default_options(batch=16, overlap=1), queue_capacity=1024)
