@@ -220,8 +220,8 @@ int cs_ctx_create(int device, size_t hbm_budget, cs_ctx** out) {
       hipEventCreateWithFlags(&c->ev_dyn, hipEventDisableTiming) != hipSuccess ||
       hipMalloc(&c->d_counter, sizeof(int)) != hipSuccess ||
       hipHostMalloc(&c->h_counter, sizeof(int), hipHostMallocDefault) != hipSuccess ||
-      hipMalloc(&c->d_sched, sizeof(int) * (PH_COUNT + 2)) != hipSuccess ||
-      hipHostMalloc(&c->h_sched, sizeof(int) * (PH_COUNT + 2), hipHostMallocDefault) != hipSuccess) {
+      hipMalloc(&c->d_sched, sizeof(int) * (PH_COUNT + 3)) != hipSuccess ||
+      hipHostMalloc(&c->h_sched, sizeof(int) * (PH_COUNT + 3), hipHostMallocDefault) != hipSuccess) {
     cs_ctx_destroy(c);
     return fail(CS_EDEVICE, "cs_ctx_create: stream or counter allocation failed");
   }
@@ -478,7 +478,7 @@ static Plan plan_sizes(const cs_net* n, bool mixed) {
   p.per_slot = 8 * (s.k_stride + s.a_stride + s.nx + s.neq + 3 * (size_t)s.ni + 8 * (size_t)nl +
                     2 * (size_t)nb +
                     2 * (size_t)s.na) +
-               4 * ((size_t)nb + piv) + nb + nl + ng + sizeof(SlotState) + 16 * 64;
+               4 * ((size_t)nb + piv + 1) + nb + nl + ng + sizeof(SlotState) + 16 * 64;
   if (mixed) {
     s.ld32 = (int)round_up(s.nk + 1, 4);
     s.k32_stride = round_up((size_t)s.nk * s.ld32, 64);
@@ -522,6 +522,7 @@ static int bind_workspace(void** ws, size_t* ws_bytes, const cs_net* n, Plan& p,
   const size_t obr = take(nl * B + 64);
   const size_t ogen = take(ng * B + 64);
   const size_t ost = take(sizeof(SlotState) * (size_t)B);
+  const size_t ojob = take(4 * ((size_t)B + 2));
   const size_t o32 = take(4 * s.k32_stride * B);
   const size_t need = off;
   char* base = nullptr;
@@ -560,6 +561,7 @@ static int bind_workspace(void** ws, size_t* ws_bytes, const cs_net* n, Plan& p,
   s.br_on = reinterpret_cast<uint8_t*>(base + obr);
   s.gen_on = reinterpret_cast<uint8_t*>(base + ogen);
   s.st = reinterpret_cast<SlotState*>(base + ost);
+  s.jobs = reinterpret_cast<int*>(base + ojob);
   s.K32 = s.k32_stride ? reinterpret_cast<float*>(base + o32) : nullptr;
   return CS_OK;
 }
@@ -583,7 +585,7 @@ struct Engine {
   hipEvent_t ev_ipm = nullptr, ev_dyn = nullptr;
   unsigned long long* d_next = nullptr;
   int* d_counts = nullptr;       // [PH_COUNT]
-  int* h_counts = nullptr;       // pinned [PH_COUNT]
+  int* h_counts = nullptr;       // pinned [PH_COUNT + 1]: stage counts, job-list overflow flag
   unsigned long long* h_next = nullptr;   // pinned
   const int* d_list = nullptr;   // outage pairs
   cs_result* d_res = nullptr;
@@ -654,6 +656,7 @@ struct Engine {
 
   int start() {
     HIPCHK(hipMemsetAsync(s.st, 0, sizeof(SlotState) * (size_t)nslots, st));
+    HIPCHK(hipMemsetAsync(s.jobs, 0, 2 * sizeof(int), st));
     HIPCHK(hipMemsetAsync(d_next, 0, sizeof(unsigned long long), st));
     HIPCHK(hipEventRecord(ev_ipm, st));
     HIPCHK(hipStreamWaitEvent(sd, ev_ipm, 0));
@@ -707,14 +710,19 @@ struct Engine {
       // geometry depends on it): those in the OPF loop at the last count and
       // whatever the refill could have added since
       const long long jobs = (long long)cnt[PH_IPM] + cnt[PH_NEW] + (assigned < N ? N - assigned : 0);
+      const int max_jobs = (int)std::min<long long>(jobs, INT_MAX);
+      // the factorisations launch one workgroup per listed slot, those with
+      // work first (at most `grid` of them, checked on the device)
+      const JobList jl{s.jobs, (int)std::min<long long>(jobs, nslots)};
       if (opts.prec == CS_PREC_MIXED) {
         // (scenarios already on FP64 factorisations are switched to job 3 here)
         rc = timed(CS_K_KKT_REFINE, st, 0, -1, [&] { launch_kkt_to_f32(s, nslots, st); });
         if (rc != CS_OK) return rc;
         if (u >= 0) launch_count_jobs(s, nslots, 1, c->d_units + u, st);
+        launch_job_list(s, nslots, PH_IPM, 1, jl.grid, st);
         rc = timed(CS_K_KKT_LU, st, 0, u, [&] {
           launch_lu_solve_f32(s.K32, s.k32_stride, s.nk, s.nk + 1, s.ld32, s.piv, pstride, s.st,
-                              PH_IPM, 1, nslots, nullptr, st);
+                              PH_IPM, 1, nslots, nullptr, st, jl);
         });
         if (rc != CS_OK) return rc;
         rc = timed(CS_K_KKT_REFINE, st, 0, -1,
@@ -722,16 +730,17 @@ struct Engine {
         if (rc != CS_OK) return rc;
         const int u3 = T ? T->unit_slot() : -1;
         if (u3 >= 0) launch_count_jobs(s, nslots, 3, c->d_units + u3, st);
+        launch_job_list(s, nslots, PH_IPM, 3, jl.grid, st);
         rc = timed(CS_K_KKT_LU64, st, 0, u3, [&] {
           launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv, pstride, s.st, PH_IPM, 3,
-                          nslots, nullptr, st, LU_KKT_FALLBACK,
-                          (int)std::min<long long>(jobs, INT_MAX));
+                          nslots, nullptr, st, LU_KKT_FALLBACK, max_jobs, jl);
         });
       } else {
         if (u >= 0) launch_count_jobs(s, nslots, 1, c->d_units + u, st);
+        launch_job_list(s, nslots, PH_IPM, 1, jl.grid, st);
         rc = timed(CS_K_KKT_LU, st, 0, u, [&] {
           launch_lu_solve(s.K, s.k_stride, s.nk, s.nk + 1, s.ldk, s.piv, pstride, s.st, PH_IPM, 1,
-                          nslots, nullptr, st, LU_KKT, (int)std::min<long long>(jobs, INT_MAX));
+                          nslots, nullptr, st, LU_KKT, max_jobs, jl);
         });
       }
       if (rc != CS_OK) return rc;
@@ -751,6 +760,7 @@ struct Engine {
     launch_phase_counts(s, nslots, d_counts, st);
     HIPCHK(hipMemcpyAsync(h_counts, d_counts, sizeof(int) * PH_COUNT, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(h_next, d_next, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_counts + PH_COUNT, s.jobs + 1, sizeof(int), hipMemcpyDeviceToHost, st));
     return CS_OK;
   }
 
@@ -763,6 +773,8 @@ struct Engine {
     int rc;
     HIPCHK(hipStreamSynchronize(st));
     for (int k = 0; k < PH_COUNT; ++k) cnt[k] = h_counts[k];
+    if (h_counts[PH_COUNT] != 0)
+      return fail(CS_EDEVICE, "internal: a factorisation launch had fewer workgroups than systems");
     if (dyn_finished) dyn_busy = false;
     assigned = std::min<long long>((long long)*h_next, N);
     const int ready = cnt[PH_DYN] + cnt[PH_DONE];
@@ -1475,8 +1487,8 @@ static int lane_create(cs_server* S, cs_net* n, size_t bytes, int index, ServerL
       hipMalloc(&L->q_res, sizeof(cs_result) * qc) != hipSuccess ||
       hipMalloc(&L->item_req, sizeof(int) * qc) != hipSuccess ||
       hipMalloc(&L->req_scale, sizeof(double) * (size_t)cs_server::R * std::max(n->nd, 1)) != hipSuccess ||
-      hipMalloc(&L->d_sched, sizeof(int) * (PH_COUNT + 2)) != hipSuccess ||
-      hipHostMalloc(&L->h_sched, sizeof(int) * (PH_COUNT + 2), hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&L->d_sched, sizeof(int) * (PH_COUNT + 3)) != hipSuccess ||
+      hipHostMalloc(&L->h_sched, sizeof(int) * (PH_COUNT + 3), hipHostMallocDefault) != hipSuccess ||
       hipMalloc(&L->g_out, sizeof(int) * 2 * qc) != hipSuccess ||
       hipMalloc(&L->g_res, sizeof(cs_result) * qc) != hipSuccess ||
       hipMalloc(&L->g_lam, sizeof(double) * std::max(n_comp, 1)) != hipSuccess ||

@@ -103,6 +103,7 @@ struct Slots {
   double* A;                    // [B][a_stride]
   double* wr; double* wi;       // [B][na]
   SlotState* st;
+  int* jobs;                    // [B + 2] job list of one launch (JobList)
 };
 
 // Per-scenario detail written by k_classify when requested (parity checks):
@@ -131,10 +132,18 @@ void launch_opf_update(const DevNet& net, const Slots& s, int count,
 // batched LU + solve; with slot states, only slots with st.job == want_job
 // in phase want_phase.  role (LuRole) picks the kernel symbol only.
 enum LuRole : int { LU_KKT = 0, LU_DYN = 1, LU_KKT_FALLBACK = 2 };
+// A device list of the slots that have work in a launch (written by
+// launch_job_list: [0] their number, [1] set when that number exceeded
+// grid, [2..] slot ids in ascending order) and the launch's workgroups, an
+// upper bound on that number.  list == nullptr: one workgroup per slot.
+struct JobList {
+  const int* list = nullptr;
+  int grid = 0;
+};
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
                      int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
                      int count, int* info, hipStream_t stream, int role = LU_KKT,
-                     int max_jobs = -1);
+                     int max_jobs = -1, const JobList& jl = JobList{});
 // orders above the register-resident kernel's limit (k_lu_big.hip)
 // nb: launch variant, the panel width 16, 32 or 64, or 1664 / 3264 (panels of
 // 16 / 32 in groups of 64); 0 = the autotuner's choice for (current device,
@@ -154,7 +163,8 @@ void launch_tune_fill(void* A, bool f32, size_t stride, int n, int ncols, int ld
                       unsigned seed, hipStream_t stream);
 void launch_lu_solve_f32(float* A, size_t stride, int n, int ncols, int lda,
                          int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
-                         int count, int* info, hipStream_t stream);
+                         int count, int* info, hipStream_t stream,
+                         const JobList& jl = JobList{});
 void launch_dyn_assemble(const DevNet& net, const Slots& s, int count, hipStream_t st);
 void launch_form_state(const DevNet& net, const Slots& s, int count, hipStream_t st);
 // scr: scratch of eig_scratch_doubles(order) doubles per matrix, scr_stride
@@ -218,5 +228,9 @@ void launch_gather_request(const int* q_out, const void* q_res, long long q0, in
                            long long q_cap, int* out, void* res, hipStream_t st);
 void launch_fill_req(int* item_req, long long q0, int n, long long q_cap, int r, hipStream_t st);
 void launch_count_jobs(const Slots& s, int count, int want, int* out, hipStream_t st);
+// s.jobs = the slots among the first count with st.phase == want_phase and
+// st.job == want_job, for a launch of grid workgroups
+void launch_job_list(const Slots& s, int count, int want_phase, int want_job, int grid,
+                     hipStream_t st);
 
 }  // namespace cs

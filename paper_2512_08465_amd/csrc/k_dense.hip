@@ -817,8 +817,15 @@ template <class T, int ROLE, int W>
 __global__ __launch_bounds__(64 * W, LuWavesPerEu<T>::value) void k_lu_solve(
     T* __restrict__ Abase, size_t stride, int n, int ncols, int lda,
     int* __restrict__ pivbase, int piv_stride, SlotState* __restrict__ st,
-    int want_phase, int want_job, int* __restrict__ info) {
-  const int slot = blockIdx.x;
+    int want_phase, int want_job, int* __restrict__ info, const int* __restrict__ list) {
+  // one slot per workgroup: the workgroup's own index, or with a job list
+  // (list[0] slots, ids from list[2]) the list's entry, so that the
+  // workgroups with work are the first ones dispatched
+  int slot = blockIdx.x;
+  if (list != nullptr) {
+    if ((int)blockIdx.x >= list[0]) return;
+    slot = list[2 + blockIdx.x];
+  }
   // with slot states: only the slots of one stage that asked for this solve
   if (st != nullptr && (st[slot].job != want_job || st[slot].phase != want_phase)) return;
   T* __restrict__ A = Abase + (size_t)slot * stride;
@@ -995,31 +1002,36 @@ static int lu_waves_for(int n, bool f32, int max_jobs = -1) {
 // launch variant that lu_waves_for picks for order n
 int lu_reg_waves(int n, bool f32) { return lu_waves_for(n, f32); }
 
+// grid workgroups: count (one per slot), or with a job list (JobList) the
+// list's bound on the slots that have work
 template <class T, int ROLE, int W>
 static void lu_launch_w(T* A, size_t stride, int n, int ncols, int lda, int* piv,
                         int piv_stride, SlotState* st, int want_phase, int want_job, int count,
-                        int* info, hipStream_t stream) {
+                        int* info, hipStream_t stream, const JobList& jl) {
   const size_t lds = lu_dynamic_lds<T, W>(n, ncols - n);
-  hipLaunchKernelGGL((k_lu_solve<T, ROLE, W>), dim3(count), dim3(LuGeo<W>::THREADS), lds,
+  const int grid = jl.list ? std::min(count, jl.grid) : count;
+  if (grid <= 0) return;
+  hipLaunchKernelGGL((k_lu_solve<T, ROLE, W>), dim3(grid), dim3(LuGeo<W>::THREADS), lds,
                      stream, A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job,
-                     info);
+                     info, jl.list);
 }
 
 template <class T, int ROLE>
 static void lu_launch(T* A, size_t stride, int n, int ncols, int lda, int* piv, int piv_stride,
                       SlotState* st, int want_phase, int want_job, int count, int* info,
-                      hipStream_t stream, int max_jobs = -1) {
+                      hipStream_t stream, int max_jobs = -1, const JobList& jl = JobList{}) {
   if (lu_waves_for(n, sizeof(T) == 4, max_jobs) == 4)
     lu_launch_w<T, ROLE, 4>(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job,
-                            count, info, stream);
+                            count, info, stream, jl);
   else
     lu_launch_w<T, ROLE, 8>(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job,
-                            count, info, stream);
+                            count, info, stream, jl);
 }
 
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
                      int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
-                     int count, int* info, hipStream_t stream, int role, int max_jobs) {
+                     int count, int* info, hipStream_t stream, int role, int max_jobs,
+                     const JobList& jl) {
   if (count <= 0) return;
   if (n > LU_MAX_N) {
     launch_lu_big(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, count,
@@ -1028,18 +1040,18 @@ void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
   }
   if (role == LU_DYN)
     lu_launch<double, LU_DYN>(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase,
-                              want_job, count, info, stream, max_jobs);
+                              want_job, count, info, stream, max_jobs, jl);
   else if (role == LU_KKT_FALLBACK)
     lu_launch<double, LU_KKT_FALLBACK>(A, stride, n, ncols, lda, piv, piv_stride, st,
-                                       want_phase, want_job, count, info, stream, max_jobs);
+                                       want_phase, want_job, count, info, stream, max_jobs, jl);
   else
     lu_launch<double, LU_KKT>(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase,
-                              want_job, count, info, stream, max_jobs);
+                              want_job, count, info, stream, max_jobs, jl);
 }
 
 void launch_lu_solve_f32(float* A, size_t stride, int n, int ncols, int lda,
                          int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
-                         int count, int* info, hipStream_t stream) {
+                         int count, int* info, hipStream_t stream, const JobList& jl) {
   if (count <= 0) return;
   if (n > LU_MAX_N) {
     launch_lu_big_f32(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job, count,
@@ -1047,7 +1059,7 @@ void launch_lu_solve_f32(float* A, size_t stride, int n, int ncols, int lda,
     return;
   }
   lu_launch<float, LU_KKT>(A, stride, n, ncols, lda, piv, piv_stride, st, want_phase, want_job,
-                           count, info, stream);
+                           count, info, stream, -1, jl);
 }
 
 // the dynamic LDS limit of a kernel: what is left of `bytes` beside its

@@ -233,6 +233,46 @@ __global__ void k_count_jobs(const SlotState* __restrict__ st, int count, int wa
   if (threadIdx.x == 0) *out = acc;
 }
 
+// The slots of one stage with a given job, in ascending order (one
+// workgroup of 1,024 threads, each scanning a contiguous range of slots):
+// list[0] = their number m, list[2 + i] = the i-th; list[1] is set when m
+// exceeds grid, the workgroups of the launch that reads the list (sticky
+// until the caller clears it).
+__global__ __launch_bounds__(1024) void k_job_list(const SlotState* __restrict__ st, int count,
+                                                   int want_phase, int want_job, int grid,
+                                                   int* __restrict__ list) {
+  __shared__ int wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (count + 1023) / 1024;
+  const int b0 = min(count, tid * per), b1 = min(count, b0 + per);
+  int c = 0;
+  for (int i = b0; i < b1; ++i) c += (st[i].job == want_job && st[i].phase == want_phase);
+  // inclusive scan of the counts over the wavefront, then over wavefronts
+  int incl = c;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int base = 0;
+  for (int w = 0; w < wave; ++w) base += wsum[w];
+  int pos = base + incl - c;
+  for (int i = b0; i < b1; ++i)
+    if (st[i].job == want_job && st[i].phase == want_phase) list[2 + pos++] = i;
+  if (tid == 1023) {
+    const int m = base + incl;
+    list[0] = m;
+    if (m > grid) list[1] = 1;
+  }
+}
+
+void launch_job_list(const Slots& s, int count, int want_phase, int want_job, int grid,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_job_list, dim3(1), dim3(1024), 0, st, s.st, count, want_phase, want_job,
+                     grid, s.jobs);
+}
+
 void launch_refill(const Slots& s, int count, unsigned long long* next, long long n_scen,
                    long long q_cap, hipStream_t st) {
   if (count <= 0) return;
