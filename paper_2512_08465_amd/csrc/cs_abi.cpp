@@ -702,21 +702,23 @@ struct Engine {
     if ((work || cnt[PH_IPM] > 0) && opts.graph > 0 && !T) {
       if ((rc = newton_graph()) != CS_OK) return rc;
     } else if (work || cnt[PH_IPM] > 0) {
-      rc = timed(CS_K_KKT_ASSEMBLE, st, cnt[PH_IPM], -1,
-                 [&] { launch_opf_eval(*D, s, nslots, opts.tol, opts.max_it, st); });
-      if (rc != CS_OK) return rc;
-      const int u = T ? T->unit_slot() : -1;
-      // at most this many slots have a system this step (the LU's launch
-      // geometry depends on it): those in the OPF loop at the last count and
-      // whatever the refill could have added since
+      // At most this many slots are in the OPF loop this step (the LU's
+      // launch geometry depends on it): those at the last count and whatever
+      // the refill could have added since.  Each per-slot launch of the step
+      // runs one workgroup per listed slot, those with work first (at most
+      // `grid` of them, checked on the device).
       const long long jobs = (long long)cnt[PH_IPM] + cnt[PH_NEW] + (assigned < N ? N - assigned : 0);
       const int max_jobs = (int)std::min<long long>(jobs, INT_MAX);
-      // the factorisations launch one workgroup per listed slot, those with
-      // work first (at most `grid` of them, checked on the device)
       const JobList jl{s.jobs, (int)std::min<long long>(jobs, nslots)};
+      launch_job_list(s, nslots, PH_IPM, JOB_ANY, jl.grid, st);
+      rc = timed(CS_K_KKT_ASSEMBLE, st, cnt[PH_IPM], -1,
+                 [&] { launch_opf_eval(*D, s, nslots, opts.tol, opts.max_it, st, jl); });
+      if (rc != CS_OK) return rc;
+      const int u = T ? T->unit_slot() : -1;
       if (opts.prec == CS_PREC_MIXED) {
         // (scenarios already on FP64 factorisations are switched to job 3 here)
-        rc = timed(CS_K_KKT_REFINE, st, 0, -1, [&] { launch_kkt_to_f32(s, nslots, st); });
+        launch_job_list(s, nslots, PH_IPM, 1, jl.grid, st);
+        rc = timed(CS_K_KKT_REFINE, st, 0, -1, [&] { launch_kkt_to_f32(s, nslots, st, jl); });
         if (rc != CS_OK) return rc;
         if (u >= 0) launch_count_jobs(s, nslots, 1, c->d_units + u, st);
         launch_job_list(s, nslots, PH_IPM, 1, jl.grid, st);
@@ -725,8 +727,9 @@ struct Engine {
                               PH_IPM, 1, nslots, nullptr, st, jl);
         });
         if (rc != CS_OK) return rc;
+        // (the same slots: the factorisation changes no job)
         rc = timed(CS_K_KKT_REFINE, st, 0, -1,
-                   [&] { launch_kkt_refine(s, nslots, pstride, opts.refine_steps, st); });
+                   [&] { launch_kkt_refine(s, nslots, pstride, opts.refine_steps, st, jl); });
         if (rc != CS_OK) return rc;
         const int u3 = T ? T->unit_slot() : -1;
         if (u3 >= 0) launch_count_jobs(s, nslots, 3, c->d_units + u3, st);
@@ -744,8 +747,9 @@ struct Engine {
         });
       }
       if (rc != CS_OK) return rc;
+      launch_job_list(s, nslots, PH_IPM, JOB_NONZERO, jl.grid, st);
       rc = timed(CS_K_IPM_UPDATE, st, cnt[PH_IPM], -1,
-                 [&] { launch_opf_update(*D, s, nslots, 1e10, st); });
+                 [&] { launch_opf_update(*D, s, nslots, 1e10, st, jl); });
       if (rc != CS_OK) return rc;
     }
     // Ask whether the dynamic stage has finished before the slot counts are

@@ -106,6 +106,28 @@ struct Slots {
   int* jobs;                    // [B + 2] job list of one launch (JobList)
 };
 
+// A device list of the slots that have work in a launch (written by
+// launch_job_list: [0] their number, [1] set when that number exceeded
+// grid, [2..] slot ids in ascending order) and the launch's workgroups, an
+// upper bound on that number.  list == nullptr: one workgroup per slot.
+// Listing the slots puts the workgroups with work first: the hardware
+// dispatches workgroups in index order, and an idle slot's workgroup that
+// waits for a free CU would hold back the busy ones behind it.
+struct JobList {
+  const int* list = nullptr;
+  int grid = 0;
+};
+// workgroups of a per-slot launch over count slots
+inline int job_grid(int count, const JobList& jl) {
+  return jl.list ? (count < jl.grid ? count : jl.grid) : count;
+}
+// the slot of this workgroup, or -1 when it has none
+__device__ inline int list_slot(const int* __restrict__ list, int count) {
+  const int b = (int)blockIdx.x;
+  if (list == nullptr) return b < count ? b : -1;
+  return b < list[0] ? list[2 + b] : -1;
+}
+
 // Per-scenario detail written by k_classify when requested (parity checks):
 // the operating point over the whole network (NaN outside the solved island or
 // when the OPF did not run) and the spectrum (NaN-padded to na).
@@ -126,20 +148,13 @@ void launch_setup_k(const DevNet& net, const Slots& s, int count, const int* out
                     hipStream_t st, int width = 2, const double* load_scale = nullptr,
                     const int* item_req = nullptr);
 void launch_opf_eval(const DevNet& net, const Slots& s, int count, double tol,
-                     int max_it, hipStream_t st);
+                     int max_it, hipStream_t st, const JobList& jl = JobList{});
 void launch_opf_update(const DevNet& net, const Slots& s, int count,
-                       double gamma_max, hipStream_t st);
+                       double gamma_max, hipStream_t st, const JobList& jl = JobList{});
 // batched LU + solve; with slot states, only slots with st.job == want_job
 // in phase want_phase.  role (LuRole) picks the kernel symbol only.
 enum LuRole : int { LU_KKT = 0, LU_DYN = 1, LU_KKT_FALLBACK = 2 };
-// A device list of the slots that have work in a launch (written by
-// launch_job_list: [0] their number, [1] set when that number exceeded
-// grid, [2..] slot ids in ascending order) and the launch's workgroups, an
-// upper bound on that number.  list == nullptr: one workgroup per slot.
-struct JobList {
-  const int* list = nullptr;
-  int grid = 0;
-};
+
 void launch_lu_solve(double* A, size_t stride, int n, int ncols, int lda,
                      int* piv, int piv_stride, SlotState* st, int want_phase, int want_job,
                      int count, int* info, hipStream_t stream, int role = LU_KKT,
@@ -214,8 +229,10 @@ void launch_merge_n3(const uint8_t* keep, long long n3, const void* kept_rec, co
                      long long k, void* out, hipStream_t st);
 
 // mixed-precision KKT solve
-void launch_kkt_to_f32(const Slots& s, int count, hipStream_t st);
-void launch_kkt_refine(const Slots& s, int count, int pstride, int max_it, hipStream_t st);
+void launch_kkt_to_f32(const Slots& s, int count, hipStream_t st,
+                       const JobList& jl = JobList{});
+void launch_kkt_refine(const Slots& s, int count, int pstride, int max_it, hipStream_t st,
+                       const JobList& jl = JobList{});
 size_t kkt_refine_lds(int nk);
 
 // slot scheduling
@@ -229,7 +246,9 @@ void launch_gather_request(const int* q_out, const void* q_res, long long q0, in
 void launch_fill_req(int* item_req, long long q0, int n, long long q_cap, int r, hipStream_t st);
 void launch_count_jobs(const Slots& s, int count, int want, int* out, hipStream_t st);
 // s.jobs = the slots among the first count with st.phase == want_phase and
-// st.job == want_job, for a launch of grid workgroups
+// st.job == want_job (JOB_ANY: any job; JOB_NONZERO: job != 0), for a launch
+// of grid workgroups
+constexpr int JOB_ANY = -1, JOB_NONZERO = -2;
 void launch_job_list(const Slots& s, int count, int want_phase, int want_job, int grid,
                      hipStream_t st);
 

@@ -233,6 +233,11 @@ __global__ void k_count_jobs(const SlotState* __restrict__ st, int count, int wa
   if (threadIdx.x == 0) *out = acc;
 }
 
+__device__ inline bool job_matches(const SlotState& S, int want_phase, int want_job) {
+  if (S.phase != want_phase) return false;
+  return want_job == JOB_ANY || (want_job == JOB_NONZERO ? S.job != 0 : S.job == want_job);
+}
+
 // The slots of one stage with a given job, in ascending order (one
 // workgroup of 1,024 threads, each scanning a contiguous range of slots):
 // list[0] = their number m, list[2 + i] = the i-th; list[1] is set when m
@@ -246,7 +251,7 @@ __global__ __launch_bounds__(1024) void k_job_list(const SlotState* __restrict__
   const int per = (count + 1023) / 1024;
   const int b0 = min(count, tid * per), b1 = min(count, b0 + per);
   int c = 0;
-  for (int i = b0; i < b1; ++i) c += (st[i].job == want_job && st[i].phase == want_phase);
+  for (int i = b0; i < b1; ++i) c += job_matches(st[i], want_phase, want_job);
   // inclusive scan of the counts over the wavefront, then over wavefronts
   int incl = c;
   for (int off = 1; off < 64; off <<= 1) {
@@ -259,7 +264,7 @@ __global__ __launch_bounds__(1024) void k_job_list(const SlotState* __restrict__
   for (int w = 0; w < wave; ++w) base += wsum[w];
   int pos = base + incl - c;
   for (int i = b0; i < b1; ++i)
-    if (st[i].job == want_job && st[i].phase == want_phase) list[2 + pos++] = i;
+    if (job_matches(st[i], want_phase, want_job)) list[2 + pos++] = i;
   if (tid == 1023) {
     const int m = base + incl;
     list[0] = m;

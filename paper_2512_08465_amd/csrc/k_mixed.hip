@@ -25,9 +25,10 @@ namespace cs {
 constexpr int MX_THREADS = 512;
 constexpr int MX_WAVES = MX_THREADS / 64;
 
-__global__ __launch_bounds__(256) void k_kkt_to_f32(Slots s, int count) {
-  const int slot = blockIdx.x;
-  if (slot >= count) return;
+__global__ __launch_bounds__(256) void k_kkt_to_f32(Slots s, int count,
+                                                    const int* __restrict__ list) {
+  const int slot = list_slot(list, count);
+  if (slot < 0) return;
   SlotState& S = s.st[slot];
   if (S.phase != PH_IPM || S.job != 1) return;
   // the KKT system only gets worse conditioned as the barrier falls: once a
@@ -168,9 +169,10 @@ __device__ double block_max(double v, double* red) {
 }
 
 __global__ __launch_bounds__(MX_THREADS) void k_kkt_refine(Slots s, int count, int pstride,
-                                                          int max_it) {
-  const int slot = blockIdx.x;
-  if (slot >= count) return;
+                                                          int max_it,
+                                                          const int* __restrict__ list) {
+  const int slot = list_slot(list, count);
+  if (slot < 0) return;
   SlotState& S = s.st[slot];
   if (S.phase != PH_IPM || S.job != 1) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -245,19 +247,22 @@ __global__ __launch_bounds__(MX_THREADS) void k_kkt_refine(Slots s, int count, i
   }
 }
 
-void launch_kkt_to_f32(const Slots& s, int count, hipStream_t st) {
-  if (count <= 0) return;
-  hipLaunchKernelGGL(k_kkt_to_f32, dim3(count), dim3(256), 0, st, s, count);
+void launch_kkt_to_f32(const Slots& s, int count, hipStream_t st, const JobList& jl) {
+  const int grid = job_grid(count, jl);
+  if (grid <= 0) return;
+  hipLaunchKernelGGL(k_kkt_to_f32, dim3(grid), dim3(256), 0, st, s, count, jl.list);
 }
 
 size_t kkt_refine_lds(int nk) {
   return (sizeof(double) * 2 + sizeof(float) + sizeof(int)) * (size_t)nk + 16;
 }
 
-void launch_kkt_refine(const Slots& s, int count, int pstride, int max_it, hipStream_t st) {
-  if (count <= 0) return;
-  hipLaunchKernelGGL(k_kkt_refine, dim3(count), dim3(MX_THREADS), kkt_refine_lds(s.nk), st, s,
-                     count, pstride, max_it);
+void launch_kkt_refine(const Slots& s, int count, int pstride, int max_it, hipStream_t st,
+                       const JobList& jl) {
+  const int grid = job_grid(count, jl);
+  if (grid <= 0) return;
+  hipLaunchKernelGGL(k_kkt_refine, dim3(grid), dim3(MX_THREADS), kkt_refine_lds(s.nk), st, s,
+                     count, pstride, max_it, jl.list);
 }
 
 }  // namespace cs

@@ -250,9 +250,9 @@ __global__ __launch_bounds__(OPF_THREADS) void k_setup(DevNet net, Slots s,
 // ------------------------------------------------------- evaluate + assemble
 __global__ __launch_bounds__(OPF_THREADS) void k_opf_eval(DevNet net, Slots s,
                                                           int count, double tol,
-                                                          int max_it) {
-  const int slot = blockIdx.x;
-  if (slot >= count) return;
+                                                          int max_it, const int* __restrict__ list) {
+  const int slot = list_slot(list, count);
+  if (slot < 0) return;
   SlotState& S = s.st[slot];
   if (S.phase != PH_IPM) return;
   const int nb = net.nb, nl = net.nl, ng = net.ng;
@@ -591,9 +591,10 @@ __global__ __launch_bounds__(OPF_THREADS) void k_opf_eval(DevNet net, Slots s,
 // ------------------------------------------------------------------ update
 __global__ __launch_bounds__(OPF_THREADS) void k_opf_update(DevNet net, Slots s,
                                                             int count,
-                                                            double gamma_max) {
-  const int slot = blockIdx.x;
-  if (slot >= count) return;
+                                                            double gamma_max,
+                                                            const int* __restrict__ list) {
+  const int slot = list_slot(list, count);
+  if (slot < 0) return;
   SlotState& S = s.st[slot];
   if (S.phase != PH_IPM || S.job == 0) return;
   const int nb = net.nb, nl = net.nl, ng = net.ng;
@@ -729,18 +730,21 @@ void launch_setup_k(const DevNet& net, const Slots& s, int count,
 }
 
 void launch_opf_eval(const DevNet& net, const Slots& s, int count, double tol,
-                     int max_it, hipStream_t st) {
-  if (count <= 0) return;
-  hipLaunchKernelGGL(k_opf_eval, dim3(count), dim3(OPF_THREADS),
+                     int max_it, hipStream_t st, const JobList& jl) {
+  const int grid = job_grid(count, jl);
+  if (grid <= 0) return;
+  hipLaunchKernelGGL(k_opf_eval, dim3(grid), dim3(OPF_THREADS),
                      opf_eval_lds(net.nb, net.nl, net.ng), st, net, s, count,
-                     tol, max_it);
+                     tol, max_it, jl.list);
 }
 
 void launch_opf_update(const DevNet& net, const Slots& s, int count,
-                       double gamma_max, hipStream_t st) {
-  if (count <= 0) return;
-  hipLaunchKernelGGL(k_opf_update, dim3(count), dim3(OPF_THREADS),
-                     sizeof(double) * (size_t)(s.ni + s.nk), st, net, s, count, gamma_max);
+                       double gamma_max, hipStream_t st, const JobList& jl) {
+  const int grid = job_grid(count, jl);
+  if (grid <= 0) return;
+  hipLaunchKernelGGL(k_opf_update, dim3(grid), dim3(OPF_THREADS),
+                     sizeof(double) * (size_t)(s.ni + s.nk), st, net, s, count, gamma_max,
+                     jl.list);
 }
 
 }  // namespace cs
