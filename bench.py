@@ -501,9 +501,9 @@ def deviation(res, g):
 # what the same counter reads for the run's 1 GiB device copy, divided by the
 # factorisations those dispatches performed.  Valid only for the kernel source
 # it was measured on (hash below); otherwise traffic is null.
-LU_TRAFFIC = dict(source_sha256_16="7ddd4a60bcbe1ff1", factorisations=2217483,
-                  fetch_kib=31730681076.5625, write_kib=25081074168.09375,
-                  copy_fetch_kib=524307.3125, copy_write_kib=1048576.0,
+LU_TRAFFIC = dict(source_sha256_16="3dae3a559862c5c6", factorisations=2217483,
+                  fetch_kib=32023448784.25, write_kib=25146651497.5,
+                  copy_fetch_kib=524307.8125, copy_write_kib=1048576.0,
                   copy_bytes=1 << 30)
 
 
