@@ -778,7 +778,7 @@ struct Engine {
     HIPCHK(hipStreamSynchronize(st));
     for (int k = 0; k < PH_COUNT; ++k) cnt[k] = h_counts[k];
     if (h_counts[PH_COUNT] != 0)
-      return fail(CS_EDEVICE, "internal: a factorisation launch had fewer workgroups than systems");
+      return fail(CS_EDEVICE, "internal: a per-slot launch had fewer workgroups than slots with work");
     if (dyn_finished) dyn_busy = false;
     assigned = std::min<long long>((long long)*h_next, N);
     const int ready = cnt[PH_DYN] + cnt[PH_DONE];
