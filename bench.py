@@ -110,7 +110,8 @@ def main():
     ap.add_argument("--graph", type=int, default=0,
                     help="Newton steps replayed from a captured HIP graph per round (0: eager)")
     ap.add_argument("--overlap", type=int, default=0,
-                    help="1: dynamic stage on a second stream beside the OPF iterations")
+                    help="1: dynamic stage on a second stream beside the OPF iterations; "
+                         "2: the same, started only in the OPF tail at the end of a list")
     ap.add_argument("--c3-slice", type=int, default=14408,
                     help="scenarios of the converter case (c3_118) screened in FP64 and "
                          "mixed after the headline legs (0: skip)")
